@@ -1,0 +1,210 @@
+/*
+ * fcfc.h -- C ABI of the MI355X (gfx950) exact pair-counting library.
+ *
+ * The library counts pairs of 3-D points into separation histograms, the
+ * kernel of every two-point correlation function estimator (DD, DR, RR):
+ *   - separations s, (s, mu) or (s_perp, pi) as defined in Sect. 2.5 of
+ *     Zhao, "Fast Correlation Function Calculator" (FCFC), with the line of
+ *     sight e_z or the pair mid-point s1 + s2;
+ *   - half-open bins [e_k, e_k+1) tested on squared edges (Sect. 3.2), with
+ *     the index look-up table of Sect. 3.2.3 for the squared separation;
+ *   - regular-grid cells (Sect. 2.1) pruned by the largest separation, and a
+ *     periodic box handled by per-cell-pair wrap offsets (Sect. 3.1);
+ *   - auto counts take each unordered pair once (Sect. 3.1), cross counts
+ *     every ordered pair (i in catalogue 1, j in catalogue 2).
+ * Counts are exact: FP32 separations on the vector ALUs, and every pair whose
+ * FP32 value lies within a proven error band of a bin edge is re-evaluated
+ * with the FP64 definition, so int64 counts equal those of an FP64 evaluation
+ * of the definition bit for bit.  Weighted counts are exact sums of the FP64
+ * products w_i*w_j rounded once to FP64.
+ *
+ * Conventions shared by every entry point:
+ *   - Return value: FCFC_OK (0) or a negative fcfc_status; nothing aborts.
+ *     fcfc_last_error() gives a thread-local text for the last failure.
+ *   - Catalogue arrays are DEVICE pointers owned by the caller: positions
+ *     N x 3 row-major float64, weights N float64 (or NULL).  The library
+ *     never frees them and keeps no reference to them after the call that
+ *     reads them returns; it copies what it needs into cell structures.
+ *   - Histogram outputs are DEVICE pointers, row-major [n1][n2] (first
+ *     dimension s or s_perp, second mu or pi; n2 = 1 for s), OVERWRITTEN.
+ *   - `stream` is a hipStream_t passed as void* (NULL = default stream).  Work
+ *     is enqueued on it; calls return before the GPU finishes unless stated.
+ *   - On an error detected on the host, nothing is enqueued and outputs are
+ *     left untouched.
+ *   - Plans and cell sets are immutable once built; concurrent counts on
+ *     different streams may share them.
+ */
+#ifndef FCFC_H
+#define FCFC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t fcfc_status;
+#define FCFC_OK 0
+#define FCFC_EINVAL -1      /* bad argument (null pointer, unknown enum, bad size) */
+#define FCFC_ENOMEM -2      /* device or host allocation failed */
+#define FCFC_EBOX -3        /* a point lies outside [0,L) (periodic) or the plan's bounds (open) */
+#define FCFC_ENONFINITE -4  /* NaN or Inf in positions or weights */
+#define FCFC_ERANGE -5      /* s_max > L/2, too many bins for LDS, weight range too wide, ... */
+#define FCFC_EEDGES -6      /* edges not strictly increasing, negative, mu edge > 1, non-uniform mu */
+#define FCFC_EGRID -7       /* cell sets were not built on the same plan */
+#define FCFC_EHIP -8        /* a HIP runtime call failed */
+#define FCFC_EMODEL -9      /* scheduler model unusable (the analytic fallback is used) */
+#define FCFC_ESTATE -10     /* call out of order (e.g. open box without bounds) */
+
+/* separation binning (Sect. 2.5) */
+#define FCFC_BIN_S 0         /* s */
+#define FCFC_BIN_S_MU 1      /* (s, mu), mu = pi / s in [0,1] */
+#define FCFC_BIN_SPERP_PI 2  /* (s_perp, pi) */
+
+/* line of sight (Sect. 2.5) */
+#define FCFC_LOS_Z 0         /* l = e_z (simulation boxes) */
+#define FCFC_LOS_MIDPOINT 1  /* l = s1 + s2 (observed catalogues; open boxes only) */
+
+/* work-list order */
+#define FCFC_ORDER_BUILT 0       /* enumeration order */
+#define FCFC_ORDER_HEURISTIC 1   /* longest-first by the analytic cost model */
+#define FCFC_ORDER_LEARNED 2     /* longest-first by the loaded MLP (falls back to 1) */
+
+typedef struct fcfc_plan_s *fcfc_plan_t;
+typedef struct fcfc_cells_s *fcfc_cells_t;
+typedef struct fcfc_batch_s *fcfc_batch_t;
+
+/* A catalogue: device pointers owned by the caller. */
+typedef struct {
+    const double *xyz;  /* n x 3, row-major float64 */
+    const double *w;    /* n float64 weights, or NULL */
+    int64_t n;
+} fcfc_catalog;
+
+/* Tuning knobs; zero means "choose".  Counts never depend on them. */
+typedef struct {
+    int32_t cells_per_rmax;  /* k: cell side = r_prune / k, 1..8 */
+    int32_t tile_points;     /* A points per wavefront tile: 64 or 128 */
+    int32_t seg_cells;       /* consecutive A cells a tile may span, 1..64 */
+    int32_t b_chunk;         /* max B points per work item, >= 256 */
+    int32_t hist_copies;     /* LDS histogram copies per workgroup: 1, 2 or 4 */
+    int32_t order;           /* FCFC_ORDER_* */
+    int32_t record_timing;   /* 1: record per-item GPU time (training data) */
+    int32_t n_hint;          /* expected catalogue size, for automatic choices */
+    int32_t lut_log2;        /* log2 of the look-up table length target, 10..15 */
+    int32_t reserved[7];
+} fcfc_tuning;
+
+/* Statistics of the last count on a plan (host copy; see fcfc_plan_stats). */
+typedef struct {
+    int64_t items;           /* work items (A tile x B row piece) */
+    int64_t candidates;      /* pair separations evaluated in FP32 */
+    int64_t rechecks;        /* pairs re-evaluated in FP64 near an edge */
+    int64_t in_range;        /* pairs counted (sum of the histogram) */
+    int64_t cells;           /* grid cells */
+    int32_t grid[3];         /* cells per axis */
+    int32_t cells_per_rmax;  /* k actually used */
+    double cell_side;        /* cell side length */
+    double kernel_ms;        /* duration of the counting kernel (HIP events) */
+    double band_d2_rel;      /* widest FP32 error band, relative to its edge */
+    int32_t lut_entries;     /* squared-separation look-up table length */
+    int32_t wg_per_cu;       /* resident counting workgroups per CU */
+} fcfc_stats;
+
+/*
+ * fcfc_plan_create -- validate the bins and box and fix every host-side
+ * choice: squared edges E_k = e_k*e_k (Sect. 3.2.1), the squared-separation
+ * look-up table with its FP32 error bands (Sect. 3.2.3), the prune radius
+ * (s_max, or sqrt(s_perp_max^2 + pi_max^2)), and, for a periodic box, the grid.
+ *   kind     FCFC_BIN_*; los FCFC_LOS_* (ignored for FCFC_BIN_S).
+ *   edges1   host array of n1+1 strictly increasing, non-negative s or s_perp edges.
+ *   edges2   host array of n2+1 edges: mu edges k/n2 (k = 0..n2) for S_MU,
+ *            pi edges for SPERP_PI; NULL and n2 = 0 for S.
+ *   box_L    > 0: periodic cube [0,L)^3 (needs prune radius <= L/2); 0: open box.
+ *   tune     NULL or knobs.
+ * Errors: FCFC_EINVAL, FCFC_EEDGES, FCFC_ERANGE (prune radius > L/2, or the
+ * histogram does not fit in LDS), FCFC_ENOMEM.  Host only; no GPU work.
+ */
+fcfc_status fcfc_plan_create(int32_t kind, int32_t los, const double *edges1, int32_t n1,
+                             const double *edges2, int32_t n2, double box_L,
+                             const fcfc_tuning *tune, fcfc_plan_t *out);
+
+/*
+ * fcfc_plan_fit_bounds -- open box: compute on the GPU the axis-aligned
+ * bounding box of all given catalogues (the first pass of the grid build,
+ * Sect. 2.1) and fix the grid over it.  Synchronises `stream` once.
+ * Errors: FCFC_ESTATE (periodic plan or grid already fixed), FCFC_ENONFINITE,
+ * FCFC_ERANGE (mid-point line of sight with the origin inside the box), FCFC_EHIP.
+ */
+fcfc_status fcfc_plan_fit_bounds(fcfc_plan_t plan, const fcfc_catalog *cats, int32_t ncat,
+                                 void *stream);
+
+/*
+ * fcfc_plan_set_bounds -- open box: fix the grid over the given host box
+ * lo[3]..hi[3] instead.  Errors: FCFC_ESTATE, FCFC_EINVAL, FCFC_ERANGE.
+ */
+fcfc_status fcfc_plan_set_bounds(fcfc_plan_t plan, const double lo[3], const double hi[3]);
+
+/*
+ * fcfc_build_cells -- validate a catalogue and build its cell list on the GPU
+ * (Sect. 2.1: cell key per point, stable radix sort by key, cell offsets),
+ * keeping cell-local FP32 coordinates for the distance kernel, FP64
+ * coordinates for the edge recheck and sorted weights.  The result owns its
+ * device memory (release with fcfc_cells_free).  Synchronises `stream` once
+ * to read the validation flags.
+ * Errors: FCFC_ESTATE (open plan without bounds), FCFC_ENONFINITE, FCFC_EBOX,
+ * FCFC_EINVAL, FCFC_ENOMEM, FCFC_EHIP.
+ */
+fcfc_status fcfc_build_cells(fcfc_plan_t plan, const fcfc_catalog *cat, void *stream,
+                             fcfc_cells_t *out);
+
+/*
+ * fcfc_count_pairs -- count pairs into histograms.
+ *   c2 == NULL: auto count of c1 (each unordered pair once).
+ *   d_counts:   device int64 [n1*n2], overwritten.
+ *   d_wcounts:  device float64 [n1*n2] or NULL; requires weights in both
+ *               cell sets.  Exact sum of w_i*w_j rounded once.
+ * Builds the work list (A tile x B row pieces of the pruned stencil) on the
+ * GPU, orders it, runs the persistent counting kernel and the final merge.
+ * Synchronises `stream` once to size the work list.
+ * Errors: FCFC_EGRID (cell sets from different plans), FCFC_EINVAL
+ * (weights requested but missing), FCFC_ERANGE (weight dynamic range too
+ * wide for exact accumulation), FCFC_ENOMEM, FCFC_EHIP.
+ */
+fcfc_status fcfc_count_pairs(fcfc_plan_t plan, fcfc_cells_t c1, fcfc_cells_t c2,
+                             int64_t *d_counts, double *d_wcounts, void *stream);
+
+/* Statistics of the last fcfc_count_pairs on this plan (synchronises the
+ * stream that count ran on).  Errors: FCFC_EINVAL, FCFC_ESTATE. */
+fcfc_status fcfc_plan_stats(fcfc_plan_t plan, fcfc_stats *out);
+
+/*
+ * fcfc_count_pairs_batched -- auto counts of many catalogues on one periodic
+ * plan in one pipeline: one segmented cell build keyed by (catalogue, cell),
+ * one work list, one persistent counting launch writing ncat histograms
+ * (d_counts is ncat x n1*n2 int64, d_wcounts likewise or NULL).  With
+ * use_graph the whole pipeline is captured into a HIP graph on first use and
+ * replayed afterwards (the catalogue pointers and sizes must then stay the
+ * same).  Synchronises `stream` once when (re)planning.
+ * Errors: as fcfc_build_cells and fcfc_count_pairs; FCFC_ESTATE for an open plan.
+ */
+fcfc_status fcfc_batch_create(fcfc_plan_t plan, const fcfc_catalog *cats, int32_t ncat,
+                              void *stream, fcfc_batch_t *out);
+fcfc_status fcfc_batch_run(fcfc_batch_t batch, int64_t *d_counts, double *d_wcounts,
+                           int32_t use_graph, void *stream);
+void fcfc_batch_free(fcfc_batch_t batch);
+
+void fcfc_cells_free(fcfc_cells_t cells);
+void fcfc_plan_free(fcfc_plan_t plan);
+
+/* Number of points and grid cells of a cell set (host values). */
+fcfc_status fcfc_cells_info(fcfc_cells_t cells, int64_t *n_points, int64_t *n_cells);
+
+const char *fcfc_status_str(fcfc_status s);
+const char *fcfc_last_error(void);
+int32_t fcfc_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FCFC_H */

@@ -1,0 +1,569 @@
+// build.hip -- GPU cell-list construction (Sect. 2.1): bounding box, cell key
+// per point with validation, stable LSD radix sort of (key, index), gather
+// into cell-local FP32 / FP64 arrays, and cell offsets.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+
+#include "internal.h"
+
+namespace fcfc {
+
+// ---------------------------------------------------------------------------
+// small utilities
+// ---------------------------------------------------------------------------
+__global__ void k_fill_u32(uint32_t* p, uint32_t v, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; i < n; i += stride) p[i] = v;
+}
+__global__ void k_fill_u64(uint64_t* p, uint64_t v, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; i < n; i += stride) p[i] = v;
+}
+
+static int grid_for(int64_t n, int block = 256, int cap = 65536) {
+    int64_t g = (n + block - 1) / block;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (int)g;
+}
+
+void fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t st) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(n)), dim3(256), 0, st, p, v, n);
+}
+void fill_u64(uint64_t* p, uint64_t v, int64_t n, hipStream_t st) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(n)), dim3(256), 0, st, p, v, n);
+}
+
+int device_cu_count() {
+    int dev = 0, cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 256;
+    if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 256;
+    return cu > 0 ? cu : 256;
+}
+
+// order-preserving map of a double to uint64 (for atomic min/max)
+__device__ inline uint64_t ord_bits(double x) {
+    uint64_t b = (uint64_t)__double_as_longlong(x);
+    return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
+}
+static double ord_value(uint64_t b) {
+    uint64_t r = (b >> 63) ? (b & 0x7FFFFFFFFFFFFFFFull) : ~b;
+    double x;
+    memcpy(&x, &r, 8);
+    return x;
+}
+
+// ---------------------------------------------------------------------------
+// exclusive scan of uint32 (2048 elements per block, recursive on block sums)
+// ---------------------------------------------------------------------------
+constexpr int SCAN_T = 256, SCAN_I = 8, SCAN_TILE = SCAN_T * SCAN_I;
+
+__device__ inline uint32_t block_exclusive_scan(uint32_t v, uint32_t* sh, uint32_t* total) {
+    // sh: SCAN_T entries
+    int t = threadIdx.x;
+    sh[t] = v;
+    __syncthreads();
+    for (int off = 1; off < SCAN_T; off <<= 1) {
+        uint32_t a = (t >= off) ? sh[t - off] : 0u;
+        __syncthreads();
+        sh[t] += a;
+        __syncthreads();
+    }
+    uint32_t incl = sh[t];
+    *total = sh[SCAN_T - 1];
+    __syncthreads();
+    return incl - v;
+}
+
+__global__ __launch_bounds__(SCAN_T) void k_scan_block(const uint32_t* __restrict__ in,
+                                                       uint32_t* __restrict__ out, int64_t n,
+                                                       uint32_t* __restrict__ bsum) {
+    __shared__ uint32_t sh[SCAN_T];
+    int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_I;
+    uint32_t v[SCAN_I];
+    uint32_t s = 0;
+#pragma unroll
+    for (int i = 0; i < SCAN_I; i++) {
+        v[i] = (base + i < n) ? in[base + i] : 0u;
+        s += v[i];
+    }
+    uint32_t tot;
+    uint32_t pre = block_exclusive_scan(s, sh, &tot);
+#pragma unroll
+    for (int i = 0; i < SCAN_I; i++) {
+        if (base + i < n) out[base + i] = pre;
+        pre += v[i];
+    }
+    if (threadIdx.x == 0 && bsum) bsum[blockIdx.x] = tot;
+}
+
+__global__ void k_scan_add(uint32_t* __restrict__ out, int64_t n, const uint32_t* __restrict__ boff) {
+    int64_t i = (int64_t)blockIdx.x * SCAN_TILE + threadIdx.x;
+    uint32_t a = boff[blockIdx.x];
+    for (int r = 0; r < SCAN_I; r++, i += SCAN_T)
+        if (i < n) out[i] += a;
+}
+
+__global__ void k_scan_total(const uint32_t* in, const uint32_t* out, int64_t n, uint32_t* total) {
+    *total = (n > 0) ? out[n - 1] + in[n - 1] : 0u;
+}
+
+size_t scan_scratch_bytes(int64_t n) {
+    size_t b = 0;
+    int64_t m = n;
+    while (m > SCAN_TILE) {
+        m = (m + SCAN_TILE - 1) / SCAN_TILE;
+        b += 2 * ((size_t)m * 4 + 256);
+    }
+    return b + 256;
+}
+
+// out may alias in only when n <= SCAN_TILE
+void scan_exclusive_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total_dev,
+                        void* scratch, hipStream_t st) {
+    if (n <= 0) {
+        if (total_dev) fill_u32(total_dev, 0u, 1, st);
+        return;
+    }
+    int64_t nb = (n + SCAN_TILE - 1) / SCAN_TILE;
+    if (nb == 1) {
+        hipLaunchKernelGGL(k_scan_block, dim3(1), dim3(SCAN_T), 0, st, in, out, n, (uint32_t*)nullptr);
+    } else {
+        uint32_t* bs = (uint32_t*)scratch;
+        uint32_t* bo = bs + ((nb * 4 + 256) / 4);
+        void* rest = (void*)(bo + ((nb * 4 + 256) / 4));
+        hipLaunchKernelGGL(k_scan_block, dim3((unsigned)nb), dim3(SCAN_T), 0, st, in, out, n, bs);
+        scan_exclusive_u32(bs, bo, nb, nullptr, rest, st);
+        hipLaunchKernelGGL(k_scan_add, dim3((unsigned)nb), dim3(SCAN_T), 0, st, out, n, bo);
+    }
+    if (total_dev) hipLaunchKernelGGL(k_scan_total, dim3(1), dim3(1), 0, st, in, out, n, total_dev);
+}
+
+// ---------------------------------------------------------------------------
+// stable LSD radix sort of (key, value) pairs, 8-bit digits
+// ---------------------------------------------------------------------------
+constexpr int RS_T = 256, RS_I = 8, RS_TILE = RS_T * RS_I, RS_WAVES = RS_T / 64;
+
+__global__ __launch_bounds__(RS_T) void k_rs_hist(const uint32_t* __restrict__ keys, int64_t n, int shift,
+                                                  uint32_t* __restrict__ hist, int nblk) {
+    __shared__ uint32_t cnt[256];
+    cnt[threadIdx.x] = 0;
+    __syncthreads();
+    int64_t base = (int64_t)blockIdx.x * RS_TILE;
+    for (int r = 0; r < RS_I; r++) {
+        int64_t i = base + r * RS_T + threadIdx.x;
+        if (i < n) atomicAdd(&cnt[(keys[i] >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    hist[(int64_t)threadIdx.x * nblk + blockIdx.x] = cnt[threadIdx.x];
+}
+
+__global__ __launch_bounds__(RS_T) void k_rs_scatter(const uint32_t* __restrict__ kin,
+                                                     const uint32_t* __restrict__ vin,
+                                                     uint32_t* __restrict__ kout,
+                                                     uint32_t* __restrict__ vout, int64_t n, int shift,
+                                                     const uint32_t* __restrict__ offs, int nblk) {
+    __shared__ uint32_t run[256];
+    __shared__ uint32_t wcnt[RS_WAVES][256];
+    int t = threadIdx.x;
+    int lane = t & 63, w = t >> 6;
+    run[t] = offs[(int64_t)t * nblk + blockIdx.x];
+    for (int q = 0; q < RS_WAVES; q++) wcnt[q][t] = 0;
+    __syncthreads();
+    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    int64_t base = (int64_t)blockIdx.x * RS_TILE;
+    for (int r = 0; r < RS_I; r++) {
+        int64_t i = base + r * RS_T + t;
+        bool valid = i < n;
+        uint32_t key = valid ? kin[i] : 0u;
+        uint32_t d = (key >> shift) & 255u;
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; b++) {
+            bool bit = (d >> b) & 1u;
+            uint64_t m = __ballot(bit);
+            peers &= bit ? m : ~m;
+        }
+        uint32_t rank = (uint32_t)__popcll(peers & lt);
+        if (valid && rank == 0) wcnt[w][d] = (uint32_t)__popcll(peers);
+        __syncthreads();
+        if (valid) {
+            uint32_t pos = run[d] + rank;
+            for (int q = 0; q < w; q++) pos += wcnt[q][d];
+            kout[pos] = key;
+            vout[pos] = vin[i];
+        }
+        __syncthreads();
+        uint32_t add = 0;
+        for (int q = 0; q < RS_WAVES; q++) {
+            add += wcnt[q][t];
+            wcnt[q][t] = 0;
+        }
+        run[t] += add;
+        __syncthreads();
+    }
+}
+
+size_t radix_scratch_bytes(int64_t n) {
+    int64_t nblk = std::max<int64_t>(1, (n + RS_TILE - 1) / RS_TILE);
+    size_t h = (size_t)nblk * 256 * 4 + 256;
+    return 2 * h + scan_scratch_bytes(nblk * 256);
+}
+
+// Sorts by the low key_bits bits.  Ping-pongs between (k,v) and (tk,tv); on
+// return k/v point at the sorted arrays (pointers may be swapped).
+void radix_sort_pairs(uint32_t** k, uint32_t** v, uint32_t** tk, uint32_t** tv, int64_t n, int key_bits,
+                      void* scratch, hipStream_t st) {
+    if (n <= 1) return;
+    int nblk = (int)((n + RS_TILE - 1) / RS_TILE);
+    uint32_t* hist = (uint32_t*)scratch;
+    uint32_t* offs = hist + (((size_t)nblk * 256 * 4 + 256) / 4);
+    void* sscr = (void*)(offs + (((size_t)nblk * 256 * 4 + 256) / 4));
+    for (int shift = 0; shift < key_bits; shift += 8) {
+        hipLaunchKernelGGL(k_rs_hist, dim3(nblk), dim3(RS_T), 0, st, *k, n, shift, hist, nblk);
+        scan_exclusive_u32(hist, offs, (int64_t)nblk * 256, nullptr, sscr, st);
+        hipLaunchKernelGGL(k_rs_scatter, dim3(nblk), dim3(RS_T), 0, st, *k, *v, *tk, *tv, n, shift, offs, nblk);
+        std::swap(*k, *tk);
+        std::swap(*v, *tv);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// bounding box over catalogues
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_aabb(const double* __restrict__ xyz, int64_t n,
+                                              uint64_t* __restrict__ mm /*lo[3], hi[3] ord bits*/,
+                                              uint32_t* __restrict__ flags) {
+    __shared__ uint64_t smin[3][256], smax[3][256];
+    __shared__ uint32_t sflag;
+    if (threadIdx.x == 0) sflag = 0;
+    uint64_t lo[3] = {~0ull, ~0ull, ~0ull}, hi[3] = {0, 0, 0};
+    uint32_t f = 0;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        for (int a = 0; a < 3; a++) {
+            double x = xyz[3 * i + a];
+            if (!isfinite(x)) {
+                f |= 1u;
+                continue;
+            }
+            uint64_t b = ord_bits(x);
+            lo[a] = b < lo[a] ? b : lo[a];
+            hi[a] = b > hi[a] ? b : hi[a];
+        }
+    }
+    for (int a = 0; a < 3; a++) {
+        smin[a][threadIdx.x] = lo[a];
+        smax[a][threadIdx.x] = hi[a];
+    }
+    __syncthreads();
+    if (f) atomicOr(&sflag, f);
+    for (int off = 128; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) {
+            for (int a = 0; a < 3; a++) {
+                uint64_t x = smin[a][threadIdx.x + off], y = smax[a][threadIdx.x + off];
+                if (x < smin[a][threadIdx.x]) smin[a][threadIdx.x] = x;
+                if (y > smax[a][threadIdx.x]) smax[a][threadIdx.x] = y;
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        for (int a = 0; a < 3; a++) {
+            atomicMin((unsigned long long*)&mm[a], (unsigned long long)smin[a][0]);
+            atomicMax((unsigned long long*)&mm[3 + a], (unsigned long long)smax[a][0]);
+        }
+        if (sflag) atomicOr(flags, sflag);
+    }
+}
+
+fcfc_status fit_bounds(Plan* p, const fcfc_catalog* cats, int ncat, hipStream_t st) {
+    uint64_t* d = nullptr;
+    FCFC_HIP(hipMallocAsync((void**)&d, 64, st));
+    uint32_t* flags = (uint32_t*)(d + 6);
+    uint64_t init[7];
+    for (int a = 0; a < 3; a++) {
+        init[a] = ~0ull;
+        init[3 + a] = 0ull;
+    }
+    init[6] = 0;
+    int64_t total = 0;
+    fill_u64(d, ~0ull, 3, st);
+    fill_u64(d + 3, 0ull, 4, st);
+    for (int c = 0; c < ncat; c++) {
+        if (cats[c].n <= 0) continue;
+        total += cats[c].n;
+        int g = grid_for(cats[c].n, 256, 4096);
+        hipLaunchKernelGGL(k_aabb, dim3(g), dim3(256), 0, st, cats[c].xyz, cats[c].n, d, flags);
+    }
+    uint64_t h[7];
+    hipError_t e1 = hipMemcpyAsync(h, d, 56, hipMemcpyDeviceToHost, st);
+    hipError_t e2 = hipStreamSynchronize(st);
+    (void)hipFreeAsync(d, st);
+    if (e1 != hipSuccess || e2 != hipSuccess) {
+        set_error("fit_bounds: %s", hipGetErrorString(e1 != hipSuccess ? e1 : e2));
+        return FCFC_EHIP;
+    }
+    if ((uint32_t)h[6] & 1u) {
+        set_error("fit_bounds: non-finite coordinate");
+        return FCFC_ENONFINITE;
+    }
+    double lo[3], hi[3];
+    if (total == 0) {
+        for (int a = 0; a < 3; a++) {
+            lo[a] = 0;
+            hi[a] = 1;
+        }
+    } else {
+        for (int a = 0; a < 3; a++) {
+            lo[a] = ord_value(h[a]);
+            hi[a] = ord_value(h[3 + a]);
+        }
+    }
+    return fcfc_set_bounds_internal(p, lo, hi);
+}
+
+// ---------------------------------------------------------------------------
+// cell keys + validation
+// ---------------------------------------------------------------------------
+struct GridArgs {
+    int nx, ny, nz;
+    double lox, loy, loz;
+    double hix, hiy, hiz;  // open box upper bounds (inclusive)
+    double side;
+    double L;
+};
+
+enum : uint32_t { VF_NONFINITE = 1u, VF_BOX = 2u, VF_WNONFINITE = 4u };
+
+__device__ inline int cell_of(double x, double lo, double side, int n) {
+    double f = floor((x - lo) / side);
+    int c = (f < 0.0) ? 0 : ((f > (double)(n - 1)) ? n - 1 : (int)f);
+    return c;
+}
+
+__global__ __launch_bounds__(256) void k_keys(const double* __restrict__ xyz, const double* __restrict__ w,
+                                              int64_t n, GridArgs g, uint32_t* __restrict__ key,
+                                              uint32_t* __restrict__ idx, uint32_t* __restrict__ flags,
+                                              uint64_t* __restrict__ wst /*[0] min nonzero |w|, [1] max*/) {
+    __shared__ uint32_t sflag;
+    __shared__ uint64_t swmin, swmax;
+    if (threadIdx.x == 0) {
+        sflag = 0;
+        swmin = ~0ull;
+        swmax = 0;
+    }
+    __syncthreads();
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t f = 0;
+    if (i < n) {
+        double x = xyz[3 * i], y = xyz[3 * i + 1], z = xyz[3 * i + 2];
+        if (!isfinite(x) || !isfinite(y) || !isfinite(z)) {
+            f |= VF_NONFINITE;
+        } else if (g.L > 0) {
+            if (!(x >= 0.0 && x < g.L && y >= 0.0 && y < g.L && z >= 0.0 && z < g.L)) f |= VF_BOX;
+        } else {
+            if (!(x >= g.lox && x <= g.hix && y >= g.loy && y <= g.hiy && z >= g.loz && z <= g.hiz)) f |= VF_BOX;
+        }
+        uint32_t cx = 0, cy = 0, cz = 0;
+        if (!f) {
+            cx = cell_of(x, g.lox, g.side, g.nx);
+            cy = cell_of(y, g.loy, g.side, g.ny);
+            cz = cell_of(z, g.loz, g.side, g.nz);
+        }
+        key[i] = (cz * (uint32_t)g.ny + cy) * (uint32_t)g.nx + cx;
+        idx[i] = (uint32_t)i;
+        if (w) {
+            double wv = w[i];
+            if (!isfinite(wv)) {
+                f |= VF_WNONFINITE;
+            } else {
+                double a = fabs(wv);
+                uint64_t b = (uint64_t)__double_as_longlong(a);  // positive: bits are ordered
+                if (a > 0.0) atomicMin((unsigned long long*)&swmin, (unsigned long long)b);
+                atomicMax((unsigned long long*)&swmax, (unsigned long long)b);
+            }
+        }
+        if (f) atomicOr(&sflag, f);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        if (sflag) atomicOr(flags, sflag);
+        if (w) {
+            if (swmin != ~0ull) atomicMin((unsigned long long*)&wst[0], (unsigned long long)swmin);
+            atomicMax((unsigned long long*)&wst[1], (unsigned long long)swmax);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// gather sorted points into cell-local FP32, absolute FP32, FP64, weights
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_gather(const double* __restrict__ xyz, const double* __restrict__ w,
+                                                const uint32_t* __restrict__ skey,
+                                                const uint32_t* __restrict__ sidx, int64_t n, GridArgs g,
+                                                float4* __restrict__ pos32, float4* __restrict__ abs32,
+                                                double* __restrict__ pos64, double* __restrict__ wout) {
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    uint32_t i = sidx[p];
+    uint32_t key = skey[p];
+    uint32_t cx = key % (uint32_t)g.nx;
+    uint32_t cy = (key / (uint32_t)g.nx) % (uint32_t)g.ny;
+    uint32_t cz = key / ((uint32_t)g.nx * (uint32_t)g.ny);
+    double x = xyz[3 * (int64_t)i], y = xyz[3 * (int64_t)i + 1], z = xyz[3 * (int64_t)i + 2];
+    double ox = g.lox + (double)cx * g.side;
+    double oy = g.loy + (double)cy * g.side;
+    double oz = g.loz + (double)cz * g.side;
+    pos32[p] = make_float4((float)(x - ox), (float)(y - oy), (float)(z - oz), __int_as_float((int)cx));
+    if (abs32) abs32[p] = make_float4((float)x, (float)y, (float)z, 0.f);
+    pos64[3 * p] = x;
+    pos64[3 * p + 1] = y;
+    pos64[3 * p + 2] = z;
+    if (wout) wout[p] = w[i];
+}
+
+__global__ void k_cell_start(const uint32_t* __restrict__ skey, int64_t n, int64_t ncell,
+                             uint32_t* __restrict__ cs) {
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p > n) return;
+    int64_t kprev = (p == 0) ? -1 : (int64_t)skey[p - 1];
+    int64_t kcur = (p == n) ? ncell : (int64_t)skey[p];
+    for (int64_t c = kprev + 1; c <= kcur; c++) cs[c] = (uint32_t)p;
+}
+
+static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+static GridArgs make_grid_args(const Plan* p) {
+    const Grid& gr = p->grid;
+    GridArgs g;
+    g.nx = gr.nx;
+    g.ny = gr.ny;
+    g.nz = gr.nz;
+    g.lox = gr.lo[0];
+    g.loy = gr.lo[1];
+    g.loz = gr.lo[2];
+    g.hix = gr.lo[0] + p->grid_ext[0];
+    g.hiy = gr.lo[1] + p->grid_ext[1];
+    g.hiz = gr.lo[2] + p->grid_ext[2];
+    g.side = gr.side;
+    g.L = gr.L;
+    return g;
+}
+
+fcfc_status build_cells(Plan* p, const fcfc_catalog* cat, hipStream_t st, Cells** out) {
+    int64_t n = cat->n;
+    const Grid& gr = p->grid;
+    int64_t ncell = gr.ncell();
+    bool weighted = cat->w != nullptr;
+    bool need_abs = (p->los == FCFC_LOS_MIDPOINT && p->kind != FCFC_BIN_S);
+    // device block owned by the cell set
+    // pos32 and w carry PAD trailing entries so that grouped scalar loads never leave the block
+    const int64_t PAD = 8;
+    size_t o_pos32 = 0;
+    size_t o_abs32 = o_pos32 + align256((size_t)(n + PAD) * 16);
+    size_t o_pos64 = o_abs32 + (need_abs ? align256((size_t)n * 16) : 0);
+    size_t o_w = o_pos64 + align256((size_t)n * 24);
+    size_t o_cs = o_w + (weighted ? align256((size_t)(n + PAD) * 8) : 0);
+    size_t total = o_cs + align256((size_t)(ncell + 1) * 4);
+    Cells* c = new (std::nothrow) Cells();
+    if (!c) return FCFC_ENOMEM;
+    char* blk = nullptr;
+    if (hipMalloc((void**)&blk, total) != hipSuccess) {
+        delete c;
+        set_error("build_cells: cannot allocate %zu bytes", total);
+        return FCFC_ENOMEM;
+    }
+    c->block = blk;
+    c->plan_id = p->id;
+    c->grid = gr;
+    c->n = n;
+    c->weighted = weighted;
+    c->has_abs = need_abs;
+    c->pos32 = (float4*)(blk + o_pos32);
+    c->abs32 = need_abs ? (float4*)(blk + o_abs32) : nullptr;
+    c->pos64 = (double*)(blk + o_pos64);
+    c->w = weighted ? (double*)(blk + o_w) : nullptr;
+    c->cell_start = (uint32_t*)(blk + o_cs);
+
+    // scratch: keys, idx, tmp keys, tmp idx, flags + weight stats, sort scratch
+    size_t s_keys = align256((size_t)std::max<int64_t>(n, 1) * 4);
+    size_t s_misc = 256;
+    size_t s_sort = align256(radix_scratch_bytes(n));
+    size_t stotal = 4 * s_keys + s_misc + s_sort;
+    char* scr = nullptr;
+    if (hipMallocAsync((void**)&scr, stotal, st) != hipSuccess) {
+        (void)hipFree(blk);
+        delete c;
+        set_error("build_cells: cannot allocate scratch");
+        return FCFC_ENOMEM;
+    }
+    uint32_t* key = (uint32_t*)scr;
+    uint32_t* idx = (uint32_t*)(scr + s_keys);
+    uint32_t* tk = (uint32_t*)(scr + 2 * s_keys);
+    uint32_t* tv = (uint32_t*)(scr + 3 * s_keys);
+    uint32_t* flags = (uint32_t*)(scr + 4 * s_keys);
+    uint64_t* wst = (uint64_t*)(scr + 4 * s_keys + 64);
+    void* sort_scr = scr + 4 * s_keys + s_misc;
+
+    GridArgs g = make_grid_args(p);
+    fill_u32((uint32_t*)(c->pos32 + n), 0u, PAD * 4, st);
+    if (weighted) fill_u64((uint64_t*)(c->w + n), 0ull, PAD, st);
+    fill_u32(flags, 0u, 1, st);
+    fill_u64(wst, ~0ull, 1, st);
+    fill_u64(wst + 1, 0ull, 1, st);
+    if (n > 0) {
+        hipLaunchKernelGGL(k_keys, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, cat->xyz, cat->w, n, g,
+                           key, idx, flags, wst);
+        int bits = 0;
+        while (bits < 32 && ((int64_t)1 << bits) < ncell) bits++;
+        bits = (bits + 7) / 8 * 8;
+        radix_sort_pairs(&key, &idx, &tk, &tv, n, bits, sort_scr, st);
+        hipLaunchKernelGGL(k_gather, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, cat->xyz, cat->w, key,
+                           idx, n, g, c->pos32, c->abs32, c->pos64, c->w);
+    }
+    hipLaunchKernelGGL(k_cell_start, dim3((unsigned)((n + 1 + 255) / 256)), dim3(256), 0, st, key, n, ncell,
+                       c->cell_start);
+    uint64_t h[3] = {0, 0, 0};
+    hipError_t e1 = hipMemcpyAsync(h, flags, 8, hipMemcpyDeviceToHost, st);
+    hipError_t e2 = hipMemcpyAsync(h + 1, wst, 16, hipMemcpyDeviceToHost, st);
+    hipError_t e3 = hipStreamSynchronize(st);
+    (void)hipFreeAsync(scr, st);
+    if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
+        (void)hipFree(blk);
+        delete c;
+        set_error("build_cells: HIP error %s", hipGetErrorString(e3 != hipSuccess ? e3 : (e2 != hipSuccess ? e2 : e1)));
+        return FCFC_EHIP;
+    }
+    uint32_t fl = (uint32_t)h[0];
+    fcfc_status s = FCFC_OK;
+    if (fl & (VF_NONFINITE | VF_WNONFINITE)) {
+        set_error("build_cells: non-finite position or weight");
+        s = FCFC_ENONFINITE;
+    } else if (fl & VF_BOX) {
+        set_error(p->L > 0 ? "build_cells: a point lies outside [0, L)" : "build_cells: a point lies outside the plan bounds");
+        s = FCFC_EBOX;
+    }
+    if (s != FCFC_OK) {
+        (void)hipFree(blk);
+        delete c;
+        return s;
+    }
+    if (weighted) {
+        double a, b;
+        memcpy(&a, &h[1], 8);
+        memcpy(&b, &h[2], 8);
+        c->wmin = (h[1] == ~0ull) ? 0.0 : a;
+        c->wmax = b;
+    }
+    *out = c;
+    return FCFC_OK;
+}
+
+}  // namespace fcfc

@@ -1,0 +1,163 @@
+// internal.h -- shared definitions of the gfx950 pair-counting library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "fcfc.h"
+
+namespace fcfc {
+
+// ---------------------------------------------------------------------------
+// error reporting
+// ---------------------------------------------------------------------------
+void set_error(const char* fmt, ...);
+void clear_error();
+
+#define FCFC_HIP(call)                                                              \
+    do {                                                                            \
+        hipError_t e_ = (call);                                                     \
+        if (e_ != hipSuccess) {                                                     \
+            ::fcfc::set_error("%s:%d: %s failed: %s", __FILE__, __LINE__, #call,    \
+                              hipGetErrorString(e_));                               \
+            return FCFC_EHIP;                                                       \
+        }                                                                           \
+    } while (0)
+
+#define FCFC_TRY(expr)                       \
+    do {                                     \
+        fcfc_status s_ = (expr);             \
+        if (s_ != FCFC_OK) return s_;        \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// grid of cubic cells (Sect. 2.1): cell (cx,cy,cz) covers
+// [lo + c*side, lo + (c+1)*side) per axis; linear key (cz*ny + cy)*nx + cx, so
+// the cells of one row (fixed cy, cz) are consecutive and their points form a
+// single contiguous range after sorting.
+// ---------------------------------------------------------------------------
+struct Grid {
+    int nx = 0, ny = 0, nz = 0;
+    double lo[3] = {0, 0, 0};
+    double side = 0;      // cell side (FP64)
+    double L = 0;         // > 0 periodic
+    int k = 0;            // cells per prune radius used to size the grid
+    int64_t ncell() const { return (int64_t)nx * ny * nz; }
+};
+
+// A work item: one A tile (consecutive sorted points of one row, spanning at
+// most a few cells) against one contiguous piece of one B row.  32 bytes.
+struct Item {
+    uint32_t a_begin;   // first A point (sorted index)
+    uint32_t b_begin;   // first B point
+    uint32_t b_end;     // one past the last B point
+    uint32_t b_rowcell; // linear index of cell (x = 0) of the B row
+    uint32_t acnt_xb0;  // bits 0..15: A point count; bits 16..31: int16 unwrapped x of first B cell
+    uint32_t meta;      // int8 dy | int8 dz << 8 | (sx+1) << 16 | (sy+1) << 18 | (sz+1) << 20 | flags << 24
+    uint32_t cost;      // ordering key
+    uint32_t tile;      // A tile index (features, batched catalogue lookup)
+};
+static_assert(sizeof(Item) == 32, "Item must be 32 bytes");
+
+enum : uint32_t { ITEM_SAMEROW = 1u };
+
+// ---------------------------------------------------------------------------
+// FP32 look-up table over a squared quantity v (Sect. 3.2.3):
+// entry j = (uint)(v * scale) covers [j/scale, (j+1)/scale).  A clean entry
+// holds the bin (or NONE); a hot entry (bit 15) holds the first edge whose
+// error band [lo_k, hi_k) meets the entry.
+// ---------------------------------------------------------------------------
+enum : uint16_t { LUT_HOT = 0x8000u, LUT_NONE = 0x7FFFu };
+
+struct Lut1D {
+    int n = 0;                 // bins
+    std::vector<double> E;     // n+1 squared edges (FP64)
+    std::vector<float> lo, hi; // n+1 FP32 band ends: v < lo_k => V < E_k; v >= hi_k => V >= E_k
+    std::vector<uint16_t> tab; // entries
+    float scale = 1.f;         // power of two
+    float vmax = 0.f;          // hi_n: v >= vmax is out of range
+    double band_rel = 0;       // widest band half-width relative to its edge
+};
+
+// error model |Q32 - Q64| <= A*sqrt(Q) + B + C*Q for a squared quantity Q
+struct ErrModel {
+    double A = 0, B = 0, C = 0;
+    double operator()(double Q) const { return A * __builtin_sqrt(Q > 0 ? Q : 0) + B + C * Q; }
+};
+
+struct Plan {
+    int kind = 0, los = 0;
+    int n1 = 0, n2 = 1, nbins = 0;
+    std::vector<double> e1, e2;
+    double L = 0;               // > 0 periodic
+    double rprune = 0;          // prune radius (FP64)
+    fcfc_tuning tune{};
+    bool grid_set = false;
+    Grid grid;
+    double grid_ext[3] = {0, 0, 0};  // open box: extent of the bounds per axis
+    double obs_dist = 0;        // open box: distance from the origin to the box
+    double coord_max = 0;       // largest |coordinate| inside the box
+    // bands and tables, set by finalize_numerics() once the grid is known
+    bool numerics_ready = false;
+    double e_axis = 0;          // bound on the FP32 error of one displacement component
+    Lut1D lut1, lut2;           // s (or s_perp) and pi tables
+    float r2prune32 = 0;        // FP32 candidate threshold (>= every relevant value)
+    float d2small = 0;          // pairs closer than this are always rechecked (mu)
+    float mu_tolA = 0, mu_tolB = 0, mu_tolC = 0;  // mu band: n*(A*rs + B*rs^2 + C)
+    bool mu_top_closed = true;
+    uint64_t id = 0;            // unique plan id (cells remember it)
+    // stats of the last count
+    fcfc_stats stats{};
+    void* stats_dev = nullptr; // device u64[4]: candidates, rechecks, items, in_range
+    hipStream_t last_stream = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    bool have_stats = false;
+    int64_t* last_counts = nullptr;  // device histogram of the last count (for stats)
+    void* timing_dev = nullptr;      // last recorded per-item times (u32) followed by the items
+    uint32_t timing_n = 0;
+    int last_pts = 0;
+    // learned scheduler (optional)
+    std::vector<float> mlp_host; // packed weights, empty if none
+    void* mlp_dev = nullptr;
+    int mlp_ok = 0;
+};
+
+struct Cells {
+    uint64_t plan_id = 0;
+    Grid grid;
+    int64_t n = 0;
+    bool weighted = false;
+    bool has_abs = false;
+    double wmin = 0, wmax = 0;  // smallest non-zero |w|, largest |w|
+    float4* pos32 = nullptr;    // cell-local FP32 (x', y', z', cellx bits)
+    float4* abs32 = nullptr;    // absolute FP32 (mid-point line of sight only)
+    double* pos64 = nullptr;    // sorted FP64 xyz (AoS)
+    double* w = nullptr;        // sorted weights
+    uint32_t* cell_start = nullptr;  // ncell + 1
+    void* block = nullptr;      // single allocation holding everything
+};
+
+// plan / numerics helpers (plan.cpp)
+const char* last_error();
+fcfc_status fcfc_set_bounds_internal(Plan* p, const double lo[3], const double hi[3]);
+fcfc_status plan_finalize_grid(Plan* p);
+fcfc_status plan_finalize_numerics(Plan* p);
+int choose_k(const Plan* p, int64_t n_hint);
+int stencil_rows(const Plan* p, bool half, std::vector<int4>& rows);  // (dy, dz, kx, 0)
+
+// build (build.hip)
+fcfc_status build_cells(Plan* p, const fcfc_catalog* cat, hipStream_t st, Cells** out);
+fcfc_status fit_bounds(Plan* p, const fcfc_catalog* cats, int ncat, hipStream_t st);
+void fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t st);
+void fill_u64(uint64_t* p, uint64_t v, int64_t n, hipStream_t st);
+
+// count (count.hip)
+fcfc_status count_pairs(Plan* p, Cells* c1, Cells* c2, int64_t* d_counts, double* d_wcounts,
+                        hipStream_t st);
+
+int device_cu_count();
+
+}  // namespace fcfc

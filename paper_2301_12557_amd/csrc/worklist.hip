@@ -1,0 +1,185 @@
+// worklist.hip -- enumeration of work items on the GPU.
+//
+// A tile is a run of at most `tile` consecutive sorted points of one A row
+// (fixed cy, cz) whose cells lie in one segment of `seg` consecutive cells.
+// For each tile and each row offset (dy, dz) of the pruned stencil, the B
+// cells that can hold a pair in range form the x range [x0 - kx, x1 + kx]
+// of the B row; since cells of a row are consecutive in the sort order their
+// points are one contiguous range.  A periodic box splits that range into at
+// most three pieces (direct, wrapped left, wrapped right), each with its own
+// image shift (the per-node-pair wrap offsets of Sect. 3.1).  Auto counts
+// use the half stencil (each unordered row pair once, Sect. 3.1) and, in the
+// A row itself, only B points after the A point (mask flag) plus the piece
+// wrapped from the right.
+#include <algorithm>
+
+#include "internal.h"
+#include "worklist.h"
+
+namespace fcfc {
+
+__device__ inline int floor_div(int a, int n) {
+    int q = a / n;
+    if ((a % n != 0) && ((a < 0) != (n < 0))) q--;
+    return q;
+}
+
+__global__ void k_tile_count(const uint32_t* __restrict__ csA, WLArgs w, uint32_t* __restrict__ tcount) {
+    int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int nseg_row = (w.nx + w.seg - 1) / w.seg;
+    int64_t nseg = (int64_t)nseg_row * w.ny * w.nz;
+    if (s >= nseg) return;
+    int64_t row = s / nseg_row;
+    int sx = (int)(s % nseg_row);
+    int x0 = sx * w.seg, x1 = min(x0 + w.seg, w.nx) - 1;
+    uint32_t p0 = csA[row * w.nx + x0], p1 = csA[row * w.nx + x1 + 1];
+    tcount[s] = (p1 - p0 + (uint32_t)w.tile - 1) / (uint32_t)w.tile;
+}
+
+__global__ void k_tile_write(const uint32_t* __restrict__ csA, const float4* __restrict__ posA, WLArgs w,
+                             const uint32_t* __restrict__ toff, Tile* __restrict__ tiles) {
+    int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int nseg_row = (w.nx + w.seg - 1) / w.seg;
+    int64_t nseg = (int64_t)nseg_row * w.ny * w.nz;
+    if (s >= nseg) return;
+    int64_t row = s / nseg_row;
+    int sx = (int)(s % nseg_row);
+    int x0 = sx * w.seg, x1 = min(x0 + w.seg, w.nx) - 1;
+    uint32_t p0 = csA[row * w.nx + x0], p1 = csA[row * w.nx + x1 + 1];
+    uint32_t t = toff[s];
+    for (uint32_t a = p0; a < p1; a += (uint32_t)w.tile, t++) {
+        uint32_t cnt = min((uint32_t)w.tile, p1 - a);
+        Tile tl;
+        tl.a_begin = a;
+        tl.a_count = cnt;
+        tl.row = (uint32_t)row;
+        int cxa = __float_as_int(posA[a].w);
+        int cxb = __float_as_int(posA[a + cnt - 1].w);
+        tl.x01 = (uint32_t)(cxa & 0xffff) | ((uint32_t)cxb << 16);
+        tiles[t] = tl;
+    }
+}
+
+// Enumerate the pieces of (tile, stencil row); emit(item) is called for
+// every work item, in a fixed order.
+template <typename F>
+__device__ inline void tile_row_items(const Tile& tl, int4 srow, const uint32_t* __restrict__ csB,
+                                      const WLArgs& w, uint32_t tile_id, F emit) {
+    int cy = (int)(tl.row % (uint32_t)w.ny), cz = (int)(tl.row / (uint32_t)w.ny);
+    int dy = srow.x, dz = srow.y, kx = srow.z;
+    int yu = cy + dy, zu = cz + dz;
+    int sy = 0, sz = 0, yb = yu, zb = zu;
+    if (w.periodic) {
+        sy = floor_div(yu, w.ny);
+        sz = floor_div(zu, w.nz);
+        if (sy < -1 || sy > 1 || sz < -1 || sz > 1) return;
+        yb = yu - sy * w.ny;
+        zb = zu - sz * w.nz;
+    } else if (yu < 0 || yu >= w.ny || zu < 0 || zu >= w.nz) {
+        return;
+    }
+    bool same = w.is_auto && dy == 0 && dz == 0;
+    int x0 = (int)(tl.x01 & 0xffff), x1 = (int)(tl.x01 >> 16);
+    int xlo = x0 - kx, xhi = x1 + kx;
+    uint32_t rowcell = ((uint32_t)zb * (uint32_t)w.ny + (uint32_t)yb) * (uint32_t)w.nx;
+    // pieces: 0 = direct, 1 = wrapped from the left (sx = -1), 2 = wrapped from the right (sx = +1)
+    for (int pc = 0; pc < 3; pc++) {
+        int c0, c1, sx;
+        if (pc == 0) {
+            c0 = max(xlo, 0);
+            c1 = min(xhi, w.nx - 1);
+            sx = 0;
+        } else if (pc == 1) {
+            if (!w.periodic || same || xlo >= 0) continue;
+            c0 = max(xlo, -w.nx) + w.nx;
+            c1 = min(xhi, -1) + w.nx;
+            sx = -1;
+        } else {
+            if (!w.periodic || xhi < w.nx) continue;
+            c0 = max(xlo, w.nx) - w.nx;
+            c1 = min(xhi, 2 * w.nx - 1) - w.nx;
+            sx = 1;
+        }
+        if (c0 > c1) continue;
+        uint32_t bb = csB[rowcell + (uint32_t)c0], be = csB[rowcell + (uint32_t)c1 + 1];
+        uint32_t flags = 0;
+        if (same && pc == 0) {
+            flags |= ITEM_SAMEROW;
+            bb = max(bb, tl.a_begin);
+        }
+        if (bb >= be) continue;
+        int xb0 = c0 + sx * w.nx;
+        uint32_t meta = ((uint32_t)(uint8_t)(int8_t)dy) | ((uint32_t)(uint8_t)(int8_t)dz << 8) |
+                        ((uint32_t)(sx + 1) << 16) | ((uint32_t)(sy + 1) << 18) | ((uint32_t)(sz + 1) << 20) |
+                        (flags << 24);
+        for (uint32_t b = bb; b < be; b += (uint32_t)w.bchunk) {
+            Item it;
+            it.a_begin = tl.a_begin;
+            it.b_begin = b;
+            it.b_end = min(be, b + (uint32_t)w.bchunk);
+            it.b_rowcell = rowcell;
+            it.acnt_xb0 = (tl.a_count & 0xffffu) | ((uint32_t)(uint16_t)(int16_t)xb0 << 16);
+            it.meta = meta;
+            uint64_t pairs = (uint64_t)tl.a_count * (uint64_t)(it.b_end - it.b_begin);
+            it.cost = (uint32_t)min<uint64_t>(pairs, 0xffffffffull);
+            it.tile = tile_id;
+            emit(it);
+        }
+    }
+}
+
+__global__ void k_item_count(const Tile* __restrict__ tiles, const uint32_t* __restrict__ ntiles_dev,
+                             const int4* __restrict__ srows, const uint32_t* __restrict__ csB, WLArgs w,
+                             uint32_t* __restrict__ icount) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t total = (int64_t)w.tiles_cap * w.nrows;
+    if (t >= total) return;
+    uint32_t ntiles = *ntiles_dev;
+    int64_t ti = t / w.nrows;
+    int r = (int)(t % w.nrows);
+    uint32_t c = 0;
+    if (ti < (int64_t)ntiles) {
+        Tile tl = tiles[ti];
+        tile_row_items(tl, srows[r], csB, w, (uint32_t)ti, [&](const Item&) { c++; });
+    }
+    icount[t] = c;
+}
+
+__global__ void k_item_write(const Tile* __restrict__ tiles, const uint32_t* __restrict__ ntiles_dev,
+                             const int4* __restrict__ srows, const uint32_t* __restrict__ csB, WLArgs w,
+                             const uint32_t* __restrict__ ioff, Item* __restrict__ items,
+                             uint32_t items_cap) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t total = (int64_t)w.tiles_cap * w.nrows;
+    if (t >= total) return;
+    uint32_t ntiles = *ntiles_dev;
+    int64_t ti = t / w.nrows;
+    int r = (int)(t % w.nrows);
+    if (ti >= (int64_t)ntiles) return;
+    Tile tl = tiles[ti];
+    uint32_t o = ioff[t];
+    tile_row_items(tl, srows[r], csB, w, (uint32_t)ti, [&](const Item& it) {
+        if (o < items_cap) items[o] = it;
+        o++;
+    });
+}
+
+// cost key for longest-first order: bitwise NOT of the cost so that an
+// ascending sort puts the largest first
+__global__ void k_item_keys(const Item* __restrict__ items, const uint32_t* __restrict__ nitems_dev,
+                            uint32_t cap, uint32_t* __restrict__ key, uint32_t* __restrict__ val) {
+    uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= cap) return;
+    uint32_t n = *nitems_dev;
+    key[i] = (i < n) ? ~items[i].cost : 0xffffffffu;
+    val[i] = i;
+}
+
+__global__ void k_item_permute(const Item* __restrict__ in, const uint32_t* __restrict__ perm,
+                               const uint32_t* __restrict__ nitems_dev, uint32_t cap, Item* __restrict__ out) {
+    uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= cap) return;
+    if (i < *nitems_dev) out[i] = in[perm[i]];
+}
+
+}  // namespace fcfc

@@ -1,0 +1,284 @@
+"""ctypes binding of libfcfc.so (include/fcfc.h) -- argument marshalling only.
+
+Every step of the pair count runs in the HIP library; this module turns torch
+device tensors into pointers and sizes and checks return codes.  If the
+library is missing it raises: there is no fallback.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "_lib", "libfcfc.so")
+
+FCFC_OK = 0
+STATUS = {0: "FCFC_OK", -1: "FCFC_EINVAL", -2: "FCFC_ENOMEM", -3: "FCFC_EBOX", -4: "FCFC_ENONFINITE",
+          -5: "FCFC_ERANGE", -6: "FCFC_EEDGES", -7: "FCFC_EGRID", -8: "FCFC_EHIP", -9: "FCFC_EMODEL",
+          -10: "FCFC_ESTATE"}
+KIND = {"s": 0, "smu": 1, "spi": 2}
+LOS = {"z": 0, "mid": 1}
+ORDER = {"built": 0, "heuristic": 1, "learned": 2}
+
+
+class FcfcError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+        self.name = STATUS.get(code, str(code))
+
+
+class Catalog(ctypes.Structure):
+    _fields_ = [("xyz", ctypes.c_void_p), ("w", ctypes.c_void_p), ("n", ctypes.c_int64)]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("cells_per_rmax", ctypes.c_int32), ("tile_points", ctypes.c_int32),
+                ("seg_cells", ctypes.c_int32), ("b_chunk", ctypes.c_int32),
+                ("hist_copies", ctypes.c_int32), ("order", ctypes.c_int32),
+                ("record_timing", ctypes.c_int32), ("n_hint", ctypes.c_int32),
+                ("lut_log2", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("items", ctypes.c_int64), ("candidates", ctypes.c_int64), ("rechecks", ctypes.c_int64),
+                ("in_range", ctypes.c_int64), ("cells", ctypes.c_int64), ("grid", ctypes.c_int32 * 3),
+                ("cells_per_rmax", ctypes.c_int32), ("cell_side", ctypes.c_double),
+                ("kernel_ms", ctypes.c_double), ("band_d2_rel", ctypes.c_double),
+                ("lut_entries", ctypes.c_int32), ("wg_per_cu", ctypes.c_int32)]
+
+    def as_dict(self):
+        d = {k: getattr(self, k) for k, _ in self._fields_}
+        d["grid"] = list(self.grid)
+        return d
+
+
+# (name, restype, argtypes) of every exported entry point of include/fcfc.h
+_P = ctypes.c_void_p
+_I32 = ctypes.c_int32
+_I64 = ctypes.c_int64
+_D = ctypes.c_double
+SIGNATURES = [
+    ("fcfc_plan_create", _I32, [_I32, _I32, _P, _I32, _P, _I32, _D, ctypes.POINTER(Tuning), ctypes.POINTER(_P)]),
+    ("fcfc_plan_fit_bounds", _I32, [_P, ctypes.POINTER(Catalog), _I32, _P]),
+    ("fcfc_plan_set_bounds", _I32, [_P, _P, _P]),
+    ("fcfc_build_cells", _I32, [_P, ctypes.POINTER(Catalog), _P, ctypes.POINTER(_P)]),
+    ("fcfc_count_pairs", _I32, [_P, _P, _P, _P, _P, _P]),
+    ("fcfc_plan_stats", _I32, [_P, ctypes.POINTER(Stats)]),
+    ("fcfc_batch_create", _I32, [_P, ctypes.POINTER(Catalog), _I32, _P, ctypes.POINTER(_P)]),
+    ("fcfc_batch_run", _I32, [_P, _P, _P, _I32, _P]),
+    ("fcfc_batch_free", None, [_P]),
+    ("fcfc_cells_free", None, [_P]),
+    ("fcfc_plan_free", None, [_P]),
+    ("fcfc_cells_info", _I32, [_P, ctypes.POINTER(_I64), ctypes.POINTER(_I64)]),
+    ("fcfc_status_str", ctypes.c_char_p, [_I32]),
+    ("fcfc_last_error", ctypes.c_char_p, []),
+    ("fcfc_version", _I32, []),
+]
+
+_lib = None
+
+
+def load():
+    """Load libfcfc.so; raise if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: run __graft_entry__.build() "
+                              "(or python paper_2301_12557_amd/build_lib.py) first")
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, res, args in SIGNATURES:
+            f = getattr(lib, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def check(code):
+    if code != FCFC_OK:
+        msg = load().fcfc_last_error().decode()
+        raise FcfcError(code, msg)
+
+
+def _stream_ptr(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _catalog(xyz, w=None):
+    import torch
+    if not (isinstance(xyz, torch.Tensor) and xyz.is_cuda and xyz.dtype == torch.float64
+            and xyz.dim() == 2 and xyz.shape[1] == 3 and xyz.is_contiguous()):
+        raise ValueError("positions must be a contiguous CUDA float64 tensor of shape (N, 3)")
+    if w is not None and not (isinstance(w, torch.Tensor) and w.is_cuda and w.dtype == torch.float64
+                              and w.dim() == 1 and w.shape[0] == xyz.shape[0] and w.is_contiguous()):
+        raise ValueError("weights must be a contiguous CUDA float64 tensor of shape (N,)")
+    return Catalog(xyz.data_ptr() if xyz.numel() else None, (w.data_ptr() if (w is not None and w.numel()) else None),
+                   xyz.shape[0])
+
+
+def make_tuning(**kw):
+    t = Tuning()
+    for k, v in kw.items():
+        if k == "order" and isinstance(v, str):
+            v = ORDER[v]
+        setattr(t, k, int(v))
+    return t
+
+
+class Plan:
+    """Owns an fcfc_plan_t."""
+
+    def __init__(self, kind, edges1, edges2=None, los="z", box=0.0, **tuning):
+        lib = load()
+        e1 = np.ascontiguousarray(np.asarray(edges1, dtype=np.float64))
+        self.kind = kind
+        self.n1 = len(e1) - 1
+        if kind == "s":
+            e2 = None
+            self.n2 = 1
+        else:
+            e2 = np.ascontiguousarray(np.asarray(edges2, dtype=np.float64))
+            self.n2 = len(e2) - 1
+        self._e1, self._e2 = e1, e2
+        self.tuning = make_tuning(**tuning)
+        h = ctypes.c_void_p()
+        check(lib.fcfc_plan_create(KIND[kind], LOS[los], e1.ctypes.data_as(_P), self.n1,
+                                   e2.ctypes.data_as(_P) if e2 is not None else None,
+                                   self.n2 if e2 is not None else 0, float(box), ctypes.byref(self.tuning),
+                                   ctypes.byref(h)))
+        self.h = h
+
+    @property
+    def shape(self):
+        return (self.n1,) if self.kind == "s" else (self.n1, self.n2)
+
+    def fit_bounds(self, catalogs, stream=None):
+        arr = (Catalog * len(catalogs))(*[_catalog(x, w) for (x, w) in catalogs])
+        check(load().fcfc_plan_fit_bounds(self.h, arr, len(catalogs), _stream_ptr(stream)))
+
+    def set_bounds(self, lo, hi):
+        lo = np.ascontiguousarray(np.asarray(lo, dtype=np.float64))
+        hi = np.ascontiguousarray(np.asarray(hi, dtype=np.float64))
+        check(load().fcfc_plan_set_bounds(self.h, lo.ctypes.data_as(_P), hi.ctypes.data_as(_P)))
+
+    def build_cells(self, xyz, w=None, stream=None):
+        return Cells(self, xyz, w, stream)
+
+    def count(self, c1, c2=None, weighted=False, out=None, wout=None, stream=None):
+        import torch
+        nb = self.n1 * self.n2
+        dev = c1.device
+        if out is None:
+            out = torch.empty(nb, dtype=torch.int64, device=dev)
+        if weighted and wout is None:
+            wout = torch.empty(nb, dtype=torch.float64, device=dev)
+        check(load().fcfc_count_pairs(self.h, c1.h, c2.h if c2 is not None else None, out.data_ptr(),
+                                      wout.data_ptr() if weighted else None, _stream_ptr(stream)))
+        return out.view(self.shape), (wout.view(self.shape) if weighted else None)
+
+    def stats(self):
+        s = Stats()
+        check(load().fcfc_plan_stats(self.h, ctypes.byref(s)))
+        return s.as_dict()
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().fcfc_plan_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Cells:
+    """Owns an fcfc_cells_t built on a plan."""
+
+    def __init__(self, plan, xyz, w=None, stream=None):
+        cat = _catalog(xyz, w)
+        h = ctypes.c_void_p()
+        check(load().fcfc_build_cells(plan.h, ctypes.byref(cat), _stream_ptr(stream), ctypes.byref(h)))
+        self.h = h
+        self.device = xyz.device
+        self.plan = plan
+
+    def info(self):
+        n = ctypes.c_int64()
+        c = ctypes.c_int64()
+        check(load().fcfc_cells_info(self.h, ctypes.byref(n), ctypes.byref(c)))
+        return n.value, c.value
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().fcfc_cells_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Owns an fcfc_batch_t: auto counts of many periodic catalogues in one pipeline."""
+
+    def __init__(self, plan, catalogs, stream=None):
+        self._keep = catalogs
+        arr = (Catalog * len(catalogs))(*[_catalog(x, w) for (x, w) in catalogs])
+        h = ctypes.c_void_p()
+        check(load().fcfc_batch_create(plan.h, arr, len(catalogs), _stream_ptr(stream), ctypes.byref(h)))
+        self.h = h
+        self.plan = plan
+        self.ncat = len(catalogs)
+
+    def run(self, out, wout=None, use_graph=True, stream=None):
+        check(load().fcfc_batch_run(self.h, out.data_ptr(), wout.data_ptr() if wout is not None else None,
+                                    int(bool(use_graph)), _stream_ptr(stream)))
+        return out
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().fcfc_batch_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def count_pairs(x1, x2=None, *, kind="s", edges1, edges2=None, los="z", box=0.0, w1=None, w2=None,
+                stream=None, return_stats=False, **tuning):
+    """Pair counts of device catalogues (torch float64 CUDA tensors).
+
+    x2=None: auto count of x1.  Weighted when w1 (and w2 for a cross count) are given.
+    Returns (counts int64 tensor, wcounts float64 tensor or None[, stats dict]).
+    """
+    weighted = w1 is not None
+    if "n_hint" not in tuning:
+        tuning["n_hint"] = int(max(x1.shape[0], 0 if x2 is None else x2.shape[0]))
+    plan = Plan(kind, edges1, edges2, los=los, box=box, **tuning)
+    try:
+        if box == 0.0:
+            cats = [(x1, None)] + ([(x2, None)] if x2 is not None else [])
+            plan.fit_bounds(cats, stream)
+        c1 = plan.build_cells(x1, w1 if weighted else None, stream)
+        c2 = plan.build_cells(x2, w2 if weighted else None, stream) if x2 is not None else None
+        counts, wcounts = plan.count(c1, c2, weighted=weighted, stream=stream)
+        st = plan.stats() if return_stats else None
+        c1.close()
+        if c2 is not None:
+            c2.close()
+    finally:
+        plan.close()
+    if return_stats:
+        return counts, wcounts, st
+    return counts, wcounts

@@ -1,0 +1,222 @@
+"""GPU parity: the HIP library against the FP64 CPU oracle, bin by bin.
+
+Integer counts must match bit for bit; weighted counts within 1e-12 relative
+(the exact fixed-point accumulation gives identical FP64 values)."""
+import itertools
+import json
+import os
+
+import numpy as np
+import pytest
+
+from paper_2301_12557_amd import synth
+from helpers import check_case, gpu_count, note, oracle_count, assert_same
+
+pytestmark = pytest.mark.gpu
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2301_12557_amd import fcfc
+    fcfc.load()
+
+
+def _hand_cases():
+    with open(os.path.join(HERE, "golden", "hand_cases.json")) as f:
+        return json.load(f)["cases"]
+
+
+@pytest.mark.parametrize("case", _hand_cases(), ids=lambda c: c["name"])
+def test_hand_cases_gpu(case):
+    e2 = case.get("edges2")
+    if e2 == "mu100":
+        e2 = synth.mu_edges(100)
+    x1 = np.array(case["x1"], dtype=np.float64)
+    x2 = np.array(case["x2"], dtype=np.float64) if "x2" in case else None
+    w1 = np.array(case["w1"]) if "w1" in case else None
+    check_case(case["name"], x1, x2, kind=case["kind"], los=case["los"], box=case["box"],
+               edges1=case["edges1"], edges2=e2, w1=w1, w2=(w1 if (w1 is not None and x2 is not None) else None))
+
+
+def _lattice(n, a):
+    g = np.arange(n) * a
+    return np.array(list(itertools.product(g, g, g)), dtype=np.float64)
+
+
+@pytest.mark.parametrize("a", [1.0, 0.3, 0.1])
+def test_lattice_knife_edges(a):
+    """Lattice pairs sit exactly on (a = 1) or within rounding of (a = 0.3, 0.1) the bin edges:
+    the FP64 recheck must reproduce the oracle."""
+    n = 9
+    x = _lattice(n, a)
+    L = n * a
+    x = np.minimum(x, np.nextafter(L, 0))
+    e = np.arange(0, 5) * a
+    check_case(f"lattice s a={a}", x, kind="s", edges1=e, box=L)
+    check_case(f"lattice smu a={a}", x, kind="smu", edges1=e, edges2=synth.mu_edges(8), box=L)
+    check_case(f"lattice spi a={a}", x, kind="spi", edges1=e[:4], edges2=e[:4], box=L)
+
+
+@pytest.mark.parametrize("weighted", [False, True])
+def test_c1_full_size(weighted):
+    """Config C1 at full size: 20,000 uniform points, L = 1000, 40 linear s bins."""
+    w = synth.workload(1, weighted=weighted)
+    check_case("C1", w["x1"], kind="s", edges1=w["edges1"], box=w["box"], w1=w["w1"])
+
+
+@pytest.mark.parametrize("weighted", [False, True])
+def test_c2_scaled(weighted):
+    """Config C2 shape (lognormal, (s,mu) 40 x 100, LOS z, periodic L = 2000) at 30k points."""
+    n = 30000
+    x = synth.lognormal_box(n, 2000.0, synth.config_seed(2), ngrid=64)
+    w1 = synth.uniform_weights(n, 0.5, 1.5, 77) if weighted else None
+    check_case("C2-30k", x, kind="smu", edges1=synth.linear_edges(0, 200, 40), edges2=synth.mu_edges(100),
+               box=2000.0, w1=w1)
+
+
+@pytest.mark.parametrize("weighted", [False, True])
+def test_c3_scaled(weighted):
+    """Config C3 shape (survey shell, (s_perp,pi) 40 x 40, mid-point LOS, open box): DD, DR, RR."""
+    nd, nr = 3000, 6000
+    d = synth.survey_shell(nd, 11)
+    r = synth.survey_shell(nr, 12)
+    wd = synth.uniform_weights(nd, 0.5, 2.0, 13) if weighted else None
+    wr = synth.uniform_weights(nr, 0.5, 2.0, 14) if weighted else None
+    e = synth.linear_edges(0, 200, 40)
+    kw = dict(kind="spi", los="mid", edges1=e, edges2=e, box=0.0)
+    check_case("C3-DD", d, w1=wd, **kw)
+    check_case("C3-DR", d, r, w1=wd, w2=wr, **kw)
+    check_case("C3-RR", r, w1=wr, **kw)
+
+
+def test_c5_scaled():
+    """Config C5 shape: log s bins [0.1, 50) (hybrid table), periodic L = 3000, clustered."""
+    n = 60000
+    x = synth.lognormal_box(n, 3000.0, synth.config_seed(5), ngrid=64)
+    check_case("C5-60k", x, kind="s", edges1=synth.log_edges(0.1, 50.0, 50), box=3000.0)
+
+
+@pytest.mark.parametrize("kind,los,box", [("s", "z", 0.0), ("smu", "z", 0.0), ("smu", "mid", 0.0),
+                                          ("spi", "z", 0.0), ("spi", "z", 120.0), ("smu", "z", 120.0)])
+def test_cross_counts(kind, los, box):
+    rng = np.random.default_rng(3)
+    if box > 0:
+        a = rng.random((1500, 3)) * box
+        b = rng.random((1100, 3)) * box
+    else:
+        a = synth.survey_shell(1500, 5, rmin=200.0, rmax=320.0)
+        b = synth.survey_shell(1100, 6, rmin=200.0, rmax=320.0)
+    e1 = np.array([0.0, 3.0, 7.5, 12.0, 20.0, 31.0, 45.0])
+    e2 = synth.mu_edges(10) if kind == "smu" else (np.array([0.0, 4.0, 10.0, 25.0, 40.0]) if kind == "spi" else None)
+    w1 = synth.uniform_weights(len(a), 0.5, 1.5, 1)
+    w2 = synth.uniform_weights(len(b), 0.5, 1.5, 2)
+    check_case(f"cross {kind}/{los}/{box}", a, b, kind=kind, los=los, box=box, edges1=e1, edges2=e2, w1=w1, w2=w2)
+
+
+def test_empty_and_tiny():
+    e = np.array([0.0, 1.0, 2.0, 5.0])
+    for n in (0, 1, 2, 3):
+        x = np.random.default_rng(n).random((n, 3)) * 4.0
+        check_case(f"tiny n={n}", x, kind="s", edges1=e, box=10.0)
+        check_case(f"tiny open n={n}", x, kind="smu", edges1=e, edges2=synth.mu_edges(4), box=0.0)
+    y = np.random.default_rng(9).random((5, 3)) * 4.0
+    check_case("cross with empty", np.zeros((0, 3)), y, kind="s", edges1=e, box=10.0)
+
+
+def test_tuning_sweep_small():
+    """Random small problems under many tuning settings: all must match the oracle."""
+    rng = np.random.default_rng(2024)
+    for t in range(24):
+        n = int(rng.integers(50, 600))
+        kind = ["s", "smu", "spi"][t % 3]
+        periodic = bool(rng.integers(0, 2))
+        L = float(rng.uniform(20, 60))
+        if periodic:
+            x = rng.random((n, 3)) * L
+        else:
+            x = rng.normal(size=(n, 3)) * L / 4 + (np.array([3 * L, 0, 0]) if kind != "s" else 0)
+        smax = L * float(rng.uniform(0.15, 0.45))
+        nb = int(rng.integers(1, 12))
+        e1 = np.sort(rng.uniform(0, smax, nb + 1))
+        if rng.random() < 0.5:
+            e1[0] = 0.0
+        e2 = synth.mu_edges(int(rng.integers(1, 9))) if kind == "smu" else np.sort(rng.uniform(0, smax * 0.7, 4))
+        los = "mid" if (not periodic and kind != "s" and rng.random() < 0.5) else "z"
+        tuning = dict(cells_per_rmax=int(rng.integers(1, 6)), tile_points=int(rng.choice([64, 128])),
+                      seg_cells=int(rng.integers(1, 5)), b_chunk=int(rng.choice([256, 1024, 16384])),
+                      hist_copies=int(rng.choice([1, 2, 4])), order=int(rng.integers(0, 2)))
+        w = synth.uniform_weights(n, 0.5, 2.0, t) if rng.random() < 0.3 else None
+        check_case(f"sweep {t}", x, kind=kind, los=los, box=L if periodic else 0.0, edges1=e1,
+                   edges2=None if kind == "s" else e2, w1=w, **tuning)
+
+
+def test_invariance_under_tuning_c2_shape():
+    """Counts do not depend on the cell size, tile, segment, chunk, histogram copies or order."""
+    n = 40000
+    x = synth.lognormal_box(n, 2000.0, 99, ngrid=64)
+    kw = dict(kind="smu", edges1=synth.linear_edges(0, 200, 40), edges2=synth.mu_edges(100), box=2000.0)
+    ref = None
+    for tune in [dict(), dict(cells_per_rmax=1), dict(cells_per_rmax=4, tile_points=64),
+                 dict(cells_per_rmax=3, seg_cells=3, b_chunk=512, hist_copies=2, order=1)]:
+        note(f"invariance {tune}")
+        g, _, _ = gpu_count(x, **kw, **tune)
+        if ref is None:
+            ref = g
+        assert np.array_equal(g, ref), tune
+    perm = np.random.default_rng(1).permutation(n)
+    g, _, _ = gpu_count(x[perm], **kw)
+    assert np.array_equal(g, ref)
+
+
+def test_c2_full_size_sampled():
+    """C2 at full size (1,000,000 clustered points): the total equals the sum over a partition of
+    the catalogue into pieces counted as autos and crosses on the GPU, and one piece is checked
+    against the oracle (cross of a 2,000-point sample with the whole catalogue)."""
+    w = synth.workload(2)
+    x = w["x1"]
+    kw = dict(kind="smu", edges1=w["edges1"], edges2=w["edges2"], box=w["box"])
+    note("C2 full auto")
+    full, _, st = gpu_count(x, **kw)
+    assert full.sum() == st["in_range"]
+    # additivity: auto(A u B) = auto(A) + auto(B) + cross(A, B)
+    h = len(x) // 2
+    a, b = x[:h], x[h:]
+    note("C2 halves")
+    aa, _, _ = gpu_count(a, **kw)
+    bb, _, _ = gpu_count(b, **kw)
+    ab, _, _ = gpu_count(a, b, **kw)
+    assert np.array_equal(aa + bb + ab, full)
+    # sampled cross against the oracle (cell list)
+    idx = np.random.default_rng(5).choice(len(x), 2000, replace=False)
+    s = x[idx]
+    note("C2 sample x full")
+    g, _, _ = gpu_count(s, x, **kw)
+    o, _ = oracle_count(s, x, method="grid", **kw)
+    assert_same(g, o, what="C2 sample x full")
+
+
+def test_errors_on_device_data():
+    import torch
+    from paper_2301_12557_amd import fcfc
+    e = np.array([0.0, 1.0, 2.0])
+    x = np.random.default_rng(0).random((100, 3)) * 10.0
+    bad = x.copy()
+    bad[5, 1] = np.nan
+    with pytest.raises(fcfc.FcfcError) as ei:
+        fcfc.count_pairs(torch.from_numpy(bad).cuda(), kind="s", edges1=e, box=10.0)
+    assert ei.value.name == "FCFC_ENONFINITE"
+    out = x.copy()
+    out[7, 2] = 10.0
+    with pytest.raises(fcfc.FcfcError) as ei:
+        fcfc.count_pairs(torch.from_numpy(out).cuda(), kind="s", edges1=e, box=10.0)
+    assert ei.value.name == "FCFC_EBOX"
+    p1 = fcfc.Plan("s", e, box=10.0)
+    p2 = fcfc.Plan("s", e, box=10.0)
+    c1 = p1.build_cells(torch.from_numpy(x).cuda())
+    with pytest.raises(fcfc.FcfcError) as ei:
+        p2.count(c1)
+    assert ei.value.name == "FCFC_EGRID"
