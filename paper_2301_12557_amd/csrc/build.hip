@@ -449,9 +449,9 @@ static GridArgs make_grid_args(const Plan* p) {
     g.lox = gr.lo[0];
     g.loy = gr.lo[1];
     g.loz = gr.lo[2];
-    g.hix = gr.lo[0] + p->grid_ext[0];
-    g.hiy = gr.lo[1] + p->grid_ext[1];
-    g.hiz = gr.lo[2] + p->grid_ext[2];
+    g.hix = p->grid_hi[0];
+    g.hiy = p->grid_hi[1];
+    g.hiz = p->grid_hi[2];
     g.side = gr.side;
     g.L = gr.L;
     return g;

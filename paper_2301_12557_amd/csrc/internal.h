@@ -98,6 +98,7 @@ struct Plan {
     bool grid_set = false;
     Grid grid;
     double grid_ext[3] = {0, 0, 0};  // open box: extent of the bounds per axis
+    double grid_hi[3] = {0, 0, 0};   // open box: upper bounds (inclusive)
     double obs_dist = 0;        // open box: distance from the origin to the box
     double coord_max = 0;       // largest |coordinate| inside the box
     // bands and tables, set by finalize_numerics() once the grid is known

@@ -421,6 +421,7 @@ fcfc_status fcfc::fcfc_set_bounds_internal(Plan* p, const double lo[3], const do
     for (int a = 0; a < 3; a++) {
         p->grid.lo[a] = lo[a];
         p->grid_ext[a] = hi[a] - lo[a];
+        p->grid_hi[a] = hi[a];
     }
     fcfc_status s = plan_finalize_grid(p);
     if (s == FCFC_OK) s = plan_finalize_numerics(p);

@@ -38,6 +38,15 @@ def test_hand_cases_gpu(case):
     x1 = np.array(case["x1"], dtype=np.float64)
     x2 = np.array(case["x2"], dtype=np.float64) if "x2" in case else None
     w1 = np.array(case["w1"]) if "w1" in case else None
+    rmax = float(case["edges1"][-1]) if case["kind"] != "spi" else float(np.hypot(case["edges1"][-1], e2[-1]))
+    if case["box"] > 0 and rmax > case["box"] / 2:
+        # the library requires the prune radius to be at most L/2 (the minimum image is then the
+        # only image in range); such a plan is rejected with FCFC_ERANGE
+        from paper_2301_12557_amd import fcfc
+        with pytest.raises(fcfc.FcfcError) as ei:
+            gpu_count(x1, x2, kind=case["kind"], los=case["los"], box=case["box"], edges1=case["edges1"], edges2=e2)
+        assert ei.value.name == "FCFC_ERANGE"
+        return
     check_case(case["name"], x1, x2, kind=case["kind"], los=case["los"], box=case["box"],
                edges1=case["edges1"], edges2=e2, w1=w1, w2=(w1 if (w1 is not None and x2 is not None) else None))
 
@@ -101,7 +110,7 @@ def test_c5_scaled():
 
 
 @pytest.mark.parametrize("kind,los,box", [("s", "z", 0.0), ("smu", "z", 0.0), ("smu", "mid", 0.0),
-                                          ("spi", "z", 0.0), ("spi", "z", 120.0), ("smu", "z", 120.0)])
+                                          ("spi", "z", 0.0), ("spi", "z", 130.0), ("smu", "z", 120.0)])
 def test_cross_counts(kind, los, box):
     rng = np.random.default_rng(3)
     if box > 0:
@@ -139,7 +148,7 @@ def test_tuning_sweep_small():
             x = rng.random((n, 3)) * L
         else:
             x = rng.normal(size=(n, 3)) * L / 4 + (np.array([3 * L, 0, 0]) if kind != "s" else 0)
-        smax = L * float(rng.uniform(0.15, 0.45))
+        smax = L * float(rng.uniform(0.15, 0.45 if kind != "spi" else 0.34))
         nb = int(rng.integers(1, 12))
         e1 = np.sort(rng.uniform(0, smax, nb + 1))
         if rng.random() < 0.5:
