@@ -17,6 +17,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "internal.h"
 #include "worklist.h"
@@ -51,11 +52,11 @@ __device__ inline Item ldc_item(const Item* p, uint32_t i) {
     return it;
 }
 
-constexpr int CT = 256;             // threads per workgroup
-constexpr int CWAVES = CT / 64;
+constexpr int CT_MAX = 1024;        // threads per workgroup (16 waves: 4 per SIMD, one workgroup per CU)
+constexpr int QCAP = 192;           // compaction queue entries per wave (63 + 64 P)
 constexpr int RB_CAP = 128;         // recheck entries per wave
+constexpr int ASTAGE = 128;         // staged A points per wave (mid-point line of sight)
 constexpr uint64_t FLUSH_PAIRS = 1ull << 30;
-constexpr int BG = 4;               // B points per scalar load group (arrays are padded by BG-1)
 
 struct CountArgs {
     const float4* posA;
@@ -91,8 +92,14 @@ struct CountArgs {
     double wscale;
     int copies;
     // LDS layout (bytes)
-    int off_lut1, off_lut2, off_band1, off_band2, off_hist, off_whist, off_rb, off_misc, lds_bytes;
+    int off_lut1, off_lut2, off_band1, off_band2, off_hist, off_whist, off_q, off_qw, off_rb, off_astage,
+        off_misc, lds_bytes;
 };
+
+// The arguments live in device memory and are read through the constant
+// address space (scalar loads); a by-value kernel argument would be copied to
+// scratch as soon as a helper takes its address.
+typedef const CountArgs FCFC_CONST& ArgsRef;
 
 struct Smem {
     const uint16_t* lut1;
@@ -102,7 +109,10 @@ struct Smem {
     uint32_t* hist;
     unsigned long long* wlo;
     unsigned long long* whi;
-    uint32_t* rb;
+    float4* q;        // this wave's compaction queue
+    double* qw;       // this wave's queued weight products
+    uint32_t* rb;     // this wave's recheck entries (a, b, item)
+    float4* astage;   // this wave's A points in absolute FP32 (mid-point line of sight)
     unsigned long long* misc;
 };
 
@@ -126,9 +136,8 @@ __device__ inline int upper_edge_count(const double* __restrict__ E, int n, doub
 }
 
 template <int KIND, int LOS>
-__device__ int exact_bin(const CountArgs& a, const double* pa, const double* pb, int sx, int sy, int sz) {
-    double ax = pa[0], ay = pa[1], az = pa[2];
-    double bx = pb[0], by = pb[1], bz = pb[2];
+__device__ int exact_bin(ArgsRef a, double ax, double ay, double az, double bx, double by, double bz,
+                         int sx, int sy, int sz) {
     double dx = bx - ax;
     double dy = by - ay;
     double dz = bz - az;
@@ -234,7 +243,7 @@ __device__ inline void add_weight(const Smem& s, int flat, double p, double wsca
 
 // Re-evaluate `cnt` queued pairs (entries base .. base+cnt-1) in FP64.
 template <int KIND, int LOS, bool W>
-__device__ void process_rechecks(const CountArgs& a, const Smem& s, int base, int cnt, int lane,
+__device__ __attribute__((always_inline)) inline void process_rechecks(ArgsRef a, const Smem& s, int base, int cnt, int lane,
                                  unsigned long long& nrechk) {
     if (lane < cnt) {
         const uint32_t* e = s.rb + (size_t)(base + lane) * 3;
@@ -243,9 +252,9 @@ __device__ void process_rechecks(const CountArgs& a, const Smem& s, int base, in
         int sx = (int)((meta >> 16) & 3u) - 1;
         int sy = (int)((meta >> 18) & 3u) - 1;
         int sz = (int)((meta >> 20) & 3u) - 1;
-        double pa[3] = {a.p64A[3 * (size_t)ia], a.p64A[3 * (size_t)ia + 1], a.p64A[3 * (size_t)ia + 2]};
-        double pb[3] = {a.p64B[3 * (size_t)ib], a.p64B[3 * (size_t)ib + 1], a.p64B[3 * (size_t)ib + 2]};
-        int flat = exact_bin<KIND, LOS>(a, pa, pb, sx, sy, sz);
+        const double* pa = a.p64A + 3 * (size_t)ia;
+        const double* pb = a.p64B + 3 * (size_t)ib;
+        int flat = exact_bin<KIND, LOS>(a, pa[0], pa[1], pa[2], pb[0], pb[1], pb[2], sx, sy, sz);
         if (flat >= 0) {
             atomicAdd(&s.hist[flat], 1u);
             if (W) {
@@ -262,9 +271,115 @@ __device__ inline void wave_sync_lds() {
     __builtin_amdgcn_wave_barrier();
 }
 
+__device__ inline uint32_t lane_prefix(uint64_t m) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+// Per-wave context of the current work item.
+struct WaveCtx {
+    uint32_t a_begin, b_begin, it;
+    int rcount;
+    unsigned long long nrechk;
+};
+
+// Bin `cnt` queued in-range pairs (entries base .. base+cnt-1), one per lane.
+// Entry: (v1, v2, v3, ids) with ids = (b - b_begin) << 7 | a_slot, and
+//   s:              v1 = d2
+//   (s,mu), z:      v1 = d2, v2 = dz
+//   (sp,pi), z:     v1 = sp2, v2 = pi2
+//   mid-point:      v1, v2, v3 = dx, dy, dz (line of sight from the staged A point)
+template <int KIND, int LOS, bool W>
+__device__ __attribute__((always_inline)) inline void bin_queue(ArgsRef a, const Smem& s, uint32_t* hist_l, int base, int cnt, int lane,
+                          uint64_t lanemask_lt, WaveCtx& c) {
+    const bool valid = lane < cnt;
+    float4 e = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (valid) e = s.q[base + lane];
+    const uint32_t ids = __float_as_uint(e.w);
+    bool amb = false;
+    int flat = -1;
+    if (KIND == FCFC_BIN_S) {
+        flat = lut_bin(s.lut1, s.band1, a.n1, a.scale1, e.x, amb);
+    } else if (KIND == FCFC_BIN_S_MU) {
+        float d2, proj_n;  // proj_n: |projection on the line of sight| * n_mu / |l|
+        const float dxx = e.x, dyy = e.y, dzz = e.z;
+        if (LOS == FCFC_LOS_Z) {
+            d2 = e.x;
+        } else {
+            d2 = __builtin_fmaf(dzz, dzz, __builtin_fmaf(dyy, dyy, dxx * dxx));
+        }
+        const int sb = lut_bin(s.lut1, s.band1, a.n1, a.scale1, d2, amb);
+        const float rs = __builtin_amdgcn_rsqf(d2);
+        if (LOS == FCFC_LOS_Z) {
+            proj_n = fabsf(e.y) * a.mu_n;
+        } else {
+            const float4 q = s.astage[ids & 127u];
+            const float lx = q.x + dxx, ly = q.y + dyy, lz = q.z + dzz;
+            const float dot = __builtin_fmaf(dzz, lz, __builtin_fmaf(dyy, ly, dxx * lx));
+            const float ll = __builtin_fmaf(lz, lz, __builtin_fmaf(ly, ly, lx * lx));
+            proj_n = fabsf(dot) * (__builtin_amdgcn_rsqf(ll) * a.mu_n);
+        }
+        const float mun = proj_n * rs;
+        int mb = (int)mun;
+        mb = mb < a.n2 - 1 ? mb : a.n2 - 1;
+        const float cr = rintf(mun);
+        const float dist = fabsf(mun - cr);
+        const float tol = __builtin_fmaf(__builtin_fmaf(a.tolB, rs, a.tolA), rs, a.tolC);
+        amb = amb || ((dist < tol) && (cr >= 1.0f) && (cr <= a.mu_n - 1.0f)) || (d2 < a.d2small);
+        flat = (sb >= 0) ? sb * a.n2 + mb : -1;
+    } else {
+        float sp2, pi2;
+        if (LOS == FCFC_LOS_Z) {
+            sp2 = e.x;
+            pi2 = e.y;
+        } else {
+            const float dxx = e.x, dyy = e.y, dzz = e.z;
+            const float d2 = __builtin_fmaf(dzz, dzz, __builtin_fmaf(dyy, dyy, dxx * dxx));
+            const float4 q = s.astage[ids & 127u];
+            const float lx = q.x + dxx, ly = q.y + dyy, lz = q.z + dzz;
+            const float dot = __builtin_fmaf(dzz, lz, __builtin_fmaf(dyy, ly, dxx * lx));
+            const float ll = __builtin_fmaf(lz, lz, __builtin_fmaf(ly, ly, lx * lx));
+            pi2 = (dot * dot) * __builtin_amdgcn_rcpf(ll);
+            sp2 = fmaxf(d2 - pi2, 0.0f);
+        }
+        // beyond a table's top band end the pair is certainly out of range
+        if (sp2 < a.vmax1 && pi2 < a.vmax2) {
+            const int b1 = lut_bin(s.lut1, s.band1, a.n1, a.scale1, sp2, amb);
+            const int b2 = lut_bin(s.lut2, s.band2, a.n2, a.scale2, pi2, amb);
+            flat = (b1 >= 0 && b2 >= 0) ? b1 * a.n2 + b2 : -1;
+        }
+    }
+    amb = amb && valid;
+    if (valid && !amb && flat >= 0) {
+        atomicAdd(&hist_l[flat], 1u);
+        if (W) add_weight(s, flat, s.qw[base + lane], a.wscale);
+    }
+    const uint64_t m = __ballot(amb);
+    if (m) {
+        const int pos = c.rcount + (int)lane_prefix(m);
+        if (amb) {
+            uint32_t* r = s.rb + (size_t)pos * 3;
+            r[0] = c.a_begin + (ids & 127u);
+            r[1] = c.b_begin + (ids >> 7);
+            r[2] = c.it;
+        }
+        c.rcount += (int)__popcll(m);
+        if (c.rcount >= 64) {
+            wave_sync_lds();
+            process_rechecks<KIND, LOS, W>(a, s, c.rcount - 64, 64, lane, c.nrechk);
+            wave_sync_lds();
+            c.rcount -= 64;
+        }
+    }
+}
+
 template <int KIND, int LOS, bool AUTO, bool W, int P>
-__global__ __launch_bounds__(CT) void k_count(const CountArgs a) {
+__global__ __launch_bounds__(CT_MAX) void k_count(const CountArgs* argp) {
+    ArgsRef a = *(const CountArgs FCFC_CONST*)argp;
     extern __shared__ __align__(16) unsigned char smem[];
+    const int tid = threadIdx.x;
+    const int nthr = blockDim.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
     Smem s;
     s.lut1 = (const uint16_t*)(smem + a.off_lut1);
     s.lut2 = (const uint16_t*)(smem + a.off_lut2);
@@ -273,41 +388,41 @@ __global__ __launch_bounds__(CT) void k_count(const CountArgs a) {
     s.hist = (uint32_t*)(smem + a.off_hist);
     s.wlo = (unsigned long long*)(smem + a.off_whist);
     s.whi = s.wlo + a.nbins;
-    s.rb = (uint32_t*)(smem + a.off_rb);
+    s.q = (float4*)(smem + a.off_q) + (size_t)wave * QCAP;
+    s.qw = (double*)(smem + a.off_qw) + (size_t)wave * QCAP;
+    s.rb = (uint32_t*)(smem + a.off_rb) + (size_t)wave * RB_CAP * 3;
+    s.astage = (float4*)(smem + a.off_astage) + (size_t)wave * ASTAGE;
     s.misc = (unsigned long long*)(smem + a.off_misc);
 
-    const int tid = threadIdx.x;
     // stage tables, clear histograms
     {
         uint32_t* d = (uint32_t*)(smem + a.off_lut1);
         const uint32_t* src = (const uint32_t*)a.lut1;
-        for (int i = tid; i < (a.nlut1 + 1) / 2; i += CT) d[i] = src[i];
+        for (int i = tid; i < (a.nlut1 + 1) / 2; i += nthr) d[i] = src[i];
         if (KIND == FCFC_BIN_SPERP_PI) {
             d = (uint32_t*)(smem + a.off_lut2);
             src = (const uint32_t*)a.lut2;
-            for (int i = tid; i < (a.nlut2 + 1) / 2; i += CT) d[i] = src[i];
+            for (int i = tid; i < (a.nlut2 + 1) / 2; i += nthr) d[i] = src[i];
         }
         float* b1 = (float*)(smem + a.off_band1);
-        for (int i = tid; i < 2 * (a.n1 + 1); i += CT) b1[i] = a.band1[i];
+        for (int i = tid; i < 2 * (a.n1 + 1); i += nthr) b1[i] = a.band1[i];
         if (KIND == FCFC_BIN_SPERP_PI) {
             float* b2 = (float*)(smem + a.off_band2);
-            for (int i = tid; i < 2 * (a.n2 + 1); i += CT) b2[i] = a.band2[i];
+            for (int i = tid; i < 2 * (a.n2 + 1); i += nthr) b2[i] = a.band2[i];
         }
-        for (int i = tid; i < a.nbins * a.copies; i += CT) s.hist[i] = 0u;
+        for (int i = tid; i < a.nbins * a.copies; i += nthr) s.hist[i] = 0u;
         if (W)
-            for (int i = tid; i < 2 * a.nbins; i += CT) s.wlo[i] = 0ull;
+            for (int i = tid; i < 2 * a.nbins; i += nthr) s.wlo[i] = 0ull;
         if (tid == 0) s.misc[0] = 0ull;
     }
     __syncthreads();
 
-    const int lane = tid & 63;
-    const int wave = tid >> 6;
     const uint64_t lanemask_lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    Smem sw = s;
-    sw.rb = s.rb + (size_t)wave * RB_CAP * 3;
     uint32_t* hist_l = s.hist + (size_t)(lane % a.copies) * a.nbins;
-    int rcount = 0;
-    unsigned long long ncand = 0, nrechk = 0;
+    WaveCtx c;
+    c.rcount = 0;
+    c.nrechk = 0;
+    unsigned long long ncand = 0;
     const uint32_t nitems = __builtin_amdgcn_readfirstlane(*a.nitems_dev);
     const float far = 1.0e18f;
 
@@ -326,8 +441,12 @@ __global__ __launch_bounds__(CT) void k_count(const CountArgs a) {
         const int idz = (int)(int8_t)((item.meta >> 8) & 0xffu);
         const int sxi = (int)((item.meta >> 16) & 3u) - 1;
         const bool samerow = AUTO && ((item.meta >> 24) & ITEM_SAMEROW);
+        const uint32_t b_begin = item.b_begin;
         const uint32_t b_end = item.b_end;
-        const uint64_t pairs = (uint64_t)acnt * (uint64_t)(b_end - item.b_begin);
+        c.a_begin = a_begin;
+        c.b_begin = b_begin;
+        c.it = it;
+        const uint64_t pairs = (uint64_t)acnt * (uint64_t)(b_end - b_begin);
         ncand += pairs;
         // u32 overflow guard of the LDS histogram: exchange it out every 2^30 claimed pairs
         {
@@ -355,7 +474,7 @@ __global__ __launch_bounds__(CT) void k_count(const CountArgs a) {
         }
         const float Dy = (float)idy * a.side32;
         const float Dz = (float)idz * a.side32;
-        float ax[P], ay[P], az[P], lx2[P], ly2[P], lz2[P];
+        float ax[P], ay[P], az[P];
         double wa[P];
         int acx[P];
         uint32_t aidx[P];
@@ -372,15 +491,14 @@ __global__ __launch_bounds__(CT) void k_count(const CountArgs a) {
             if (LOS == FCFC_LOS_MIDPOINT && KIND != FCFC_BIN_S) {
                 float4 q = make_float4(far, far, far, 0.f);
                 if (i < acnt) q = a.absA[a_begin + i];
-                lx2[p] = 2.0f * q.x;
-                ly2[p] = 2.0f * q.y;
-                lz2[p] = 2.0f * q.z;
+                s.astage[i] = make_float4(2.0f * q.x, 2.0f * q.y, 2.0f * q.z, 0.f);
             }
             if (W) wa[p] = (i < acnt) ? a.wA[a_begin + i] : 0.0;
         }
+        int qn = 0;
         int xu = xb0;
         int xw = xb0 - sxi * a.nx;
-        uint32_t j = item.b_begin;
+        uint32_t j = b_begin;
         const uint32_t rowcell = item.b_rowcell;
         while (j < b_end && xw < a.nx) {
             uint32_t cell_end = ldc_u32(a.csB, rowcell + (uint32_t)xw + 1u);
@@ -389,131 +507,89 @@ __global__ __launch_bounds__(CT) void k_count(const CountArgs a) {
                 float axx[P];
 #pragma unroll
                 for (int p = 0; p < P; p++) axx[p] = ax[p] - (float)(xu - acx[p]) * a.side32;
-                for (; j < cell_end; j += BG) {
-                    // a group of BG B points in one scalar load (arrays carry BG-1 points of padding)
-                    float4 bg[BG];
-                    double wg[BG];
+                auto cell_loop = [&](auto mask_tag) __attribute__((always_inline)) {
+                    constexpr bool MASK = decltype(mask_tag)::value;
+                    float4 nb = ldc_f4(a.posB, j);
+                    double nw = W ? ldc_f64(a.wB, j) : 0.0;
+                    for (; j < cell_end; j++) {
+                        const float4 b = nb;
+                        const double wb = nw;
+                        // prefetch the next B point (arrays carry padding past the last point)
+                        nb = ldc_f4(a.posB, j + 1);
+                        if (W) nw = ldc_f64(a.wB, j + 1);
 #pragma unroll
-                    for (int q = 0; q < BG; q++) {
-                        bg[q] = ldc_f4(a.posB, j + q);
-                        if (W) wg[q] = ldc_f64(a.wB, j + q);
-                    }
-#pragma unroll
-                    for (int q = 0; q < BG; q++) {
-                    if (q == 0 || j + q < cell_end) {
-                    const uint32_t jb = j + q;
-                    const float4 b = bg[q];
-                    const double wb = W ? wg[q] : 0.0;
-#pragma unroll
-                    for (int p = 0; p < P; p++) {
-                        const float dx = b.x - axx[p];
-                        const float dy = b.y - ay[p];
-                        const float dz = b.z - az[p];
-                        bool amb = false;
-                        int flat = -1;
-                        bool in;
-                        float d2 = 0.f, sp2 = 0.f, pi2 = 0.f;
-                        if (KIND == FCFC_BIN_SPERP_PI && LOS == FCFC_LOS_Z) {
-                            sp2 = __builtin_fmaf(dy, dy, dx * dx);
-                            pi2 = dz * dz;
-                            in = (sp2 < a.vmax1) && (pi2 < a.vmax2);
-                        } else {
-                            d2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
-                            in = d2 < a.r2prune;
-                        }
-                        if (samerow) in = in && (jb > aidx[p]);
-                        if (in) {
-                            if (KIND == FCFC_BIN_S) {
-                                flat = lut_bin(s.lut1, s.band1, a.n1, a.scale1, d2, amb);
-                            } else if (KIND == FCFC_BIN_S_MU) {
-                                int sb = lut_bin(s.lut1, s.band1, a.n1, a.scale1, d2, amb);
-                                const float rs = __builtin_amdgcn_rsqf(d2);
-                                float mun;
-                                if (LOS == FCFC_LOS_Z) {
-                                    mun = fabsf(dz) * (rs * a.mu_n);
-                                } else {
-                                    const float lx = lx2[p] + dx, ly = ly2[p] + dy, lz = lz2[p] + dz;
-                                    const float dot = __builtin_fmaf(dz, lz, __builtin_fmaf(dy, ly, dx * lx));
-                                    const float ll = __builtin_fmaf(lz, lz, __builtin_fmaf(ly, ly, lx * lx));
-                                    mun = fabsf(dot) * (__builtin_amdgcn_rsqf(ll) * (rs * a.mu_n));
-                                }
-                                int mb = (int)mun;
-                                mb = mb < a.n2 - 1 ? mb : a.n2 - 1;
-                                const float cr = rintf(mun);
-                                const float dist = fabsf(mun - cr);
-                                const float tol = __builtin_fmaf(__builtin_fmaf(a.tolB, rs, a.tolA), rs, a.tolC);
-                                amb = amb || ((dist < tol) && (cr >= 1.0f) && (cr <= a.mu_n - 1.0f)) ||
-                                      (d2 < a.d2small);
-                                flat = (sb >= 0) ? sb * a.n2 + mb : -1;
+                        for (int p = 0; p < P; p++) {
+                            const float dx = b.x - axx[p];
+                            const float dy = b.y - ay[p];
+                            const float dz = b.z - az[p];
+                            bool in;
+                            float v1, v2, v3 = 0.f;
+                            if (KIND == FCFC_BIN_SPERP_PI && LOS == FCFC_LOS_Z) {
+                                v1 = __builtin_fmaf(dy, dy, dx * dx);
+                                v2 = dz * dz;
+                                in = (v1 < a.vmax1) && (v2 < a.vmax2);
                             } else {
-                                if (LOS == FCFC_LOS_MIDPOINT) {
-                                    const float lx = lx2[p] + dx, ly = ly2[p] + dy, lz = lz2[p] + dz;
-                                    const float dot = __builtin_fmaf(dz, lz, __builtin_fmaf(dy, ly, dx * lx));
-                                    const float ll = __builtin_fmaf(lz, lz, __builtin_fmaf(ly, ly, lx * lx));
-                                    pi2 = (dot * dot) * __builtin_amdgcn_rcpf(ll);
-                                    sp2 = fmaxf(d2 - pi2, 0.0f);
-                                }
-                                // beyond a table's top band end the pair is certainly out of range
-                                if (sp2 < a.vmax1 && pi2 < a.vmax2) {
-                                    int b1 = lut_bin(s.lut1, s.band1, a.n1, a.scale1, sp2, amb);
-                                    int b2 = lut_bin(s.lut2, s.band2, a.n2, a.scale2, pi2, amb);
-                                    flat = (b1 >= 0 && b2 >= 0) ? b1 * a.n2 + b2 : -1;
+                                const float d2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
+                                in = d2 < a.r2prune;
+                                if (LOS == FCFC_LOS_MIDPOINT && KIND != FCFC_BIN_S) {
+                                    v1 = dx;
+                                    v2 = dy;
+                                    v3 = dz;
+                                } else {
+                                    v1 = d2;
+                                    v2 = dz;
                                 }
                             }
-                            if (!amb && flat >= 0) {
-                                atomicAdd(&hist_l[flat], 1u);
-                                if (W) add_weight(s, flat, wa[p] * wb, a.wscale);
+                            if (MASK) in = in && (j > aidx[p]);
+                            const uint64_t m = __ballot(in);
+                            const int slot = qn + (int)lane_prefix(m);
+                            if (in) {
+                                const uint32_t ids = ((j - b_begin) << 7) | (uint32_t)(lane + 64 * p);
+                                s.q[slot] = make_float4(v1, v2, v3, __uint_as_float(ids));
+                                if (W) s.qw[slot] = wa[p] * wb;
                             }
+                            qn += (int)__popcll(m);
                         }
-                        // queue ambiguous pairs (wave-uniform bookkeeping)
-                        const uint64_t m = __ballot(amb);
-                        if (m) {
-                            const int pos = rcount + (int)__popcll(m & lanemask_lt);
-                            if (amb) {
-                                uint32_t* e = sw.rb + (size_t)pos * 3;
-                                e[0] = aidx[p];
-                                e[1] = jb;
-                                e[2] = it;
-                            }
-                            rcount += (int)__popcll(m);
-                            if (rcount >= 64) {
-                                wave_sync_lds();
-                                process_rechecks<KIND, LOS, W>(a, sw, rcount - 64, 64, lane, nrechk);
-                                wave_sync_lds();
-                                rcount -= 64;
-                            }
+                        while (qn >= 64) {
+                            wave_sync_lds();
+                            bin_queue<KIND, LOS, W>(a, s, hist_l, qn - 64, 64, lane, lanemask_lt, c);
+                            wave_sync_lds();
+                            qn -= 64;
                         }
                     }
-                    }
-                    }
-                }
+                };
+                if (samerow)
+                    cell_loop(std::integral_constant<bool, true>());
+                else
+                    cell_loop(std::integral_constant<bool, false>());
                 j = cell_end;
             }
             xw++;
             xu++;
+        }
+        if (qn > 0) {
+            wave_sync_lds();
+            bin_queue<KIND, LOS, W>(a, s, hist_l, 0, qn, lane, lanemask_lt, c);
+            wave_sync_lds();
         }
         if (a.times && lane == 0) {
             unsigned long long t1 = wall_clock64();
             a.times[it] = (uint32_t)min<unsigned long long>(t1 - t0, 0xffffffffull);
         }
     }
-    if (rcount > 0) {
+    if (c.rcount > 0) {
         wave_sync_lds();
-        process_rechecks<KIND, LOS, W>(a, sw, 0, rcount, lane, nrechk);
+        process_rechecks<KIND, LOS, W>(a, s, 0, c.rcount, lane, c.nrechk);
     }
     if (lane == 0 && a.stats) {
         atomicAdd(&a.stats[0], ncand);
-        atomicAdd(&a.stats[1], nrechk);
+        atomicAdd(&a.stats[1], c.nrechk);
     }
     __syncthreads();
-    unsigned long long tot = 0;
-    for (int b = tid; b < a.nbins; b += CT) {
-        uint32_t c = 0;
-        for (int r = 0; r < a.copies; r++) c += s.hist[r * a.nbins + b];
-        if (c) {
-            atomicAdd(&a.out_counts[b], (unsigned long long)c);
-            tot += c;
-        }
+    for (int b = tid; b < a.nbins; b += nthr) {
+        uint32_t cnt = 0;
+        for (int r = 0; r < a.copies; r++) cnt += s.hist[r * a.nbins + b];
+        if (cnt) atomicAdd(&a.out_counts[b], (unsigned long long)cnt);
         if (W) {
             unsigned long long lo = s.wlo[b], hi = s.whi[b];
             if (lo | hi) {
@@ -526,7 +602,6 @@ __global__ __launch_bounds__(CT) void k_count(const CountArgs a) {
             }
         }
     }
-    if (a.stats && tot) atomicAdd(&a.stats[2], tot);
 }
 
 // 128-bit fixed-point sums -> FP64, rounded to nearest even, times 2^-S
@@ -560,7 +635,7 @@ __global__ void k_finalize_w(const unsigned long long* __restrict__ acc, int nbi
 // ---------------------------------------------------------------------------
 // kernel table
 // ---------------------------------------------------------------------------
-typedef void (*CountKernel)(CountArgs);
+typedef void (*CountKernel)(const CountArgs*);
 
 template <int KIND, int LOS, bool AUTO, bool W>
 static CountKernel pick_p(int P) {
@@ -663,18 +738,32 @@ fcfc_status count_pairs(Plan* p, Cells* c1, Cells* c2, int64_t* d_counts, double
     off += al16(p->nbins * 4 * copies);
     a.off_whist = off;
     off += weighted ? al16(p->nbins * 16) : 0;
-    a.off_rb = off;
-    off += CWAVES * RB_CAP * 12;
-    a.off_misc = off;
-    off += 16;
-    a.lds_bytes = off;
+    const int shared_bytes = off;
+    const bool mid = (p->los == FCFC_LOS_MIDPOINT && p->kind != FCFC_BIN_S);
+    const int per_wave = QCAP * 16 + (weighted ? QCAP * 8 : 0) + RB_CAP * 12 + (mid ? ASTAGE * 16 : 0);
     int dev = 0, maxlds = 65536;
     FCFC_HIP(hipGetDevice(&dev));
     if (hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) maxlds = 65536;
-    if (a.lds_bytes > maxlds) {
-        set_error("count_pairs: %d bytes of LDS needed (tables + histogram), device allows %d", a.lds_bytes, maxlds);
+    // as many waves per workgroup (up to 16, one workgroup per CU) as the LDS allows
+    int waves = 16;
+    while (waves > 1 && shared_bytes + waves * per_wave + 16 > maxlds) waves--;
+    if (shared_bytes + waves * per_wave + 16 > maxlds) {
+        set_error("count_pairs: %d bytes of LDS needed (tables + histogram), device allows %d",
+                  shared_bytes + per_wave + 16, maxlds);
         return FCFC_ERANGE;
     }
+    const int CT = waves * 64;
+    a.off_q = off;
+    off += waves * QCAP * 16;
+    a.off_qw = off;
+    off += weighted ? waves * QCAP * 8 : 0;
+    a.off_rb = off;
+    off += waves * RB_CAP * 12;
+    a.off_astage = off;
+    off += mid ? waves * ASTAGE * 16 : 0;
+    a.off_misc = off;
+    off += 16;
+    a.lds_bytes = off;
 
     // ---- small tables to the device (one block)
     size_t tb_l1 = (size_t)al16(a.nlut1 * 2 + 4), tb_l2 = (size_t)al16(a.nlut2 * 2 + 4);
@@ -731,8 +820,9 @@ fcfc_status count_pairs(Plan* p, Cells* c1, Cells* c2, int64_t* d_counts, double
     size_t s_ic = ((size_t)npair_tr * 4 + 255) & ~(size_t)255;
     size_t s_scan = (std::max(scan_scratch_bytes(nseg), scan_scratch_bytes(npair_tr)) + 255) & ~(size_t)255;
     size_t s_ctr = 256;
+    size_t s_args = (sizeof(CountArgs) + 255) & ~(size_t)255;
     size_t s_acc = weighted ? (((size_t)p->nbins * 16 + 255) & ~(size_t)255) : 0;
-    size_t s1 = s_tab + 2 * s_tc + s_tiles + 2 * s_ic + s_scan + s_ctr + s_acc;
+    size_t s1 = s_tab + 2 * s_tc + s_tiles + 2 * s_ic + s_scan + s_ctr + s_args + s_acc;
     char* scr = nullptr;
     if (hipMallocAsync((void**)&scr, s1, st) != hipSuccess) {
         set_error("count_pairs: cannot allocate %zu bytes of scratch", s1);
@@ -755,9 +845,12 @@ fcfc_status count_pairs(Plan* p, Cells* c1, Cells* c2, int64_t* d_counts, double
     q += s_scan;
     uint32_t* ctr = (uint32_t*)q;  // [0] ntiles [1] nitems [2] cursor
     q += s_ctr;
+    CountArgs* args_dev = (CountArgs*)q;
+    q += s_args;
     unsigned long long* wacc = (unsigned long long*)q;
 
-    FCFC_HIP(hipMemcpyAsync(tab, htab.data(), tb_total, hipMemcpyHostToDevice, st));
+    p->host_stage.swap(htab);
+    FCFC_HIP(hipMemcpyAsync(tab, p->host_stage.data(), tb_total, hipMemcpyHostToDevice, st));
     DevTables dt;
     {
         char* o = tab;
@@ -877,10 +970,13 @@ fcfc_status count_pairs(Plan* p, Cells* c1, Cells* c2, int64_t* d_counts, double
         occ = 1;
     int cus = device_cu_count();
     int64_t nblk = (int64_t)cus * occ;
-    int64_t need = ((int64_t)nitems + CWAVES - 1) / CWAVES;
+    int64_t need = ((int64_t)nitems + waves - 1) / waves;
     if (nblk > need) nblk = std::max<int64_t>(1, need);
     FCFC_HIP(hipEventRecord(p->ev0, st));
-    hipLaunchKernelGGL(kern, dim3((unsigned)nblk), dim3(CT), (size_t)a.lds_bytes, st, a);
+    p->host_args.resize(sizeof(CountArgs));
+    memcpy(p->host_args.data(), &a, sizeof(CountArgs));
+    FCFC_HIP(hipMemcpyAsync(args_dev, p->host_args.data(), sizeof(CountArgs), hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(kern, dim3((unsigned)nblk), dim3(CT), (size_t)a.lds_bytes, st, (const CountArgs*)args_dev);
     FCFC_HIP(hipGetLastError());
     FCFC_HIP(hipEventRecord(p->ev1, st));
     if (weighted)

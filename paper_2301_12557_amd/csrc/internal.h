@@ -120,6 +120,8 @@ struct Plan {
     void* timing_dev = nullptr;      // last recorded per-item times (u32) followed by the items
     uint32_t timing_n = 0;
     int last_pts = 0;
+    std::vector<char> host_stage;    // host copies of uploaded tables / kernel arguments
+    std::vector<char> host_args;
     // learned scheduler (optional)
     std::vector<float> mlp_host; // packed weights, empty if none
     void* mlp_dev = nullptr;

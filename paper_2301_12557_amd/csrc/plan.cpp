@@ -224,7 +224,7 @@ fcfc_status plan_finalize_numerics(Plan* p) {
     d2m.A = 2.0 * sqrt(3.0) * e;
     d2m.B = 3.0 * e * e;
     d2m.C = 3.3 * u + 1e-15;
-    int lg = p->tune.lut_log2 > 0 ? std::min(14, std::max(8, p->tune.lut_log2)) : 14;
+    int lg = p->tune.lut_log2 > 0 ? std::min(14, std::max(8, p->tune.lut_log2)) : 13;
 
     if (p->kind == FCFC_BIN_S || p->kind == FCFC_BIN_S_MU) {
         FCFC_TRY(build_lut(p->lut1, p->e1, d2m, lg));
