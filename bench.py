@@ -53,6 +53,24 @@ def workload(name, weighted):
     return w, desc
 
 
+def measured_traffic(kernel_variant):
+    """HBM bytes per launch of the counting kernel from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE runs (profiles/k_count_c2_traffic.json), if they were taken on the current
+    kernel source and the same kernel variant; otherwise None."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "k_count_c2_traffic.json")
+    try:
+        rec = json.load(open(path))
+        src = open(os.path.join(ROOT, "paper_2301_12557_amd", "csrc", "count.hip"), "rb").read()
+        if rec.get("count_hip_sha256_16") != hashlib.sha256(src).hexdigest()[:16]:
+            return None
+        if rec.get("variant") != kernel_variant:
+            return None
+        return float(rec["hbm_bytes_per_launch"])
+    except Exception:
+        return None
+
+
 def cpu_baseline(w, target_s):
     """The FP64 cell-list oracle, as it stands, on a sample: the cross count of a random subset of
     the catalogue against the whole catalogue (every pair of the subset with every point)."""
@@ -145,7 +163,8 @@ def main():
         "config": {"workload": desc, "points": len(w["x1"]), "bins": nb,
                    "weighted": bool(weighted), "tuning": tune},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+                     "frac": achieved / PEAK_FP32_TFLOPS,
+                     "traffic": measured_traffic(f"{args.workload}/{'weighted' if weighted else 'unweighted'}"),
                      "kernel": "k_count", "kernel_ms": kernel_ms,
                      "per_unit": f"{FLOP_PER_DISTANCE} flop per distance evaluation",
                      "units_per_launch": cand},

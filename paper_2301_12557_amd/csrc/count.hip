@@ -53,10 +53,10 @@ __device__ inline Item ldc_item(const Item* p, uint32_t i) {
 }
 
 constexpr int CT_MAX = 1024;        // threads per workgroup (16 waves: 4 per SIMD, one workgroup per CU)
-constexpr int QCAP = 192;           // compaction queue entries per wave (63 + 64 P)
+constexpr int QCAP = 192;           // compaction queue entries per wave (63 + 64 P), plus one dump entry
 constexpr int RB_CAP = 128;         // recheck entries per wave
 constexpr int ASTAGE = 128;         // staged A points per wave (mid-point line of sight)
-constexpr uint64_t FLUSH_PAIRS = 1ull << 30;
+constexpr uint64_t FLUSH_PAIRS = 1ull << 26;  // per wave
 
 struct CountArgs {
     const float4* posA;
@@ -215,11 +215,15 @@ __device__ int exact_bin(ArgsRef a, double ax, double ay, double az, double bx, 
 // ---------------------------------------------------------------------------
 // FP32 look-up with bands: returns bin (>= 0), -1 (out of range) or sets amb.
 // ---------------------------------------------------------------------------
-__device__ inline int lut_bin(const uint16_t* __restrict__ lut, const float* __restrict__ band, int n,
-                              float scale, float v, bool& amb) {
-    uint32_t e = lut[(uint32_t)(v * scale)];
-    if (!(e & 0x8000u)) return (e == 0x7fffu) ? -1 : (int)e;
-    // hot entry: count edges certainly <= v starting at the first banded edge
+__device__ inline uint32_t lut_entry(const uint16_t* __restrict__ lut, float scale, float v) {
+    return lut[(uint32_t)(v * scale)];
+}
+// A clean entry holds the bin, or 0x7fff for "out of range".
+__device__ inline int lut_clean_bin(uint32_t e) { return (e == 0x7fffu) ? -1 : (int)e; }
+// A hot entry (bit 15) holds the first edge whose band meets the entry: count the
+// edges certainly <= v (reverse-free forward traversal over the few banded
+// edges) and flag v inside a band as ambiguous.
+__device__ inline int lut_hot_bin(const float* __restrict__ band, int n, uint32_t e, float v, bool& amb) {
     int k = (int)(e & 0x7fffu);
     int c = k;
     for (; k <= n; k++) {
@@ -232,6 +236,13 @@ __device__ inline int lut_bin(const uint16_t* __restrict__ lut, const float* __r
     }
     return (c >= 1 && c <= n) ? c - 1 : -1;
 }
+
+// Kernel constants kept in registers.
+struct KConst {
+    float scale1, scale2, vmax1, vmax2, r2prune, d2small, mu_n, mu_nm1, tolA, tolB, tolC, side32;
+    int n1, n2, nbins, nx, copies;
+    double wscale;
+};
 
 __device__ inline void add_weight(const Smem& s, int flat, double p, double wscale) {
     long long t = (long long)(p * wscale);
@@ -288,44 +299,56 @@ struct WaveCtx {
 //   (s,mu), z:      v1 = d2, v2 = dz
 //   (sp,pi), z:     v1 = sp2, v2 = pi2
 //   mid-point:      v1, v2, v3 = dx, dy, dz (line of sight from the staged A point)
+// The common path is branch-free; hot table entries and rechecks take
+// wave-uniform branches that are rarely entered.
 template <int KIND, int LOS, bool W>
-__device__ __attribute__((always_inline)) inline void bin_queue(ArgsRef a, const Smem& s, uint32_t* hist_l, int base, int cnt, int lane,
-                          uint64_t lanemask_lt, WaveCtx& c) {
+__device__ __attribute__((always_inline)) inline void bin_queue(ArgsRef a, const KConst& k, const Smem& s,
+                                                                uint32_t* hist_l, int base, int cnt, int lane,
+                                                                WaveCtx& c) {
     const bool valid = lane < cnt;
     float4 e = make_float4(0.f, 0.f, 0.f, 0.f);
     if (valid) e = s.q[base + lane];
     const uint32_t ids = __float_as_uint(e.w);
     bool amb = false;
-    int flat = -1;
+    int flat;
     if (KIND == FCFC_BIN_S) {
-        flat = lut_bin(s.lut1, s.band1, a.n1, a.scale1, e.x, amb);
+        const float d2 = e.x;
+        const uint32_t ent = lut_entry(s.lut1, k.scale1, d2);
+        int sb = lut_clean_bin(ent);
+        const bool hot = (ent & 0x8000u) != 0u;
+        if (__builtin_amdgcn_ballot_w64(hot)) {
+            if (hot) sb = lut_hot_bin(s.band1, k.n1, ent, d2, amb);
+        }
+        flat = sb;
     } else if (KIND == FCFC_BIN_S_MU) {
         float d2, proj_n;  // proj_n: |projection on the line of sight| * n_mu / |l|
-        const float dxx = e.x, dyy = e.y, dzz = e.z;
         if (LOS == FCFC_LOS_Z) {
             d2 = e.x;
+            proj_n = fabsf(e.y) * k.mu_n;
         } else {
+            const float dxx = e.x, dyy = e.y, dzz = e.z;
             d2 = __builtin_fmaf(dzz, dzz, __builtin_fmaf(dyy, dyy, dxx * dxx));
-        }
-        const int sb = lut_bin(s.lut1, s.band1, a.n1, a.scale1, d2, amb);
-        const float rs = __builtin_amdgcn_rsqf(d2);
-        if (LOS == FCFC_LOS_Z) {
-            proj_n = fabsf(e.y) * a.mu_n;
-        } else {
             const float4 q = s.astage[ids & 127u];
             const float lx = q.x + dxx, ly = q.y + dyy, lz = q.z + dzz;
             const float dot = __builtin_fmaf(dzz, lz, __builtin_fmaf(dyy, ly, dxx * lx));
             const float ll = __builtin_fmaf(lz, lz, __builtin_fmaf(ly, ly, lx * lx));
-            proj_n = fabsf(dot) * (__builtin_amdgcn_rsqf(ll) * a.mu_n);
+            proj_n = fabsf(dot) * (__builtin_amdgcn_rsqf(ll) * k.mu_n);
         }
+        const uint32_t ent = lut_entry(s.lut1, k.scale1, d2);
+        int sb = lut_clean_bin(ent);
+        const bool hot = (ent & 0x8000u) != 0u;
+        if (__builtin_amdgcn_ballot_w64(hot)) {
+            if (hot) sb = lut_hot_bin(s.band1, k.n1, ent, d2, amb);
+        }
+        const float rs = __builtin_amdgcn_rsqf(d2);
         const float mun = proj_n * rs;
-        int mb = (int)mun;
-        mb = mb < a.n2 - 1 ? mb : a.n2 - 1;
+        const int mb = min((int)mun, k.n2 - 1);
         const float cr = rintf(mun);
         const float dist = fabsf(mun - cr);
-        const float tol = __builtin_fmaf(__builtin_fmaf(a.tolB, rs, a.tolA), rs, a.tolC);
-        amb = amb || ((dist < tol) && (cr >= 1.0f) && (cr <= a.mu_n - 1.0f)) || (d2 < a.d2small);
-        flat = (sb >= 0) ? sb * a.n2 + mb : -1;
+        const float tol = __builtin_fmaf(__builtin_fmaf(k.tolB, rs, k.tolA), rs, k.tolC);
+        const bool near_edge = (dist < tol) & (cr >= 1.0f) & (cr <= k.mu_nm1);
+        amb = amb | near_edge | (d2 < k.d2small);
+        flat = (sb >= 0) ? (int)__umul24((uint32_t)sb, (uint32_t)k.n2) + mb : -1;
     } else {
         float sp2, pi2;
         if (LOS == FCFC_LOS_Z) {
@@ -342,18 +365,26 @@ __device__ __attribute__((always_inline)) inline void bin_queue(ArgsRef a, const
             sp2 = fmaxf(d2 - pi2, 0.0f);
         }
         // beyond a table's top band end the pair is certainly out of range
-        if (sp2 < a.vmax1 && pi2 < a.vmax2) {
-            const int b1 = lut_bin(s.lut1, s.band1, a.n1, a.scale1, sp2, amb);
-            const int b2 = lut_bin(s.lut2, s.band2, a.n2, a.scale2, pi2, amb);
-            flat = (b1 >= 0 && b2 >= 0) ? b1 * a.n2 + b2 : -1;
+        const bool inr = (sp2 < k.vmax1) & (pi2 < k.vmax2);
+        const float sp2c = inr ? sp2 : 0.0f;
+        const float pi2c = inr ? pi2 : 0.0f;
+        const uint32_t e1 = lut_entry(s.lut1, k.scale1, sp2c);
+        const uint32_t e2 = lut_entry(s.lut2, k.scale2, pi2c);
+        int b1 = lut_clean_bin(e1), b2 = lut_clean_bin(e2);
+        const bool hot1 = (e1 & 0x8000u) != 0u, hot2 = (e2 & 0x8000u) != 0u;
+        if (__builtin_amdgcn_ballot_w64(hot1 | hot2)) {
+            if (hot1) b1 = lut_hot_bin(s.band1, k.n1, e1, sp2c, amb);
+            if (hot2) b2 = lut_hot_bin(s.band2, k.n2, e2, pi2c, amb);
         }
+        amb = amb & inr;
+        flat = (inr & (b1 >= 0) & (b2 >= 0)) ? (int)__umul24((uint32_t)b1, (uint32_t)k.n2) + b2 : -1;
     }
-    amb = amb && valid;
-    if (valid && !amb && flat >= 0) {
+    amb = amb & valid;
+    if (valid & !amb & (flat >= 0)) {
         atomicAdd(&hist_l[flat], 1u);
-        if (W) add_weight(s, flat, s.qw[base + lane], a.wscale);
+        if (W) add_weight(s, flat, s.qw[base + lane], k.wscale);
     }
-    const uint64_t m = __ballot(amb);
+    const uint64_t m = __builtin_amdgcn_ballot_w64(amb);
     if (m) {
         const int pos = c.rcount + (int)lane_prefix(m);
         if (amb) {
@@ -379,7 +410,7 @@ __global__ __launch_bounds__(CT_MAX) void k_count(const CountArgs* argp) {
     const int tid = threadIdx.x;
     const int nthr = blockDim.x;
     const int lane = tid & 63;
-    const int wave = tid >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     Smem s;
     s.lut1 = (const uint16_t*)(smem + a.off_lut1);
     s.lut2 = (const uint16_t*)(smem + a.off_lut2);
@@ -388,8 +419,8 @@ __global__ __launch_bounds__(CT_MAX) void k_count(const CountArgs* argp) {
     s.hist = (uint32_t*)(smem + a.off_hist);
     s.wlo = (unsigned long long*)(smem + a.off_whist);
     s.whi = s.wlo + a.nbins;
-    s.q = (float4*)(smem + a.off_q) + (size_t)wave * QCAP;
-    s.qw = (double*)(smem + a.off_qw) + (size_t)wave * QCAP;
+    s.q = (float4*)(smem + a.off_q) + (size_t)wave * (QCAP + 1);
+    s.qw = (double*)(smem + a.off_qw) + (size_t)wave * (QCAP + 1);
     s.rb = (uint32_t*)(smem + a.off_rb) + (size_t)wave * RB_CAP * 3;
     s.astage = (float4*)(smem + a.off_astage) + (size_t)wave * ASTAGE;
     s.misc = (unsigned long long*)(smem + a.off_misc);
@@ -417,8 +448,26 @@ __global__ __launch_bounds__(CT_MAX) void k_count(const CountArgs* argp) {
     }
     __syncthreads();
 
-    const uint64_t lanemask_lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    uint32_t* hist_l = s.hist + (size_t)(lane % a.copies) * a.nbins;
+    KConst k;
+    k.scale1 = a.scale1;
+    k.scale2 = a.scale2;
+    k.vmax1 = a.vmax1;
+    k.vmax2 = a.vmax2;
+    k.r2prune = a.r2prune;
+    k.d2small = a.d2small;
+    k.mu_n = a.mu_n;
+    k.mu_nm1 = a.mu_n - 1.0f;
+    k.tolA = a.tolA;
+    k.tolB = a.tolB;
+    k.tolC = a.tolC;
+    k.side32 = a.side32;
+    k.n1 = a.n1;
+    k.n2 = a.n2;
+    k.nbins = a.nbins;
+    k.nx = a.nx;
+    k.copies = a.copies;
+    k.wscale = a.wscale;
+    uint32_t* hist_l = s.hist + (size_t)(lane % k.copies) * k.nbins;
     WaveCtx c;
     c.rcount = 0;
     c.nrechk = 0;
@@ -426,14 +475,56 @@ __global__ __launch_bounds__(CT_MAX) void k_count(const CountArgs* argp) {
     const uint32_t nitems = __builtin_amdgcn_readfirstlane(*a.nitems_dev);
     const float far = 1.0e18f;
 
-    for (;;) {
-        uint32_t it = 0;
-        if (lane == 0) it = atomicAdd(a.cursor, 1u);
-        it = __builtin_amdgcn_readfirstlane(it);
-        if (it >= nitems) break;
+    // Items are pulled dynamically; the index of the item after next and the
+    // inputs (item record, A points, B cell offsets) of the next item are
+    // fetched while the current one is processed.
+    struct ItemIn {
+        Item item;
+        float4 av[P];
+        float4 aabs[P];
+        double aw[P];
+        uint32_t csv;  // lane t: start of B cell xw0 + t of the item's row
+    };
+    auto load_in = [&](uint32_t itx, ItemIn& in) __attribute__((always_inline)) {
+        in.item = ldc_item(a.items, itx);
+        const uint32_t a_begin = in.item.a_begin;
+        const uint32_t acnt = in.item.acnt_xb0 & 0xffffu;
+#pragma unroll
+        for (int p = 0; p < P; p++) {
+            const uint32_t i = (uint32_t)(lane + 64 * p);
+            in.av[p] = make_float4(far, far, far, __int_as_float(0));
+            if (i < acnt) in.av[p] = a.posA[a_begin + i];
+            if (LOS == FCFC_LOS_MIDPOINT && KIND != FCFC_BIN_S) {
+                in.aabs[p] = make_float4(far, far, far, 0.f);
+                if (i < acnt) in.aabs[p] = a.absA[a_begin + i];
+            }
+            if (W) in.aw[p] = (i < acnt) ? a.wA[a_begin + i] : 0.0;
+        }
+        const int xb0 = (int)(int16_t)(in.item.acnt_xb0 >> 16);
+        const int sxi = (int)((in.item.meta >> 16) & 3u) - 1;
+        const int xw0 = xb0 - sxi * a.nx;
+        const int cx = min(xw0 + lane, a.nx);
+        in.csv = a.csB[in.item.b_rowcell + (uint32_t)cx];
+    };
+
+    unsigned long long wave_pairs = 0;  // pairs claimed since this wave last emptied the histogram
+    uint32_t cur_it = 0, nxt_it = 0;
+    if (lane == 0) {
+        cur_it = atomicAdd(a.cursor, 1u);
+        nxt_it = atomicAdd(a.cursor, 1u);
+    }
+    cur_it = __builtin_amdgcn_readfirstlane(cur_it);
+    nxt_it = __builtin_amdgcn_readfirstlane(nxt_it);
+    ItemIn cur, nxt;
+    if (cur_it < nitems) load_in(cur_it, cur);
+    while (cur_it < nitems) {
+        uint32_t nn = 0;
+        if (lane == 0) nn = atomicAdd(a.cursor, 1u);
+        if (nxt_it < nitems) load_in(nxt_it, nxt);
+        const uint32_t it = cur_it;
         unsigned long long t0 = 0;
         if (a.times && lane == 0) t0 = wall_clock64();
-        const Item item = ldc_item(a.items, it);
+        const Item& item = cur.item;
         const uint32_t a_begin = item.a_begin;
         const uint32_t acnt = item.acnt_xb0 & 0xffffu;
         const int xb0 = (int)(int16_t)(item.acnt_xb0 >> 16);
@@ -448,65 +539,64 @@ __global__ __launch_bounds__(CT_MAX) void k_count(const CountArgs* argp) {
         c.it = it;
         const uint64_t pairs = (uint64_t)acnt * (uint64_t)(b_end - b_begin);
         ncand += pairs;
-        // u32 overflow guard of the LDS histogram: exchange it out every 2^30 claimed pairs
-        {
-            unsigned long long old = 0;
-            if (lane == 0) old = atomicAdd(&s.misc[0], (unsigned long long)pairs);
-            old = __shfl(old, 0);
-            if ((old / FLUSH_PAIRS) != ((old + pairs) / FLUSH_PAIRS)) {
-                for (int b = lane; b < a.nbins * a.copies; b += 64) {
-                    uint32_t v = atomicExch(&s.hist[b], 0u);
-                    if (v) atomicAdd(&a.out_counts[b % a.nbins], (unsigned long long)v);
-                }
-                if (W) {
-                    for (int b = lane; b < a.nbins; b += 64) {
-                        unsigned long long lo = atomicExch(&s.wlo[b], 0ull);
-                        unsigned long long hi = atomicExch(&s.whi[b], 0ull);
-                        __int128 v = ((__int128)(long long)hi << 32) + (__int128)lo;
-                        unsigned long long vlo = (unsigned long long)v;
-                        unsigned long long vhi = (unsigned long long)(v >> 64);
-                        unsigned long long o = atomicAdd(&a.out_w[2 * b], vlo);
-                        if (o + vlo < o) vhi += 1ull;
-                        if (vhi) atomicAdd(&a.out_w[2 * b + 1], vhi);
-                    }
+        // u32 overflow guard of the LDS histogram: every wave empties it (atomic
+        // exchange) after claiming 2^26 pairs, so it never holds 16 * (2^26 + item)
+        // < 2^31 increments
+        wave_pairs += pairs;
+        if (wave_pairs >= FLUSH_PAIRS) {
+            wave_pairs = 0;
+            for (int b = lane; b < a.nbins * a.copies; b += 64) {
+                uint32_t v = atomicExch(&s.hist[b], 0u);
+                if (v) atomicAdd(&a.out_counts[b % a.nbins], (unsigned long long)v);
+            }
+            if (W) {
+                for (int b = lane; b < a.nbins; b += 64) {
+                    unsigned long long lo = atomicExch(&s.wlo[b], 0ull);
+                    unsigned long long hi = atomicExch(&s.whi[b], 0ull);
+                    __int128 v = ((__int128)(long long)hi << 32) + (__int128)lo;
+                    unsigned long long vlo = (unsigned long long)v;
+                    unsigned long long vhi = (unsigned long long)(v >> 64);
+                    unsigned long long o = atomicAdd(&a.out_w[2 * b], vlo);
+                    if (o + vlo < o) vhi += 1ull;
+                    if (vhi) atomicAdd(&a.out_w[2 * b + 1], vhi);
                 }
             }
         }
-        const float Dy = (float)idy * a.side32;
-        const float Dz = (float)idz * a.side32;
+        const float Dy = (float)idy * k.side32;
+        const float Dz = (float)idz * k.side32;
         float ax[P], ay[P], az[P];
         double wa[P];
         int acx[P];
-        uint32_t aidx[P];
+        uint32_t aidx[P], ids_lane[P];
 #pragma unroll
         for (int p = 0; p < P; p++) {
-            uint32_t i = (uint32_t)(lane + 64 * p);
+            const uint32_t i = (uint32_t)(lane + 64 * p);
             aidx[p] = a_begin + i;
-            float4 v = make_float4(far, far, far, __int_as_float(0));
-            if (i < acnt) v = a.posA[a_begin + i];
+            ids_lane[p] = i;
+            const float4 v = cur.av[p];
             ax[p] = v.x;
             ay[p] = v.y - Dy;
             az[p] = v.z - Dz;
             acx[p] = __float_as_int(v.w);
             if (LOS == FCFC_LOS_MIDPOINT && KIND != FCFC_BIN_S) {
-                float4 q = make_float4(far, far, far, 0.f);
-                if (i < acnt) q = a.absA[a_begin + i];
+                const float4 q = cur.aabs[p];
                 s.astage[i] = make_float4(2.0f * q.x, 2.0f * q.y, 2.0f * q.z, 0.f);
             }
-            if (W) wa[p] = (i < acnt) ? a.wA[a_begin + i] : 0.0;
+            if (W) wa[p] = cur.aw[p];
         }
         int qn = 0;
         int xu = xb0;
         int xw = xb0 - sxi * a.nx;
+        int t = 0;
         uint32_t j = b_begin;
-        const uint32_t rowcell = item.b_rowcell;
         while (j < b_end && xw < a.nx) {
-            uint32_t cell_end = ldc_u32(a.csB, rowcell + (uint32_t)xw + 1u);
+            uint32_t cell_end = (t + 1 < 64) ? __builtin_amdgcn_readlane(cur.csv, t + 1)
+                                             : ldc_u32(a.csB, item.b_rowcell + (uint32_t)xw + 1u);
             cell_end = cell_end < b_end ? cell_end : b_end;
             if (cell_end > j) {
                 float axx[P];
 #pragma unroll
-                for (int p = 0; p < P; p++) axx[p] = ax[p] - (float)(xu - acx[p]) * a.side32;
+                for (int p = 0; p < P; p++) axx[p] = ax[p] - (float)(xu - acx[p]) * k.side32;
                 auto cell_loop = [&](auto mask_tag) __attribute__((always_inline)) {
                     constexpr bool MASK = decltype(mask_tag)::value;
                     float4 nb = ldc_f4(a.posB, j);
@@ -514,6 +604,7 @@ __global__ __launch_bounds__(CT_MAX) void k_count(const CountArgs* argp) {
                     for (; j < cell_end; j++) {
                         const float4 b = nb;
                         const double wb = nw;
+                        const uint32_t jbits = (j - b_begin) << 7;
                         // prefetch the next B point (arrays carry padding past the last point)
                         nb = ldc_f4(a.posB, j + 1);
                         if (W) nw = ldc_f64(a.wB, j + 1);
@@ -527,10 +618,10 @@ __global__ __launch_bounds__(CT_MAX) void k_count(const CountArgs* argp) {
                             if (KIND == FCFC_BIN_SPERP_PI && LOS == FCFC_LOS_Z) {
                                 v1 = __builtin_fmaf(dy, dy, dx * dx);
                                 v2 = dz * dz;
-                                in = (v1 < a.vmax1) && (v2 < a.vmax2);
+                                in = (v1 < k.vmax1) & (v2 < k.vmax2);
                             } else {
                                 const float d2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
-                                in = d2 < a.r2prune;
+                                in = d2 < k.r2prune;
                                 if (LOS == FCFC_LOS_MIDPOINT && KIND != FCFC_BIN_S) {
                                     v1 = dx;
                                     v2 = dy;
@@ -540,19 +631,17 @@ __global__ __launch_bounds__(CT_MAX) void k_count(const CountArgs* argp) {
                                     v2 = dz;
                                 }
                             }
-                            if (MASK) in = in && (j > aidx[p]);
-                            const uint64_t m = __ballot(in);
-                            const int slot = qn + (int)lane_prefix(m);
-                            if (in) {
-                                const uint32_t ids = ((j - b_begin) << 7) | (uint32_t)(lane + 64 * p);
-                                s.q[slot] = make_float4(v1, v2, v3, __uint_as_float(ids));
-                                if (W) s.qw[slot] = wa[p] * wb;
-                            }
+                            if (MASK) in = in & (j > aidx[p]);
+                            const uint64_t m = __builtin_amdgcn_ballot_w64(in);
+                            // every lane writes; lanes out of range write the dump entry QCAP
+                            const int slot = in ? qn + (int)lane_prefix(m) : QCAP;
+                            s.q[slot] = make_float4(v1, v2, v3, __uint_as_float(jbits | ids_lane[p]));
+                            if (W) s.qw[slot] = wa[p] * wb;
                             qn += (int)__popcll(m);
                         }
                         while (qn >= 64) {
                             wave_sync_lds();
-                            bin_queue<KIND, LOS, W>(a, s, hist_l, qn - 64, 64, lane, lanemask_lt, c);
+                            bin_queue<KIND, LOS, W>(a, k, s, hist_l, qn - 64, 64, lane, c);
                             wave_sync_lds();
                             qn -= 64;
                         }
@@ -566,16 +655,20 @@ __global__ __launch_bounds__(CT_MAX) void k_count(const CountArgs* argp) {
             }
             xw++;
             xu++;
+            t++;
         }
         if (qn > 0) {
             wave_sync_lds();
-            bin_queue<KIND, LOS, W>(a, s, hist_l, 0, qn, lane, lanemask_lt, c);
+            bin_queue<KIND, LOS, W>(a, k, s, hist_l, 0, qn, lane, c);
             wave_sync_lds();
         }
         if (a.times && lane == 0) {
             unsigned long long t1 = wall_clock64();
             a.times[it] = (uint32_t)min<unsigned long long>(t1 - t0, 0xffffffffull);
         }
+        cur = nxt;
+        cur_it = nxt_it;
+        nxt_it = __builtin_amdgcn_readfirstlane(nn);
     }
     if (c.rcount > 0) {
         wave_sync_lds();
@@ -703,7 +796,7 @@ fcfc_status count_pairs(Plan* p, Cells* c1, Cells* c2, int64_t* d_counts, double
     // ---- tuning
     int T = p->tune.tile_points == 64 ? 64 : 128;
     int P = T / 64;
-    int seg = p->tune.seg_cells > 0 ? std::min(64, p->tune.seg_cells) : 0;
+    int seg = p->tune.seg_cells > 0 ? std::min(32, p->tune.seg_cells) : 0;
     if (seg == 0) {
         double ppc = (double)c1->n / std::max<int64_t>(1, g.ncell());
         seg = (int)std::max(1.0, std::min(16.0, floor((double)T / std::max(ppc, 1e-9))));
@@ -740,7 +833,7 @@ fcfc_status count_pairs(Plan* p, Cells* c1, Cells* c2, int64_t* d_counts, double
     off += weighted ? al16(p->nbins * 16) : 0;
     const int shared_bytes = off;
     const bool mid = (p->los == FCFC_LOS_MIDPOINT && p->kind != FCFC_BIN_S);
-    const int per_wave = QCAP * 16 + (weighted ? QCAP * 8 : 0) + RB_CAP * 12 + (mid ? ASTAGE * 16 : 0);
+    const int per_wave = (QCAP + 1) * 16 + (weighted ? (QCAP + 1) * 8 : 0) + RB_CAP * 12 + (mid ? ASTAGE * 16 : 0);
     int dev = 0, maxlds = 65536;
     FCFC_HIP(hipGetDevice(&dev));
     if (hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) maxlds = 65536;
@@ -754,9 +847,9 @@ fcfc_status count_pairs(Plan* p, Cells* c1, Cells* c2, int64_t* d_counts, double
     }
     const int CT = waves * 64;
     a.off_q = off;
-    off += waves * QCAP * 16;
+    off += waves * (QCAP + 1) * 16;
     a.off_qw = off;
-    off += weighted ? waves * QCAP * 8 : 0;
+    off += weighted ? waves * (QCAP + 1) * 8 : 0;
     a.off_rb = off;
     off += waves * RB_CAP * 12;
     a.off_astage = off;
@@ -905,7 +998,7 @@ fcfc_status count_pairs(Plan* p, Cells* c1, Cells* c2, int64_t* d_counts, double
         uint32_t* v1 = (uint32_t*)(scr2 + 2 * s_items + 3 * s_sort);
         void* rs = scr2 + 2 * s_items + 4 * s_sort;
         hipLaunchKernelGGL(k_item_keys, dim3((nitems + 255) / 256), dim3(256), 0, st, items, &ctr[1], nitems, k0, v0);
-        radix_sort_pairs(&k0, &v0, &k1, &v1, nitems, 32, rs, st);
+        radix_sort_pairs(&k0, &v0, &k1, &v1, nitems, 8, rs, st);
         hipLaunchKernelGGL(k_item_permute, dim3((nitems + 255) / 256), dim3(256), 0, st, items, v0, &ctr[1], nitems,
                            items2);
         run_items = items2;

@@ -164,14 +164,23 @@ __global__ void k_item_write(const Tile* __restrict__ tiles, const uint32_t* __r
     });
 }
 
-// cost key for longest-first order: bitwise NOT of the cost so that an
-// ascending sort puts the largest first
+// Longest-first key: the cost rounded to a power of sqrt(2) (bucket 0..63),
+// reversed so that an ascending stable sort puts the largest first while
+// items of one bucket keep their enumeration order (A tiles and B rows stay
+// close together in memory).
 __global__ void k_item_keys(const Item* __restrict__ items, const uint32_t* __restrict__ nitems_dev,
                             uint32_t cap, uint32_t* __restrict__ key, uint32_t* __restrict__ val) {
     uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= cap) return;
     uint32_t n = *nitems_dev;
-    key[i] = (i < n) ? ~items[i].cost : 0xffffffffu;
+    uint32_t k = 255u;
+    if (i < n) {
+        uint32_t c = items[i].cost;
+        uint32_t lg = c ? 31u - (uint32_t)__clz(c) : 0u;  // floor(log2 c)
+        uint32_t half = (lg >= 1 && ((c >> (lg - 1)) & 1u)) ? 1u : 0u;
+        k = 63u - min(63u, 2u * lg + half);
+    }
+    key[i] = k;
     val[i] = i;
 }
 
