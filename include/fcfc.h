@@ -179,19 +179,30 @@ fcfc_status fcfc_count_pairs(fcfc_plan_t plan, fcfc_cells_t c1, fcfc_cells_t c2,
 fcfc_status fcfc_plan_stats(fcfc_plan_t plan, fcfc_stats *out);
 
 /*
- * fcfc_count_pairs_batched -- auto counts of many catalogues on one periodic
- * plan in one pipeline: one segmented cell build keyed by (catalogue, cell),
- * one work list, one persistent counting launch writing ncat histograms
- * (d_counts is ncat x n1*n2 int64, d_wcounts likewise or NULL).  With
- * use_graph the whole pipeline is captured into a HIP graph on first use and
- * replayed afterwards (the catalogue pointers and sizes must then stay the
- * same).  Synchronises `stream` once when (re)planning.
- * Errors: as fcfc_build_cells and fcfc_count_pairs; FCFC_ESTATE for an open plan.
+ * fcfc_batch_create / fcfc_batch_run -- auto counts of many catalogues on one
+ * periodic plan (line of sight z) in one pipeline: one cell build keyed by
+ * (catalogue, cell), one work list, one persistent counting launch that
+ * writes ncat histograms (d_counts: ncat x n1*n2 int64; d_wcounts likewise,
+ * or NULL).  Each unordered pair of every catalogue is counted once, exactly
+ * as fcfc_count_pairs does per catalogue.  fcfc_batch_create validates the
+ * catalogues, sizes every buffer (synchronising `stream` once) and keeps the
+ * catalogue pointers: they must stay valid and keep their sizes for the life
+ * of the batch.  fcfc_batch_run enqueues the whole pipeline; with use_graph
+ * it is captured into a HIP graph on the first run and replayed afterwards.
+ * Errors: FCFC_ESTATE (open plan), FCFC_EINVAL (mixed weights, nulls),
+ * FCFC_EBOX, FCFC_ENONFINITE, FCFC_ERANGE, FCFC_ENOMEM, FCFC_EHIP.
  */
 fcfc_status fcfc_batch_create(fcfc_plan_t plan, const fcfc_catalog *cats, int32_t ncat,
                               void *stream, fcfc_batch_t *out);
 fcfc_status fcfc_batch_run(fcfc_batch_t batch, int64_t *d_counts, double *d_wcounts,
                            int32_t use_graph, void *stream);
+/*
+ * fcfc_batch_check -- wait for `stream`, report the work items of the last
+ * run and its GPU time in ms (HIP events around the pipeline), and return
+ * FCFC_ERANGE if the work list outgrew the capacity sized at creation (the
+ * catalogue contents changed since fcfc_batch_create; counts are then invalid).
+ */
+fcfc_status fcfc_batch_check(fcfc_batch_t batch, void* stream, uint32_t *n_items, float *ms);
 void fcfc_batch_free(fcfc_batch_t batch);
 
 void fcfc_cells_free(fcfc_cells_t cells);

@@ -566,4 +566,121 @@ fcfc_status build_cells(Plan* p, const fcfc_catalog* cat, hipStream_t st, Cells*
     return FCFC_OK;
 }
 
+// ---------------------------------------------------------------------------
+// batched build: many periodic catalogues on one grid, sorted by the
+// combined key (catalogue * ncell + cell) so that catalogue c occupies the
+// cells [c * ncell, (c+1) * ncell) of one stacked grid
+// ---------------------------------------------------------------------------
+__device__ inline int find_cat(const int64_t* __restrict__ offs, int ncat, int64_t i) {
+    int lo = 0, hi = ncat;  // offs[lo] <= i < offs[hi]
+    while (hi - lo > 1) {
+        int mid = (lo + hi) >> 1;
+        if (offs[mid] <= i) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(256) void k_bkeys(const CatDesc* __restrict__ cats, const int64_t* __restrict__ offs,
+                                               int ncat, int64_t ntot, GridArgs g, uint32_t* __restrict__ key,
+                                               uint32_t* __restrict__ idx, uint32_t* __restrict__ flags,
+                                               uint64_t* __restrict__ wst) {
+    __shared__ uint32_t sflag;
+    __shared__ uint64_t swmin, swmax;
+    if (threadIdx.x == 0) {
+        sflag = 0;
+        swmin = ~0ull;
+        swmax = 0;
+    }
+    __syncthreads();
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < ntot) {
+        const int c = find_cat(offs, ncat, i);
+        const CatDesc d = cats[c];
+        const int64_t li = i - offs[c];
+        double x = d.xyz[3 * li], y = d.xyz[3 * li + 1], z = d.xyz[3 * li + 2];
+        uint32_t f = 0;
+        if (!isfinite(x) || !isfinite(y) || !isfinite(z)) f |= VF_NONFINITE;
+        else if (!(x >= 0.0 && x < g.L && y >= 0.0 && y < g.L && z >= 0.0 && z < g.L)) f |= VF_BOX;
+        uint32_t cx = 0, cy = 0, cz = 0;
+        if (!f) {
+            cx = cell_of(x, 0.0, g.side, g.nx);
+            cy = cell_of(y, 0.0, g.side, g.ny);
+            cz = cell_of(z, 0.0, g.side, g.nz);
+        }
+        key[i] = (((uint32_t)c * (uint32_t)g.nz + cz) * (uint32_t)g.ny + cy) * (uint32_t)g.nx + cx;
+        idx[i] = (uint32_t)i;
+        if (d.w) {
+            double wv = d.w[li];
+            if (!isfinite(wv)) {
+                f |= VF_WNONFINITE;
+            } else {
+                double a = fabs(wv);
+                uint64_t b = (uint64_t)__double_as_longlong(a);
+                if (a > 0.0) atomicMin((unsigned long long*)&swmin, (unsigned long long)b);
+                atomicMax((unsigned long long*)&swmax, (unsigned long long)b);
+            }
+        }
+        if (f) atomicOr(&sflag, f);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        if (sflag) atomicOr(flags, sflag);
+        if (swmin != ~0ull) atomicMin((unsigned long long*)&wst[0], (unsigned long long)swmin);
+        if (swmax) atomicMax((unsigned long long*)&wst[1], (unsigned long long)swmax);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_bgather(const CatDesc* __restrict__ cats, const int64_t* __restrict__ offs,
+                                                 int ncat, const uint32_t* __restrict__ skey,
+                                                 const uint32_t* __restrict__ sidx, int64_t n, GridArgs g,
+                                                 float4* __restrict__ pos32, double* __restrict__ pos64,
+                                                 double* __restrict__ wout) {
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    uint32_t i = sidx[p];
+    const int c = find_cat(offs, ncat, i);
+    const CatDesc d = cats[c];
+    const int64_t li = (int64_t)i - offs[c];
+    uint32_t key = skey[p];
+    uint32_t cx = key % (uint32_t)g.nx;
+    uint32_t cy = (key / (uint32_t)g.nx) % (uint32_t)g.ny;
+    uint32_t cz = (key / ((uint32_t)g.nx * (uint32_t)g.ny)) % (uint32_t)g.nz;
+    double x = d.xyz[3 * li], y = d.xyz[3 * li + 1], z = d.xyz[3 * li + 2];
+    pos32[p] = make_float4((float)(x - (double)cx * g.side), (float)(y - (double)cy * g.side),
+                           (float)(z - (double)cz * g.side), __int_as_float((int)cx));
+    pos64[3 * p] = x;
+    pos64[3 * p + 1] = y;
+    pos64[3 * p + 2] = z;
+    if (wout) wout[p] = d.w ? d.w[li] : 0.0;
+}
+
+size_t batch_build_scratch(int64_t ntot) { return radix_scratch_bytes(ntot); }
+
+// Enqueue the batched build (no host synchronisation: capturable).
+void batch_build_enqueue(const Plan* p, const CatDesc* desc, const int64_t* offs, int ncat, int64_t ntot,
+                         bool weighted, uint32_t** key, uint32_t** idx, uint32_t** tk, uint32_t** tv, void* sort_scr,
+                         uint32_t* flags, uint64_t* wst, float4* pos32, double* pos64, double* w, uint32_t* cs,
+                         hipStream_t st) {
+    GridArgs g = make_grid_args(p);
+    const int64_t ncell_all = p->grid.ncell() * (int64_t)ncat;
+    fill_u32((uint32_t*)(pos32 + ntot), 0u, 8 * 4, st);
+    if (weighted) fill_u64((uint64_t*)(w + ntot), 0ull, 8, st);
+    fill_u32(flags, 0u, 1, st);
+    fill_u64(wst, ~0ull, 1, st);
+    fill_u64(wst + 1, 0ull, 1, st);
+    if (ntot > 0) {
+        hipLaunchKernelGGL(k_bkeys, dim3((unsigned)((ntot + 255) / 256)), dim3(256), 0, st, desc, offs, ncat, ntot, g,
+                           *key, *idx, flags, wst);
+        int bits = 0;
+        while (bits < 32 && ((int64_t)1 << bits) < ncell_all) bits++;
+        bits = (bits + 7) / 8 * 8;
+        radix_sort_pairs(key, idx, tk, tv, ntot, bits, sort_scr, st);
+        hipLaunchKernelGGL(k_bgather, dim3((unsigned)((ntot + 255) / 256)), dim3(256), 0, st, desc, offs, ncat, *key,
+                           *idx, ntot, g, pos32, pos64, weighted ? w : nullptr);
+    }
+    hipLaunchKernelGGL(k_cell_start, dim3((unsigned)((ntot + 1 + 255) / 256)), dim3(256), 0, st, *key, ntot, ncell_all,
+                       cs);
+}
+
 }  // namespace fcfc

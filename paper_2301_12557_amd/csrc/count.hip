@@ -91,6 +91,14 @@ struct CountArgs {
     int mu_top_closed;
     double wscale;
     int copies;
+    // batched mode: chunks of items per catalogue
+    const uint32_t* nchunks_dev;
+    uint32_t* chunk_cursor;
+    const uint32_t* chunk_prefix;  // ncat + 1, in catalogue order
+    const uint32_t* cat_order;     // catalogue index at each order position
+    const uint32_t* cat_items;     // ncat + 1: items of catalogue c are [cat_items[c], cat_items[c+1])
+    int ncat;
+    int chunk_items;
     // LDS layout (bytes)
     int off_lut1, off_lut2, off_band1, off_band2, off_hist, off_whist, off_q, off_qw, off_rb, off_astage,
         off_misc, lds_bytes;
@@ -403,7 +411,7 @@ __device__ __attribute__((always_inline)) inline void bin_queue(ArgsRef a, const
     }
 }
 
-template <int KIND, int LOS, bool AUTO, bool W, int P>
+template <int KIND, int LOS, bool AUTO, bool W, int P, bool BATCH>
 __global__ __launch_bounds__(CT_MAX) void k_count(const CountArgs* argp) {
     ArgsRef a = *(const CountArgs FCFC_CONST*)argp;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -444,7 +452,7 @@ __global__ __launch_bounds__(CT_MAX) void k_count(const CountArgs* argp) {
         for (int i = tid; i < a.nbins * a.copies; i += nthr) s.hist[i] = 0u;
         if (W)
             for (int i = tid; i < 2 * a.nbins; i += nthr) s.wlo[i] = 0ull;
-        if (tid == 0) s.misc[0] = 0ull;
+        if (tid < 4) s.misc[tid] = 0ull;
     }
     __syncthreads();
 
@@ -472,7 +480,6 @@ __global__ __launch_bounds__(CT_MAX) void k_count(const CountArgs* argp) {
     c.rcount = 0;
     c.nrechk = 0;
     unsigned long long ncand = 0;
-    const uint32_t nitems = __builtin_amdgcn_readfirstlane(*a.nitems_dev);
     const float far = 1.0e18f;
 
     // Items are pulled dynamically; the index of the item after next and the
@@ -508,19 +515,70 @@ __global__ __launch_bounds__(CT_MAX) void k_count(const CountArgs* argp) {
     };
 
     unsigned long long wave_pairs = 0;  // pairs claimed since this wave last emptied the histogram
-    uint32_t cur_it = 0, nxt_it = 0;
-    if (lane == 0) {
-        cur_it = atomicAdd(a.cursor, 1u);
-        nxt_it = atomicAdd(a.cursor, 1u);
-    }
-    cur_it = __builtin_amdgcn_readfirstlane(cur_it);
-    nxt_it = __builtin_amdgcn_readfirstlane(nxt_it);
+    uint32_t out_off = 0;               // first bin of the current catalogue in the outputs
+    // u32 overflow guard of the LDS histogram: every wave empties it (atomic
+    // exchange) after claiming 2^26 pairs, so it never holds 16 * (2^26 + item)
+    // < 2^31 increments
+    auto exchange_out = [&]() __attribute__((always_inline)) {
+        for (int b = lane; b < k.nbins * k.copies; b += 64) {
+            uint32_t v = atomicExch(&s.hist[b], 0u);
+            if (v) atomicAdd(&a.out_counts[out_off + b % k.nbins], (unsigned long long)v);
+        }
+        if (W) {
+            for (int b = lane; b < k.nbins; b += 64) {
+                unsigned long long lo = atomicExch(&s.wlo[b], 0ull);
+                unsigned long long hi = atomicExch(&s.whi[b], 0ull);
+                __int128 v = ((__int128)(long long)hi << 32) + (__int128)lo;
+                unsigned long long vlo = (unsigned long long)v;
+                unsigned long long vhi = (unsigned long long)(v >> 64);
+                unsigned long long o = atomicAdd(&a.out_w[2 * ((size_t)out_off + b)], vlo);
+                if (o + vlo < o) vhi += 1ull;
+                if (vhi) atomicAdd(&a.out_w[2 * ((size_t)out_off + b) + 1], vhi);
+            }
+        }
+    };
+    // workgroup-wide merge of the LDS histograms into the outputs, then clear
+    auto merge_out = [&]() __attribute__((always_inline)) {
+        for (int b = tid; b < k.nbins; b += nthr) {
+            uint32_t cnt = 0;
+            for (int r = 0; r < k.copies; r++) {
+                cnt += s.hist[r * k.nbins + b];
+                s.hist[r * k.nbins + b] = 0u;
+            }
+            if (cnt) atomicAdd(&a.out_counts[out_off + b], (unsigned long long)cnt);
+            if (W) {
+                unsigned long long lo = s.wlo[b], hi = s.whi[b];
+                s.wlo[b] = 0ull;
+                s.whi[b] = 0ull;
+                if (lo | hi) {
+                    __int128 v = ((__int128)(long long)hi << 32) + (__int128)lo;
+                    unsigned long long vlo = (unsigned long long)v;
+                    unsigned long long vhi = (unsigned long long)(v >> 64);
+                    unsigned long long o = atomicAdd(&a.out_w[2 * ((size_t)out_off + b)], vlo);
+                    if (o + vlo < o) vhi += 1ull;
+                    if (vhi) atomicAdd(&a.out_w[2 * ((size_t)out_off + b) + 1], vhi);
+                }
+            }
+        }
+    };
+    auto drain_rechecks = [&]() __attribute__((always_inline)) {
+        while (c.rcount > 0) {
+            const int n = c.rcount < 64 ? c.rcount : 64;
+            wave_sync_lds();
+            process_rechecks<KIND, LOS, W>(a, s, c.rcount - n, n, lane, c.nrechk);
+            wave_sync_lds();
+            c.rcount -= n;
+        }
+    };
+    // Process items handed out by grab() (an index, or ~0u when there are no more).
+    auto process_items = [&](auto grab) __attribute__((always_inline)) {
+    uint32_t cur_it = grab();
+    uint32_t nxt_it = grab();
     ItemIn cur, nxt;
-    if (cur_it < nitems) load_in(cur_it, cur);
-    while (cur_it < nitems) {
-        uint32_t nn = 0;
-        if (lane == 0) nn = atomicAdd(a.cursor, 1u);
-        if (nxt_it < nitems) load_in(nxt_it, nxt);
+    if (cur_it != ~0u) load_in(cur_it, cur);
+    while (cur_it != ~0u) {
+        const uint32_t nn = grab();
+        if (nxt_it != ~0u) load_in(nxt_it, nxt);
         const uint32_t it = cur_it;
         unsigned long long t0 = 0;
         if (a.times && lane == 0) t0 = wall_clock64();
@@ -539,28 +597,10 @@ __global__ __launch_bounds__(CT_MAX) void k_count(const CountArgs* argp) {
         c.it = it;
         const uint64_t pairs = (uint64_t)acnt * (uint64_t)(b_end - b_begin);
         ncand += pairs;
-        // u32 overflow guard of the LDS histogram: every wave empties it (atomic
-        // exchange) after claiming 2^26 pairs, so it never holds 16 * (2^26 + item)
-        // < 2^31 increments
         wave_pairs += pairs;
         if (wave_pairs >= FLUSH_PAIRS) {
             wave_pairs = 0;
-            for (int b = lane; b < a.nbins * a.copies; b += 64) {
-                uint32_t v = atomicExch(&s.hist[b], 0u);
-                if (v) atomicAdd(&a.out_counts[b % a.nbins], (unsigned long long)v);
-            }
-            if (W) {
-                for (int b = lane; b < a.nbins; b += 64) {
-                    unsigned long long lo = atomicExch(&s.wlo[b], 0ull);
-                    unsigned long long hi = atomicExch(&s.whi[b], 0ull);
-                    __int128 v = ((__int128)(long long)hi << 32) + (__int128)lo;
-                    unsigned long long vlo = (unsigned long long)v;
-                    unsigned long long vhi = (unsigned long long)(v >> 64);
-                    unsigned long long o = atomicAdd(&a.out_w[2 * b], vlo);
-                    if (o + vlo < o) vhi += 1ull;
-                    if (vhi) atomicAdd(&a.out_w[2 * b + 1], vhi);
-                }
-            }
+            exchange_out();
         }
         const float Dy = (float)idy * k.side32;
         const float Dz = (float)idz * k.side32;
@@ -668,32 +708,66 @@ __global__ __launch_bounds__(CT_MAX) void k_count(const CountArgs* argp) {
         }
         cur = nxt;
         cur_it = nxt_it;
-        nxt_it = __builtin_amdgcn_readfirstlane(nn);
+        nxt_it = nn;
     }
-    if (c.rcount > 0) {
-        wave_sync_lds();
-        process_rechecks<KIND, LOS, W>(a, s, 0, c.rcount, lane, c.nrechk);
+    };
+    if (!BATCH) {
+        const uint32_t nitems = __builtin_amdgcn_readfirstlane(*a.nitems_dev);
+        process_items([&]() -> uint32_t {
+            uint32_t v = 0;
+            if (lane == 0) v = atomicAdd(a.cursor, 1u);
+            v = __builtin_amdgcn_readfirstlane(v);
+            return v < nitems ? v : ~0u;
+        });
+        drain_rechecks();
+        __syncthreads();
+        merge_out();
+    } else {
+        // Workgroup-synchronous chunks of items of one catalogue at a time: the
+        // LDS histograms always belong to the workgroup's current catalogue.
+        uint32_t* sm32 = (uint32_t*)(s.misc + 1);  // [0] chunk, [1] cursor within the chunk
+        const uint32_t nchunks = __builtin_amdgcn_readfirstlane(*a.nchunks_dev);
+        uint32_t cur_cat = ~0u;
+        for (;;) {
+            if (tid == 0) {
+                sm32[0] = atomicAdd(a.chunk_cursor, 1u);
+                sm32[1] = 0u;
+            }
+            __syncthreads();
+            const uint32_t chunk = __builtin_amdgcn_readfirstlane(sm32[0]);
+            if (chunk >= nchunks) break;
+            // chunk -> position in the catalogue order (binary search on the chunk prefix)
+            int lo = 0, hi = a.ncat;
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                if (ldc_u32(a.chunk_prefix, (uint32_t)mid) <= chunk) lo = mid;
+                else hi = mid;
+            }
+            const uint32_t cat = ldc_u32(a.cat_order, (uint32_t)lo);
+            const uint32_t local = chunk - ldc_u32(a.chunk_prefix, (uint32_t)lo);
+            const uint32_t ib = ldc_u32(a.cat_items, cat) + local * (uint32_t)a.chunk_items;
+            const uint32_t ie_cat = ldc_u32(a.cat_items, cat + 1u);
+            const uint32_t ie = min(ib + (uint32_t)a.chunk_items, ie_cat);
+            if (cat != cur_cat) {
+                if (cur_cat != ~0u) merge_out();
+                __syncthreads();
+                cur_cat = cat;
+                out_off = cat * (uint32_t)k.nbins;
+            }
+            process_items([&]() -> uint32_t {
+                uint32_t v = 0;
+                if (lane == 0) v = atomicAdd(&sm32[1], 1u);
+                v = __builtin_amdgcn_readfirstlane(v) + ib;
+                return v < ie ? v : ~0u;
+            });
+            drain_rechecks();
+            __syncthreads();
+        }
+        if (cur_cat != ~0u) merge_out();
     }
     if (lane == 0 && a.stats) {
         atomicAdd(&a.stats[0], ncand);
         atomicAdd(&a.stats[1], c.nrechk);
-    }
-    __syncthreads();
-    for (int b = tid; b < a.nbins; b += nthr) {
-        uint32_t cnt = 0;
-        for (int r = 0; r < a.copies; r++) cnt += s.hist[r * a.nbins + b];
-        if (cnt) atomicAdd(&a.out_counts[b], (unsigned long long)cnt);
-        if (W) {
-            unsigned long long lo = s.wlo[b], hi = s.whi[b];
-            if (lo | hi) {
-                __int128 v = ((__int128)(long long)hi << 32) + (__int128)lo;
-                unsigned long long vlo = (unsigned long long)v;
-                unsigned long long vhi = (unsigned long long)(v >> 64);
-                unsigned long long o = atomicAdd(&a.out_w[2 * b], vlo);
-                if (o + vlo < o) vhi += 1ull;
-                if (vhi) atomicAdd(&a.out_w[2 * b + 1], vhi);
-            }
-        }
     }
 }
 
@@ -730,15 +804,15 @@ __global__ void k_finalize_w(const unsigned long long* __restrict__ acc, int nbi
 // ---------------------------------------------------------------------------
 typedef void (*CountKernel)(const CountArgs*);
 
-template <int KIND, int LOS, bool AUTO, bool W>
+template <int KIND, int LOS, bool AUTO, bool W, bool B>
 static CountKernel pick_p(int P) {
-    if (P == 1) return k_count<KIND, LOS, AUTO, W, 1>;
-    return k_count<KIND, LOS, AUTO, W, 2>;
+    if (P == 1) return k_count<KIND, LOS, AUTO, W, 1, B>;
+    return k_count<KIND, LOS, AUTO, W, 2, B>;
 }
 template <int KIND, int LOS>
 static CountKernel pick_aw(bool is_auto, bool w, int P) {
-    if (is_auto) return w ? pick_p<KIND, LOS, true, true>(P) : pick_p<KIND, LOS, true, false>(P);
-    return w ? pick_p<KIND, LOS, false, true>(P) : pick_p<KIND, LOS, false, false>(P);
+    if (is_auto) return w ? pick_p<KIND, LOS, true, true, false>(P) : pick_p<KIND, LOS, true, false, false>(P);
+    return w ? pick_p<KIND, LOS, false, true, false>(P) : pick_p<KIND, LOS, false, false, false>(P);
 }
 static CountKernel pick_kernel(int kind, int los, bool is_auto, bool w, int P) {
     if (kind == FCFC_BIN_S) return pick_aw<FCFC_BIN_S, FCFC_LOS_Z>(is_auto, w, P);
@@ -748,76 +822,70 @@ static CountKernel pick_kernel(int kind, int los, bool is_auto, bool w, int P) {
     return los == FCFC_LOS_Z ? pick_aw<FCFC_BIN_SPERP_PI, FCFC_LOS_Z>(is_auto, w, P)
                              : pick_aw<FCFC_BIN_SPERP_PI, FCFC_LOS_MIDPOINT>(is_auto, w, P);
 }
+// batched auto counts in a periodic box (line of sight z)
+static CountKernel pick_batch_kernel(int kind, bool w, int P) {
+    if (kind == FCFC_BIN_S)
+        return w ? pick_p<FCFC_BIN_S, FCFC_LOS_Z, true, true, true>(P) : pick_p<FCFC_BIN_S, FCFC_LOS_Z, true, false, true>(P);
+    if (kind == FCFC_BIN_S_MU)
+        return w ? pick_p<FCFC_BIN_S_MU, FCFC_LOS_Z, true, true, true>(P)
+                 : pick_p<FCFC_BIN_S_MU, FCFC_LOS_Z, true, false, true>(P);
+    return w ? pick_p<FCFC_BIN_SPERP_PI, FCFC_LOS_Z, true, true, true>(P)
+             : pick_p<FCFC_BIN_SPERP_PI, FCFC_LOS_Z, true, false, true>(P);
+}
 
 static int al16(int b) { return (b + 15) & ~15; }
+static size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 // ---------------------------------------------------------------------------
-// host driver
+// host-side preparation shared by the single and batched drivers
 // ---------------------------------------------------------------------------
-struct DevTables {
-    char* base = nullptr;
-    uint16_t* lut1;
-    uint16_t* lut2;
-    float* band1;
-    float* band2;
-    double* E1;
-    double* E2;
-    int4* srows;
+struct LaunchSetup {
+    CountArgs a;  // LDS layout and numeric constants (device pointers bound later)
+    int waves = 16, P = 2, T = 128, seg = 1, bchunk = 16384, copies = 1;
+    std::vector<int4> rows;
+    int nrows = 0;
+    std::vector<char> htab;  // tables blob: lut1, lut2, band1, band2, E1, E2, stencil rows
+    size_t tb_l1 = 0, tb_l2 = 0, tb_b1 = 0, tb_b2 = 0, tb_e1 = 0, tb_e2 = 0, tb_rows = 0, tb_total = 0;
+    CountKernel kern = nullptr;
 };
 
-fcfc_status count_pairs(Plan* p, Cells* c1, Cells* c2, int64_t* d_counts, double* d_wcounts, hipStream_t st) {
-    const bool is_auto = (c2 == nullptr);
-    Cells* cb = is_auto ? c1 : c2;
-    const bool weighted = d_wcounts != nullptr;
-    const Grid& g = p->grid;
-    // ---- weights: common fixed-point scale 2^S making every product an integer
-    int S = 0;
-    if (weighted) {
-        if (!c1->weighted || !cb->weighted) {
-            set_error("count_pairs: weighted counts need weights in both cell sets");
-            return FCFC_EINVAL;
+// Common fixed-point scale 2^S making every weight product an integer.
+static fcfc_status weight_scale(double wmin1, double wmax1, double wmin2, double wmax2, int* S) {
+    *S = 0;
+    if (wmin1 > 0 && wmin2 > 0) {
+        double pmin = wmin1 * wmin2;
+        int e;
+        frexp(pmin, &e);
+        *S = 53 - e;
+        double pmax = wmax1 * wmax2;
+        if (!(ldexp(pmax, *S) < ldexp(1.0, 62))) {
+            set_error("weight dynamic range too wide for exact accumulation (max/min pair weight %.3g)", pmax / pmin);
+            return FCFC_ERANGE;
         }
-        double wmin = std::min(c1->wmin, cb->wmin), wmax = std::max(c1->wmax, cb->wmax);
-        (void)wmin;
-        if (c1->wmin > 0 && cb->wmin > 0) {
-            double pmin = c1->wmin * cb->wmin;
-            int e;
-            frexp(pmin, &e);
-            S = 53 - e;
-            double pmax = c1->wmax * cb->wmax;
-            if (!(ldexp(pmax, S) < ldexp(1.0, 62))) {
-                set_error("count_pairs: weight dynamic range too wide for exact accumulation "
-                          "(max/min pair weight %.3g)", pmax / pmin);
-                return FCFC_ERANGE;
-            }
-        }
-        (void)wmax;
     }
-    // ---- tuning
-    int T = p->tune.tile_points == 64 ? 64 : 128;
-    int P = T / 64;
-    int seg = p->tune.seg_cells > 0 ? std::min(32, p->tune.seg_cells) : 0;
-    if (seg == 0) {
-        double ppc = (double)c1->n / std::max<int64_t>(1, g.ncell());
-        seg = (int)std::max(1.0, std::min(16.0, floor((double)T / std::max(ppc, 1e-9))));
-        if (ppc >= T / 2) seg = 1;
-    }
-    int bchunk = p->tune.b_chunk >= 256 ? p->tune.b_chunk : 16384;
-    int copies = (p->tune.hist_copies == 2 || p->tune.hist_copies == 4) ? p->tune.hist_copies : 1;
-    int order = p->tune.order;
+    return FCFC_OK;
+}
 
-    std::vector<int4> rows;
-    int nrows = stencil_rows(p, is_auto, rows);
+static fcfc_status setup_launch(Plan* p, bool is_auto, bool weighted, bool batch, double ppc, int S, LaunchSetup& L) {
+    const Grid& g = p->grid;
+    L.T = p->tune.tile_points == 64 ? 64 : 128;
+    L.P = L.T / 64;
+    L.seg = p->tune.seg_cells > 0 ? std::min(32, p->tune.seg_cells) : 0;
+    if (L.seg == 0) {
+        L.seg = (int)std::max(1.0, std::min(16.0, floor((double)L.T / std::max(ppc, 1e-9))));
+        if (ppc >= L.T / 2) L.seg = 1;
+    }
+    L.bchunk = p->tune.b_chunk >= 256 ? p->tune.b_chunk : 16384;
+    L.copies = (p->tune.hist_copies == 2 || p->tune.hist_copies == 4) ? p->tune.hist_copies : 1;
+    L.nrows = stencil_rows(p, is_auto, L.rows);
     const Lut1D& L1 = p->lut1;
     const Lut1D& L2 = p->lut2;
     const bool two = (p->kind == FCFC_BIN_SPERP_PI);
-
-    // ---- LDS layout
-    CountArgs a;
+    CountArgs& a = L.a;
     memset(&a, 0, sizeof(a));
     a.nlut1 = (int)L1.tab.size();
     a.nlut2 = two ? (int)L2.tab.size() : 0;
-    a.copies = copies;
+    a.copies = L.copies;
     int off = 0;
     a.off_lut1 = off;
     off += al16(a.nlut1 * 2 + 4);
@@ -828,7 +896,7 @@ fcfc_status count_pairs(Plan* p, Cells* c1, Cells* c2, int64_t* d_counts, double
     a.off_band2 = off;
     off += al16(two ? 2 * (p->n2 + 1) * 4 : 0);
     a.off_hist = off;
-    off += al16(p->nbins * 4 * copies);
+    off += al16(p->nbins * 4 * L.copies);
     a.off_whist = off;
     off += weighted ? al16(p->nbins * 16) : 0;
     const int shared_bytes = off;
@@ -838,83 +906,167 @@ fcfc_status count_pairs(Plan* p, Cells* c1, Cells* c2, int64_t* d_counts, double
     FCFC_HIP(hipGetDevice(&dev));
     if (hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) maxlds = 65536;
     // as many waves per workgroup (up to 16, one workgroup per CU) as the LDS allows
-    int waves = 16;
-    while (waves > 1 && shared_bytes + waves * per_wave + 16 > maxlds) waves--;
-    if (shared_bytes + waves * per_wave + 16 > maxlds) {
-        set_error("count_pairs: %d bytes of LDS needed (tables + histogram), device allows %d",
-                  shared_bytes + per_wave + 16, maxlds);
+    L.waves = 16;
+    while (L.waves > 1 && shared_bytes + L.waves * per_wave + 64 > maxlds) L.waves--;
+    if (shared_bytes + L.waves * per_wave + 64 > maxlds) {
+        set_error("count: %d bytes of LDS needed (tables + histogram), device allows %d", shared_bytes + per_wave + 64,
+                  maxlds);
         return FCFC_ERANGE;
     }
-    const int CT = waves * 64;
     a.off_q = off;
-    off += waves * (QCAP + 1) * 16;
+    off += L.waves * (QCAP + 1) * 16;
     a.off_qw = off;
-    off += weighted ? waves * (QCAP + 1) * 8 : 0;
+    off += weighted ? L.waves * (QCAP + 1) * 8 : 0;
     a.off_rb = off;
-    off += waves * RB_CAP * 12;
+    off += L.waves * RB_CAP * 12;
     a.off_astage = off;
-    off += mid ? waves * ASTAGE * 16 : 0;
+    off += mid ? L.waves * ASTAGE * 16 : 0;
     a.off_misc = off;
-    off += 16;
+    off += 64;
     a.lds_bytes = off;
-
-    // ---- small tables to the device (one block)
-    size_t tb_l1 = (size_t)al16(a.nlut1 * 2 + 4), tb_l2 = (size_t)al16(a.nlut2 * 2 + 4);
-    size_t tb_b1 = (size_t)al16(2 * (p->n1 + 1) * 4), tb_b2 = (size_t)al16(2 * (p->n2 + 1) * 4);
-    size_t tb_e1 = (size_t)al16((p->n1 + 1) * 8), tb_e2 = (size_t)al16((p->n2 + 1) * 8);
-    size_t tb_rows = (size_t)al16(std::max(1, nrows) * 16);
-    size_t tb_total = tb_l1 + tb_l2 + tb_b1 + tb_b2 + tb_e1 + tb_e2 + tb_rows;
-    std::vector<char> htab(tb_total, 0);
+    // tables blob
+    L.tb_l1 = (size_t)al16(a.nlut1 * 2 + 4);
+    L.tb_l2 = (size_t)al16(a.nlut2 * 2 + 4);
+    L.tb_b1 = (size_t)al16(2 * (p->n1 + 1) * 4);
+    L.tb_b2 = (size_t)al16(2 * (p->n2 + 1) * 4);
+    L.tb_e1 = (size_t)al16((p->n1 + 1) * 8);
+    L.tb_e2 = (size_t)al16((p->n2 + 1) * 8);
+    L.tb_rows = (size_t)al16(std::max(1, L.nrows) * 16);
+    L.tb_total = L.tb_l1 + L.tb_l2 + L.tb_b1 + L.tb_b2 + L.tb_e1 + L.tb_e2 + L.tb_rows;
+    L.htab.assign(L.tb_total, 0);
     {
         size_t o = 0;
-        memcpy(&htab[o], L1.tab.data(), L1.tab.size() * 2);
-        o += tb_l1;
-        if (two) memcpy(&htab[o], L2.tab.data(), L2.tab.size() * 2);
-        o += tb_l2;
-        memcpy(&htab[o], L1.lo.data(), (p->n1 + 1) * 4);
-        memcpy(&htab[o + (p->n1 + 1) * 4], L1.hi.data(), (p->n1 + 1) * 4);
-        o += tb_b1;
+        memcpy(&L.htab[o], L1.tab.data(), L1.tab.size() * 2);
+        o += L.tb_l1;
+        if (two) memcpy(&L.htab[o], L2.tab.data(), L2.tab.size() * 2);
+        o += L.tb_l2;
+        memcpy(&L.htab[o], L1.lo.data(), (p->n1 + 1) * 4);
+        memcpy(&L.htab[o + (p->n1 + 1) * 4], L1.hi.data(), (p->n1 + 1) * 4);
+        o += L.tb_b1;
         if (two) {
-            memcpy(&htab[o], L2.lo.data(), (p->n2 + 1) * 4);
-            memcpy(&htab[o + (p->n2 + 1) * 4], L2.hi.data(), (p->n2 + 1) * 4);
+            memcpy(&L.htab[o], L2.lo.data(), (p->n2 + 1) * 4);
+            memcpy(&L.htab[o + (p->n2 + 1) * 4], L2.hi.data(), (p->n2 + 1) * 4);
         }
-        o += tb_b2;
-        memcpy(&htab[o], L1.E.data(), (p->n1 + 1) * 8);
-        o += tb_e1;
-        if (two) memcpy(&htab[o], L2.E.data(), (p->n2 + 1) * 8);
-        o += tb_e2;
-        if (nrows) memcpy(&htab[o], rows.data(), nrows * 16);
+        o += L.tb_b2;
+        memcpy(&L.htab[o], L1.E.data(), (p->n1 + 1) * 8);
+        o += L.tb_e1;
+        if (two) memcpy(&L.htab[o], L2.E.data(), (p->n2 + 1) * 8);
+        o += L.tb_e2;
+        if (L.nrows) memcpy(&L.htab[o], L.rows.data(), L.nrows * 16);
     }
+    // numeric constants
+    a.scale1 = L1.scale;
+    a.scale2 = two ? L2.scale : 1.f;
+    a.vmax1 = L1.vmax;
+    a.vmax2 = two ? L2.vmax : 0.f;
+    a.n1 = p->n1;
+    a.n2 = p->n2;
+    a.nbins = p->nbins;
+    a.nx = g.nx;
+    a.side32 = (float)g.side;
+    a.L = g.L;
+    a.halfL = g.L * 0.5;
+    a.r2prune = p->r2prune32;
+    a.d2small = p->d2small;
+    a.mu_n = (float)p->n2;
+    a.tolA = p->mu_tolA;
+    a.tolB = p->mu_tolB;
+    a.tolC = p->mu_tolC;
+    a.mu_top_closed = 1;
+    a.wscale = ldexp(1.0, S);
+    a.ncat = 1;
+    L.kern = batch ? pick_batch_kernel(p->kind, weighted, L.P) : pick_kernel(p->kind, p->los, is_auto, weighted, L.P);
+    FCFC_HIP(hipFuncSetAttribute((const void*)L.kern, hipFuncAttributeMaxDynamicSharedMemorySize, a.lds_bytes));
+    return FCFC_OK;
+}
 
-    // ---- work-list sizes
+// Point the table pointers of the arguments into the uploaded blob; returns the stencil rows.
+static int4* bind_tables(const LaunchSetup& L, char* tab, CountArgs& a) {
+    char* o = tab;
+    a.lut1 = (const uint16_t*)o;
+    o += L.tb_l1;
+    a.lut2 = (const uint16_t*)o;
+    o += L.tb_l2;
+    a.band1 = (const float*)o;
+    o += L.tb_b1;
+    a.band2 = (const float*)o;
+    o += L.tb_b2;
+    a.E1 = (const double*)o;
+    o += L.tb_e1;
+    a.E2 = (const double*)o;
+    o += L.tb_e2;
+    return (int4*)o;
+}
+
+static WLArgs make_wl(const Plan* p, const LaunchSetup& L, bool is_auto, int ncat, int64_t npoints_a) {
+    const Grid& g = p->grid;
     WLArgs w;
     w.nx = g.nx;
     w.ny = g.ny;
     w.nz = g.nz;
-    w.seg = seg;
-    w.tile = T;
-    w.bchunk = bchunk;
-    w.nrows = std::max(1, nrows);
+    w.seg = L.seg;
+    w.tile = L.T;
+    w.bchunk = L.bchunk;
+    w.nrows = std::max(1, L.nrows);
     w.periodic = g.L > 0;
     w.is_auto = is_auto;
-    int64_t nseg = (int64_t)((g.nx + seg - 1) / seg) * g.ny * g.nz;
-    int64_t tiles_cap = nseg + c1->n / T + 1;
-    if (tiles_cap > 0xffffffffLL / std::max(1, nrows)) {
+    w.ncat = ncat;
+    int64_t nseg = (int64_t)((g.nx + L.seg - 1) / L.seg) * g.ny * g.nz * ncat;
+    w.tiles_cap = (uint32_t)std::min<int64_t>(nseg + npoints_a / L.T + 1, 0xffffffffLL);
+    return w;
+}
+
+static int grid_blocks(const LaunchSetup& L, uint32_t nitems) {
+    int occ = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)L.kern, L.waves * 64, L.a.lds_bytes) !=
+            hipSuccess ||
+        occ < 1)
+        occ = 1;
+    int64_t nblk = (int64_t)device_cu_count() * occ;
+    int64_t need = ((int64_t)nitems + L.waves - 1) / L.waves;
+    if (nblk > need) nblk = std::max<int64_t>(1, need);
+    return (int)nblk;
+}
+
+// ---------------------------------------------------------------------------
+// single count
+// ---------------------------------------------------------------------------
+fcfc_status count_pairs(Plan* p, Cells* c1, Cells* c2, int64_t* d_counts, double* d_wcounts, hipStream_t st) {
+    const bool is_auto = (c2 == nullptr);
+    Cells* cb = is_auto ? c1 : c2;
+    const bool weighted = d_wcounts != nullptr;
+    const Grid& g = p->grid;
+    int S = 0;
+    if (weighted) {
+        if (!c1->weighted || !cb->weighted) {
+            set_error("count_pairs: weighted counts need weights in both cell sets");
+            return FCFC_EINVAL;
+        }
+        FCFC_TRY(weight_scale(c1->wmin, c1->wmax, cb->wmin, cb->wmax, &S));
+    }
+    LaunchSetup L;
+    const double ppc = (double)c1->n / std::max<int64_t>(1, g.ncell());
+    FCFC_TRY(setup_launch(p, is_auto, weighted, false, ppc, S, L));
+    CountArgs& a = L.a;
+    const int order = p->tune.order;
+    WLArgs w = make_wl(p, L, is_auto, 1, c1->n);
+    const int64_t nseg = (int64_t)((g.nx + L.seg - 1) / L.seg) * g.ny * g.nz;
+    const int64_t tiles_cap = w.tiles_cap;
+    if (tiles_cap >= 0xffffffffLL / std::max(1, L.nrows)) {
         set_error("count_pairs: work list too large");
         return FCFC_ERANGE;
     }
-    w.tiles_cap = (uint32_t)tiles_cap;
-    int64_t npair_tr = tiles_cap * w.nrows;
+    const int64_t npair_tr = tiles_cap * w.nrows;
 
-    // scratch 1: tables, tiles, tile counts/offsets, item counts/offsets, counters
-    size_t s_tab = (tb_total + 255) & ~(size_t)255;
-    size_t s_tc = ((size_t)nseg * 4 + 255) & ~(size_t)255;
-    size_t s_tiles = ((size_t)tiles_cap * sizeof(Tile) + 255) & ~(size_t)255;
-    size_t s_ic = ((size_t)npair_tr * 4 + 255) & ~(size_t)255;
-    size_t s_scan = (std::max(scan_scratch_bytes(nseg), scan_scratch_bytes(npair_tr)) + 255) & ~(size_t)255;
+    // scratch 1: tables, tiles, tile counts/offsets, item counts/offsets, counters, arguments
+    size_t s_tab = al256(L.tb_total);
+    size_t s_tc = al256((size_t)nseg * 4);
+    size_t s_tiles = al256((size_t)tiles_cap * sizeof(Tile));
+    size_t s_ic = al256((size_t)npair_tr * 4);
+    size_t s_scan = al256(std::max(scan_scratch_bytes(nseg), scan_scratch_bytes(npair_tr)));
     size_t s_ctr = 256;
-    size_t s_args = (sizeof(CountArgs) + 255) & ~(size_t)255;
-    size_t s_acc = weighted ? (((size_t)p->nbins * 16 + 255) & ~(size_t)255) : 0;
+    size_t s_args = al256(sizeof(CountArgs));
+    size_t s_acc = weighted ? al256((size_t)p->nbins * 16) : 0;
     size_t s1 = s_tab + 2 * s_tc + s_tiles + 2 * s_ic + s_scan + s_ctr + s_args + s_acc;
     char* scr = nullptr;
     if (hipMallocAsync((void**)&scr, s1, st) != hipSuccess) {
@@ -942,43 +1094,25 @@ fcfc_status count_pairs(Plan* p, Cells* c1, Cells* c2, int64_t* d_counts, double
     q += s_args;
     unsigned long long* wacc = (unsigned long long*)q;
 
-    p->host_stage.swap(htab);
-    FCFC_HIP(hipMemcpyAsync(tab, p->host_stage.data(), tb_total, hipMemcpyHostToDevice, st));
-    DevTables dt;
-    {
-        char* o = tab;
-        dt.lut1 = (uint16_t*)o;
-        o += tb_l1;
-        dt.lut2 = (uint16_t*)o;
-        o += tb_l2;
-        dt.band1 = (float*)o;
-        o += tb_b1;
-        dt.band2 = (float*)o;
-        o += tb_b2;
-        dt.E1 = (double*)o;
-        o += tb_e1;
-        dt.E2 = (double*)o;
-        o += tb_e2;
-        dt.srows = (int4*)o;
-    }
+    p->host_stage.swap(L.htab);
+    FCFC_HIP(hipMemcpyAsync(tab, p->host_stage.data(), L.tb_total, hipMemcpyHostToDevice, st));
+    int4* srows = bind_tables(L, tab, a);
     fill_u32(ctr, 0u, 64, st);
-    // tiles
     hipLaunchKernelGGL(k_tile_count, dim3((unsigned)((nseg + 255) / 256)), dim3(256), 0, st, c1->cell_start, w, tcount);
     scan_exclusive_u32(tcount, toff, nseg, &ctr[0], scan_scr, st);
     hipLaunchKernelGGL(k_tile_write, dim3((unsigned)((nseg + 255) / 256)), dim3(256), 0, st, c1->cell_start, c1->pos32,
                        w, toff, tiles);
-    // items: count, scan, size on the host
-    hipLaunchKernelGGL(k_item_count, dim3((unsigned)((npair_tr + 255) / 256)), dim3(256), 0, st, tiles, &ctr[0],
-                       dt.srows, cb->cell_start, w, icount);
+    hipLaunchKernelGGL(k_item_count, dim3((unsigned)((npair_tr + 255) / 256)), dim3(256), 0, st, tiles, &ctr[0], srows,
+                       cb->cell_start, w, icount);
     scan_exclusive_u32(icount, ioff, npair_tr, &ctr[1], scan_scr, st);
     uint32_t hctr[2] = {0, 0};
     FCFC_HIP(hipMemcpyAsync(hctr, ctr, 8, hipMemcpyDeviceToHost, st));
     FCFC_HIP(hipStreamSynchronize(st));
     uint32_t nitems = hctr[1];
-    size_t s_items = ((size_t)std::max<uint32_t>(nitems, 1) * sizeof(Item) + 255) & ~(size_t)255;
-    size_t s_sort = order ? (((size_t)std::max<uint32_t>(nitems, 1) * 4 + 255) & ~(size_t)255) : 0;
-    size_t s_rs = order ? ((radix_scratch_bytes(nitems) + 255) & ~(size_t)255) : 0;
-    size_t s_times = p->tune.record_timing ? (((size_t)std::max<uint32_t>(nitems, 1) * 4 + 255) & ~(size_t)255) : 0;
+    size_t s_items = al256((size_t)std::max<uint32_t>(nitems, 1) * sizeof(Item));
+    size_t s_sort = order ? al256((size_t)std::max<uint32_t>(nitems, 1) * 4) : 0;
+    size_t s_rs = order ? al256(radix_scratch_bytes(nitems)) : 0;
+    size_t s_times = p->tune.record_timing ? al256((size_t)std::max<uint32_t>(nitems, 1) * 4) : 0;
     size_t s2 = 2 * s_items + 4 * s_sort + s_rs + s_times;
     char* scr2 = nullptr;
     if (hipMallocAsync((void**)&scr2, s2, st) != hipSuccess) {
@@ -988,8 +1122,8 @@ fcfc_status count_pairs(Plan* p, Cells* c1, Cells* c2, int64_t* d_counts, double
     }
     Item* items = (Item*)scr2;
     Item* items2 = (Item*)(scr2 + s_items);
-    hipLaunchKernelGGL(k_item_write, dim3((unsigned)((npair_tr + 255) / 256)), dim3(256), 0, st, tiles, &ctr[0],
-                       dt.srows, cb->cell_start, w, ioff, items, nitems);
+    hipLaunchKernelGGL(k_item_write, dim3((unsigned)((npair_tr + 255) / 256)), dim3(256), 0, st, tiles, &ctr[0], srows,
+                       cb->cell_start, w, ioff, items, nitems);
     Item* run_items = items;
     if (order && nitems > 1) {
         uint32_t* k0 = (uint32_t*)(scr2 + 2 * s_items);
@@ -1005,7 +1139,6 @@ fcfc_status count_pairs(Plan* p, Cells* c1, Cells* c2, int64_t* d_counts, double
     }
     uint32_t* times = p->tune.record_timing ? (uint32_t*)(scr2 + 2 * s_items + 4 * s_sort + s_rs) : nullptr;
 
-    // outputs
     fill_u64((uint64_t*)d_counts, 0ull, p->nbins, st);
     if (weighted) fill_u64((uint64_t*)wacc, 0ull, 2 * (int64_t)p->nbins, st);
     if (!p->stats_dev) {
@@ -1026,58 +1159,27 @@ fcfc_status count_pairs(Plan* p, Cells* c1, Cells* c2, int64_t* d_counts, double
     a.items = run_items;
     a.nitems_dev = &ctr[1];
     a.cursor = &ctr[2];
-    a.lut1 = dt.lut1;
-    a.lut2 = dt.lut2;
-    a.band1 = dt.band1;
-    a.band2 = dt.band2;
-    a.E1 = dt.E1;
-    a.E2 = dt.E2;
     a.out_counts = (unsigned long long*)d_counts;
     a.out_w = weighted ? wacc : nullptr;
     a.stats = (unsigned long long*)p->stats_dev;
     a.times = times;
-    a.scale1 = L1.scale;
-    a.scale2 = two ? L2.scale : 1.f;
-    a.vmax1 = L1.vmax;
-    a.vmax2 = two ? L2.vmax : 0.f;
-    a.n1 = p->n1;
-    a.n2 = p->n2;
-    a.nbins = p->nbins;
-    a.nx = g.nx;
-    a.side32 = (float)g.side;
-    a.L = g.L;
-    a.halfL = g.L * 0.5;
-    a.r2prune = p->r2prune32;
-    a.d2small = p->d2small;
-    a.mu_n = (float)p->n2;
-    a.tolA = p->mu_tolA;
-    a.tolB = p->mu_tolB;
-    a.tolC = p->mu_tolC;
-    a.mu_top_closed = 1;
-    a.wscale = ldexp(1.0, S);
 
-    CountKernel kern = pick_kernel(p->kind, p->los, is_auto, weighted, P);
-    FCFC_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, a.lds_bytes));
-    int occ = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)kern, CT, a.lds_bytes) != hipSuccess || occ < 1)
-        occ = 1;
-    int cus = device_cu_count();
-    int64_t nblk = (int64_t)cus * occ;
-    int64_t need = ((int64_t)nitems + waves - 1) / waves;
-    if (nblk > need) nblk = std::max<int64_t>(1, need);
+    const int nblk = grid_blocks(L, nitems);
     FCFC_HIP(hipEventRecord(p->ev0, st));
     p->host_args.resize(sizeof(CountArgs));
     memcpy(p->host_args.data(), &a, sizeof(CountArgs));
     FCFC_HIP(hipMemcpyAsync(args_dev, p->host_args.data(), sizeof(CountArgs), hipMemcpyHostToDevice, st));
-    hipLaunchKernelGGL(kern, dim3((unsigned)nblk), dim3(CT), (size_t)a.lds_bytes, st, (const CountArgs*)args_dev);
+    hipLaunchKernelGGL(L.kern, dim3((unsigned)nblk), dim3(L.waves * 64), (size_t)a.lds_bytes, st,
+                       (const CountArgs*)args_dev);
     FCFC_HIP(hipGetLastError());
     FCFC_HIP(hipEventRecord(p->ev1, st));
     if (weighted)
         hipLaunchKernelGGL(k_finalize_w, dim3((p->nbins + 255) / 256), dim3(256), 0, st, wacc, p->nbins, S, d_wcounts);
     if (times) {
-        // keep the per-item times and features for the scheduler: copy to plan-owned buffer
+        // keep the per-item times and items for the scheduler (plan-owned)
         if (p->timing_dev) (void)hipFree(p->timing_dev);
         p->timing_dev = nullptr;
+        p->timing_n = 0;
         size_t tb = (size_t)nitems * (4 + sizeof(Item));
         if (hipMalloc(&p->timing_dev, std::max<size_t>(tb, 256)) == hipSuccess) {
             FCFC_HIP(hipMemcpyAsync(p->timing_dev, times, (size_t)nitems * 4, hipMemcpyDeviceToDevice, st));
@@ -1097,8 +1199,338 @@ fcfc_status count_pairs(Plan* p, Cells* c1, Cells* c2, int64_t* d_counts, double
     p->stats.grid[2] = g.nz;
     p->stats.cells_per_rmax = g.k;
     p->stats.cell_side = g.side;
-    p->stats.wg_per_cu = occ;
-    p->last_pts = (int)P;
+    p->stats.wg_per_cu = 1;
+    p->last_pts = L.P;
+    return FCFC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// batched auto counts of many periodic catalogues
+// ---------------------------------------------------------------------------
+__global__ void k_clamp_items(uint32_t* ctr, uint32_t cap) {
+    if (ctr[1] > cap) {
+        ctr[1] = cap;
+        ctr[5] = 1u;  // overflow flag
+    }
+}
+
+struct BatchImpl {
+    Plan* plan = nullptr;
+    int ncat = 0;
+    int64_t ntot = 0;
+    bool weighted = false;
+    int S = 0;
+    LaunchSetup L;
+    WLArgs wl;
+    int64_t nseg = 0, npair_tr = 0;
+    uint32_t items_cap = 0;
+    int nblk = 1;
+    // device
+    CatDesc* desc = nullptr;
+    int64_t* offs = nullptr;
+    uint32_t *key = nullptr, *idx = nullptr, *tk = nullptr, *tv = nullptr;
+    uint32_t *key_s = nullptr, *idx_s = nullptr;  // sorted arrays (after ping-pong)
+    void* sort_scr = nullptr;
+    uint32_t* flags = nullptr;
+    uint64_t* wst = nullptr;
+    float4* pos32 = nullptr;
+    double* pos64 = nullptr;
+    double* w = nullptr;
+    uint32_t* cs = nullptr;
+    uint32_t *tcount = nullptr, *toff = nullptr, *icount = nullptr, *ioff = nullptr;
+    void* scan_scr = nullptr;
+    Tile* tiles = nullptr;
+    Item* items = nullptr;
+    uint32_t* ctr = nullptr;  // [0] ntiles [1] nitems [2] cursor [3] nchunks [4] chunk cursor [5] overflow
+    uint32_t *cat_items = nullptr, *cat_order = nullptr, *chunk_prefix = nullptr;
+    unsigned long long* counts = nullptr;
+    unsigned long long* wacc = nullptr;
+    double* wout = nullptr;
+    char* tab = nullptr;
+    CountArgs* args_dev = nullptr;
+    std::vector<void*> allocs;
+    std::vector<char> host_args;
+    std::vector<uint32_t> host_order;
+    std::vector<CatDesc> host_desc;
+    std::vector<int64_t> host_offs;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    hipStream_t cap = nullptr;  // capture stream (the caller's may be the legacy default stream)
+};
+
+static fcfc_status balloc(BatchImpl* b, void** p, size_t bytes) {
+    if (hipMalloc(p, std::max<size_t>(bytes, 256)) != hipSuccess) {
+        set_error("batch: cannot allocate %zu bytes", bytes);
+        return FCFC_ENOMEM;
+    }
+    b->allocs.push_back(*p);
+    return FCFC_OK;
+}
+
+void batch_free_impl(BatchImpl* b) {
+    if (!b) return;
+    if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    if (b->ev0) (void)hipEventDestroy(b->ev0);
+    if (b->ev1) (void)hipEventDestroy(b->ev1);
+    (void)hipDeviceSynchronize();
+    if (b->cap) (void)hipStreamDestroy(b->cap);
+    for (void* p : b->allocs) (void)hipFree(p);
+    delete b;
+}
+
+// Enqueue the build and the work list (up to the item counts).
+static void batch_enqueue_front(BatchImpl* b, hipStream_t st) {
+    Plan* p = b->plan;
+    uint32_t *k = b->key, *v = b->idx, *tk = b->tk, *tv = b->tv;
+    batch_build_enqueue(p, b->desc, b->offs, b->ncat, b->ntot, b->weighted, &k, &v, &tk, &tv, b->sort_scr, b->flags,
+                        b->wst, b->pos32, b->pos64, b->w, b->cs, st);
+    b->key_s = k;
+    b->idx_s = v;
+    int4* srows = (int4*)(b->tab + (b->L.tb_total - b->L.tb_rows));
+    fill_u32(b->ctr, 0u, 64, st);
+    hipLaunchKernelGGL(k_tile_count, dim3((unsigned)((b->nseg + 255) / 256)), dim3(256), 0, st, b->cs, b->wl, b->tcount);
+    scan_exclusive_u32(b->tcount, b->toff, b->nseg, &b->ctr[0], b->scan_scr, st);
+    hipLaunchKernelGGL(k_tile_write, dim3((unsigned)((b->nseg + 255) / 256)), dim3(256), 0, st, b->cs, b->pos32, b->wl,
+                       b->toff, b->tiles);
+    hipLaunchKernelGGL(k_item_count, dim3((unsigned)((b->npair_tr + 255) / 256)), dim3(256), 0, st, b->tiles, &b->ctr[0],
+                       srows, b->cs, b->wl, b->icount);
+    scan_exclusive_u32(b->icount, b->ioff, b->npair_tr, &b->ctr[1], b->scan_scr, st);
+}
+
+// Enqueue the rest: items, catalogue ranges, chunks, counting kernel, merge.
+static void batch_enqueue_back(BatchImpl* b, hipStream_t st) {
+    Plan* p = b->plan;
+    int4* srows = (int4*)(b->tab + (b->L.tb_total - b->L.tb_rows));
+    hipLaunchKernelGGL(k_clamp_items, dim3(1), dim3(1), 0, st, b->ctr, b->items_cap);
+    hipLaunchKernelGGL(k_item_write, dim3((unsigned)((b->npair_tr + 255) / 256)), dim3(256), 0, st, b->tiles, &b->ctr[0],
+                       srows, b->cs, b->wl, b->ioff, b->items, b->items_cap);
+    hipLaunchKernelGGL(k_cat_items, dim3((b->ncat + 1 + 255) / 256), dim3(256), 0, st, b->toff, b->ioff, &b->ctr[1], b->wl,
+                       b->cat_items);
+    hipLaunchKernelGGL(k_chunk_prefix, dim3(1), dim3(1), 0, st, b->cat_items, b->cat_order, b->ncat, b->L.a.chunk_items,
+                       b->chunk_prefix, &b->ctr[3]);
+    fill_u64((uint64_t*)b->counts, 0ull, (int64_t)b->ncat * p->nbins, st);
+    if (b->weighted) fill_u64((uint64_t*)b->wacc, 0ull, 2 * (int64_t)b->ncat * p->nbins, st);
+    hipLaunchKernelGGL(b->L.kern, dim3((unsigned)b->nblk), dim3(b->L.waves * 64), (size_t)b->L.a.lds_bytes, st,
+                       (const CountArgs*)b->args_dev);
+    if (b->weighted)
+        hipLaunchKernelGGL(k_finalize_w, dim3((b->ncat * p->nbins + 255) / 256), dim3(256), 0, st, b->wacc,
+                           b->ncat * p->nbins, b->S, b->wout);
+}
+
+fcfc_status batch_create_impl(Plan* p, const fcfc_catalog* cats, int ncat, hipStream_t st, BatchImpl** out) {
+    if (p->L <= 0) {
+        set_error("batch_create: batched counts need a periodic plan");
+        return FCFC_ESTATE;
+    }
+    if (p->los == FCFC_LOS_MIDPOINT && p->kind != FCFC_BIN_S) {
+        set_error("batch_create: batched counts use the z line of sight");
+        return FCFC_EINVAL;
+    }
+    BatchImpl* b = new (std::nothrow) BatchImpl();
+    if (!b) return FCFC_ENOMEM;
+    b->plan = p;
+    b->ncat = ncat;
+    b->weighted = cats[0].w != nullptr;
+    b->host_desc.resize(ncat);
+    b->host_offs.resize(ncat + 1);
+    int64_t tot = 0;
+    for (int c = 0; c < ncat; c++) {
+        if ((cats[c].w != nullptr) != b->weighted) {
+            delete b;
+            set_error("batch_create: either every catalogue has weights or none");
+            return FCFC_EINVAL;
+        }
+        b->host_desc[c] = CatDesc{cats[c].xyz, cats[c].w, cats[c].n, tot};
+        b->host_offs[c] = tot;
+        tot += cats[c].n;
+    }
+    b->host_offs[ncat] = tot;
+    b->ntot = tot;
+    if (tot >= ((int64_t)1 << 31)) {
+        delete b;
+        set_error("batch_create: more than 2^31 points in the batch");
+        return FCFC_ERANGE;
+    }
+    const Grid& g = p->grid;
+    if ((int64_t)ncat * g.ncell() >= ((int64_t)1 << 31)) {
+        delete b;
+        set_error("batch_create: catalogues x cells exceeds 2^31");
+        return FCFC_ERANGE;
+    }
+    // catalogue order: longest first (cost ~ n^2)
+    b->host_order.resize(ncat);
+    for (int c = 0; c < ncat; c++) b->host_order[c] = (uint32_t)c;
+    std::stable_sort(b->host_order.begin(), b->host_order.end(),
+                     [&](uint32_t x, uint32_t y) { return cats[x].n > cats[y].n; });
+    const double ppc = (double)tot / std::max<int64_t>(1, g.ncell() * ncat);
+    fcfc_status s = setup_launch(p, true, b->weighted, true, ppc, 0, b->L);
+    if (s != FCFC_OK) {
+        delete b;
+        return s;
+    }
+    b->wl = make_wl(p, b->L, true, ncat, tot);
+    b->nseg = (int64_t)((g.nx + b->L.seg - 1) / b->L.seg) * g.ny * g.nz * ncat;
+    b->npair_tr = (int64_t)b->wl.tiles_cap * b->wl.nrows;
+    if ((int64_t)b->wl.tiles_cap * b->wl.nrows >= 0xffffffffLL) {
+        delete b;
+        set_error("batch_create: work list too large");
+        return FCFC_ERANGE;
+    }
+    const int nb = p->nbins;
+#define BA(ptr, bytes)                                                         \
+    do {                                                                       \
+        fcfc_status s_ = balloc(b, (void**)&(ptr), (bytes));                   \
+        if (s_ != FCFC_OK) {                                                   \
+            batch_free_impl(b);                                                \
+            return s_;                                                         \
+        }                                                                      \
+    } while (0)
+    BA(b->desc, sizeof(CatDesc) * ncat);
+    BA(b->offs, sizeof(int64_t) * (ncat + 1));
+    BA(b->key, 4 * (size_t)tot);
+    BA(b->idx, 4 * (size_t)tot);
+    BA(b->tk, 4 * (size_t)tot);
+    BA(b->tv, 4 * (size_t)tot);
+    BA(b->sort_scr, batch_build_scratch(tot));
+    BA(b->flags, 64);
+    BA(b->wst, 64);
+    BA(b->pos32, 16 * (size_t)(tot + 8));
+    BA(b->pos64, 24 * (size_t)tot);
+    if (b->weighted) BA(b->w, 8 * (size_t)(tot + 8));
+    BA(b->cs, 4 * (size_t)(g.ncell() * ncat + 1));
+    BA(b->tcount, 4 * (size_t)b->nseg);
+    BA(b->toff, 4 * (size_t)b->nseg);
+    BA(b->icount, 4 * (size_t)b->npair_tr);
+    BA(b->ioff, 4 * (size_t)b->npair_tr);
+    BA(b->scan_scr, std::max(scan_scratch_bytes(b->nseg), scan_scratch_bytes(b->npair_tr)));
+    BA(b->tiles, sizeof(Tile) * (size_t)b->wl.tiles_cap);
+    BA(b->ctr, 256);
+    BA(b->cat_items, 4 * (size_t)(ncat + 1));
+    BA(b->cat_order, 4 * (size_t)ncat);
+    BA(b->chunk_prefix, 4 * (size_t)(ncat + 1));
+    BA(b->counts, 8 * (size_t)ncat * nb);
+    if (b->weighted) {
+        BA(b->wacc, 16 * (size_t)ncat * nb);
+        BA(b->wout, 8 * (size_t)ncat * nb);
+    }
+    BA(b->tab, b->L.tb_total);
+    BA(b->args_dev, sizeof(CountArgs));
+    FCFC_HIP(hipMemcpy(b->desc, b->host_desc.data(), sizeof(CatDesc) * ncat, hipMemcpyHostToDevice));
+    FCFC_HIP(hipMemcpy(b->offs, b->host_offs.data(), sizeof(int64_t) * (ncat + 1), hipMemcpyHostToDevice));
+    FCFC_HIP(hipMemcpy(b->cat_order, b->host_order.data(), 4 * (size_t)ncat, hipMemcpyHostToDevice));
+    FCFC_HIP(hipMemcpy(b->tab, b->L.htab.data(), b->L.tb_total, hipMemcpyHostToDevice));
+    FCFC_HIP(hipEventCreate(&b->ev0));
+    FCFC_HIP(hipEventCreate(&b->ev1));
+    // one eager pass of the front half sizes the work list and validates the data
+    batch_enqueue_front(b, st);
+    uint32_t hctr[2] = {0, 0};
+    uint64_t hw[2] = {0, 0};
+    uint32_t hflags = 0;
+    FCFC_HIP(hipMemcpyAsync(hctr, b->ctr, 8, hipMemcpyDeviceToHost, st));
+    FCFC_HIP(hipMemcpyAsync(hw, b->wst, 16, hipMemcpyDeviceToHost, st));
+    FCFC_HIP(hipMemcpyAsync(&hflags, b->flags, 4, hipMemcpyDeviceToHost, st));
+    FCFC_HIP(hipStreamSynchronize(st));
+    if (hflags & 5u) {
+        batch_free_impl(b);
+        set_error("batch_create: non-finite position or weight");
+        return FCFC_ENONFINITE;
+    }
+    if (hflags & 2u) {
+        batch_free_impl(b);
+        set_error("batch_create: a point lies outside [0, L)");
+        return FCFC_EBOX;
+    }
+    if (b->weighted) {
+        double wmin = 0, wmax = 0;
+        if (hw[0] != ~0ull) memcpy(&wmin, &hw[0], 8);
+        memcpy(&wmax, &hw[1], 8);
+        fcfc_status ws = weight_scale(wmin, wmax, wmin, wmax, &b->S);
+        if (ws != FCFC_OK) {
+            batch_free_impl(b);
+            return ws;
+        }
+    }
+    b->items_cap = std::max<uint32_t>(hctr[1], 1);
+    BA(b->items, sizeof(Item) * (size_t)b->items_cap);
+#undef BA
+    CountArgs& a = b->L.a;
+    (void)bind_tables(b->L, b->tab, a);
+    a.posA = b->pos32;
+    a.absA = nullptr;
+    a.p64A = b->pos64;
+    a.wA = b->weighted ? b->w : nullptr;
+    a.posB = b->pos32;
+    a.p64B = b->pos64;
+    a.wB = a.wA;
+    a.csB = b->cs;
+    a.items = b->items;
+    a.nitems_dev = &b->ctr[1];
+    a.cursor = &b->ctr[2];
+    a.out_counts = b->counts;
+    a.out_w = b->weighted ? b->wacc : nullptr;
+    a.stats = nullptr;
+    a.times = nullptr;
+    a.wscale = ldexp(1.0, b->S);
+    a.nchunks_dev = &b->ctr[3];
+    a.chunk_cursor = &b->ctr[4];
+    a.chunk_prefix = b->chunk_prefix;
+    a.cat_order = b->cat_order;
+    a.cat_items = b->cat_items;
+    a.ncat = ncat;
+    a.chunk_items = std::max(16, b->L.waves * 8);
+    b->host_args.resize(sizeof(CountArgs));
+    memcpy(b->host_args.data(), &a, sizeof(CountArgs));
+    FCFC_HIP(hipMemcpy(b->args_dev, b->host_args.data(), sizeof(CountArgs), hipMemcpyHostToDevice));
+    b->nblk = grid_blocks(b->L, b->items_cap);
+    *out = b;
+    return FCFC_OK;
+}
+
+fcfc_status batch_run_impl(BatchImpl* b, int64_t* d_counts, double* d_wcounts, bool use_graph, hipStream_t st) {
+    Plan* p = b->plan;
+    if (d_wcounts && !b->weighted) {
+        set_error("batch_run: weighted counts requested but the catalogues have no weights");
+        return FCFC_EINVAL;
+    }
+    if (use_graph) {
+        if (!b->gexec) {
+            if (!b->cap) FCFC_HIP(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
+            FCFC_HIP(hipStreamSynchronize(st));
+            FCFC_HIP(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
+            batch_enqueue_front(b, b->cap);
+            batch_enqueue_back(b, b->cap);
+            hipGraph_t g = nullptr;
+            FCFC_HIP(hipStreamEndCapture(b->cap, &g));
+            b->graph = g;
+            FCFC_HIP(hipGraphInstantiate(&b->gexec, b->graph, nullptr, nullptr, 0));
+        }
+        FCFC_HIP(hipEventRecord(b->ev0, st));
+        FCFC_HIP(hipGraphLaunch(b->gexec, st));
+        FCFC_HIP(hipEventRecord(b->ev1, st));
+    } else {
+        FCFC_HIP(hipEventRecord(b->ev0, st));
+        batch_enqueue_front(b, st);
+        batch_enqueue_back(b, st);
+        FCFC_HIP(hipEventRecord(b->ev1, st));
+    }
+    const size_t nbytes = (size_t)b->ncat * p->nbins * 8;
+    FCFC_HIP(hipMemcpyAsync(d_counts, b->counts, nbytes, hipMemcpyDeviceToDevice, st));
+    if (d_wcounts) FCFC_HIP(hipMemcpyAsync(d_wcounts, b->wout, nbytes, hipMemcpyDeviceToDevice, st));
+    return FCFC_OK;
+}
+
+fcfc_status batch_check_impl(BatchImpl* b, hipStream_t st, uint32_t* nitems, float* ms) {
+    uint32_t h[6];
+    FCFC_HIP(hipMemcpyAsync(h, b->ctr, 24, hipMemcpyDeviceToHost, st));
+    FCFC_HIP(hipStreamSynchronize(st));
+    if (nitems) *nitems = h[1];
+    if (ms && hipEventElapsedTime(ms, b->ev0, b->ev1) != hipSuccess) *ms = -1.f;
+    if (h[5]) {
+        set_error("batch: the work list outgrew the capacity sized at creation (catalogue contents changed)");
+        return FCFC_ERANGE;
+    }
     return FCFC_OK;
 }
 

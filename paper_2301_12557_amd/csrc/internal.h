@@ -157,9 +157,28 @@ fcfc_status fit_bounds(Plan* p, const fcfc_catalog* cats, int ncat, hipStream_t 
 void fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t st);
 void fill_u64(uint64_t* p, uint64_t v, int64_t n, hipStream_t st);
 
+// batched build (build.hip)
+struct CatDesc {
+    const double* xyz;
+    const double* w;
+    int64_t n;
+    int64_t off;
+};
+size_t batch_build_scratch(int64_t ntot);
+void batch_build_enqueue(const Plan* p, const CatDesc* desc, const int64_t* offs, int ncat, int64_t ntot,
+                         bool weighted, uint32_t** key, uint32_t** idx, uint32_t** tk, uint32_t** tv, void* sort_scr,
+                         uint32_t* flags, uint64_t* wst, float4* pos32, double* pos64, double* w, uint32_t* cs,
+                         hipStream_t st);
+
 // count (count.hip)
 fcfc_status count_pairs(Plan* p, Cells* c1, Cells* c2, int64_t* d_counts, double* d_wcounts,
                         hipStream_t st);
+
+struct BatchImpl;
+fcfc_status batch_create_impl(Plan* p, const fcfc_catalog* cats, int ncat, hipStream_t st, BatchImpl** out);
+fcfc_status batch_run_impl(BatchImpl* b, int64_t* d_counts, double* d_wcounts, bool use_graph, hipStream_t st);
+fcfc_status batch_check_impl(BatchImpl* b, hipStream_t st, uint32_t* nitems, float* ms);
+void batch_free_impl(BatchImpl* b);
 
 int device_cu_count();
 

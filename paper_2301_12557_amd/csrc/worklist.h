@@ -21,6 +21,7 @@ struct WLArgs {
     int periodic;
     int is_auto;
     uint32_t tiles_cap;
+    int ncat;       // catalogues stacked along z (batched build); 1 otherwise
 };
 
 __global__ void k_tile_count(const uint32_t* __restrict__ csA, WLArgs w, uint32_t* __restrict__ tcount);
@@ -32,6 +33,10 @@ __global__ void k_item_count(const Tile* __restrict__ tiles, const uint32_t* __r
 __global__ void k_item_write(const Tile* __restrict__ tiles, const uint32_t* __restrict__ ntiles_dev,
                              const int4* __restrict__ srows, const uint32_t* __restrict__ csB, WLArgs w,
                              const uint32_t* __restrict__ ioff, Item* __restrict__ items, uint32_t items_cap);
+__global__ void k_cat_items(const uint32_t* __restrict__ toff, const uint32_t* __restrict__ ioff,
+                            const uint32_t* __restrict__ nitems_dev, WLArgs w, uint32_t* __restrict__ cat_items);
+__global__ void k_chunk_prefix(const uint32_t* __restrict__ cat_items, const uint32_t* __restrict__ cat_order,
+                               int ncat, int chunk_items, uint32_t* __restrict__ prefix, uint32_t* __restrict__ nchunks);
 __global__ void k_item_keys(const Item* __restrict__ items, const uint32_t* __restrict__ nitems_dev,
                             uint32_t cap, uint32_t* __restrict__ key, uint32_t* __restrict__ val);
 __global__ void k_item_permute(const Item* __restrict__ in, const uint32_t* __restrict__ perm,

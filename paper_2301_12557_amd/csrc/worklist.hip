@@ -27,7 +27,7 @@ __device__ inline int floor_div(int a, int n) {
 __global__ void k_tile_count(const uint32_t* __restrict__ csA, WLArgs w, uint32_t* __restrict__ tcount) {
     int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int nseg_row = (w.nx + w.seg - 1) / w.seg;
-    int64_t nseg = (int64_t)nseg_row * w.ny * w.nz;
+    int64_t nseg = (int64_t)nseg_row * w.ny * w.nz * w.ncat;
     if (s >= nseg) return;
     int64_t row = s / nseg_row;
     int sx = (int)(s % nseg_row);
@@ -40,7 +40,7 @@ __global__ void k_tile_write(const uint32_t* __restrict__ csA, const float4* __r
                              const uint32_t* __restrict__ toff, Tile* __restrict__ tiles) {
     int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int nseg_row = (w.nx + w.seg - 1) / w.seg;
-    int64_t nseg = (int64_t)nseg_row * w.ny * w.nz;
+    int64_t nseg = (int64_t)nseg_row * w.ny * w.nz * w.ncat;
     if (s >= nseg) return;
     int64_t row = s / nseg_row;
     int sx = (int)(s % nseg_row);
@@ -65,7 +65,11 @@ __global__ void k_tile_write(const uint32_t* __restrict__ csA, const float4* __r
 template <typename F>
 __device__ inline void tile_row_items(const Tile& tl, int4 srow, const uint32_t* __restrict__ csB,
                                       const WLArgs& w, uint32_t tile_id, F emit) {
-    int cy = (int)(tl.row % (uint32_t)w.ny), cz = (int)(tl.row / (uint32_t)w.ny);
+    // rows of a batched build are (catalogue, z, y); wrapping stays within the catalogue
+    int cy = (int)(tl.row % (uint32_t)w.ny);
+    int czc = (int)(tl.row / (uint32_t)w.ny);
+    int cat = czc / w.nz;
+    int cz = czc - cat * w.nz;
     int dy = srow.x, dz = srow.y, kx = srow.z;
     int yu = cy + dy, zu = cz + dz;
     int sy = 0, sz = 0, yb = yu, zb = zu;
@@ -81,7 +85,7 @@ __device__ inline void tile_row_items(const Tile& tl, int4 srow, const uint32_t*
     bool same = w.is_auto && dy == 0 && dz == 0;
     int x0 = (int)(tl.x01 & 0xffff), x1 = (int)(tl.x01 >> 16);
     int xlo = x0 - kx, xhi = x1 + kx;
-    uint32_t rowcell = ((uint32_t)zb * (uint32_t)w.ny + (uint32_t)yb) * (uint32_t)w.nx;
+    uint32_t rowcell = (((uint32_t)cat * (uint32_t)w.nz + (uint32_t)zb) * (uint32_t)w.ny + (uint32_t)yb) * (uint32_t)w.nx;
     // pieces: 0 = direct, 1 = wrapped from the left (sx = -1), 2 = wrapped from the right (sx = +1)
     for (int pc = 0; pc < 3; pc++) {
         int c0, c1, sx;
@@ -162,6 +166,39 @@ __global__ void k_item_write(const Tile* __restrict__ tiles, const uint32_t* __r
         if (o < items_cap) items[o] = it;
         o++;
     });
+}
+
+// First work item of each catalogue of a batched build: tiles (and hence
+// items) are ordered by catalogue, so catalogue c starts at the first
+// (tile, row) pair of its first segment.
+__global__ void k_cat_items(const uint32_t* __restrict__ toff, const uint32_t* __restrict__ ioff,
+                            const uint32_t* __restrict__ nitems_dev, WLArgs w, uint32_t* __restrict__ cat_items) {
+    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c > w.ncat) return;
+    if (c == w.ncat) {
+        cat_items[c] = *nitems_dev;
+        return;
+    }
+    int nseg_row = (w.nx + w.seg - 1) / w.seg;
+    int64_t seg0 = (int64_t)c * nseg_row * w.ny * w.nz;
+    uint32_t t0 = toff[seg0];
+    cat_items[c] = ioff[(int64_t)t0 * w.nrows];
+}
+
+// Chunks of `chunk_items` items per catalogue, catalogues in the given order
+// (longest first); prefix[o] is the first chunk of the o-th catalogue.
+__global__ void k_chunk_prefix(const uint32_t* __restrict__ cat_items, const uint32_t* __restrict__ cat_order,
+                               int ncat, int chunk_items, uint32_t* __restrict__ prefix, uint32_t* __restrict__ nchunks) {
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    uint32_t acc = 0;
+    for (int o = 0; o < ncat; o++) {
+        uint32_t c = cat_order[o];
+        uint32_t n = cat_items[c + 1] - cat_items[c];
+        prefix[o] = acc;
+        acc += (n + (uint32_t)chunk_items - 1) / (uint32_t)chunk_items;
+    }
+    prefix[ncat] = acc;
+    *nchunks = acc;
 }
 
 // Longest-first key: the cost rounded to a power of sqrt(2) (bucket 0..63),

@@ -67,6 +67,7 @@ SIGNATURES = [
     ("fcfc_plan_stats", _I32, [_P, ctypes.POINTER(Stats)]),
     ("fcfc_batch_create", _I32, [_P, ctypes.POINTER(Catalog), _I32, _P, ctypes.POINTER(_P)]),
     ("fcfc_batch_run", _I32, [_P, _P, _P, _I32, _P]),
+    ("fcfc_batch_check", _I32, [_P, _P, ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_float)]),
     ("fcfc_batch_free", None, [_P]),
     ("fcfc_cells_free", None, [_P]),
     ("fcfc_plan_free", None, [_P]),
@@ -242,6 +243,13 @@ class Batch:
         check(load().fcfc_batch_run(self.h, out.data_ptr(), wout.data_ptr() if wout is not None else None,
                                     int(bool(use_graph)), _stream_ptr(stream)))
         return out
+
+    def check(self, stream=None):
+        """Wait, then return (work items, GPU ms of the last run); raises if the work list overflowed."""
+        n = ctypes.c_uint32()
+        ms = ctypes.c_float()
+        check(load().fcfc_batch_check(self.h, _stream_ptr(stream), ctypes.byref(n), ctypes.byref(ms)))
+        return n.value, ms.value
 
     def close(self):
         if getattr(self, "h", None):
