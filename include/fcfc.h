@@ -73,6 +73,7 @@ typedef int32_t fcfc_status;
 typedef struct fcfc_plan_s *fcfc_plan_t;
 typedef struct fcfc_cells_s *fcfc_cells_t;
 typedef struct fcfc_batch_s *fcfc_batch_t;
+typedef struct fcfc_model_s *fcfc_model_t;
 
 /* A catalogue: device pointers owned by the caller. */
 typedef struct {
@@ -109,6 +110,8 @@ typedef struct {
     double band_d2_rel;      /* widest FP32 error band, relative to its edge */
     int32_t lut_entries;     /* squared-separation look-up table length */
     int32_t wg_per_cu;       /* resident counting workgroups per CU */
+    int32_t order_used;      /* FCFC_ORDER_* the work list actually ran in */
+    int32_t reserved;
 } fcfc_stats;
 
 /*
@@ -210,6 +213,86 @@ void fcfc_plan_free(fcfc_plan_t plan);
 
 /* Number of points and grid cells of a cell set (host values). */
 fcfc_status fcfc_cells_info(fcfc_cells_t cells, int64_t *n_points, int64_t *n_cells);
+
+/*
+ * Learned work-item cost model.  Not part of the paper's method, which
+ * leaves better load balancing to future work (Sect. 4.2, 4.3 and 6): a small
+ * multilayer perceptron, 4 -> 64 -> 64 -> 64 -> 1 FP32 with ReLU, that maps
+ * the features of a work item to log2(1 + its counting time in GPU wall-clock
+ * ticks).  Features, per item: log2(1 + A points), log2(1 + B points), the
+ * transverse cell-row separation sqrt(dy^2 + dz^2) in cells, and cells per
+ * prune radius.  Inputs and target are standardised with stored means and
+ * standard deviations (norm[10]: x mean[4], x std[4], y mean, y std).
+ * Parameters are one packed FP32 array of fcfc_model_nparams() values:
+ * W1[64][4] b1[64] W2[64][64] b2[64] W3[64][64] b3[64] W4[64] b4.
+ * The model orders work items and picks the cell size; it never changes
+ * a count.  Forward, backward and the Adam update are GPU kernels.
+ */
+int32_t fcfc_model_nparams(void);
+/* New model, He-uniform weights from `seed`, zero biases, identity norm. */
+fcfc_status fcfc_model_create(uint64_t seed, fcfc_model_t *out);
+void fcfc_model_free(fcfc_model_t model);
+/* Host copies of the parameters and/or the normalisation (either may be NULL). */
+fcfc_status fcfc_model_get(fcfc_model_t model, float *params, float *norm);
+/* Replace parameters and/or normalisation (either may be NULL) and reset the
+ * optimiser state.  Errors: FCFC_EINVAL (non-finite or non-positive scale). */
+fcfc_status fcfc_model_set(fcfc_model_t model, const float *params, const float *norm);
+/* d_out[i] = prediction for d_feat[i*4 .. i*4+3] (device arrays, m rows). */
+fcfc_status fcfc_model_predict(fcfc_model_t model, const float *d_feat, int64_t m, float *d_out,
+                               void *stream);
+/* Gradient of 0.5 * sum (y - t)^2 over the m samples, in standardised units,
+ * with respect to the packed parameters (host grad[nparams]); *loss gets the
+ * loss.  Synchronises `stream`. */
+fcfc_status fcfc_model_grad(fcfc_model_t model, const float *d_feat, const float *d_target, int64_t m,
+                            float *grad, float *loss, void *stream);
+/* Set the normalisation from the samples, then `epochs` passes of Adam
+ * (beta 0.9 / 0.999, eps 1e-8) over minibatches of `batch` (>= 64) samples
+ * shuffled with `seed`.  *final_loss: mean loss of the last epoch.
+ * Errors: FCFC_EINVAL (m < 2, epochs < 1, batch < 64, lr <= 0). */
+fcfc_status fcfc_model_train(fcfc_model_t model, const float *d_feat, const float *d_target, int64_t m,
+                             int32_t epochs, int32_t batch, float lr, uint64_t seed, void *stream,
+                             float *final_loss);
+/* Versioned binary file (magic, parameter count, norm, parameters).
+ * fcfc_model_load: FCFC_EMODEL for a missing, short or non-finite file. */
+fcfc_status fcfc_model_save(fcfc_model_t model, const char *path);
+fcfc_status fcfc_model_load(const char *path, fcfc_model_t *out);
+
+/*
+ * fcfc_plan_timings -- training data: features (d_feat, cap x 4) and
+ * log2(1 + ticks) (d_logt, cap) of every work item of the last count run on
+ * this plan with record_timing = 1.  *n gets the item count; with d_feat NULL
+ * only *n is set.  Errors: FCFC_ESTATE (no recorded count), FCFC_EINVAL
+ * (cap < *n).
+ */
+fcfc_status fcfc_plan_timings(fcfc_plan_t plan, float *d_feat, float *d_logt, int64_t cap, int64_t *n,
+                              void *stream);
+/* Attach a model (not owned; NULL detaches) used by FCFC_ORDER_LEARNED.
+ * Without one, or if a prediction is not finite, the count runs in
+ * FCFC_ORDER_HEURISTIC and fcfc_stats.order_used says so. */
+fcfc_status fcfc_plan_set_model(fcfc_plan_t plan, fcfc_model_t model);
+/*
+ * fcfc_plan_predict -- build the work list of fcfc_count_pairs(plan, c1, c2)
+ * without counting, and return the model's predicted counting time: the sum
+ * of the predicted item times divided by the number of resident wavefronts,
+ * in ms (*pred_ms), and the item count.  Synchronises `stream`.
+ */
+fcfc_status fcfc_plan_predict(fcfc_plan_t plan, fcfc_cells_t c1, fcfc_cells_t c2, fcfc_model_t model,
+                              void *stream, double *pred_ms, int64_t *n_items);
+/*
+ * fcfc_choose_cells -- pick cells per prune radius k in 1..6 for counting
+ * c1 (x c2, or auto with c2 NULL): for each k, a plan with the given bins,
+ * box and tuning (cells_per_rmax = k) is made, the catalogues are gridded and
+ * fcfc_plan_predict scores the work list; *best_k is the k with the lowest
+ * predicted time, pred_ms[k-1] each prediction (NaN where a k is not
+ * possible).  With model NULL, *best_k is the analytic choice (cell side such
+ * that a cell holds about 24 points on average, App. B) and pred_ms is NaN.
+ * Open boxes fit the bounds to the catalogues.  Errors: as fcfc_plan_create
+ * and fcfc_build_cells.
+ */
+fcfc_status fcfc_choose_cells(fcfc_model_t model, int32_t kind, int32_t los, const double *edges1,
+                              int32_t n1, const double *edges2, int32_t n2, double box_L,
+                              const fcfc_tuning *tune, const fcfc_catalog *c1, const fcfc_catalog *c2,
+                              void *stream, int32_t *best_k, double pred_ms[6]);
 
 const char *fcfc_status_str(fcfc_status s);
 const char *fcfc_last_error(void);

@@ -92,6 +92,7 @@ extern "C" fcfc_status fcfc_plan_stats(fcfc_plan_t plan, fcfc_stats* out) {
     for (int64_t v : cnt) tot += v;
     p->stats.in_range = tot;
     p->stats.kernel_ms = ms;
+    if (p->stats.order_used == FCFC_ORDER_LEARNED && h[5] != 0) p->stats.order_used = FCFC_ORDER_HEURISTIC;
     *out = p->stats;
     return FCFC_OK;
 }

@@ -1028,10 +1028,53 @@ static int grid_blocks(const LaunchSetup& L, uint32_t nitems) {
     return (int)nblk;
 }
 
+// sum over i of 2^pred[i] - 1 (predicted ticks) into *out
+__global__ __launch_bounds__(256) void k_sum_exp2m1(const float* __restrict__ pred, uint32_t n, double* out) {
+    __shared__ double part[4];
+    double acc = 0;
+    for (uint32_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
+        const float v = pred[i];
+        acc += (double)exp2f(fminf(fmaxf(v, 0.f), 40.f)) - 1.0;
+    }
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) atomicAdd(out, part[0] + part[1] + part[2] + part[3]);
+}
+
+__global__ __launch_bounds__(256) void k_pred_check(const float* __restrict__ pred, uint32_t n,
+                                                    unsigned long long* bad) {
+    bool b = false;
+    for (uint32_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) b |= !isfinite(pred[i]);
+    if (__any(b) && (threadIdx.x & 63) == 0) atomicOr(bad, 1ull);
+}
+
+// learned sort key: half-octave buckets of the predicted time, longest first;
+// the heuristic key (cost = A points x B points) if any prediction was bad
+__global__ void k_pred_keys(const Item* __restrict__ items, const float* __restrict__ pred,
+                            const unsigned long long* __restrict__ bad, uint32_t n, uint32_t* __restrict__ key,
+                            uint32_t* __restrict__ val) {
+    uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint32_t k;
+    if (*bad) {
+        const uint32_t c = items[i].cost;
+        const uint32_t lg = c ? 31u - (uint32_t)__clz(c) : 0u;
+        const uint32_t half = (lg >= 1 && ((c >> (lg - 1)) & 1u)) ? 1u : 0u;
+        k = 63u - min(63u, 2u * lg + half);
+    } else {
+        const float b = fminf(fmaxf(2.f * pred[i], 0.f), 63.f);
+        k = 63u - (uint32_t)b;
+    }
+    key[i] = k;
+    val[i] = i;
+}
+
 // ---------------------------------------------------------------------------
 // single count
 // ---------------------------------------------------------------------------
-fcfc_status count_pairs(Plan* p, Cells* c1, Cells* c2, int64_t* d_counts, double* d_wcounts, hipStream_t st) {
+fcfc_status count_pairs(Plan* p, Cells* c1, Cells* c2, int64_t* d_counts, double* d_wcounts, hipStream_t st,
+                        PredictReq* pr) {
     const bool is_auto = (c2 == nullptr);
     Cells* cb = is_auto ? c1 : c2;
     const bool weighted = d_wcounts != nullptr;
@@ -1048,7 +1091,8 @@ fcfc_status count_pairs(Plan* p, Cells* c1, Cells* c2, int64_t* d_counts, double
     const double ppc = (double)c1->n / std::max<int64_t>(1, g.ncell());
     FCFC_TRY(setup_launch(p, is_auto, weighted, false, ppc, S, L));
     CountArgs& a = L.a;
-    const int order = p->tune.order;
+    const int order = pr ? 0 : p->tune.order;
+    const Model* model = pr ? pr->model : (order == FCFC_ORDER_LEARNED ? p->model : nullptr);
     WLArgs w = make_wl(p, L, is_auto, 1, c1->n);
     const int64_t nseg = (int64_t)((g.nx + L.seg - 1) / L.seg) * g.ny * g.nz;
     const int64_t tiles_cap = w.tiles_cap;
@@ -1112,8 +1156,9 @@ fcfc_status count_pairs(Plan* p, Cells* c1, Cells* c2, int64_t* d_counts, double
     size_t s_items = al256((size_t)std::max<uint32_t>(nitems, 1) * sizeof(Item));
     size_t s_sort = order ? al256((size_t)std::max<uint32_t>(nitems, 1) * 4) : 0;
     size_t s_rs = order ? al256(radix_scratch_bytes(nitems)) : 0;
-    size_t s_times = p->tune.record_timing ? al256((size_t)std::max<uint32_t>(nitems, 1) * 4) : 0;
-    size_t s2 = 2 * s_items + 4 * s_sort + s_rs + s_times;
+    size_t s_times = (p->tune.record_timing && !pr) ? al256((size_t)std::max<uint32_t>(nitems, 1) * 4) : 0;
+    size_t s_pred = model ? al256((size_t)std::max<uint32_t>(nitems, 1) * 20) : 0;
+    size_t s2 = 2 * s_items + 4 * s_sort + s_rs + s_times + s_pred;
     char* scr2 = nullptr;
     if (hipMallocAsync((void**)&scr2, s2, st) != hipSuccess) {
         (void)hipFreeAsync(scr, st);
@@ -1125,13 +1170,54 @@ fcfc_status count_pairs(Plan* p, Cells* c1, Cells* c2, int64_t* d_counts, double
     hipLaunchKernelGGL(k_item_write, dim3((unsigned)((npair_tr + 255) / 256)), dim3(256), 0, st, tiles, &ctr[0], srows,
                        cb->cell_start, w, ioff, items, nitems);
     Item* run_items = items;
+    float* pred = model ? (float*)(scr2 + 2 * s_items + 4 * s_sort + s_rs + s_times) : nullptr;
+    const float kcells = (float)(p->rprune / g.side);
+    if (pr) {
+        // predict-only: score the work list and stop
+        const int nblk = grid_blocks(L, nitems);
+        double sum_ticks = 0;
+        if (nitems > 0) {
+            model_item_costs(model, items, nitems, kcells, pred + nitems, pred, st);
+            double* dsum = (double*)&ctr[8];
+            fill_u64((uint64_t*)dsum, 0ull, 1, st);
+            hipLaunchKernelGGL(k_sum_exp2m1, dim3(std::min<uint32_t>((nitems + 255) / 256, 1024)), dim3(256), 0, st,
+                               pred, nitems, dsum);
+            FCFC_HIP(hipMemcpyAsync(&sum_ticks, dsum, 8, hipMemcpyDeviceToHost, st));
+        }
+        FCFC_HIP(hipStreamSynchronize(st));
+        (void)hipFreeAsync(scr2, st);
+        (void)hipFreeAsync(scr, st);
+        int khz = 0;
+        if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, 0) != hipSuccess || khz <= 0) khz = 100000;
+        pr->items = nitems;
+        pr->pred_ms = sum_ticks / ((double)nblk * L.waves) / (double)khz;
+        return FCFC_OK;
+    }
+    if (!p->stats_dev) {
+        FCFC_HIP(hipMalloc(&p->stats_dev, 64));
+        FCFC_HIP(hipEventCreate(&p->ev0));
+        FCFC_HIP(hipEventCreate(&p->ev1));
+    }
+    fill_u64((uint64_t*)p->stats_dev, 0ull, 8, st);
     if (order && nitems > 1) {
         uint32_t* k0 = (uint32_t*)(scr2 + 2 * s_items);
         uint32_t* v0 = (uint32_t*)(scr2 + 2 * s_items + s_sort);
         uint32_t* k1 = (uint32_t*)(scr2 + 2 * s_items + 2 * s_sort);
         uint32_t* v1 = (uint32_t*)(scr2 + 2 * s_items + 3 * s_sort);
         void* rs = scr2 + 2 * s_items + 4 * s_sort;
-        hipLaunchKernelGGL(k_item_keys, dim3((nitems + 255) / 256), dim3(256), 0, st, items, &ctr[1], nitems, k0, v0);
+        if (model) {
+            // learned order: longest predicted first; any non-finite prediction
+            // sends the whole list back to the heuristic key (flag in stats[5])
+            model_item_costs(model, items, nitems, kcells, pred + nitems, pred, st);
+            unsigned long long* bad = (unsigned long long*)p->stats_dev + 5;
+            hipLaunchKernelGGL(k_pred_check, dim3(std::min<uint32_t>((nitems + 255) / 256, 1024)), dim3(256), 0, st,
+                               pred, nitems, bad);
+            hipLaunchKernelGGL(k_pred_keys, dim3((nitems + 255) / 256), dim3(256), 0, st, items, pred, bad, nitems, k0,
+                               v0);
+        } else {
+            hipLaunchKernelGGL(k_item_keys, dim3((nitems + 255) / 256), dim3(256), 0, st, items, &ctr[1], nitems, k0,
+                               v0);
+        }
         radix_sort_pairs(&k0, &v0, &k1, &v1, nitems, 8, rs, st);
         hipLaunchKernelGGL(k_item_permute, dim3((nitems + 255) / 256), dim3(256), 0, st, items, v0, &ctr[1], nitems,
                            items2);
@@ -1141,12 +1227,6 @@ fcfc_status count_pairs(Plan* p, Cells* c1, Cells* c2, int64_t* d_counts, double
 
     fill_u64((uint64_t*)d_counts, 0ull, p->nbins, st);
     if (weighted) fill_u64((uint64_t*)wacc, 0ull, 2 * (int64_t)p->nbins, st);
-    if (!p->stats_dev) {
-        FCFC_HIP(hipMalloc(&p->stats_dev, 64));
-        FCFC_HIP(hipEventCreate(&p->ev0));
-        FCFC_HIP(hipEventCreate(&p->ev1));
-    }
-    fill_u64((uint64_t*)p->stats_dev, 0ull, 8, st);
 
     a.posA = c1->pos32;
     a.absA = c1->abs32;
@@ -1200,6 +1280,7 @@ fcfc_status count_pairs(Plan* p, Cells* c1, Cells* c2, int64_t* d_counts, double
     p->stats.cells_per_rmax = g.k;
     p->stats.cell_side = g.side;
     p->stats.wg_per_cu = 1;
+    p->stats.order_used = model ? FCFC_ORDER_LEARNED : (order ? FCFC_ORDER_HEURISTIC : FCFC_ORDER_BUILT);
     p->last_pts = L.P;
     return FCFC_OK;
 }

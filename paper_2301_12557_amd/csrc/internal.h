@@ -122,10 +122,8 @@ struct Plan {
     int last_pts = 0;
     std::vector<char> host_stage;    // host copies of uploaded tables / kernel arguments
     std::vector<char> host_args;
-    // learned scheduler (optional)
-    std::vector<float> mlp_host; // packed weights, empty if none
-    void* mlp_dev = nullptr;
-    int mlp_ok = 0;
+    // learned cost model for FCFC_ORDER_LEARNED (not owned)
+    struct Model* model = nullptr;
 };
 
 struct Cells {
@@ -171,8 +169,20 @@ void batch_build_enqueue(const Plan* p, const CatDesc* desc, const int64_t* offs
                          hipStream_t st);
 
 // count (count.hip)
+// Learned cost model (mlp.hip): predicted log2(1 + ticks) of n work items
+// into pred[n]; feat is scratch of 4 n floats.
+struct Model;
+void model_item_costs(const Model* md, const Item* items, uint32_t n, float kcells, float* feat, float* pred,
+                      hipStream_t st);
+// Predict-only count: with `predict` set, count_pairs builds the work list,
+// scores it with the model and returns the predicted time (ms) without counting.
+struct PredictReq {
+    const Model* model = nullptr;
+    double pred_ms = 0;
+    int64_t items = 0;
+};
 fcfc_status count_pairs(Plan* p, Cells* c1, Cells* c2, int64_t* d_counts, double* d_wcounts,
-                        hipStream_t st);
+                        hipStream_t st, PredictReq* pr = nullptr);
 
 struct BatchImpl;
 fcfc_status batch_create_impl(Plan* p, const fcfc_catalog* cats, int ncat, hipStream_t st, BatchImpl** out);

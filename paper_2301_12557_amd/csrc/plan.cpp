@@ -445,7 +445,7 @@ extern "C" void fcfc_plan_free(fcfc_plan_t plan) {
     Plan* p = (Plan*)plan;
     if (!p) return;
     if (p->stats_dev) (void)hipFree(p->stats_dev);
-    if (p->mlp_dev) (void)hipFree(p->mlp_dev);
+    if (p->timing_dev) (void)hipFree(p->timing_dev);
     if (p->ev0) (void)hipEventDestroy(p->ev0);
     if (p->ev1) (void)hipEventDestroy(p->ev1);
     delete p;

@@ -45,11 +45,14 @@ class Stats(ctypes.Structure):
                 ("in_range", ctypes.c_int64), ("cells", ctypes.c_int64), ("grid", ctypes.c_int32 * 3),
                 ("cells_per_rmax", ctypes.c_int32), ("cell_side", ctypes.c_double),
                 ("kernel_ms", ctypes.c_double), ("band_d2_rel", ctypes.c_double),
-                ("lut_entries", ctypes.c_int32), ("wg_per_cu", ctypes.c_int32)]
+                ("lut_entries", ctypes.c_int32), ("wg_per_cu", ctypes.c_int32),
+                ("order_used", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_}
         d["grid"] = list(self.grid)
+        d.pop("reserved")
+        d["order_used"] = {v: k for k, v in ORDER.items()}.get(self.order_used, self.order_used)
         return d
 
 
@@ -72,6 +75,23 @@ SIGNATURES = [
     ("fcfc_cells_free", None, [_P]),
     ("fcfc_plan_free", None, [_P]),
     ("fcfc_cells_info", _I32, [_P, ctypes.POINTER(_I64), ctypes.POINTER(_I64)]),
+    ("fcfc_model_nparams", _I32, []),
+    ("fcfc_model_create", _I32, [ctypes.c_uint64, ctypes.POINTER(_P)]),
+    ("fcfc_model_free", None, [_P]),
+    ("fcfc_model_get", _I32, [_P, _P, _P]),
+    ("fcfc_model_set", _I32, [_P, _P, _P]),
+    ("fcfc_model_predict", _I32, [_P, _P, _I64, _P, _P]),
+    ("fcfc_model_grad", _I32, [_P, _P, _P, _I64, _P, ctypes.POINTER(ctypes.c_float), _P]),
+    ("fcfc_model_train", _I32, [_P, _P, _P, _I64, _I32, _I32, ctypes.c_float, ctypes.c_uint64, _P,
+                                ctypes.POINTER(ctypes.c_float)]),
+    ("fcfc_model_save", _I32, [_P, ctypes.c_char_p]),
+    ("fcfc_model_load", _I32, [ctypes.c_char_p, ctypes.POINTER(_P)]),
+    ("fcfc_plan_timings", _I32, [_P, _P, _P, _I64, ctypes.POINTER(_I64), _P]),
+    ("fcfc_plan_set_model", _I32, [_P, _P]),
+    ("fcfc_plan_predict", _I32, [_P, _P, _P, _P, _P, ctypes.POINTER(_D), ctypes.POINTER(_I64)]),
+    ("fcfc_choose_cells", _I32, [_P, _I32, _I32, _P, _I32, _P, _I32, _D, ctypes.POINTER(Tuning),
+                                 ctypes.POINTER(Catalog), ctypes.POINTER(Catalog), _P, ctypes.POINTER(_I32),
+                                 ctypes.POINTER(_D)]),
     ("fcfc_status_str", ctypes.c_char_p, [_I32]),
     ("fcfc_last_error", ctypes.c_char_p, []),
     ("fcfc_version", _I32, []),
@@ -186,6 +206,32 @@ class Plan:
         check(load().fcfc_plan_stats(self.h, ctypes.byref(s)))
         return s.as_dict()
 
+    def set_model(self, model):
+        """Attach a Model for order="learned" (None detaches); the plan keeps a reference."""
+        self._model = model
+        check(load().fcfc_plan_set_model(self.h, model.h if model is not None else None))
+
+    def timings(self, stream=None):
+        """(features (n, 4), log2(1 + ticks) (n,)) float32 device tensors of the last
+        count recorded with record_timing=1."""
+        import torch
+        lib = load()
+        n = ctypes.c_int64()
+        check(lib.fcfc_plan_timings(self.h, None, None, 0, ctypes.byref(n), _stream_ptr(stream)))
+        feat = torch.empty((n.value, 4), dtype=torch.float32, device="cuda")
+        logt = torch.empty(n.value, dtype=torch.float32, device="cuda")
+        check(lib.fcfc_plan_timings(self.h, feat.data_ptr(), logt.data_ptr(), n.value, ctypes.byref(n),
+                                    _stream_ptr(stream)))
+        return feat, logt
+
+    def predict(self, model, c1, c2=None, stream=None):
+        """(predicted counting ms, work items) of count(c1, c2) under `model`."""
+        ms = ctypes.c_double()
+        n = ctypes.c_int64()
+        check(load().fcfc_plan_predict(self.h, c1.h, c2.h if c2 is not None else None, model.h,
+                                       _stream_ptr(stream), ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value
+
     def close(self):
         if getattr(self, "h", None):
             load().fcfc_plan_free(self.h)
@@ -261,6 +307,102 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+class Model:
+    """Owns an fcfc_model_t: the learned work-item cost model (4 -> 64 -> 64 -> 64 -> 1)."""
+
+    def __init__(self, seed=0, path=None):
+        h = ctypes.c_void_p()
+        if path is not None:
+            check(load().fcfc_model_load(os.fsencode(path), ctypes.byref(h)))
+        else:
+            check(load().fcfc_model_create(int(seed), ctypes.byref(h)))
+        self.h = h
+
+    @staticmethod
+    def nparams():
+        return int(load().fcfc_model_nparams())
+
+    def get(self):
+        p = np.empty(self.nparams(), dtype=np.float32)
+        nrm = np.empty(10, dtype=np.float32)
+        check(load().fcfc_model_get(self.h, p.ctypes.data_as(_P), nrm.ctypes.data_as(_P)))
+        return p, nrm
+
+    def set(self, params=None, norm=None):
+        p = None if params is None else np.ascontiguousarray(params, dtype=np.float32)
+        n = None if norm is None else np.ascontiguousarray(norm, dtype=np.float32)
+        if p is not None and p.size != self.nparams():
+            raise ValueError(f"params must have {self.nparams()} values")
+        if n is not None and n.size != 10:
+            raise ValueError("norm must have 10 values")
+        check(load().fcfc_model_set(self.h, p.ctypes.data_as(_P) if p is not None else None,
+                                    n.ctypes.data_as(_P) if n is not None else None))
+
+    @staticmethod
+    def _feat(x):
+        import torch
+        if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == torch.float32 and x.dim() == 2
+                and x.shape[1] == 4 and x.is_contiguous()):
+            raise ValueError("features must be a contiguous CUDA float32 tensor of shape (M, 4)")
+        return x
+
+    def predict(self, feat, stream=None):
+        import torch
+        feat = self._feat(feat)
+        out = torch.empty(feat.shape[0], dtype=torch.float32, device=feat.device)
+        check(load().fcfc_model_predict(self.h, feat.data_ptr(), feat.shape[0], out.data_ptr(), _stream_ptr(stream)))
+        return out
+
+    def grad(self, feat, target, stream=None):
+        feat = self._feat(feat)
+        g = np.empty(self.nparams(), dtype=np.float32)
+        loss = ctypes.c_float()
+        check(load().fcfc_model_grad(self.h, feat.data_ptr(), target.contiguous().data_ptr(), feat.shape[0],
+                                     g.ctypes.data_as(_P), ctypes.byref(loss), _stream_ptr(stream)))
+        return g, loss.value
+
+    def train(self, feat, target, epochs=30, batch=256, lr=1e-3, seed=0, stream=None):
+        feat = self._feat(feat)
+        loss = ctypes.c_float()
+        check(load().fcfc_model_train(self.h, feat.data_ptr(), target.contiguous().data_ptr(), feat.shape[0],
+                                      int(epochs), int(batch), float(lr), int(seed), _stream_ptr(stream),
+                                      ctypes.byref(loss)))
+        return loss.value
+
+    def save(self, path):
+        check(load().fcfc_model_save(self.h, os.fsencode(path)))
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().fcfc_model_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def choose_cells(x1, x2=None, *, model=None, kind="s", edges1, edges2=None, los="z", box=0.0, stream=None,
+                 **tuning):
+    """(best cells per prune radius, predicted ms for k = 1..6) from the library's chooser."""
+    e1 = np.ascontiguousarray(np.asarray(edges1, dtype=np.float64))
+    e2 = None if kind == "s" else np.ascontiguousarray(np.asarray(edges2, dtype=np.float64))
+    t = make_tuning(**tuning)
+    c1 = _catalog(x1)
+    c2 = _catalog(x2) if x2 is not None else None
+    k = ctypes.c_int32()
+    pred = (ctypes.c_double * 6)()
+    check(load().fcfc_choose_cells(model.h if model is not None else None, KIND[kind], LOS[los],
+                                   e1.ctypes.data_as(_P), len(e1) - 1,
+                                   e2.ctypes.data_as(_P) if e2 is not None else None,
+                                   len(e2) - 1 if e2 is not None else 0, float(box), ctypes.byref(t),
+                                   ctypes.byref(c1), ctypes.byref(c2) if c2 is not None else None,
+                                   _stream_ptr(stream), ctypes.byref(k), pred))
+    return k.value, list(pred)
 
 
 def count_pairs(x1, x2=None, *, kind="s", edges1, edges2=None, los="z", box=0.0, w1=None, w2=None,

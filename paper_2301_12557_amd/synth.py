@@ -51,7 +51,7 @@ def gaussian_field(ngrid, L, slope, sigma, rng):
     with np.errstate(divide="ignore"):
         amp = np.where(k2 > 0, k2 ** (slope / 4.0), 0.0)   # sqrt(P) = k^(slope/2)
     gk *= amp
-    G = np.fft.irfftn(gk, s=(ngrid, ngrid, ngrid))
+    G = np.fft.irfftn(gk, s=(ngrid, ngrid, ngrid), axes=(0, 1, 2))
     G -= G.mean()
     G *= sigma / G.std()
     return G
@@ -175,3 +175,33 @@ def mock_sizes(nmock=200, lo=100_000, hi=500_000, seed=None, scale=1.0):
 
 def mock(m, n, L=1000.0, ngrid=256):
     return lognormal_box(int(n), L, MOCK_SEED_BASE + int(m), ngrid=ngrid)
+
+
+def lognormal_box_torch(n, L, seed, device="cuda", ngrid=256, slope=-1.5, sigma=1.0):
+    """The generator of lognormal_box with torch operations on `device` (float64),
+    for producing many large mocks quickly.  Seeded with torch's Philox generator
+    of that device, so its draws differ from the numpy version's."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed) & 0x7FFFFFFFFFFFFFFF)
+    L = float(L)
+    noise = torch.randn((ngrid, ngrid, ngrid), generator=g, device=device, dtype=torch.float64)
+    gk = torch.fft.rfftn(noise)
+    kf = 2.0 * torch.pi / L
+    kx = torch.fft.fftfreq(ngrid, d=1.0 / ngrid, device=device, dtype=torch.float64) * kf
+    kz = torch.fft.rfftfreq(ngrid, d=1.0 / ngrid, device=device, dtype=torch.float64) * kf
+    k2 = kx[:, None, None] ** 2 + kx[None, :, None] ** 2 + kz[None, None, :] ** 2
+    amp = torch.where(k2 > 0, k2.clamp_min(1e-300) ** (slope / 4.0), torch.zeros_like(k2))
+    G = torch.fft.irfftn(gk * amp, s=(ngrid, ngrid, ngrid))
+    G = (G - G.mean()) * (sigma / G.std())
+    rho = torch.exp(G - 0.5 * sigma * sigma).reshape(-1)
+    cdf = torch.cumsum(rho, 0)
+    u = torch.rand(int(n), generator=g, device=device, dtype=torch.float64) * cdf[-1]
+    idx = torch.searchsorted(cdf, u, right=True).clamp_max(ngrid ** 3 - 1)
+    iz = idx % ngrid
+    iy = (idx // ngrid) % ngrid
+    ix = idx // (ngrid * ngrid)
+    off = torch.rand((int(n), 3), generator=g, device=device, dtype=torch.float64)
+    cell = L / ngrid
+    x = torch.stack([(ix + off[:, 0]) * cell, (iy + off[:, 1]) * cell, (iz + off[:, 2]) * cell], dim=1)
+    return x.clamp_(0.0, float(np.nextafter(L, 0.0))).contiguous()

@@ -124,3 +124,44 @@ def test_midpoint_observer_inside_box_rejected():
     hi = np.array([5.0, 5.0, 5.0])
     assert lib.fcfc_plan_set_bounds(h, lo.ctypes.data_as(ctypes.c_void_p), hi.ctypes.data_as(ctypes.c_void_p)) == -5
     lib.fcfc_plan_free(h)
+
+
+def test_model_file_errors(tmp_path):
+    """A missing, foreign or truncated model file is FCFC_EMODEL (checked before any GPU work)."""
+    lib = fcfc.load()
+    assert lib.fcfc_model_nparams() == 8705
+    h = ctypes.c_void_p()
+    assert lib.fcfc_model_load(os.fsencode(str(tmp_path / "none.bin")), ctypes.byref(h)) == -9
+    bad = tmp_path / "bad.bin"
+    bad.write_bytes(b"NOTAMODEL" + bytes(100))
+    assert lib.fcfc_model_load(os.fsencode(str(bad)), ctypes.byref(h)) == -9
+    short = tmp_path / "short.bin"
+    short.write_bytes(b"FCFCMLP1" + np.int32(8705).tobytes() + bytes(40) + bytes(400))
+    assert lib.fcfc_model_load(os.fsencode(str(short)), ctypes.byref(h)) == -9
+    wrong = tmp_path / "wrong.bin"
+    wrong.write_bytes(b"FCFCMLP1" + np.int32(100).tobytes() + bytes(40 + 400))
+    assert lib.fcfc_model_load(os.fsencode(str(wrong)), ctypes.byref(h)) == -9
+    assert not h.value
+
+
+def test_model_entry_points_reject_nulls():
+    lib = fcfc.load()
+    assert lib.fcfc_model_create(0, None) == -1
+    assert lib.fcfc_plan_set_model(None, None) == -1
+    assert lib.fcfc_model_predict(None, None, 0, None, None) == -1
+    assert lib.fcfc_model_train(None, None, None, 0, 1, 64, ctypes.c_float(1e-3), 0, None, None) == -1
+    k = ctypes.c_int32()
+    assert lib.fcfc_choose_cells(None, 0, 0, None, 0, None, 0, 10.0, None, None, None, None,
+                                 ctypes.byref(k), None) == -1
+
+
+def test_plan_timings_before_any_count():
+    lib = fcfc.load()
+    e1 = np.asarray([0.0, 1.0, 2.0])
+    p = ctypes.c_void_p()
+    assert lib.fcfc_plan_create(0, 0, e1.ctypes.data_as(ctypes.c_void_p), 2, None, 0, 10.0, None,
+                                ctypes.byref(p)) == 0
+    n = ctypes.c_int64()
+    assert lib.fcfc_plan_timings(p, None, None, 0, ctypes.byref(n), None) == -10
+    assert lib.fcfc_plan_set_model(p, None) == 0
+    lib.fcfc_plan_free(p)
