@@ -118,7 +118,6 @@ def main():
         k, v = kv.split("=")
         tune[k] = int(v)
     tune.setdefault("n_hint", len(w["x1"]))
-    tune.setdefault("order", 1)
     plan = fcfc.Plan(w["kind"], w["edges1"], w["edges2"], los=w["los"], box=w["box"], **tune)
     nb = plan.n1 * plan.n2
     out = torch.empty(nb, dtype=torch.int64, device=dev)

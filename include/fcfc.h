@@ -65,10 +65,10 @@ typedef int32_t fcfc_status;
 #define FCFC_LOS_Z 0         /* l = e_z (simulation boxes) */
 #define FCFC_LOS_MIDPOINT 1  /* l = s1 + s2 (observed catalogues; open boxes only) */
 
-/* work-list order */
-#define FCFC_ORDER_BUILT 0       /* enumeration order */
-#define FCFC_ORDER_HEURISTIC 1   /* longest-first by the analytic cost model */
-#define FCFC_ORDER_LEARNED 2     /* longest-first by the loaded MLP (falls back to 1) */
+/* work-list order (0, the default, is the heuristic) */
+#define FCFC_ORDER_HEURISTIC 0   /* longest first by A points x B points */
+#define FCFC_ORDER_BUILT 1       /* enumeration order (row by row) */
+#define FCFC_ORDER_LEARNED 2     /* longest first by the attached cost model (else heuristic) */
 
 typedef struct fcfc_plan_s *fcfc_plan_t;
 typedef struct fcfc_cells_s *fcfc_cells_t;
@@ -272,9 +272,10 @@ fcfc_status fcfc_plan_timings(fcfc_plan_t plan, float *d_feat, float *d_logt, in
 fcfc_status fcfc_plan_set_model(fcfc_plan_t plan, fcfc_model_t model);
 /*
  * fcfc_plan_predict -- build the work list of fcfc_count_pairs(plan, c1, c2)
- * without counting, and return the model's predicted counting time: the sum
- * of the predicted item times divided by the number of resident wavefronts,
- * in ms (*pred_ms), and the item count.  Synchronises `stream`.
+ * without counting, and return the model's predicted counting time: the larger
+ * of the summed predicted item times divided by the number of resident
+ * wavefronts and the largest predicted item time, in ms (*pred_ms), and the
+ * item count.  Synchronises `stream`.
  */
 fcfc_status fcfc_plan_predict(fcfc_plan_t plan, fcfc_cells_t c1, fcfc_cells_t c2, fcfc_model_t model,
                               void *stream, double *pred_ms, int64_t *n_items);
@@ -293,6 +294,35 @@ fcfc_status fcfc_choose_cells(fcfc_model_t model, int32_t kind, int32_t los, con
                               int32_t n1, const double *edges2, int32_t n2, double box_L,
                               const fcfc_tuning *tune, const fcfc_catalog *c1, const fcfc_catalog *c2,
                               void *stream, int32_t *best_k, double pred_ms[6]);
+
+/*
+ * fcfc_autotune -- pick the tuning knobs of a count by timing it.  Not part
+ * of the paper, which studies the cell size by hand (Sect. 2.1, App. B).
+ * Runs build + count (best of two, GPU events) on the given catalogues for:
+ * the analytic tuning; the cell sizes the model predicts fastest (its two
+ * best k), or without a model the analytic k +- 1; then, from the fastest,
+ * 2 and 4 histogram copies, the other tile width, look-up tables of 2^12
+ * and 2^14 entries and, with a model, the learned work order, keeping each
+ * change that is faster.  Settings that are not possible for these bins are
+ * skipped.  With the learned order in *best, counts need the model attached
+ * (fcfc_plan_set_model) to use it.
+ *   base       NULL or knobs kept fixed (n_hint and the order are kept).
+ *   weighted   1: time weighted counts (c1 and c2 need weights).
+ *   cache_path NULL, or a text file of earlier results keyed by a signature
+ *              (library version, device, bins, box, line of sight, weighting,
+ *              catalogue sizes to a half-octave): a hit returns without any
+ *              trial (*trials = 0); a miss tunes and appends a line.
+ *   best       every knob set explicitly; *best_ms its time; *heuristic_ms
+ *              the analytic tuning's time (NaN on a cache hit); *trials the
+ *              configurations timed.  Counts never depend on the knobs.
+ * Errors: as fcfc_plan_create, fcfc_build_cells and fcfc_count_pairs;
+ * FCFC_EINVAL for null arguments or missing weights.
+ */
+fcfc_status fcfc_autotune(fcfc_model_t model, int32_t kind, int32_t los, const double *edges1,
+                          int32_t n1, const double *edges2, int32_t n2, double box_L,
+                          const fcfc_tuning *base, const fcfc_catalog *c1, const fcfc_catalog *c2,
+                          int32_t weighted, const char *cache_path, void *stream, fcfc_tuning *best,
+                          double *best_ms, double *heuristic_ms, int32_t *trials);
 
 const char *fcfc_status_str(fcfc_status s);
 const char *fcfc_last_error(void);

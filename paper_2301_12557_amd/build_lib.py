@@ -14,7 +14,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUTDIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(OUTDIR, "libfcfc.so")
-SOURCES = ["plan.cpp", "api.cpp", "build.hip", "worklist.hip", "count.hip", "batch.hip", "mlp.hip"]
+SOURCES = ["plan.cpp", "api.cpp", "build.hip", "worklist.hip", "count.hip", "batch.hip", "mlp.hip", "tune.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -35,7 +35,7 @@ def _compile(src):
 
 def build(verbose=False):
     os.makedirs(OUTDIR, exist_ok=True)
-    srcs = [s for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
+    srcs = list(SOURCES)
     with cf.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
         objs = list(ex.map(_compile, srcs))
     tmp = LIB + ".tmp"

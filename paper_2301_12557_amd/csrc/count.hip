@@ -576,12 +576,20 @@ __global__ __launch_bounds__(CT_MAX) void k_count(const CountArgs* argp) {
     uint32_t nxt_it = grab();
     ItemIn cur, nxt;
     if (cur_it != ~0u) load_in(cur_it, cur);
+    // timing: an item's time runs from its start to the next item's start on
+    // this wave (fetch and loop overhead included), the last one to the end
+    unsigned long long t_prev = 0;
+    uint32_t prev_it = ~0u;
     while (cur_it != ~0u) {
+        const uint32_t it = cur_it;
+        if (a.times && lane == 0) {
+            const unsigned long long t = wall_clock64();
+            if (prev_it != ~0u) a.times[prev_it] = (uint32_t)min<unsigned long long>(t - t_prev, 0xffffffffull);
+            t_prev = t;
+            prev_it = it;
+        }
         const uint32_t nn = grab();
         if (nxt_it != ~0u) load_in(nxt_it, nxt);
-        const uint32_t it = cur_it;
-        unsigned long long t0 = 0;
-        if (a.times && lane == 0) t0 = wall_clock64();
         const Item& item = cur.item;
         const uint32_t a_begin = item.a_begin;
         const uint32_t acnt = item.acnt_xb0 & 0xffffu;
@@ -702,14 +710,12 @@ __global__ __launch_bounds__(CT_MAX) void k_count(const CountArgs* argp) {
             bin_queue<KIND, LOS, W>(a, k, s, hist_l, 0, qn, lane, c);
             wave_sync_lds();
         }
-        if (a.times && lane == 0) {
-            unsigned long long t1 = wall_clock64();
-            a.times[it] = (uint32_t)min<unsigned long long>(t1 - t0, 0xffffffffull);
-        }
         cur = nxt;
         cur_it = nxt_it;
         nxt_it = nn;
     }
+    if (a.times && lane == 0 && prev_it != ~0u)
+        a.times[prev_it] = (uint32_t)min<unsigned long long>(wall_clock64() - t_prev, 0xffffffffull);
     };
     if (!BATCH) {
         const uint32_t nitems = __builtin_amdgcn_readfirstlane(*a.nitems_dev);
@@ -1028,18 +1034,31 @@ static int grid_blocks(const LaunchSetup& L, uint32_t nitems) {
     return (int)nblk;
 }
 
-// sum over i of 2^pred[i] - 1 (predicted ticks) into *out
+// sum and maximum over i of 2^pred[i] - 1 (predicted ticks): out[0] += sum;
+// out[1] = max, as the bits of a non-negative double (ordered like integers)
 __global__ __launch_bounds__(256) void k_sum_exp2m1(const float* __restrict__ pred, uint32_t n, double* out) {
-    __shared__ double part[4];
-    double acc = 0;
+    __shared__ double part[4], pmax[4];
+    double acc = 0, mx = 0;
     for (uint32_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
         const float v = pred[i];
-        acc += (double)exp2f(fminf(fmaxf(v, 0.f), 40.f)) - 1.0;
+        const double t = (double)exp2f(fminf(fmaxf(v, 0.f), 40.f)) - 1.0;
+        acc += t;
+        mx = fmax(mx, t);
     }
-    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
-    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = acc;
+    for (int o = 32; o > 0; o >>= 1) {
+        acc += __shfl_xor(acc, o);
+        mx = fmax(mx, __shfl_xor(mx, o));
+    }
+    if ((threadIdx.x & 63) == 0) {
+        part[threadIdx.x >> 6] = acc;
+        pmax[threadIdx.x >> 6] = mx;
+    }
     __syncthreads();
-    if (threadIdx.x == 0) atomicAdd(out, part[0] + part[1] + part[2] + part[3]);
+    if (threadIdx.x == 0) {
+        atomicAdd(out, part[0] + part[1] + part[2] + part[3]);
+        const double m = fmax(fmax(pmax[0], pmax[1]), fmax(pmax[2], pmax[3]));
+        atomicMax((unsigned long long*)(out + 1), (unsigned long long)__double_as_longlong(m));
+    }
 }
 
 __global__ __launch_bounds__(256) void k_pred_check(const float* __restrict__ pred, uint32_t n,
@@ -1091,8 +1110,8 @@ fcfc_status count_pairs(Plan* p, Cells* c1, Cells* c2, int64_t* d_counts, double
     const double ppc = (double)c1->n / std::max<int64_t>(1, g.ncell());
     FCFC_TRY(setup_launch(p, is_auto, weighted, false, ppc, S, L));
     CountArgs& a = L.a;
-    const int order = pr ? 0 : p->tune.order;
-    const Model* model = pr ? pr->model : (order == FCFC_ORDER_LEARNED ? p->model : nullptr);
+    const bool sorted = !pr && p->tune.order != FCFC_ORDER_BUILT;
+    const Model* model = pr ? pr->model : (p->tune.order == FCFC_ORDER_LEARNED ? p->model : nullptr);
     WLArgs w = make_wl(p, L, is_auto, 1, c1->n);
     const int64_t nseg = (int64_t)((g.nx + L.seg - 1) / L.seg) * g.ny * g.nz;
     const int64_t tiles_cap = w.tiles_cap;
@@ -1154,8 +1173,8 @@ fcfc_status count_pairs(Plan* p, Cells* c1, Cells* c2, int64_t* d_counts, double
     FCFC_HIP(hipStreamSynchronize(st));
     uint32_t nitems = hctr[1];
     size_t s_items = al256((size_t)std::max<uint32_t>(nitems, 1) * sizeof(Item));
-    size_t s_sort = order ? al256((size_t)std::max<uint32_t>(nitems, 1) * 4) : 0;
-    size_t s_rs = order ? al256(radix_scratch_bytes(nitems)) : 0;
+    size_t s_sort = sorted ? al256((size_t)std::max<uint32_t>(nitems, 1) * 4) : 0;
+    size_t s_rs = sorted ? al256(radix_scratch_bytes(nitems)) : 0;
     size_t s_times = (p->tune.record_timing && !pr) ? al256((size_t)std::max<uint32_t>(nitems, 1) * 4) : 0;
     size_t s_pred = model ? al256((size_t)std::max<uint32_t>(nitems, 1) * 20) : 0;
     size_t s2 = 2 * s_items + 4 * s_sort + s_rs + s_times + s_pred;
@@ -1175,14 +1194,14 @@ fcfc_status count_pairs(Plan* p, Cells* c1, Cells* c2, int64_t* d_counts, double
     if (pr) {
         // predict-only: score the work list and stop
         const int nblk = grid_blocks(L, nitems);
-        double sum_ticks = 0;
+        double tk[2] = {0, 0};  // predicted ticks: sum, largest item
         if (nitems > 0) {
             model_item_costs(model, items, nitems, kcells, pred + nitems, pred, st);
             double* dsum = (double*)&ctr[8];
-            fill_u64((uint64_t*)dsum, 0ull, 1, st);
+            fill_u64((uint64_t*)dsum, 0ull, 2, st);
             hipLaunchKernelGGL(k_sum_exp2m1, dim3(std::min<uint32_t>((nitems + 255) / 256, 1024)), dim3(256), 0, st,
                                pred, nitems, dsum);
-            FCFC_HIP(hipMemcpyAsync(&sum_ticks, dsum, 8, hipMemcpyDeviceToHost, st));
+            FCFC_HIP(hipMemcpyAsync(tk, dsum, 16, hipMemcpyDeviceToHost, st));
         }
         FCFC_HIP(hipStreamSynchronize(st));
         (void)hipFreeAsync(scr2, st);
@@ -1190,7 +1209,8 @@ fcfc_status count_pairs(Plan* p, Cells* c1, Cells* c2, int64_t* d_counts, double
         int khz = 0;
         if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, 0) != hipSuccess || khz <= 0) khz = 100000;
         pr->items = nitems;
-        pr->pred_ms = sum_ticks / ((double)nblk * L.waves) / (double)khz;
+        // the schedule can finish no earlier than the mean load of a wave or the largest item
+        pr->pred_ms = std::max(tk[0] / ((double)nblk * L.waves), tk[1]) / (double)khz;
         return FCFC_OK;
     }
     if (!p->stats_dev) {
@@ -1199,7 +1219,7 @@ fcfc_status count_pairs(Plan* p, Cells* c1, Cells* c2, int64_t* d_counts, double
         FCFC_HIP(hipEventCreate(&p->ev1));
     }
     fill_u64((uint64_t*)p->stats_dev, 0ull, 8, st);
-    if (order && nitems > 1) {
+    if (sorted && nitems > 1) {
         uint32_t* k0 = (uint32_t*)(scr2 + 2 * s_items);
         uint32_t* v0 = (uint32_t*)(scr2 + 2 * s_items + s_sort);
         uint32_t* k1 = (uint32_t*)(scr2 + 2 * s_items + 2 * s_sort);
@@ -1280,7 +1300,7 @@ fcfc_status count_pairs(Plan* p, Cells* c1, Cells* c2, int64_t* d_counts, double
     p->stats.cells_per_rmax = g.k;
     p->stats.cell_side = g.side;
     p->stats.wg_per_cu = 1;
-    p->stats.order_used = model ? FCFC_ORDER_LEARNED : (order ? FCFC_ORDER_HEURISTIC : FCFC_ORDER_BUILT);
+    p->stats.order_used = model ? FCFC_ORDER_LEARNED : (sorted ? FCFC_ORDER_HEURISTIC : FCFC_ORDER_BUILT);
     p->last_pts = L.P;
     return FCFC_OK;
 }

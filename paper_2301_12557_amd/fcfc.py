@@ -18,7 +18,7 @@ STATUS = {0: "FCFC_OK", -1: "FCFC_EINVAL", -2: "FCFC_ENOMEM", -3: "FCFC_EBOX", -
           -10: "FCFC_ESTATE"}
 KIND = {"s": 0, "smu": 1, "spi": 2}
 LOS = {"z": 0, "mid": 1}
-ORDER = {"built": 0, "heuristic": 1, "learned": 2}
+ORDER = {"heuristic": 0, "built": 1, "learned": 2}
 
 
 class FcfcError(RuntimeError):
@@ -92,6 +92,10 @@ SIGNATURES = [
     ("fcfc_choose_cells", _I32, [_P, _I32, _I32, _P, _I32, _P, _I32, _D, ctypes.POINTER(Tuning),
                                  ctypes.POINTER(Catalog), ctypes.POINTER(Catalog), _P, ctypes.POINTER(_I32),
                                  ctypes.POINTER(_D)]),
+    ("fcfc_autotune", _I32, [_P, _I32, _I32, _P, _I32, _P, _I32, _D, ctypes.POINTER(Tuning),
+                             ctypes.POINTER(Catalog), ctypes.POINTER(Catalog), _I32, ctypes.c_char_p, _P,
+                             ctypes.POINTER(Tuning), ctypes.POINTER(_D), ctypes.POINTER(_D),
+                             ctypes.POINTER(_I32)]),
     ("fcfc_status_str", ctypes.c_char_p, [_I32]),
     ("fcfc_last_error", ctypes.c_char_p, []),
     ("fcfc_version", _I32, []),
@@ -403,6 +407,35 @@ def choose_cells(x1, x2=None, *, model=None, kind="s", edges1, edges2=None, los=
                                    ctypes.byref(c1), ctypes.byref(c2) if c2 is not None else None,
                                    _stream_ptr(stream), ctypes.byref(k), pred))
     return k.value, list(pred)
+
+
+TUNING_KEYS = ("cells_per_rmax", "tile_points", "seg_cells", "b_chunk", "hist_copies", "order",
+               "record_timing", "n_hint", "lut_log2")
+
+
+def autotune(x1, x2=None, *, model=None, kind="s", edges1, edges2=None, los="z", box=0.0, w1=None, w2=None,
+             cache=None, stream=None, **tuning):
+    """Time candidate tunings on these catalogues (see fcfc_autotune).
+
+    Returns (tuning dict, best ms, analytic-tuning ms, configurations timed)."""
+    e1 = np.ascontiguousarray(np.asarray(edges1, dtype=np.float64))
+    e2 = None if kind == "s" else np.ascontiguousarray(np.asarray(edges2, dtype=np.float64))
+    t = make_tuning(**tuning)
+    weighted = w1 is not None
+    c1 = _catalog(x1, w1)
+    c2 = _catalog(x2, w2) if x2 is not None else None
+    best = Tuning()
+    bms = ctypes.c_double()
+    hms = ctypes.c_double()
+    ntr = ctypes.c_int32()
+    check(load().fcfc_autotune(model.h if model is not None else None, KIND[kind], LOS[los],
+                               e1.ctypes.data_as(_P), len(e1) - 1,
+                               e2.ctypes.data_as(_P) if e2 is not None else None,
+                               len(e2) - 1 if e2 is not None else 0, float(box), ctypes.byref(t),
+                               ctypes.byref(c1), ctypes.byref(c2) if c2 is not None else None, int(weighted),
+                               os.fsencode(cache) if cache else None, _stream_ptr(stream), ctypes.byref(best),
+                               ctypes.byref(bms), ctypes.byref(hms), ctypes.byref(ntr)))
+    return {k: int(getattr(best, k)) for k in TUNING_KEYS}, bms.value, hms.value, ntr.value
 
 
 def count_pairs(x1, x2=None, *, kind="s", edges1, edges2=None, los="z", box=0.0, w1=None, w2=None,

@@ -157,7 +157,7 @@ def test_tuning_sweep_small():
         los = "mid" if (not periodic and kind != "s" and rng.random() < 0.5) else "z"
         tuning = dict(cells_per_rmax=int(rng.integers(1, 6)), tile_points=int(rng.choice([64, 128])),
                       seg_cells=int(rng.integers(1, 5)), b_chunk=int(rng.choice([256, 1024, 16384])),
-                      hist_copies=int(rng.choice([1, 2, 4])), order=int(rng.integers(0, 2)))
+                      hist_copies=int(rng.choice([1, 2, 4])), order=str(rng.choice(["built", "heuristic"])))
         w = synth.uniform_weights(n, 0.5, 2.0, t) if rng.random() < 0.3 else None
         check_case(f"sweep {t}", x, kind=kind, los=los, box=L if periodic else 0.0, edges1=e1,
                    edges2=None if kind == "s" else e2, w1=w, **tuning)
@@ -170,7 +170,7 @@ def test_invariance_under_tuning_c2_shape():
     kw = dict(kind="smu", edges1=synth.linear_edges(0, 200, 40), edges2=synth.mu_edges(100), box=2000.0)
     ref = None
     for tune in [dict(), dict(cells_per_rmax=1), dict(cells_per_rmax=4, tile_points=64),
-                 dict(cells_per_rmax=3, seg_cells=3, b_chunk=512, hist_copies=2, order=1)]:
+                 dict(cells_per_rmax=3, seg_cells=3, b_chunk=512, hist_copies=2, order="built")]:
         note(f"invariance {tune}")
         g, _, _ = gpu_count(x, **kw, **tune)
         if ref is None:
