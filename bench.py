@@ -37,6 +37,13 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target length of the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tune", default="", help="tuning overrides, e.g. cells_per_rmax=3,tile_points=128")
+    ap.add_argument("--no-c4", action="store_true", help="skip the batched-mocks comparison")
+    ap.add_argument("--c4-mocks", type=int, default=200)
+    ap.add_argument("--c4-repeats", type=int, default=5)
+    ap.add_argument("--no-learned", action="store_true", help="skip training and the held-out C5 comparison")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="first copy this many MiB device-to-device (a plain copy of known size, to calibrate "
+                         "HBM traffic counters against)")
     return ap.parse_args()
 
 
@@ -54,21 +61,25 @@ def workload(name, weighted):
 
 
 def measured_traffic(kernel_variant):
-    """HBM bytes per launch of the counting kernel from the committed rocprofv3 FETCH_SIZE /
-    WRITE_SIZE runs (profiles/k_count_c2_traffic.json), if they were taken on the current
-    kernel source and the same kernel variant; otherwise None."""
+    """HBM bytes per launch of the counting kernel from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE summary (profiles/k_count_c2_*_traffic.md), if it was
+    taken on the current kernel source and the same kernel variant; else None."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "k_count_c2_traffic.json")
     try:
-        rec = json.load(open(path))
         src = open(os.path.join(ROOT, "paper_2301_12557_amd", "csrc", "count.hip"), "rb").read()
-        if rec.get("count_hip_sha256_16") != hashlib.sha256(src).hexdigest()[:16]:
-            return None
-        if rec.get("variant") != kernel_variant:
-            return None
-        return float(rec["hbm_bytes_per_launch"])
+        digest = hashlib.sha256(src).hexdigest()[:16]
+        pdir = os.path.join(ROOT, "profiles")
+        for fn in sorted(os.listdir(pdir)):
+            if not fn.endswith("_traffic.md"):
+                continue
+            for line in open(os.path.join(pdir, fn)):
+                if line.startswith("traffic-record:"):
+                    rec = json.loads(line.split(":", 1)[1])
+                    if rec.get("variant") == kernel_variant and rec.get("count_hip_sha256_16") == digest:
+                        return float(rec["hbm_bytes_per_launch"])
     except Exception:
         return None
+    return None
 
 
 def cpu_baseline(w, target_s):
@@ -99,6 +110,179 @@ def cpu_baseline(w, target_s):
                       f"{len(x)} points: {int(c.sum())} in-range pairs in {dt:.2f} s"}
 
 
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def _sync_time(fn):
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3, r
+
+
+def record_timings(fcfc, x, kind, e1, e2, box, ks):
+    """Per-item features and log2 times of counts of x at each cells-per-radius k."""
+    import torch
+    feats, ts = [], []
+    for k in ks:
+        plan = fcfc.Plan(kind, e1, e2, box=box, n_hint=len(x), cells_per_rmax=k, record_timing=1)
+        c = plan.build_cells(x)
+        plan.count(c)
+        f, t = plan.timings()
+        feats.append(f)
+        ts.append(t)
+        c.close()
+        plan.close()
+    return torch.cat(feats), torch.cat(ts)
+
+
+def train_cost_model(fcfc, synth, x_c2, w_c2, mocks):
+    """Train the cost model on item timings of the C2 catalogue (k = 2..4) and of
+    four C4 mocks (smallest, largest, two others; k = 1..5)."""
+    import torch
+    feats, ts, src = [], [], []
+    f, t = record_timings(fcfc, x_c2, "smu", w_c2["edges1"], w_c2["edges2"], w_c2["box"], [2, 3, 4])
+    feats.append(f)
+    ts.append(t)
+    src.append(f"C2 k=2..4: {len(t)} items")
+    sizes = [len(m) for m in mocks]
+    pick = sorted({int(np.argmin(sizes)), int(np.argmax(sizes)), 0, 1})
+    e1, e2 = synth.linear_edges(0, 200, 40), synth.mu_edges(100)
+    for m in pick:
+        f, t = record_timings(fcfc, mocks[m], "smu", e1, e2, 1000.0, [1, 2, 3, 4, 5])
+        feats.append(f)
+        ts.append(t)
+        src.append(f"C4 mock {m} (N={sizes[m]}) k=1..5: {len(t)} items")
+    F, T = torch.cat(feats), torch.cat(ts)
+    md = fcfc.Model(seed=2301)
+    ms, loss = _sync_time(lambda: md.train(F, T, epochs=6, batch=512, lr=2e-3, seed=7))
+    return md, {"samples": int(len(T)), "epochs": 6, "batch": 512, "lr": 2e-3, "final_loss": loss,
+                "train_s": ms / 1e3, "sources": src}
+
+
+def make_mocks(synth, nmock):
+    sizes = synth.mock_sizes(nmock)
+    return [synth.lognormal_box_torch(int(n), 1000.0, synth.MOCK_SEED_BASE + m, device="cuda")
+            for m, n in enumerate(sizes)]
+
+
+def c4_section(fcfc, synth, mocks, model, repeats):
+    """Catalogues/s of 200 C4 mocks: plain per-catalogue launches (P), the batched
+    pipeline in a HIP graph (B), and the batched pipeline with the tuning that the
+    autotuner picks with the learned model proposing (BL).  Every arm's histograms
+    must equal P's."""
+    import torch
+    e1, e2 = synth.linear_edges(0, 200, 40), synth.mu_edges(100)
+    nm = len(mocks)
+    sizes = [len(m) for m in mocks]
+    nhint = int(np.mean(sizes))
+    nb = 40 * 100
+    plan = fcfc.Plan("smu", e1, e2, box=1000.0, n_hint=nhint)
+    outP = torch.empty(nm * nb, dtype=torch.int64, device="cuda")
+
+    def run_plain():
+        for i, x in enumerate(mocks):
+            c = plan.build_cells(x)
+            plan.count(c, out=outP[i * nb:(i + 1) * nb])
+            c.close()
+
+    run_plain()
+    tP = [_sync_time(run_plain)[0] for _ in range(repeats)]
+    st = plan.stats()
+
+    def batch_arm(pl):
+        out = torch.empty(nm * nb, dtype=torch.int64, device="cuda")
+        create_ms, b = _sync_time(lambda: fcfc.Batch(pl, [(x, None) for x in mocks]))
+        first_ms, _ = _sync_time(lambda: b.run(out, use_graph=True))
+        b.check()
+        ts = []
+        for _ in range(repeats):
+            ms, _ = _sync_time(lambda: b.run(out, use_graph=True))
+            ts.append(ms)
+        n_items, gpu_ms = b.check()
+        equal = bool(torch.equal(out, outP))
+        b.close()
+        return ts, create_ms, first_ms, n_items, equal
+
+    tB, cB, fB, iB, eqB = batch_arm(plan)
+    med = int(np.argsort(sizes)[nm // 2])
+    tune_ms, tuned = _sync_time(lambda: fcfc.autotune(mocks[med], model=model, kind="smu", edges1=e1, edges2=e2,
+                                                      box=1000.0, n_hint=nhint))
+    tk = {k: v for k, v in tuned[0].items() if k not in ("record_timing", "order")}
+    planL = fcfc.Plan("smu", e1, e2, box=1000.0, **tk)
+    tL, cL, fL, iL, eqL = batch_arm(planL)
+
+    def arm(ts, extra=None):
+        ts = np.asarray(ts)
+        r = {"mocks_per_s": nm / (ts.mean() / 1e3), "mocks_per_s_sd": float(np.std(nm / (ts / 1e3))),
+             "ms_mean": float(ts.mean()), "ms_sd": float(ts.std()), "runs": len(ts)}
+        if extra:
+            r.update(extra)
+        return r
+
+    return {
+        "workload": f"C4: {nm} periodic L=1000 lognormal mocks, N uniform in [100k, 500k] "
+                    f"(total {sum(sizes)} points), (s,mu) 40x100 bins s in [0,200), LOS z, auto, int64",
+        "arms": {
+            "P": arm(tP, {"what": "per-catalogue build + count launches on one stream, analytic tuning",
+                          "cells_per_rmax": st["cells_per_rmax"]}),
+            "B": arm(tB, {"what": "batched pipeline replayed from a HIP graph, analytic tuning",
+                          "create_ms": cB, "first_run_ms": fB, "items": iB, "counts_equal_P": eqB}),
+            "BL": arm(tL, {"what": "batched pipeline (HIP graph) with the autotuned tuning, cell sizes proposed by "
+                                   "the learned model, tuned on the median-size mock",
+                           "tuning": tk, "autotune_ms": tune_ms, "autotune_trials": tuned[3],
+                           "create_ms": cL, "first_run_ms": fL, "items": iL, "counts_equal_P": eqL}),
+        },
+        "BL_over_P": float(np.mean(tP) / np.mean(tL)),
+        "B_over_P": float(np.mean(tP) / np.mean(tB)),
+        "BL_over_B": float(np.mean(tB) / np.mean(tL)),
+    }
+
+
+def c5_section(fcfc, synth, model):
+    """Held-out C5 (not in the training set): the analytic cell size vs the model's
+    choice vs the autotuned tuning, build + count time (best of 3) and kernel time."""
+    e = synth.log_edges(0.1, 50.0, 50)
+    x = synth.lognormal_box_torch(10_000_000, 3000.0, synth.config_seed(5), device="cuda")
+
+    def measure(reps=3, mdl=None, **tune):
+        tune.setdefault("n_hint", len(x))
+        plan = fcfc.Plan("s", e, None, box=3000.0, **tune)
+        if mdl is not None:
+            plan.set_model(mdl)
+        best, kern = np.inf, np.inf
+        for _ in range(reps):
+            def go():
+                c = plan.build_cells(x)
+                plan.count(c)
+                return c
+            ms, c = _sync_time(go)
+            c.close()
+            best = min(best, ms)
+            kern = min(kern, plan.stats()["kernel_ms"])
+        st = plan.stats()
+        plan.close()
+        return {"ms": best, "kernel_ms": kern, "cells_per_rmax": st["cells_per_rmax"], "order": st["order_used"]}
+
+    kh, _ = fcfc.choose_cells(x, model=None, kind="s", edges1=e, box=3000.0)
+    kl, pred = fcfc.choose_cells(x, model=model, kind="s", edges1=e, box=3000.0)
+    tmsec, tuned = _sync_time(lambda: fcfc.autotune(x, model=model, kind="s", edges1=e, box=3000.0))
+    tk = {k: v for k, v in tuned[0].items() if k != "record_timing"}
+    res = {
+        "workload": "C5: periodic L=3000, 10,000,000 lognormal points (GPU generator), 50 log s bins [0.1,50), auto",
+        "analytic": measure(),
+        "learned_k": dict(measure(cells_per_rmax=kl), predicted_ms_by_k=pred),
+        "learned_order": measure(order="learned", mdl=model),
+        "autotuned": dict(measure(mdl=model, **tk), tuning=tk, autotune_ms=tmsec, trials=tuned[3]),
+    }
+    res["learned_k_gain"] = res["analytic"]["ms"] / res["learned_k"]["ms"]
+    res["autotuned_gain"] = res["analytic"]["ms"] / res["autotuned"]["ms"]
+    return res
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -107,6 +291,13 @@ def main():
     import torch
     from paper_2301_12557_amd import fcfc
 
+    if args.copy_mib > 0:
+        n = args.copy_mib * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     weighted = not args.unweighted
     w, desc = workload(args.workload, weighted)
     weighted = weighted and w["w1"] is not None
@@ -132,6 +323,7 @@ def main():
 
     for _ in range(args.warmup):
         step()
+    log(f"{args.workload}: warmup done")
     torch.cuda.synchronize()
     kms = []
     stats = None
@@ -177,7 +369,28 @@ def main():
                    "wg_per_cu": stats["wg_per_cu"], "lut_entries": stats["lut_entries"],
                    "band_d2_rel": stats["band_d2_rel"], "device": torch.cuda.get_device_name(0)},
     }
+    if not (args.no_c4 and args.no_learned):
+        from paper_2301_12557_amd import synth
+        mocks = make_mocks(synth, args.c4_mocks)
+        log(f"generated {len(mocks)} C4 mocks")
+        model, train = (None, None)
+        if not args.no_learned:
+            w2 = w if args.workload == "c2" else synth.workload(2)
+            x2 = x if args.workload == "c2" else torch.from_numpy(w2["x1"]).to(dev)
+            model, train = train_cost_model(fcfc, synth, x2, w2, mocks)
+            res["learned"] = {"training": train}
+            log(f"cost model trained on {train['samples']} items, loss {train['final_loss']:.3f}")
+        if not args.no_c4:
+            res["c4"] = c4_section(fcfc, synth, mocks, model, args.c4_repeats)
+            log(f"C4 mocks/s: P {res['c4']['arms']['P']['mocks_per_s']:.1f} B {res['c4']['arms']['B']['mocks_per_s']:.1f}"
+                f" BL {res['c4']['arms']['BL']['mocks_per_s']:.1f}")
+        del mocks
+        torch.cuda.empty_cache()
+        if not args.no_learned:
+            res["learned"]["c5_heldout"] = c5_section(fcfc, synth, model)
+            log("C5 held-out comparison done")
     if not args.no_cpu_baseline:
+        log("timing the CPU oracle")
         res["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
     print(json.dumps(res), flush=True)
 

@@ -324,6 +324,18 @@ fcfc_status fcfc_autotune(fcfc_model_t model, int32_t kind, int32_t los, const d
                           int32_t weighted, const char *cache_path, void *stream, fcfc_tuning *best,
                           double *best_ms, double *heuristic_ms, int32_t *trials);
 
+/*
+ * fcfc_diag_transcendental -- measure, over every FP32 input in [2^-64, 2^64)
+ * (a range holding every squared separation and |l|^2 the kernel can form),
+ * the largest relative error of the hardware reciprocal square root and
+ * reciprocal used for mu (Sect. 2.5) and the mid-point pi, against the FP64
+ * value of the exact function.  *assumed gets the bound the FP32 error bands
+ * are built with; the bands are sound only if both measured values stay below
+ * it.  Synchronises `stream`.  Errors: FCFC_EINVAL, FCFC_EHIP.
+ */
+fcfc_status fcfc_diag_transcendental(double *rsq_max_rel, double *rcp_max_rel, double *assumed,
+                                     void *stream);
+
 const char *fcfc_status_str(fcfc_status s);
 const char *fcfc_last_error(void);
 int32_t fcfc_version(void);

@@ -154,6 +154,8 @@ fcfc_status build_cells(Plan* p, const fcfc_catalog* cat, hipStream_t st, Cells*
 fcfc_status fit_bounds(Plan* p, const fcfc_catalog* cats, int ncat, hipStream_t st);
 void fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t st);
 void fill_u64(uint64_t* p, uint64_t v, int64_t n, hipStream_t st);
+// relative error bound assumed for the hardware FP32 rsq and rcp (plan.cpp)
+double trans_rel_bound();
 
 // batched build (build.hip)
 struct CatDesc {

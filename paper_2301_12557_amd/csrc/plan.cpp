@@ -32,6 +32,7 @@ static const double U32 = 5.9604644775390625e-08;  // 2^-24, FP32 unit round-off
 // root (v_rcp_f32, v_rsq_f32); a GPU test measures the true maximum over the
 // inputs the kernels use and checks it stays below this.
 static const double TRANS_REL = 4.0 * 1.1920928955078125e-07;
+double trans_rel_bound() { return TRANS_REL; }
 
 static std::atomic<uint64_t> g_plan_id{1};
 

@@ -96,6 +96,7 @@ SIGNATURES = [
                              ctypes.POINTER(Catalog), ctypes.POINTER(Catalog), _I32, ctypes.c_char_p, _P,
                              ctypes.POINTER(Tuning), ctypes.POINTER(_D), ctypes.POINTER(_D),
                              ctypes.POINTER(_I32)]),
+    ("fcfc_diag_transcendental", _I32, [ctypes.POINTER(_D), ctypes.POINTER(_D), ctypes.POINTER(_D), _P]),
     ("fcfc_status_str", ctypes.c_char_p, [_I32]),
     ("fcfc_last_error", ctypes.c_char_p, []),
     ("fcfc_version", _I32, []),
@@ -407,6 +408,13 @@ def choose_cells(x1, x2=None, *, model=None, kind="s", edges1, edges2=None, los=
                                    ctypes.byref(c1), ctypes.byref(c2) if c2 is not None else None,
                                    _stream_ptr(stream), ctypes.byref(k), pred))
     return k.value, list(pred)
+
+
+def diag_transcendental(stream=None):
+    """(measured max relative error of rsq, of rcp, the bound the error bands assume)."""
+    a, b, c = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    check(load().fcfc_diag_transcendental(ctypes.byref(a), ctypes.byref(b), ctypes.byref(c), _stream_ptr(stream)))
+    return a.value, b.value, c.value
 
 
 TUNING_KEYS = ("cells_per_rmax", "tile_points", "seg_cells", "b_chunk", "hist_copies", "order",

@@ -229,3 +229,12 @@ def test_errors_on_device_data():
     with pytest.raises(fcfc.FcfcError) as ei:
         p2.count(c1)
     assert ei.value.name == "FCFC_EGRID"
+
+
+def test_hardware_rsq_rcp_within_band_bound():
+    """The FP32 mu and mid-point pi bands assume a relative error bound for the
+    hardware rsq and rcp; measured over every FP32 input in [2^-64, 2^64)."""
+    from paper_2301_12557_amd import fcfc
+    rs, rc, bound = fcfc.diag_transcendental()
+    note(f"max rel error rsq {rs:.3e} rcp {rc:.3e} (bands assume {bound:.3e})")
+    assert 0 < rs <= bound and 0 < rc <= bound
