@@ -118,7 +118,7 @@ struct Smem {
     unsigned long long* wlo;
     unsigned long long* whi;
     float4* q;        // this wave's compaction queue
-    double* qw;       // this wave's queued weight products
+    double* aw;       // this wave's A point weights, by tile slot
     uint32_t* rb;     // this wave's recheck entries (a, b, item)
     float4* astage;   // this wave's A points in absolute FP32 (mid-point line of sight)
     unsigned long long* misc;
@@ -302,11 +302,13 @@ struct WaveCtx {
 };
 
 // Bin `cnt` queued in-range pairs (entries base .. base+cnt-1), one per lane.
-// Entry: (v1, v2, v3, ids) with ids = (b - b_begin) << 7 | a_slot, and
+// Entry: (v1, v2, ids) with ids = (b - b_begin) << 7 | a_slot, and
 //   s:              v1 = d2
 //   (s,mu), z:      v1 = d2, v2 = dz
 //   (sp,pi), z:     v1 = sp2, v2 = pi2
-//   mid-point:      v1, v2, v3 = dx, dy, dz (line of sight from the staged A point)
+//   mid-point:      (dx, dy, dz, ids) (line of sight from the staged A point)
+// Weighted pairs take the A weight from the wave's staged weights and the B
+// weight from memory.
 // The common path is branch-free; hot table entries and rechecks take
 // wave-uniform branches that are rarely entered.
 template <int KIND, int LOS, bool W>
@@ -316,7 +318,12 @@ __device__ __attribute__((always_inline)) inline void bin_queue(ArgsRef a, const
     const bool valid = lane < cnt;
     float4 e = make_float4(0.f, 0.f, 0.f, 0.f);
     if (valid) e = s.q[base + lane];
-    const uint32_t ids = __float_as_uint(e.w);
+    // entry (v1, v2, ids) or, mid-point, (dx, dy, dz, ids)
+    constexpr bool MIDQ = (LOS == FCFC_LOS_MIDPOINT && KIND != FCFC_BIN_S);
+    const uint32_t ids = __float_as_uint(MIDQ ? e.w : e.z);
+    // the B weight of the pair, fetched early (product formed only for pairs in range)
+    double wb = 0.0;
+    if (W && valid) wb = a.wB[c.b_begin + (ids >> 7)];
     bool amb = false;
     int flat;
     if (KIND == FCFC_BIN_S) {
@@ -390,7 +397,7 @@ __device__ __attribute__((always_inline)) inline void bin_queue(ArgsRef a, const
     amb = amb & valid;
     if (valid & !amb & (flat >= 0)) {
         atomicAdd(&hist_l[flat], 1u);
-        if (W) add_weight(s, flat, s.qw[base + lane], k.wscale);
+        if (W) add_weight(s, flat, s.aw[ids & 127u] * wb, k.wscale);
     }
     const uint64_t m = __builtin_amdgcn_ballot_w64(amb);
     if (m) {
@@ -428,7 +435,7 @@ __global__ __launch_bounds__(CT_MAX) void k_count(const CountArgs* argp) {
     s.wlo = (unsigned long long*)(smem + a.off_whist);
     s.whi = s.wlo + a.nbins;
     s.q = (float4*)(smem + a.off_q) + (size_t)wave * (QCAP + 1);
-    s.qw = (double*)(smem + a.off_qw) + (size_t)wave * (QCAP + 1);
+    s.aw = (double*)(smem + a.off_qw) + (size_t)wave * ASTAGE;
     s.rb = (uint32_t*)(smem + a.off_rb) + (size_t)wave * RB_CAP * 3;
     s.astage = (float4*)(smem + a.off_astage) + (size_t)wave * ASTAGE;
     s.misc = (unsigned long long*)(smem + a.off_misc);
@@ -613,7 +620,6 @@ __global__ __launch_bounds__(CT_MAX) void k_count(const CountArgs* argp) {
         const float Dy = (float)idy * k.side32;
         const float Dz = (float)idz * k.side32;
         float ax[P], ay[P], az[P];
-        double wa[P];
         int acx[P];
         uint32_t aidx[P], ids_lane[P];
 #pragma unroll
@@ -630,7 +636,7 @@ __global__ __launch_bounds__(CT_MAX) void k_count(const CountArgs* argp) {
                 const float4 q = cur.aabs[p];
                 s.astage[i] = make_float4(2.0f * q.x, 2.0f * q.y, 2.0f * q.z, 0.f);
             }
-            if (W) wa[p] = cur.aw[p];
+            if (W) s.aw[i] = cur.aw[p];
         }
         int qn = 0;
         int xu = xb0;
@@ -648,14 +654,11 @@ __global__ __launch_bounds__(CT_MAX) void k_count(const CountArgs* argp) {
                 auto cell_loop = [&](auto mask_tag) __attribute__((always_inline)) {
                     constexpr bool MASK = decltype(mask_tag)::value;
                     float4 nb = ldc_f4(a.posB, j);
-                    double nw = W ? ldc_f64(a.wB, j) : 0.0;
                     for (; j < cell_end; j++) {
                         const float4 b = nb;
-                        const double wb = nw;
                         const uint32_t jbits = (j - b_begin) << 7;
                         // prefetch the next B point (arrays carry padding past the last point)
                         nb = ldc_f4(a.posB, j + 1);
-                        if (W) nw = ldc_f64(a.wB, j + 1);
 #pragma unroll
                         for (int p = 0; p < P; p++) {
                             const float dx = b.x - axx[p];
@@ -681,10 +684,20 @@ __global__ __launch_bounds__(CT_MAX) void k_count(const CountArgs* argp) {
                             }
                             if (MASK) in = in & (j > aidx[p]);
                             const uint64_t m = __builtin_amdgcn_ballot_w64(in);
-                            // every lane writes; lanes out of range write the dump entry QCAP
-                            const int slot = in ? qn + (int)lane_prefix(m) : QCAP;
-                            s.q[slot] = make_float4(v1, v2, v3, __uint_as_float(jbits | ids_lane[p]));
-                            if (W) s.qw[slot] = wa[p] * wb;
+                            // queue position of every lane (qn + lanes below in the mask);
+                            // lanes out of range write the dump entry QCAP
+                            const uint32_t pre = __builtin_amdgcn_mbcnt_hi(
+                                (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, (uint32_t)qn));
+                            const uint32_t slot = in ? pre : (uint32_t)QCAP;
+                            const float idf = __uint_as_float(jbits | ids_lane[p]);
+                            if (LOS == FCFC_LOS_MIDPOINT && KIND != FCFC_BIN_S) {
+                                s.q[slot] = make_float4(v1, v2, v3, idf);
+                            } else {
+                                float* qe = (float*)(s.q + slot);
+                                qe[0] = v1;
+                                qe[1] = v2;
+                                qe[2] = idf;
+                            }
                             qn += (int)__popcll(m);
                         }
                         while (qn >= 64) {
@@ -907,7 +920,7 @@ static fcfc_status setup_launch(Plan* p, bool is_auto, bool weighted, bool batch
     off += weighted ? al16(p->nbins * 16) : 0;
     const int shared_bytes = off;
     const bool mid = (p->los == FCFC_LOS_MIDPOINT && p->kind != FCFC_BIN_S);
-    const int per_wave = (QCAP + 1) * 16 + (weighted ? (QCAP + 1) * 8 : 0) + RB_CAP * 12 + (mid ? ASTAGE * 16 : 0);
+    const int per_wave = (QCAP + 1) * 16 + (weighted ? ASTAGE * 8 : 0) + RB_CAP * 12 + (mid ? ASTAGE * 16 : 0);
     int dev = 0, maxlds = 65536;
     FCFC_HIP(hipGetDevice(&dev));
     if (hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) maxlds = 65536;
@@ -922,7 +935,7 @@ static fcfc_status setup_launch(Plan* p, bool is_auto, bool weighted, bool batch
     a.off_q = off;
     off += L.waves * (QCAP + 1) * 16;
     a.off_qw = off;
-    off += weighted ? L.waves * (QCAP + 1) * 8 : 0;
+    off += weighted ? L.waves * ASTAGE * 8 : 0;
     a.off_rb = off;
     off += L.waves * RB_CAP * 12;
     a.off_astage = off;
