@@ -70,8 +70,8 @@ struct CountArgs {
     const Item* items;
     const uint32_t* nitems_dev;
     uint32_t* cursor;
-    const uint16_t* lut1;
-    const uint16_t* lut2;
+    const int16_t* lut1;
+    const int16_t* lut2;
     const float* band1;  // lo[0..n1], hi[0..n1]
     const float* band2;
     const double* E1;    // FP64 squared edges
@@ -90,6 +90,7 @@ struct CountArgs {
     float mu_n, tolA, tolB, tolC;
     int mu_top_closed;
     double wscale;
+    int wpre;  // 1: staged A weights carry the scale 2^S (see prescale_ok)
     int copies;
     // batched mode: chunks of items per catalogue
     const uint32_t* nchunks_dev;
@@ -110,8 +111,8 @@ struct CountArgs {
 typedef const CountArgs FCFC_CONST& ArgsRef;
 
 struct Smem {
-    const uint16_t* lut1;
-    const uint16_t* lut2;
+    const int16_t* lut1;
+    const int16_t* lut2;
     const float* band1;
     const float* band2;
     uint32_t* hist;
@@ -223,22 +224,22 @@ __device__ int exact_bin(ArgsRef a, double ax, double ay, double az, double bx, 
 // ---------------------------------------------------------------------------
 // FP32 look-up with bands: returns bin (>= 0), -1 (out of range) or sets amb.
 // ---------------------------------------------------------------------------
-__device__ inline uint32_t lut_entry(const uint16_t* __restrict__ lut, float scale, float v) {
-    return lut[(uint32_t)(v * scale)];
+__device__ inline int lut_entry(const int16_t* __restrict__ lut, float scale, float v) {
+    return (int)lut[(uint32_t)(v * scale)];
 }
-// A clean entry holds the bin, or 0x7fff for "out of range".
-__device__ inline int lut_clean_bin(uint32_t e) { return (e == 0x7fffu) ? -1 : (int)e; }
-// A hot entry (bit 15) holds the first edge whose band meets the entry: count the
-// edges certainly <= v (reverse-free forward traversal over the few banded
-// edges) and flag v inside a band as ambiguous.
-__device__ inline int lut_hot_bin(const float* __restrict__ band, int n, uint32_t e, float v, bool& amb) {
-    int k = (int)(e & 0x7fffu);
+// A clean entry (>= -1) is the bin itself, -1 meaning out of range.  A hot
+// entry (<= -2) holds -2 - k, k the first edge whose band meets the entry:
+// count the edges certainly <= v by a forward traversal over the few banded
+// edges.  Returns the bin, -1 (out of range) or -2 (v inside a band: the pair
+// needs the FP64 recheck).
+__device__ inline int lut_hot_bin(const float* __restrict__ band, int n, int e, float v) {
+    int k = -2 - e;
     int c = k;
     for (; k <= n; k++) {
         if (v >= band[n + 1 + k]) {
             c = k + 1;
         } else {
-            if (v >= band[k]) amb = true;
+            if (v >= band[k]) return -2;
             break;
         }
     }
@@ -250,10 +251,12 @@ struct KConst {
     float scale1, scale2, vmax1, vmax2, r2prune, d2small, mu_n, mu_nm1, tolA, tolB, tolC, side32;
     int n1, n2, nbins, nx, copies;
     double wscale;
+    int wpre;
 };
 
-__device__ inline void add_weight(const Smem& s, int flat, double p, double wscale) {
-    long long t = (long long)(p * wscale);
+// q: the pair weight times 2^S, an integer below 2^62 in magnitude
+__device__ inline void add_weight(const Smem& s, int flat, double q) {
+    long long t = (long long)q;
     unsigned long long lo = (unsigned long long)(uint32_t)(t & 0xffffffffll);
     unsigned long long hi = (unsigned long long)(t >> 32);
     atomicAdd(&s.wlo[flat], lo);
@@ -278,7 +281,7 @@ __device__ __attribute__((always_inline)) inline void process_rechecks(ArgsRef a
             atomicAdd(&s.hist[flat], 1u);
             if (W) {
                 double p = a.wA[ia] * a.wB[ib];
-                add_weight(s, flat, p, a.wscale);
+                add_weight(s, flat, p * a.wscale);
             }
         }
     }
@@ -328,12 +331,12 @@ __device__ __attribute__((always_inline)) inline void bin_queue(ArgsRef a, const
     int flat;
     if (KIND == FCFC_BIN_S) {
         const float d2 = e.x;
-        const uint32_t ent = lut_entry(s.lut1, k.scale1, d2);
-        int sb = lut_clean_bin(ent);
-        const bool hot = (ent & 0x8000u) != 0u;
+        int sb = lut_entry(s.lut1, k.scale1, d2);
+        const bool hot = sb < -1;
         if (__builtin_amdgcn_ballot_w64(hot)) {
-            if (hot) sb = lut_hot_bin(s.band1, k.n1, ent, d2, amb);
+            if (hot) sb = lut_hot_bin(s.band1, k.n1, sb, d2);
         }
+        amb = sb == -2;
         flat = sb;
     } else if (KIND == FCFC_BIN_S_MU) {
         float d2, proj_n;  // proj_n: |projection on the line of sight| * n_mu / |l|
@@ -349,11 +352,10 @@ __device__ __attribute__((always_inline)) inline void bin_queue(ArgsRef a, const
             const float ll = __builtin_fmaf(lz, lz, __builtin_fmaf(ly, ly, lx * lx));
             proj_n = fabsf(dot) * (__builtin_amdgcn_rsqf(ll) * k.mu_n);
         }
-        const uint32_t ent = lut_entry(s.lut1, k.scale1, d2);
-        int sb = lut_clean_bin(ent);
-        const bool hot = (ent & 0x8000u) != 0u;
+        int sb = lut_entry(s.lut1, k.scale1, d2);
+        const bool hot = sb < -1;
         if (__builtin_amdgcn_ballot_w64(hot)) {
-            if (hot) sb = lut_hot_bin(s.band1, k.n1, ent, d2, amb);
+            if (hot) sb = lut_hot_bin(s.band1, k.n1, sb, d2);
         }
         const float rs = __builtin_amdgcn_rsqf(d2);
         const float mun = proj_n * rs;
@@ -362,7 +364,7 @@ __device__ __attribute__((always_inline)) inline void bin_queue(ArgsRef a, const
         const float dist = fabsf(mun - cr);
         const float tol = __builtin_fmaf(__builtin_fmaf(k.tolB, rs, k.tolA), rs, k.tolC);
         const bool near_edge = (dist < tol) & (cr >= 1.0f) & (cr <= k.mu_nm1);
-        amb = amb | near_edge | (d2 < k.d2small);
+        amb = (sb == -2) | near_edge | (d2 < k.d2small);
         flat = (sb >= 0) ? (int)__umul24((uint32_t)sb, (uint32_t)k.n2) + mb : -1;
     } else {
         float sp2, pi2;
@@ -383,21 +385,25 @@ __device__ __attribute__((always_inline)) inline void bin_queue(ArgsRef a, const
         const bool inr = (sp2 < k.vmax1) & (pi2 < k.vmax2);
         const float sp2c = inr ? sp2 : 0.0f;
         const float pi2c = inr ? pi2 : 0.0f;
-        const uint32_t e1 = lut_entry(s.lut1, k.scale1, sp2c);
-        const uint32_t e2 = lut_entry(s.lut2, k.scale2, pi2c);
-        int b1 = lut_clean_bin(e1), b2 = lut_clean_bin(e2);
-        const bool hot1 = (e1 & 0x8000u) != 0u, hot2 = (e2 & 0x8000u) != 0u;
+        int b1 = lut_entry(s.lut1, k.scale1, sp2c);
+        int b2 = lut_entry(s.lut2, k.scale2, pi2c);
+        const bool hot1 = b1 < -1, hot2 = b2 < -1;
         if (__builtin_amdgcn_ballot_w64(hot1 | hot2)) {
-            if (hot1) b1 = lut_hot_bin(s.band1, k.n1, e1, sp2c, amb);
-            if (hot2) b2 = lut_hot_bin(s.band2, k.n2, e2, pi2c, amb);
+            if (hot1) b1 = lut_hot_bin(s.band1, k.n1, b1, sp2c);
+            if (hot2) b2 = lut_hot_bin(s.band2, k.n2, b2, pi2c);
         }
-        amb = amb & inr;
+        amb = ((b1 == -2) | (b2 == -2)) & inr;
         flat = (inr & (b1 >= 0) & (b2 >= 0)) ? (int)__umul24((uint32_t)b1, (uint32_t)k.n2) + b2 : -1;
     }
     amb = amb & valid;
     if (valid & !amb & (flat >= 0)) {
         atomicAdd(&hist_l[flat], 1u);
-        if (W) add_weight(s, flat, s.aw[ids & 127u] * wb, k.wscale);
+        if (W) {
+            // fl(wa * 2^S * wb) == fl(wa * wb) * 2^S when nothing overflows or
+            // underflows, which the host checked before setting wpre
+            const double q = s.aw[ids & 127u] * wb;
+            add_weight(s, flat, k.wpre ? q : q * k.wscale);
+        }
     }
     const uint64_t m = __builtin_amdgcn_ballot_w64(amb);
     if (m) {
@@ -427,8 +433,8 @@ __global__ __launch_bounds__(CT_MAX) void k_count(const CountArgs* argp) {
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     Smem s;
-    s.lut1 = (const uint16_t*)(smem + a.off_lut1);
-    s.lut2 = (const uint16_t*)(smem + a.off_lut2);
+    s.lut1 = (const int16_t*)(smem + a.off_lut1);
+    s.lut2 = (const int16_t*)(smem + a.off_lut2);
     s.band1 = (const float*)(smem + a.off_band1);
     s.band2 = (const float*)(smem + a.off_band2);
     s.hist = (uint32_t*)(smem + a.off_hist);
@@ -482,6 +488,7 @@ __global__ __launch_bounds__(CT_MAX) void k_count(const CountArgs* argp) {
     k.nx = a.nx;
     k.copies = a.copies;
     k.wscale = a.wscale;
+    k.wpre = a.wpre;
     uint32_t* hist_l = s.hist + (size_t)(lane % k.copies) * k.nbins;
     WaveCtx c;
     c.rcount = 0;
@@ -636,7 +643,7 @@ __global__ __launch_bounds__(CT_MAX) void k_count(const CountArgs* argp) {
                 const float4 q = cur.aabs[p];
                 s.astage[i] = make_float4(2.0f * q.x, 2.0f * q.y, 2.0f * q.z, 0.f);
             }
-            if (W) s.aw[i] = cur.aw[p];
+            if (W) s.aw[i] = k.wpre ? cur.aw[p] * k.wscale : cur.aw[p];
         }
         int qn = 0;
         int xu = xb0;
@@ -869,6 +876,16 @@ struct LaunchSetup {
 };
 
 // Common fixed-point scale 2^S making every weight product an integer.
+// Whether A weights may carry the scale 2^S before the product is formed:
+// fl(wa 2^S wb) equals fl(wa wb) 2^S exactly when wa 2^S, wa wb and the scaled
+// product all stay normal and finite.
+static int prescale_ok(double wminA, double wmaxA, double wminB, double wmaxB, int S) {
+    if (!(wminA > 0) || !(wminB > 0)) return 0;
+    const double lo = ldexp(1.0, -1000), hi = ldexp(1.0, 1000);
+    const double s = ldexp(1.0, S);
+    return (wminA * wminB >= lo && wmaxA * s < hi && wminA * s >= lo && wmaxA * wmaxB * s < hi) ? 1 : 0;
+}
+
 static fcfc_status weight_scale(double wmin1, double wmax1, double wmin2, double wmax2, int* S) {
     *S = 0;
     if (wmin1 > 0 && wmin2 > 0) {
@@ -1002,9 +1019,9 @@ static fcfc_status setup_launch(Plan* p, bool is_auto, bool weighted, bool batch
 // Point the table pointers of the arguments into the uploaded blob; returns the stencil rows.
 static int4* bind_tables(const LaunchSetup& L, char* tab, CountArgs& a) {
     char* o = tab;
-    a.lut1 = (const uint16_t*)o;
+    a.lut1 = (const int16_t*)o;
     o += L.tb_l1;
-    a.lut2 = (const uint16_t*)o;
+    a.lut2 = (const int16_t*)o;
     o += L.tb_l2;
     a.band1 = (const float*)o;
     o += L.tb_b1;
@@ -1122,6 +1139,7 @@ fcfc_status count_pairs(Plan* p, Cells* c1, Cells* c2, int64_t* d_counts, double
     LaunchSetup L;
     const double ppc = (double)c1->n / std::max<int64_t>(1, g.ncell());
     FCFC_TRY(setup_launch(p, is_auto, weighted, false, ppc, S, L));
+    if (weighted) L.a.wpre = prescale_ok(c1->wmin, c1->wmax, cb->wmin, cb->wmax, S);
     CountArgs& a = L.a;
     const bool sorted = !pr && p->tune.order != FCFC_ORDER_BUILT;
     const Model* model = pr ? pr->model : (p->tune.order == FCFC_ORDER_LEARNED ? p->model : nullptr);
@@ -1334,6 +1352,7 @@ struct BatchImpl {
     int64_t ntot = 0;
     bool weighted = false;
     int S = 0;
+    int wpre = 0;
     LaunchSetup L;
     WLArgs wl;
     int64_t nseg = 0, npair_tr = 0;
@@ -1561,6 +1580,7 @@ fcfc_status batch_create_impl(Plan* p, const fcfc_catalog* cats, int ncat, hipSt
         if (hw[0] != ~0ull) memcpy(&wmin, &hw[0], 8);
         memcpy(&wmax, &hw[1], 8);
         fcfc_status ws = weight_scale(wmin, wmax, wmin, wmax, &b->S);
+        b->wpre = prescale_ok(wmin, wmax, wmin, wmax, b->S);
         if (ws != FCFC_OK) {
             batch_free_impl(b);
             return ws;
@@ -1587,6 +1607,7 @@ fcfc_status batch_create_impl(Plan* p, const fcfc_catalog* cats, int ncat, hipSt
     a.stats = nullptr;
     a.times = nullptr;
     a.wscale = ldexp(1.0, b->S);
+    a.wpre = b->wpre;
     a.nchunks_dev = &b->ctr[3];
     a.chunk_cursor = &b->ctr[4];
     a.chunk_prefix = b->chunk_prefix;

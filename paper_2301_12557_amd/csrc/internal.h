@@ -66,17 +66,19 @@ enum : uint32_t { ITEM_SAMEROW = 1u };
 
 // ---------------------------------------------------------------------------
 // FP32 look-up table over a squared quantity v (Sect. 3.2.3):
-// entry j = (uint)(v * scale) covers [j/scale, (j+1)/scale).  A clean entry
-// holds the bin (or NONE); a hot entry (bit 15) holds the first edge whose
-// error band [lo_k, hi_k) meets the entry.
+// entry j = (uint)(v * scale) covers [j/scale, (j+1)/scale).  Entries are
+// int16: a clean entry holds the bin (>= 0) or LUT_NONE (-1, out of range); a
+// hot entry holds -2 - k with k the first edge whose error band [lo_k, hi_k)
+// meets the entry.
 // ---------------------------------------------------------------------------
-enum : uint16_t { LUT_HOT = 0x8000u, LUT_NONE = 0x7FFFu };
+enum : int16_t { LUT_NONE = -1 };
+inline int16_t lut_hot_code(int k) { return (int16_t)(-2 - k); }
 
 struct Lut1D {
     int n = 0;                 // bins
     std::vector<double> E;     // n+1 squared edges (FP64)
     std::vector<float> lo, hi; // n+1 FP32 band ends: v < lo_k => V < E_k; v >= hi_k => V >= E_k
-    std::vector<uint16_t> tab; // entries
+    std::vector<int16_t> tab;  // entries
     float scale = 1.f;         // power of two
     float vmax = 0.f;          // hi_n: v >= vmax is out of range
     double band_rel = 0;       // widest band half-width relative to its edge

@@ -202,12 +202,12 @@ static fcfc_status build_lut(Lut1D& t, const std::vector<double>& edges, const E
             }
         }
         if (klo >= 0) {
-            t.tab[j] = (uint16_t)(LUT_HOT | (uint16_t)klo);
+            t.tab[j] = lut_hot_code(klo);
         } else {
             int c = 0;
             for (int k = 0; k <= t.n; k++)
                 if ((double)t.hi[k] <= a) c = k + 1;
-            t.tab[j] = (c >= 1 && c <= t.n) ? (uint16_t)(c - 1) : (uint16_t)LUT_NONE;
+            t.tab[j] = (c >= 1 && c <= t.n) ? (int16_t)(c - 1) : (int16_t)LUT_NONE;
         }
     }
     return FCFC_OK;

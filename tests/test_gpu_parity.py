@@ -126,6 +126,21 @@ def test_cross_counts(kind, los, box):
     check_case(f"cross {kind}/{los}/{box}", a, b, kind=kind, los=los, box=box, edges1=e1, edges2=e2, w1=w1, w2=w2)
 
 
+@pytest.mark.parametrize("sa,sb", [(1e300, 1e-300), (1e-300, 1e300), (3.0, 0.25)])
+def test_cross_weights_far_from_one(sa, sb):
+    """Weights of very different magnitudes (pair weights near 1): with A weights
+    near 1e300 the kernel must not pre-scale them by 2^S (that would overflow)
+    and still sum exactly; with B weights near 1e300 it may."""
+    rng = np.random.default_rng(8)
+    a = rng.random((1200, 3)) * 120.0
+    b = rng.random((900, 3)) * 120.0
+    e1 = np.array([0.0, 3.0, 7.5, 12.0, 20.0, 31.0, 45.0])
+    w1 = sa * synth.uniform_weights(len(a), 1.0, 2.0, 3)
+    w2 = sb * synth.uniform_weights(len(b), 1.0, 2.0, 4)
+    check_case(f"cross weights {sa:g}/{sb:g}", a, b, kind="smu", los="z", box=120.0, edges1=e1,
+               edges2=synth.mu_edges(10), w1=w1, w2=w2)
+
+
 def test_empty_and_tiny():
     e = np.array([0.0, 1.0, 2.0, 5.0])
     for n in (0, 1, 2, 3):
