@@ -1047,8 +1047,10 @@ static WLArgs make_wl(const Plan* p, const LaunchSetup& L, bool is_auto, int nca
     w.periodic = g.L > 0;
     w.is_auto = is_auto;
     w.ncat = ncat;
-    int64_t nseg = (int64_t)((g.nx + L.seg - 1) / L.seg) * g.ny * g.nz * ncat;
-    w.tiles_cap = (uint32_t)std::min<int64_t>(nseg + npoints_a / L.T + 1, 0xffffffffLL);
+    // tiles end at `tile` points, at a span of `seg` cells, or at a row end
+    const int64_t nrow = (int64_t)g.ny * g.nz * ncat;
+    w.tiles_cap = (uint32_t)std::min<int64_t>(nrow * ((g.nx + L.seg - 1) / L.seg + 1) + npoints_a / L.T + 1,
+                                              0xffffffffLL);
     return w;
 }
 
@@ -1144,7 +1146,7 @@ fcfc_status count_pairs(Plan* p, Cells* c1, Cells* c2, int64_t* d_counts, double
     const bool sorted = !pr && p->tune.order != FCFC_ORDER_BUILT;
     const Model* model = pr ? pr->model : (p->tune.order == FCFC_ORDER_LEARNED ? p->model : nullptr);
     WLArgs w = make_wl(p, L, is_auto, 1, c1->n);
-    const int64_t nseg = (int64_t)((g.nx + L.seg - 1) / L.seg) * g.ny * g.nz;
+    const int64_t nseg = (int64_t)g.ny * g.nz;  // A rows (tile counts per row)
     const int64_t tiles_cap = w.tiles_cap;
     if (tiles_cap >= 0xffffffffLL / std::max(1, L.nrows)) {
         set_error("count_pairs: work list too large");
@@ -1504,7 +1506,7 @@ fcfc_status batch_create_impl(Plan* p, const fcfc_catalog* cats, int ncat, hipSt
         return s;
     }
     b->wl = make_wl(p, b->L, true, ncat, tot);
-    b->nseg = (int64_t)((g.nx + b->L.seg - 1) / b->L.seg) * g.ny * g.nz * ncat;
+    b->nseg = (int64_t)g.ny * g.nz * ncat;  // A rows
     b->npair_tr = (int64_t)b->wl.tiles_cap * b->wl.nrows;
     if ((int64_t)b->wl.tiles_cap * b->wl.nrows >= 0xffffffffLL) {
         delete b;

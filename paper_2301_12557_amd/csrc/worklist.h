@@ -14,7 +14,7 @@ struct Tile {
 
 struct WLArgs {
     int nx, ny, nz;
-    int seg;        // cells per segment
+    int seg;        // most cells a tile may span
     int tile;       // points per tile
     int bchunk;     // B points per item
     int nrows;      // stencil rows

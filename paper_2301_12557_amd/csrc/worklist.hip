@@ -1,7 +1,7 @@
 // worklist.hip -- enumeration of work items on the GPU.
 //
 // A tile is a run of at most `tile` consecutive sorted points of one A row
-// (fixed cy, cz) whose cells lie in one segment of `seg` consecutive cells.
+// (fixed cy, cz) spanning at most `seg` consecutive cells.
 // For each tile and each row offset (dy, dz) of the pruned stencil, the B
 // cells that can hold a pair in range form the x range [x0 - kx, x1 + kx]
 // of the B row; since cells of a row are consecutive in the sort order their
@@ -24,40 +24,49 @@ __device__ inline int floor_div(int a, int n) {
     return q;
 }
 
+// Tiles of one A row: runs of up to `tile` consecutive sorted points, cut
+// early only where a run would reach into a cell `seg` cells past the cell
+// of its first point.  Calls emit(first point, count, first cell, last cell)
+// in order.
+template <typename F>
+__device__ inline void row_tiles(const uint32_t* __restrict__ csA, int64_t rowcell, const WLArgs& w, F emit) {
+    const uint32_t p1 = csA[rowcell + w.nx];
+    uint32_t a = csA[rowcell];
+    int c = 0;
+    while (a < p1) {
+        while (csA[rowcell + c + 1] <= a) c++;  // cell holding point a
+        const uint32_t lim = csA[rowcell + min(c + w.seg, w.nx)];
+        const uint32_t e = min(min(a + (uint32_t)w.tile, lim), p1);
+        int c2 = c;
+        while (csA[rowcell + c2 + 1] <= e - 1) c2++;  // cell holding the last point
+        emit(a, e - a, c, c2);
+        a = e;
+    }
+}
+
 __global__ void k_tile_count(const uint32_t* __restrict__ csA, WLArgs w, uint32_t* __restrict__ tcount) {
-    int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int nseg_row = (w.nx + w.seg - 1) / w.seg;
-    int64_t nseg = (int64_t)nseg_row * w.ny * w.nz * w.ncat;
-    if (s >= nseg) return;
-    int64_t row = s / nseg_row;
-    int sx = (int)(s % nseg_row);
-    int x0 = sx * w.seg, x1 = min(x0 + w.seg, w.nx) - 1;
-    uint32_t p0 = csA[row * w.nx + x0], p1 = csA[row * w.nx + x1 + 1];
-    tcount[s] = (p1 - p0 + (uint32_t)w.tile - 1) / (uint32_t)w.tile;
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t nrow = (int64_t)w.ny * w.nz * w.ncat;
+    if (r >= nrow) return;
+    uint32_t n = 0;
+    row_tiles(csA, r * w.nx, w, [&](uint32_t, uint32_t, int, int) { n++; });
+    tcount[r] = n;
 }
 
 __global__ void k_tile_write(const uint32_t* __restrict__ csA, const float4* __restrict__ posA, WLArgs w,
                              const uint32_t* __restrict__ toff, Tile* __restrict__ tiles) {
-    int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int nseg_row = (w.nx + w.seg - 1) / w.seg;
-    int64_t nseg = (int64_t)nseg_row * w.ny * w.nz * w.ncat;
-    if (s >= nseg) return;
-    int64_t row = s / nseg_row;
-    int sx = (int)(s % nseg_row);
-    int x0 = sx * w.seg, x1 = min(x0 + w.seg, w.nx) - 1;
-    uint32_t p0 = csA[row * w.nx + x0], p1 = csA[row * w.nx + x1 + 1];
-    uint32_t t = toff[s];
-    for (uint32_t a = p0; a < p1; a += (uint32_t)w.tile, t++) {
-        uint32_t cnt = min((uint32_t)w.tile, p1 - a);
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t nrow = (int64_t)w.ny * w.nz * w.ncat;
+    if (r >= nrow) return;
+    uint32_t t = toff[r];
+    row_tiles(csA, r * w.nx, w, [&](uint32_t a, uint32_t cnt, int cxa, int cxb) {
         Tile tl;
         tl.a_begin = a;
         tl.a_count = cnt;
-        tl.row = (uint32_t)row;
-        int cxa = __float_as_int(posA[a].w);
-        int cxb = __float_as_int(posA[a + cnt - 1].w);
+        tl.row = (uint32_t)r;
         tl.x01 = (uint32_t)(cxa & 0xffff) | ((uint32_t)cxb << 16);
-        tiles[t] = tl;
-    }
+        tiles[t++] = tl;
+    });
 }
 
 // Enumerate the pieces of (tile, stencil row); emit(item) is called for
@@ -179,9 +188,8 @@ __global__ void k_cat_items(const uint32_t* __restrict__ toff, const uint32_t* _
         cat_items[c] = *nitems_dev;
         return;
     }
-    int nseg_row = (w.nx + w.seg - 1) / w.seg;
-    int64_t seg0 = (int64_t)c * nseg_row * w.ny * w.nz;
-    uint32_t t0 = toff[seg0];
+    const int64_t row0 = (int64_t)c * w.ny * w.nz;  // first A row of the catalogue
+    uint32_t t0 = toff[row0];
     cat_items[c] = ioff[(int64_t)t0 * w.nrows];
 }
 
