@@ -660,12 +660,16 @@ __global__ __launch_bounds__(CT_MAX) void k_count(const CountArgs* argp) {
                 for (int p = 0; p < P; p++) axx[p] = ax[p] - (float)(xu - acx[p]) * k.side32;
                 auto cell_loop = [&](auto mask_tag) __attribute__((always_inline)) {
                     constexpr bool MASK = decltype(mask_tag)::value;
-                    float4 nb = ldc_f4(a.posB, j);
-                    for (; j < cell_end; j++) {
-                        const float4 b = nb;
-                        const uint32_t jbits = (j - b_begin) << 7;
+                    // running scalar pointer to the next B point and its queue id bits
+                    const float FCFC_CONST* bp = (const float FCFC_CONST*)a.posB + 4 * (size_t)j;
+                    uint32_t jbits = (j - b_begin) << 7;
+                    float3 nb = make_float3(bp[0], bp[1], bp[2]);
+#pragma unroll 2
+                    for (; j < cell_end; j++, jbits += 128u) {
+                        const float3 b = nb;
                         // prefetch the next B point (arrays carry padding past the last point)
-                        nb = ldc_f4(a.posB, j + 1);
+                        bp += 4;
+                        nb = make_float3(bp[0], bp[1], bp[2]);
 #pragma unroll
                         for (int p = 0; p < P; p++) {
                             const float dx = b.x - axx[p];
