@@ -223,6 +223,70 @@ def test_c2_full_size_sampled():
     assert_same(g, o, what="C2 sample x full")
 
 
+def test_c2_full_size_weighted_sampled():
+    """C2 weighted at full size, as the benchmark counts it: a 2,000-point sample crossed with
+    the whole catalogue, counts and FP64 weighted sums, against the oracle."""
+    w = synth.workload(2, weighted=True)
+    x, wt = w["x1"], w["w1"]
+    kw = dict(kind="smu", edges1=w["edges1"], edges2=w["edges2"], box=w["box"])
+    idx = np.random.default_rng(6).choice(len(x), 2000, replace=False)
+    note("C2 weighted sample x full")
+    g, gw, _ = gpu_count(x[idx], x, w1=wt[idx], w2=wt, **kw)
+    o, ow = oracle_count(x[idx], x, method="grid", w1=wt[idx], w2=wt, **kw)
+    assert_same(g, o, gw, ow, what="C2 weighted sample x full")
+
+
+def test_c3_full_size_sampled():
+    """C3 at full size (2,000,000 data, 40,000,000 randoms, open box, mid-point line of sight,
+    weights): DD of the whole data set satisfies additivity over two halves, and samples of
+    DD and DR (1,000 data points against all data; 40 against all randoms) match the oracle."""
+    w = synth.workload(3, weighted=True)
+    d, r, wd, wr = w["x1"], w["x2"], w["w1"], w["w2"]
+    kw = dict(kind="spi", los="mid", edges1=w["edges1"], edges2=w["edges2"], box=0.0)
+    note("C3 DD full")
+    full, fw, st = gpu_count(d, w1=wd, **kw)
+    assert full.sum() == st["in_range"]
+    h = len(d) // 2
+    note("C3 DD halves")
+    aa, _, _ = gpu_count(d[:h], **kw)
+    bb, _, _ = gpu_count(d[h:], **kw)
+    ab, _, _ = gpu_count(d[:h], d[h:], **kw)
+    assert np.array_equal(aa + bb + ab, full)
+    rng = np.random.default_rng(7)
+    idx = rng.choice(len(d), 1000, replace=False)
+    note("C3 DD sample x full data")
+    g, gw, _ = gpu_count(d[idx], d, w1=wd[idx], w2=wd, **kw)
+    o, ow = oracle_count(d[idx], d, method="grid", w1=wd[idx], w2=wd, **kw)
+    assert_same(g, o, gw, ow, what="C3 DD sample")
+    idx = rng.choice(len(d), 40, replace=False)
+    note("C3 DR sample x full randoms")
+    g, gw, _ = gpu_count(d[idx], r, w1=wd[idx], w2=wr, **kw)
+    o, ow = oracle_count(d[idx], r, method="grid", w1=wd[idx], w2=wr, **kw)
+    assert_same(g, o, gw, ow, what="C3 DR sample")
+
+
+def test_c5_full_size_sampled():
+    """C5 at full size (10,000,000 clustered points, log bins down to s = 0.1): additivity over
+    two halves and a 3,000-point sample against the whole catalogue, checked by the oracle."""
+    w = synth.workload(5)
+    x = w["x1"]
+    kw = dict(kind="s", edges1=w["edges1"], box=w["box"])
+    note("C5 full auto")
+    full, _, st = gpu_count(x, **kw)
+    assert full.sum() == st["in_range"]
+    h = len(x) // 2
+    note("C5 halves")
+    aa, _, _ = gpu_count(x[:h], **kw)
+    bb, _, _ = gpu_count(x[h:], **kw)
+    ab, _, _ = gpu_count(x[:h], x[h:], **kw)
+    assert np.array_equal(aa + bb + ab, full)
+    idx = np.random.default_rng(8).choice(len(x), 3000, replace=False)
+    note("C5 sample x full")
+    g, _, _ = gpu_count(x[idx], x, **kw)
+    o, _ = oracle_count(x[idx], x, method="grid", **kw)
+    assert_same(g, o, what="C5 sample x full")
+
+
 def test_errors_on_device_data():
     import torch
     from paper_2301_12557_amd import fcfc
