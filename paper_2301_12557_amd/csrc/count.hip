@@ -328,6 +328,7 @@ __device__ __attribute__((always_inline)) inline void bin_queue(ArgsRef a, const
     double wb = 0.0;
     if (W && valid) wb = a.wB[c.b_begin + (ids >> 7)];
     bool amb = false;
+    bool okb;  // a bin was found (flat is meaningful)
     int flat;
     if (KIND == FCFC_BIN_S) {
         const float d2 = e.x;
@@ -337,6 +338,7 @@ __device__ __attribute__((always_inline)) inline void bin_queue(ArgsRef a, const
             if (hot) sb = lut_hot_bin(s.band1, k.n1, sb, d2);
         }
         amb = sb == -2;
+        okb = sb >= 0;
         flat = sb;
     } else if (KIND == FCFC_BIN_S_MU) {
         float d2, proj_n;  // proj_n: |projection on the line of sight| * n_mu / |l|
@@ -365,7 +367,8 @@ __device__ __attribute__((always_inline)) inline void bin_queue(ArgsRef a, const
         const float tol = __builtin_fmaf(__builtin_fmaf(k.tolB, rs, k.tolA), rs, k.tolC);
         const bool near_edge = (dist < tol) & (cr >= 1.0f) & (cr <= k.mu_nm1);
         amb = (sb == -2) | near_edge | (d2 < k.d2small);
-        flat = (sb >= 0) ? (int)__umul24((uint32_t)sb, (uint32_t)k.n2) + mb : -1;
+        okb = sb >= 0;
+        flat = (int)__umul24((uint32_t)sb, (uint32_t)k.n2) + mb;
     } else {
         float sp2, pi2;
         if (LOS == FCFC_LOS_Z) {
@@ -393,10 +396,12 @@ __device__ __attribute__((always_inline)) inline void bin_queue(ArgsRef a, const
             if (hot2) b2 = lut_hot_bin(s.band2, k.n2, b2, pi2c);
         }
         amb = ((b1 == -2) | (b2 == -2)) & inr;
-        flat = (inr & (b1 >= 0) & (b2 >= 0)) ? (int)__umul24((uint32_t)b1, (uint32_t)k.n2) + b2 : -1;
+        okb = inr & (b1 >= 0) & (b2 >= 0);
+        flat = (int)__umul24((uint32_t)b1, (uint32_t)k.n2) + b2;
     }
     amb = amb & valid;
-    if (valid & !amb & (flat >= 0)) {
+    const uint64_t m = __builtin_amdgcn_ballot_w64(amb);
+    if (valid & okb & !amb) {
         atomicAdd(&hist_l[flat], 1u);
         if (W) {
             // fl(wa * 2^S * wb) == fl(wa * wb) * 2^S when nothing overflows or
@@ -405,10 +410,9 @@ __device__ __attribute__((always_inline)) inline void bin_queue(ArgsRef a, const
             add_weight(s, flat, k.wpre ? q : q * k.wscale);
         }
     }
-    const uint64_t m = __builtin_amdgcn_ballot_w64(amb);
     if (m) {
         const int pos = c.rcount + (int)lane_prefix(m);
-        if (amb) {
+        if ((m >> lane) & 1ull) {
             uint32_t* r = s.rb + (size_t)pos * 3;
             r[0] = c.a_begin + (ids & 127u);
             r[1] = c.b_begin + (ids >> 7);
