@@ -366,7 +366,8 @@ def main():
                    "kernel_distance_evals_per_s": cand / (kernel_ms * 1e-3),
                    "in_range_flop_frac": FLOP_PER_DISTANCE * pairs / (kernel_ms * 1e-3) / 1e12 / PEAK_FP32_TFLOPS,
                    "items": int(stats["items"]), "grid": stats["grid"], "cells_per_rmax": stats["cells_per_rmax"],
-                   "wg_per_cu": stats["wg_per_cu"], "lut_entries": stats["lut_entries"],
+                   "wg_per_cu": stats["wg_per_cu"], "group_waves": stats["group_waves"],
+                   "lut_entries": stats["lut_entries"],
                    "band_d2_rel": stats["band_d2_rel"], "device": torch.cuda.get_device_name(0)},
     }
     if not (args.no_c4 and args.no_learned):

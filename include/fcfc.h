@@ -93,7 +93,8 @@ typedef struct {
     int32_t record_timing;   /* 1: record per-item GPU time (training data) */
     int32_t n_hint;          /* expected catalogue size, for automatic choices */
     int32_t lut_log2;        /* log2 of the look-up table length target, 10..15 */
-    int32_t reserved[7];
+    int32_t group_waves;     /* wavefronts per counting workgroup, 1..16 (0: as many as fit) */
+    int32_t reserved[6];
 } fcfc_tuning;
 
 /* Statistics of the last count on a plan (host copy; see fcfc_plan_stats). */
@@ -111,7 +112,7 @@ typedef struct {
     int32_t lut_entries;     /* squared-separation look-up table length */
     int32_t wg_per_cu;       /* resident counting workgroups per CU */
     int32_t order_used;      /* FCFC_ORDER_* the work list actually ran in */
-    int32_t reserved;
+    int32_t group_waves;     /* wavefronts per counting workgroup */
 } fcfc_stats;
 
 /*
@@ -302,7 +303,8 @@ fcfc_status fcfc_choose_cells(fcfc_model_t model, int32_t kind, int32_t los, con
  * the analytic tuning; the cell sizes the model predicts fastest (its two
  * best k), or without a model the analytic k +- 1; then, from the fastest,
  * 2 and 4 histogram copies, the other tile width, look-up tables of 2^12
- * and 2^14 entries and, with a model, the learned work order, keeping each
+ * and 2^14 entries, workgroups of 16, 14 and 12 wavefronts and, with a
+ * model, the learned work order, keeping each
  * change that is faster.  Settings that are not possible for these bins are
  * skipped.  With the learned order in *best, counts need the model attached
  * (fcfc_plan_set_model) to use it.

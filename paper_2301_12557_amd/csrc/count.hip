@@ -56,6 +56,13 @@ constexpr int CT_MAX = 1024;        // threads per workgroup (16 waves: 4 per SI
 constexpr int QCAP = 192;           // compaction queue entries per wave (63 + 64 P), plus one dump entry
 constexpr int RB_CAP = 128;         // recheck entries per wave
 constexpr int ASTAGE = 128;         // staged A points per wave (mid-point line of sight)
+
+// queue entry size in floats: (v1, v2, ids), or (dx, dy, dz, ids) for the
+// mid-point line of sight
+template <int KIND, int LOS>
+struct QStride {
+    static constexpr int value = (LOS == FCFC_LOS_MIDPOINT && KIND != FCFC_BIN_S) ? 4 : 3;
+};
 constexpr uint64_t FLUSH_PAIRS = 1ull << 26;  // per wave
 
 struct CountArgs {
@@ -118,7 +125,7 @@ struct Smem {
     uint32_t* hist;
     unsigned long long* wlo;
     unsigned long long* whi;
-    float4* q;        // this wave's compaction queue
+    float* qf;        // this wave's compaction queue (entries of QStride floats)
     double* aw;       // this wave's A point weights, by tile slot
     uint32_t* rb;     // this wave's recheck entries (a, b, item)
     float4* astage;   // this wave's A points in absolute FP32 (mid-point line of sight)
@@ -319,11 +326,22 @@ __device__ __attribute__((always_inline)) inline void bin_queue(ArgsRef a, const
                                                                 uint32_t* hist_l, int base, int cnt, int lane,
                                                                 WaveCtx& c) {
     const bool valid = lane < cnt;
-    float4 e = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (valid) e = s.q[base + lane];
     // entry (v1, v2, ids) or, mid-point, (dx, dy, dz, ids)
     constexpr bool MIDQ = (LOS == FCFC_LOS_MIDPOINT && KIND != FCFC_BIN_S);
-    const uint32_t ids = __float_as_uint(MIDQ ? e.w : e.z);
+    constexpr int QS = QStride<KIND, LOS>::value;
+    float4 e = make_float4(0.f, 0.f, 0.f, 0.f);
+    uint32_t ids = 0;
+    if (valid) {
+        const float* qe = s.qf + (size_t)(base + lane) * QS;
+        if (MIDQ) {
+            e = *(const float4*)qe;
+            ids = __float_as_uint(e.w);
+        } else {
+            e.x = qe[0];
+            e.y = qe[1];
+            ids = __float_as_uint(qe[2]);
+        }
+    }
     // the B weight of the pair, fetched early (product formed only for pairs in range)
     double wb = 0.0;
     if (W && valid) wb = a.wB[c.b_begin + (ids >> 7)];
@@ -444,7 +462,8 @@ __global__ __launch_bounds__(CT_MAX) void k_count(const CountArgs* argp) {
     s.hist = (uint32_t*)(smem + a.off_hist);
     s.wlo = (unsigned long long*)(smem + a.off_whist);
     s.whi = s.wlo + a.nbins;
-    s.q = (float4*)(smem + a.off_q) + (size_t)wave * (QCAP + 1);
+    constexpr int QS = QStride<KIND, LOS>::value;
+    s.qf = (float*)(smem + a.off_q) + (size_t)wave * (QCAP + 1) * QS;
     s.aw = (double*)(smem + a.off_qw) + (size_t)wave * ASTAGE;
     s.rb = (uint32_t*)(smem + a.off_rb) + (size_t)wave * RB_CAP * 3;
     s.astage = (float4*)(smem + a.off_astage) + (size_t)wave * ASTAGE;
@@ -705,10 +724,10 @@ __global__ __launch_bounds__(CT_MAX) void k_count(const CountArgs* argp) {
                                 (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, (uint32_t)qn));
                             const uint32_t slot = in ? pre : (uint32_t)QCAP;
                             const float idf = __uint_as_float(jbits | ids_lane[p]);
-                            if (LOS == FCFC_LOS_MIDPOINT && KIND != FCFC_BIN_S) {
-                                s.q[slot] = make_float4(v1, v2, v3, idf);
+                            float* qe = s.qf + (size_t)slot * QS;
+                            if (QS == 4) {
+                                *(float4*)qe = make_float4(v1, v2, v3, idf);
                             } else {
-                                float* qe = (float*)(s.q + slot);
                                 qe[0] = v1;
                                 qe[1] = v2;
                                 qe[2] = idf;
@@ -945,20 +964,40 @@ static fcfc_status setup_launch(Plan* p, bool is_auto, bool weighted, bool batch
     off += weighted ? al16(p->nbins * 16) : 0;
     const int shared_bytes = off;
     const bool mid = (p->los == FCFC_LOS_MIDPOINT && p->kind != FCFC_BIN_S);
-    const int per_wave = (QCAP + 1) * 16 + (weighted ? ASTAGE * 8 : 0) + RB_CAP * 12 + (mid ? ASTAGE * 16 : 0);
+    const int qbytes = (QCAP + 1) * (mid ? 16 : 12);
+    const int per_wave = qbytes + (weighted ? ASTAGE * 8 : 0) + RB_CAP * 12 + (mid ? ASTAGE * 16 : 0);
     int dev = 0, maxlds = 65536;
     FCFC_HIP(hipGetDevice(&dev));
     if (hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) maxlds = 65536;
-    // as many waves per workgroup (up to 16, one workgroup per CU) as the LDS allows
-    L.waves = 16;
-    while (L.waves > 1 && shared_bytes + L.waves * per_wave + 64 > maxlds) L.waves--;
-    if (shared_bytes + L.waves * per_wave + 64 > maxlds) {
+    L.kern = batch ? pick_batch_kernel(p->kind, weighted, L.P) : pick_kernel(p->kind, p->los, is_auto, weighted, L.P);
+    FCFC_HIP(hipFuncSetAttribute((const void*)L.kern, hipFuncAttributeMaxDynamicSharedMemorySize, maxlds));
+    auto lds_for = [&](int w) { return shared_bytes + w * per_wave + 64; };
+    if (p->tune.group_waves >= 1 && p->tune.group_waves <= 16) {
+        L.waves = p->tune.group_waves;
+        while (L.waves > 1 && lds_for(L.waves) > maxlds) L.waves--;
+    } else {
+        // Default workgroup size, from timings on MI355X: two 12-wave workgroups
+        // per CU (three waves per SIMD each) when they fit, else one workgroup of
+        // the largest even wave count that fits (odd counts leave the SIMDs
+        // unevenly loaded and ran measurably slower).
+        L.waves = 16;
+        while (L.waves > 1 && lds_for(L.waves) > maxlds) L.waves--;
+        int occ12 = 0;
+        if (lds_for(12) <= maxlds &&
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ12, (const void*)L.kern, 12 * 64, lds_for(12)) ==
+                hipSuccess &&
+            occ12 >= 2)
+            L.waves = 12;
+        else if (L.waves > 2)
+            L.waves &= ~1;
+    }
+    if (lds_for(L.waves) > maxlds) {
         set_error("count: %d bytes of LDS needed (tables + histogram), device allows %d", shared_bytes + per_wave + 64,
                   maxlds);
         return FCFC_ERANGE;
     }
     a.off_q = off;
-    off += L.waves * (QCAP + 1) * 16;
+    off += L.waves * qbytes;
     a.off_qw = off;
     off += weighted ? L.waves * ASTAGE * 8 : 0;
     a.off_rb = off;
@@ -1019,7 +1058,6 @@ static fcfc_status setup_launch(Plan* p, bool is_auto, bool weighted, bool batch
     a.mu_top_closed = 1;
     a.wscale = ldexp(1.0, S);
     a.ncat = 1;
-    L.kern = batch ? pick_batch_kernel(p->kind, weighted, L.P) : pick_kernel(p->kind, p->los, is_auto, weighted, L.P);
     FCFC_HIP(hipFuncSetAttribute((const void*)L.kern, hipFuncAttributeMaxDynamicSharedMemorySize, a.lds_bytes));
     return FCFC_OK;
 }
@@ -1062,12 +1100,13 @@ static WLArgs make_wl(const Plan* p, const LaunchSetup& L, bool is_auto, int nca
     return w;
 }
 
-static int grid_blocks(const LaunchSetup& L, uint32_t nitems) {
+static int grid_blocks(const LaunchSetup& L, uint32_t nitems, int* occ_out = nullptr) {
     int occ = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)L.kern, L.waves * 64, L.a.lds_bytes) !=
             hipSuccess ||
         occ < 1)
         occ = 1;
+    if (occ_out) *occ_out = occ;
     int64_t nblk = (int64_t)device_cu_count() * occ;
     int64_t need = ((int64_t)nitems + L.waves - 1) / L.waves;
     if (nblk > need) nblk = std::max<int64_t>(1, need);
@@ -1305,7 +1344,8 @@ fcfc_status count_pairs(Plan* p, Cells* c1, Cells* c2, int64_t* d_counts, double
     a.stats = (unsigned long long*)p->stats_dev;
     a.times = times;
 
-    const int nblk = grid_blocks(L, nitems);
+    int occ = 1;
+    const int nblk = grid_blocks(L, nitems, &occ);
     FCFC_HIP(hipEventRecord(p->ev0, st));
     p->host_args.resize(sizeof(CountArgs));
     memcpy(p->host_args.data(), &a, sizeof(CountArgs));
@@ -1340,7 +1380,8 @@ fcfc_status count_pairs(Plan* p, Cells* c1, Cells* c2, int64_t* d_counts, double
     p->stats.grid[2] = g.nz;
     p->stats.cells_per_rmax = g.k;
     p->stats.cell_side = g.side;
-    p->stats.wg_per_cu = 1;
+    p->stats.wg_per_cu = occ;
+    p->stats.group_waves = L.waves;
     p->stats.order_used = model ? FCFC_ORDER_LEARNED : (sorted ? FCFC_ORDER_HEURISTIC : FCFC_ORDER_BUILT);
     p->last_pts = L.P;
     return FCFC_OK;

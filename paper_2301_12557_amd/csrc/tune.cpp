@@ -1,5 +1,6 @@
 // tune.cpp -- the autotuner: picks the tuning knobs of a count (cells per
-// prune radius, histogram copies, tile width, look-up table length) by timing
+// prune radius, histogram copies, tile width, look-up table length,
+// workgroup size, work order) by timing
 // real builds and counts on a sample catalogue.  The learned cost model, when
 // given, proposes the cell sizes to try; the analytic choice is always tried;
 // measured GPU time decides.  Knobs never change a count.
@@ -99,12 +100,14 @@ bool cache_lookup(const char* path, const std::string& sig, fcfc_tuning* t, doub
     bool hit = false;
     while (fgets(line, sizeof(line), f)) {
         char s[600];
-        int k, tile, seg, cop, lut, ord;
+        int k, tile, seg, cop, lut, ord, gw;
         double m;
-        if (sscanf(line, "%599s %d %d %d %d %d %d %lf", s, &k, &tile, &seg, &cop, &lut, &ord, &m) == 8 && sig == s &&
-            k >= 1 && k <= 8 && (tile == 64 || tile == 128) && seg >= 0 && seg <= 64 &&
-            (cop == 1 || cop == 2 || cop == 4) && lut >= 10 && lut <= 15 && ord >= 0 && ord <= 2 && isfinite(m)) {
+        if (sscanf(line, "%599s %d %d %d %d %d %d %d %lf", s, &k, &tile, &seg, &cop, &lut, &ord, &gw, &m) == 9 &&
+            sig == s && k >= 1 && k <= 8 && (tile == 64 || tile == 128) && seg >= 0 && seg <= 64 &&
+            (cop == 1 || cop == 2 || cop == 4) && lut >= 10 && lut <= 15 && ord >= 0 && ord <= 2 && gw >= 0 &&
+            gw <= 16 && isfinite(m)) {
             t->order = ord;
+            t->group_waves = gw;
             t->cells_per_rmax = k;
             t->tile_points = tile;
             t->seg_cells = seg;
@@ -121,8 +124,8 @@ bool cache_lookup(const char* path, const std::string& sig, fcfc_tuning* t, doub
 void cache_store(const char* path, const std::string& sig, const fcfc_tuning& t, double ms) {
     FILE* f = fopen(path, "a");
     if (!f) return;
-    fprintf(f, "%s %d %d %d %d %d %d %.6f\n", sig.c_str(), t.cells_per_rmax, t.tile_points, t.seg_cells,
-            t.hist_copies, t.lut_log2, t.order, ms);
+    fprintf(f, "%s %d %d %d %d %d %d %d %.6f\n", sig.c_str(), t.cells_per_rmax, t.tile_points, t.seg_cells,
+            t.hist_copies, t.lut_log2, t.order, t.group_waves, ms);
     fclose(f);
 }
 
@@ -239,7 +242,18 @@ extern "C" fcfc_status fcfc_autotune(fcfc_model_t model, int32_t kind, int32_t l
         t.lut_log2 = lg;
         consider(t);
     }
-    // 5. the learned work order
+    // 5. workgroup size (wavefronts per workgroup)
+    const int gws[3] = {16, 14, 12};
+    {
+        const fcfc_tuning t1 = bt;
+        for (int gw : gws) {
+            if (t1.group_waves == gw) continue;
+            fcfc_tuning t = t1;
+            t.group_waves = gw;
+            consider(t);
+        }
+    }
+    // 6. the learned work order
     if (model && bt.order != FCFC_ORDER_LEARNED) {
         fcfc_tuning t = bt;
         t.order = FCFC_ORDER_LEARNED;

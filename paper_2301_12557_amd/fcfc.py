@@ -37,7 +37,8 @@ class Tuning(ctypes.Structure):
                 ("seg_cells", ctypes.c_int32), ("b_chunk", ctypes.c_int32),
                 ("hist_copies", ctypes.c_int32), ("order", ctypes.c_int32),
                 ("record_timing", ctypes.c_int32), ("n_hint", ctypes.c_int32),
-                ("lut_log2", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7)]
+                ("lut_log2", ctypes.c_int32), ("group_waves", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 6)]
 
 
 class Stats(ctypes.Structure):
@@ -46,12 +47,11 @@ class Stats(ctypes.Structure):
                 ("cells_per_rmax", ctypes.c_int32), ("cell_side", ctypes.c_double),
                 ("kernel_ms", ctypes.c_double), ("band_d2_rel", ctypes.c_double),
                 ("lut_entries", ctypes.c_int32), ("wg_per_cu", ctypes.c_int32),
-                ("order_used", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("order_used", ctypes.c_int32), ("group_waves", ctypes.c_int32)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_}
         d["grid"] = list(self.grid)
-        d.pop("reserved")
         d["order_used"] = {v: k for k, v in ORDER.items()}.get(self.order_used, self.order_used)
         return d
 
@@ -418,7 +418,7 @@ def diag_transcendental(stream=None):
 
 
 TUNING_KEYS = ("cells_per_rmax", "tile_points", "seg_cells", "b_chunk", "hist_copies", "order",
-               "record_timing", "n_hint", "lut_log2")
+               "record_timing", "n_hint", "lut_log2", "group_waves")
 
 
 def autotune(x1, x2=None, *, model=None, kind="s", edges1, edges2=None, los="z", box=0.0, w1=None, w2=None,
