@@ -91,7 +91,11 @@ int choose_k(const Plan* p, int64_t n_hint) {
 fcfc_status plan_finalize_grid(Plan* p) {
     Grid& g = p->grid;
     int k = choose_k(p, p->tune.n_hint);
-    double target = p->rprune / k;
+    // cells a hair wider than r/k: with the side exactly r/k, the prune margin
+    // would keep one more cell on every side of the stencil (rows whose
+    // nearest gap is exactly r could never hold a pair, but cannot be told
+    // apart from rows just inside it)
+    double target = p->rprune / k * (1.0 + 1e-6);
     const int64_t max_cells = (int64_t)1 << 26;
     if (p->L > 0) {
         int64_t n = (int64_t)floor(p->L / target);
