@@ -32,7 +32,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c5"])
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c5"])
+    ap.add_argument("--c3-rr", action="store_true", help="C3: also count RR (40M randoms, ~2e13 pairs)")
     ap.add_argument("--unweighted", action="store_true", help="count without weights")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target length of the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -49,12 +50,15 @@ def parse():
 
 def workload(name, weighted):
     from paper_2301_12557_amd import synth
-    c = {"c1": 1, "c2": 2, "c5": 5}[name]
+    c = {"c1": 1, "c2": 2, "c3": 3, "c5": 5}[name]
     w = synth.workload(c, weighted=weighted and c != 5)
     desc = {
         1: "C1 periodic L=1000, 20,000 uniform points, 40 linear s bins [0,200), auto",
         2: "C2 periodic L=2000, 1,000,000 lognormal points (256^3 field, P~k^-1.5, sigma_G=1), "
            "(s,mu) 40x100 bins s in [0,200) mu in [0,1], LOS z, auto",
+        3: "C3 open survey shell r in [1000,2000], RA 60 deg x Dec 30 deg, data 2,000,000 + randoms 40,000,000, "
+           "(s_perp,pi) 40x40 bins over [0,200), mid-point LOS, weights U[0.5,2); one step = bounds + both "
+           "cell builds + DD + DR (+ RR with --c3-rr)",
         5: "C5 periodic L=3000, 10,000,000 lognormal points, 50 log s bins [0.1,50), auto",
     }[c]
     return w, desc
@@ -283,6 +287,70 @@ def c5_section(fcfc, synth, model):
     return res
 
 
+def c3_main(args, fcfc, torch):
+    """C3 (open box, mid-point line of sight): DD and DR (and RR) per step."""
+    weighted = not args.unweighted
+    w, desc = workload("c3", weighted)
+    dev = torch.device("cuda:0")
+    d = torch.from_numpy(w["x1"]).to(dev)
+    r = torch.from_numpy(w["x2"]).to(dev)
+    wd = torch.from_numpy(w["w1"]).to(dev) if weighted else None
+    wr = torch.from_numpy(w["w2"]).to(dev) if weighted else None
+    tune = {}
+    for kv in filter(None, args.tune.split(",")):
+        k, v = kv.split("=")
+        tune[k] = int(v)
+    tune.setdefault("n_hint", len(w["x2"]))
+
+    def step():
+        plan = fcfc.Plan("spi", w["edges1"], w["edges2"], los="mid", box=0.0, **tune)
+        plan.fit_bounds([(d, None), (r, None)])
+        cd = plan.build_cells(d, wd)
+        cr = plan.build_cells(r, wr)
+        st = {}
+        plan.count(cd, weighted=weighted)
+        st["DD"] = plan.stats()
+        plan.count(cd, cr, weighted=weighted)
+        st["DR"] = plan.stats()
+        if args.c3_rr:
+            plan.count(cr, weighted=weighted)
+            st["RR"] = plan.stats()
+        cd.close()
+        cr.close()
+        plan.close()
+        return st
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        st = step()
+    torch.cuda.synchronize()
+    ms_step = (time.perf_counter() - t0) * 1e3 / args.steps
+    pairs = sum(int(v["in_range"]) for v in st.values())
+    dr = st["DR"]
+    achieved = FLOP_PER_DISTANCE * dr["candidates"] / (dr["kernel_ms"] * 1e-3) / 1e12
+    res = {
+        "metric": "exact pairs/s (1 GPU, % FP32 roofline); mocks/s batched+learned vs plain",
+        "value": pairs / (ms_step * 1e-3), "unit": "pairs/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": desc, "data_points": len(w["x1"]), "random_points": len(w["x2"]),
+                   "bins": 40 * 40, "weighted": bool(weighted), "tuning": tune},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None, "kernel": "k_count (DR)",
+                     "kernel_ms": dr["kernel_ms"], "per_unit": f"{FLOP_PER_DISTANCE} flop per distance evaluation",
+                     "units_per_launch": int(dr["candidates"])},
+        "detail": {name: {"in_range_pairs": int(v["in_range"]), "distance_evaluations": int(v["candidates"]),
+                          "kernel_ms": v["kernel_ms"], "kernel_pairs_per_s": v["in_range"] / (v["kernel_ms"] * 1e-3),
+                          "candidates_per_pair": v["candidates"] / max(v["in_range"], 1),
+                          "recheck_rate": v["rechecks"] / max(v["candidates"], 1), "grid": v["grid"],
+                          "group_waves": v["group_waves"]} for name, v in st.items()},
+    }
+    print(json.dumps(res), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -298,6 +366,9 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
         del a, b
+    if args.workload == "c3":
+        c3_main(args, fcfc, torch)
+        return
     weighted = not args.unweighted
     w, desc = workload(args.workload, weighted)
     weighted = weighted and w["w1"] is not None
