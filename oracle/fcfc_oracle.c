@@ -17,8 +17,8 @@
  *   line of sight), and add the pair to the histogram bin whose half-open
  *   interval contains it.  Bins are compared through squared edges
  *   (Sect. 3.2.1: squared distances against pre-computed squared edges,
- *   zero-based bin indices, s_min^2 <= s^2 < s_max^2 as in Eqs. idx_map_lin /
- *   idx_map_log).
+ *   zero-based bin indices, s_min^2 <= s^2 < s_max^2 as in the linear and
+ *   logarithmic index maps of Sect. 3.2.2).
  *
  * Readings where the paper is silent (the same readings the GPU path follows):
  *   - Every operation is IEEE-754 binary64, round to nearest even, evaluated
