@@ -141,6 +141,25 @@ def test_cross_weights_far_from_one(sa, sb):
                edges2=synth.mu_edges(10), w1=w1, w2=w2)
 
 
+def test_weighted_sums_bit_exact():
+    """Both sides round the same exact sum of FP64 pair weights once, so the
+    weighted histograms agree bit for bit (not just within 1e-12)."""
+    w = synth.workload(1, weighted=True)
+    g, gw, _ = gpu_count(w["x1"], kind="s", edges1=w["edges1"], box=w["box"], w1=w["w1"])
+    o, ow = oracle_count(w["x1"], kind="s", edges1=w["edges1"], box=w["box"], w1=w["w1"])
+    assert np.array_equal(g, o) and np.array_equal(gw, ow)
+    rng = np.random.default_rng(9)
+    a = synth.survey_shell(1500, 11, rmin=200.0, rmax=320.0)
+    b = synth.survey_shell(1200, 12, rmin=200.0, rmax=320.0)
+    wa = 1e300 * rng.uniform(1.0, 2.0, len(a))
+    wb = 1e-300 * rng.uniform(1.0, 2.0, len(b))
+    kw = dict(kind="spi", los="mid", edges1=np.array([0.0, 4.0, 9.0, 20.0, 33.0]),
+              edges2=np.array([0.0, 5.0, 12.0, 30.0]), box=0.0)
+    g, gw, _ = gpu_count(a, b, w1=wa, w2=wb, **kw)
+    o, ow = oracle_count(a, b, w1=wa, w2=wb, **kw)
+    assert np.array_equal(g, o) and np.array_equal(gw, ow)
+
+
 def test_empty_and_tiny():
     e = np.array([0.0, 1.0, 2.0, 5.0])
     for n in (0, 1, 2, 3):
