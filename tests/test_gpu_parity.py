@@ -170,6 +170,36 @@ def test_empty_and_tiny():
     check_case("cross with empty", np.zeros((0, 3)), y, kind="s", edges1=e, box=10.0)
 
 
+def test_degenerate_catalogues():
+    """Coincident points (d = 0: s-bin 0, mu = 0, every pair through the FP64 recheck
+    of tiny separations), and one dense clump inside a single cell (tiles within a
+    cell, B pieces split by b_chunk, the same-row rule inside one cell)."""
+    rng = np.random.default_rng(31)
+    x = np.concatenate([np.full((600, 3), 7.25), rng.random((900, 3)) * 20.0])
+    e = np.array([0.0, 0.5, 2.0, 4.0, 6.0])
+    check_case("coincident smu", x, kind="smu", edges1=e, edges2=synth.mu_edges(5), box=20.0)
+    check_case("coincident s open", x, kind="s", edges1=e, box=0.0)
+    clump = 50.0 + rng.normal(0.0, 0.3, (12000, 3))
+    bg = rng.random((3000, 3)) * 100.0
+    y = np.concatenate([clump, bg])
+    e2 = np.array([0.0, 0.2, 0.5, 1.0, 3.0, 8.0])
+    check_case("dense clump", y, kind="smu", edges1=e2, edges2=synth.mu_edges(4), box=100.0, method="grid")
+    check_case("dense clump small chunks", y, kind="s", edges1=e2, box=100.0, method="grid", b_chunk=300)
+
+
+def test_histogram_size_limits():
+    """The largest unweighted histogram the LDS holds counts exactly; a weighted one
+    too large for the LDS limbs is refused with FCFC_ERANGE (nothing is counted)."""
+    from paper_2301_12557_amd import fcfc
+    x = np.random.default_rng(4).random((3000, 3)) * 60.0
+    e1 = synth.linear_edges(0, 20, 240)
+    check_case("24000 bins", x, kind="smu", edges1=e1, edges2=synth.mu_edges(100), box=60.0)
+    w = np.random.default_rng(5).uniform(0.5, 1.5, len(x))
+    with pytest.raises(fcfc.FcfcError) as ei:
+        gpu_count(x, kind="smu", edges1=e1, edges2=synth.mu_edges(100), box=60.0, w1=w)
+    assert ei.value.name == "FCFC_ERANGE"
+
+
 def test_tuning_sweep_small():
     """Random small problems under many tuning settings: all must match the oracle."""
     rng = np.random.default_rng(2024)
