@@ -173,7 +173,9 @@ fcfc_status fcfc_build_cells(fcfc_plan_t plan, const fcfc_catalog *cat, void *st
  * Synchronises `stream` once to size the work list.
  * Errors: FCFC_EGRID (cell sets from different plans), FCFC_EINVAL
  * (weights requested but missing), FCFC_ERANGE (weight dynamic range too
- * wide for exact accumulation), FCFC_ENOMEM, FCFC_EHIP.
+ * wide for exact accumulation, or a weighted histogram whose 16 bytes per
+ * bin of exact accumulators do not fit the LDS next to the counts: about
+ * 7,000 bins on MI355X), FCFC_ENOMEM, FCFC_EHIP.
  */
 fcfc_status fcfc_count_pairs(fcfc_plan_t plan, fcfc_cells_t c1, fcfc_cells_t c2,
                              int64_t *d_counts, double *d_wcounts, void *stream);
