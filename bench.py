@@ -42,6 +42,7 @@ def parse():
     ap.add_argument("--c4-mocks", type=int, default=200)
     ap.add_argument("--c4-repeats", type=int, default=5)
     ap.add_argument("--no-learned", action="store_true", help="skip training and the held-out C5 comparison")
+    ap.add_argument("--no-peaks", action="store_true", help="skip the roofline microbenchmarks")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="first copy this many MiB device-to-device (a plain copy of known size, to calibrate "
                          "HBM traffic counters against)")
@@ -441,6 +442,20 @@ def main():
                    "lut_entries": stats["lut_entries"],
                    "band_d2_rel": stats["band_d2_rel"], "device": torch.cuda.get_device_name(0)},
     }
+    if not args.no_peaks:
+        pk = fcfc.diag_peaks()
+        kernel_s = kernel_ms * 1e-3
+        atomic_time = pairs * (1.0 / pk["lds_u32_per_s"] + (2.0 / pk["lds_u64_per_s"] if weighted else 0.0))
+        res["roofline"]["measured_peaks"] = {
+            "fp32_fma_tflops_nonpacked": pk["fma_tflops"],
+            "note": "one FMA per lane per instruction; the published 157.3 TFLOP/s counts packed FP32",
+            "copy_gbps": pk["copy_gbps"], "lds_add_u32_per_s": pk["lds_u32_per_s"],
+            "lds_add_u64_per_s": pk["lds_u64_per_s"]}
+        res["lds_atomic_roofline"] = {
+            "atomics_per_pair": "1 ds_add_u32" + (" + 2 ds_add_u64" if weighted else ""),
+            "atomic_time_ms_at_peak": atomic_time * 1e3, "kernel_ms": kernel_ms,
+            "frac": atomic_time / kernel_s}
+        log(f"measured peaks: {pk}")
     if not (args.no_c4 and args.no_learned):
         from paper_2301_12557_amd import synth
         mocks = make_mocks(synth, args.c4_mocks)

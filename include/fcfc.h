@@ -340,6 +340,18 @@ fcfc_status fcfc_autotune(fcfc_model_t model, int32_t kind, int32_t los, const d
 fcfc_status fcfc_diag_transcendental(double *rsq_max_rel, double *rcp_max_rel, double *assumed,
                                      void *stream);
 
+/*
+ * fcfc_diag_peaks -- roofline microbenchmarks on the current device, timed with
+ * HIP events: FP32 FMA rate (one FMA per lane per instruction, no packed
+ * math; TFLOP/s, 2 flops per FMA), conflict-free LDS ds_add_u32 and
+ * ds_add_u64 rates (atomics per second, whole device) and a 1 GiB
+ * device-to-device copy (GB/s, bytes read + written).  Any output may be
+ * NULL.  Allocates about 2 GiB while it runs; synchronises `stream`.
+ * Errors: FCFC_ENOMEM, FCFC_EHIP.
+ */
+fcfc_status fcfc_diag_peaks(double *fma_tflops, double *lds_u32_per_s, double *lds_u64_per_s,
+                            double *copy_gbps, void *stream);
+
 const char *fcfc_status_str(fcfc_status s);
 const char *fcfc_last_error(void);
 int32_t fcfc_version(void);

@@ -97,6 +97,7 @@ SIGNATURES = [
                              ctypes.POINTER(Tuning), ctypes.POINTER(_D), ctypes.POINTER(_D),
                              ctypes.POINTER(_I32)]),
     ("fcfc_diag_transcendental", _I32, [ctypes.POINTER(_D), ctypes.POINTER(_D), ctypes.POINTER(_D), _P]),
+    ("fcfc_diag_peaks", _I32, [ctypes.POINTER(_D), ctypes.POINTER(_D), ctypes.POINTER(_D), ctypes.POINTER(_D), _P]),
     ("fcfc_status_str", ctypes.c_char_p, [_I32]),
     ("fcfc_last_error", ctypes.c_char_p, []),
     ("fcfc_version", _I32, []),
@@ -415,6 +416,13 @@ def diag_transcendental(stream=None):
     a, b, c = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
     check(load().fcfc_diag_transcendental(ctypes.byref(a), ctypes.byref(b), ctypes.byref(c), _stream_ptr(stream)))
     return a.value, b.value, c.value
+
+
+def diag_peaks(stream=None):
+    """Measured device rates: dict with fma_tflops, lds_u32_per_s, lds_u64_per_s, copy_gbps."""
+    v = [ctypes.c_double() for _ in range(4)]
+    check(load().fcfc_diag_peaks(*[ctypes.byref(x) for x in v], _stream_ptr(stream)))
+    return dict(zip(("fma_tflops", "lds_u32_per_s", "lds_u64_per_s", "copy_gbps"), (x.value for x in v)))
 
 
 TUNING_KEYS = ("cells_per_rmax", "tile_points", "seg_cells", "b_chunk", "hist_copies", "order",

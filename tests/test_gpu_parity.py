@@ -366,3 +366,14 @@ def test_hardware_rsq_rcp_within_band_bound():
     rs, rc, bound = fcfc.diag_transcendental()
     note(f"max rel error rsq {rs:.3e} rcp {rc:.3e} (bands assume {bound:.3e})")
     assert 0 < rs <= bound and 0 < rc <= bound
+
+
+def test_roofline_microbenchmarks_are_plausible():
+    """The measured FP32 FMA, LDS atomic and copy rates the bench reports beside the
+    published peaks: positive, and not above the published figures."""
+    from paper_2301_12557_amd import fcfc
+    pk = fcfc.diag_peaks()
+    note(f"peaks {pk}")
+    assert 10.0 < pk["fma_tflops"] <= 157.3 * 1.05
+    assert pk["lds_u32_per_s"] > 1e12 and pk["lds_u64_per_s"] > 1e11
+    assert 100.0 < pk["copy_gbps"] <= 8000.0 * 1.1
