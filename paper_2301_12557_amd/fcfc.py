@@ -147,6 +147,15 @@ def _catalog(xyz, w=None):
                    xyz.shape[0])
 
 
+def _out_tensor(t, n, dtype, name):
+    """Check a caller-provided device output: contiguous, on the GPU, of the right type and size."""
+    import torch
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == dtype and t.is_contiguous()
+            and t.numel() == n):
+        raise ValueError(f"{name} must be a contiguous CUDA {dtype} tensor with {n} elements")
+    return t
+
+
 def make_tuning(**kw):
     t = Tuning()
     for k, v in kw.items():
@@ -201,8 +210,11 @@ class Plan:
         dev = c1.device
         if out is None:
             out = torch.empty(nb, dtype=torch.int64, device=dev)
+        _out_tensor(out, nb, torch.int64, "out")
         if weighted and wout is None:
             wout = torch.empty(nb, dtype=torch.float64, device=dev)
+        if weighted:
+            _out_tensor(wout, nb, torch.float64, "wout")
         check(load().fcfc_count_pairs(self.h, c1.h, c2.h if c2 is not None else None, out.data_ptr(),
                                       wout.data_ptr() if weighted else None, _stream_ptr(stream)))
         return out.view(self.shape), (wout.view(self.shape) if weighted else None)
@@ -292,6 +304,11 @@ class Batch:
         self.ncat = len(catalogs)
 
     def run(self, out, wout=None, use_graph=True, stream=None):
+        import torch
+        nb = self.ncat * self.plan.n1 * self.plan.n2
+        _out_tensor(out, nb, torch.int64, "out")
+        if wout is not None:
+            _out_tensor(wout, nb, torch.float64, "wout")
         check(load().fcfc_batch_run(self.h, out.data_ptr(), wout.data_ptr() if wout is not None else None,
                                     int(bool(use_graph)), _stream_ptr(stream)))
         return out
@@ -361,18 +378,24 @@ class Model:
         check(load().fcfc_model_predict(self.h, feat.data_ptr(), feat.shape[0], out.data_ptr(), _stream_ptr(stream)))
         return out
 
+    def _target(self, target, m):
+        import torch
+        return _out_tensor(target, m, torch.float32, "target")
+
     def grad(self, feat, target, stream=None):
         feat = self._feat(feat)
+        target = self._target(target, feat.shape[0])
         g = np.empty(self.nparams(), dtype=np.float32)
         loss = ctypes.c_float()
-        check(load().fcfc_model_grad(self.h, feat.data_ptr(), target.contiguous().data_ptr(), feat.shape[0],
+        check(load().fcfc_model_grad(self.h, feat.data_ptr(), target.data_ptr(), feat.shape[0],
                                      g.ctypes.data_as(_P), ctypes.byref(loss), _stream_ptr(stream)))
         return g, loss.value
 
     def train(self, feat, target, epochs=30, batch=256, lr=1e-3, seed=0, stream=None):
         feat = self._feat(feat)
+        target = self._target(target, feat.shape[0])
         loss = ctypes.c_float()
-        check(load().fcfc_model_train(self.h, feat.data_ptr(), target.contiguous().data_ptr(), feat.shape[0],
+        check(load().fcfc_model_train(self.h, feat.data_ptr(), target.data_ptr(), feat.shape[0],
                                       int(epochs), int(batch), float(lr), int(seed), _stream_ptr(stream),
                                       ctypes.byref(loss)))
         return loss.value

@@ -165,3 +165,15 @@ def test_plan_timings_before_any_count():
     assert lib.fcfc_plan_timings(p, None, None, 0, ctypes.byref(n), None) == -10
     assert lib.fcfc_plan_set_model(p, None) == 0
     lib.fcfc_plan_free(p)
+
+
+def test_binding_rejects_host_tensors_and_bad_outputs():
+    """The binding refuses inputs and outputs the library could not use, before any GPU work."""
+    torch = pytest.importorskip("torch")
+    x = torch.zeros((10, 3), dtype=torch.float64)
+    with pytest.raises(ValueError):
+        fcfc._catalog(x)                      # host tensor
+    with pytest.raises(ValueError):
+        fcfc._out_tensor(torch.zeros(5, dtype=torch.int64), 5, torch.int64, "out")   # host tensor
+    with pytest.raises(ValueError):
+        fcfc._out_tensor(torch.zeros(5, dtype=torch.float64), 5, torch.int64, "out")  # wrong dtype
