@@ -43,6 +43,9 @@ def parse():
     ap.add_argument("--c4-repeats", type=int, default=5)
     ap.add_argument("--no-learned", action="store_true", help="skip training and the held-out C5 comparison")
     ap.add_argument("--no-peaks", action="store_true", help="skip the roofline microbenchmarks")
+    ap.add_argument("--shards", type=int, default=0,
+                    help="also count each of G work-list shards (one GPU's share of a G-GPU run) and report "
+                         "their kernel times")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="first copy this many MiB device-to-device (a plain copy of known size, to calibrate "
                          "HBM traffic counters against)")
@@ -442,6 +445,28 @@ def main():
                    "lut_entries": stats["lut_entries"],
                    "band_d2_rel": stats["band_d2_rel"], "device": torch.cuda.get_device_name(0)},
     }
+    if args.shards > 1:
+        G = args.shards
+        cells = plan.build_cells(x, wt)
+        sk, tot = [], None
+        for g in range(G):
+            ps = fcfc.Plan(w["kind"], w["edges1"], w["edges2"], los=w["los"], box=w["box"],
+                           **dict(tune, shard_count=G, shard_index=g))
+            cs = ps.build_cells(x, wt)
+            best = np.inf
+            for _ in range(3):
+                c, _ = ps.count(cs, weighted=weighted)
+                best = min(best, ps.stats()["kernel_ms"])
+            tot = c.clone() if tot is None else tot + c
+            sk.append(best)
+            cs.close()
+            ps.close()
+        cells.close()
+        res["shards"] = {"count": G, "kernel_ms": sk, "max_kernel_ms": max(sk),
+                         "whole_kernel_ms": kernel_ms, "balance": float(np.mean(sk) / max(sk)),
+                         "sum_equals_whole": bool(torch.equal(tot.reshape(-1), out.reshape(-1))),
+                         "note": "each shard counted alone on this GPU, at its real shape; no multi-GPU time"}
+        log(f"shards: max {max(sk):.3f} ms of whole {kernel_ms:.3f} ms")
     if not args.no_peaks:
         pk = fcfc.diag_peaks()
         kernel_s = kernel_ms * 1e-3

@@ -94,7 +94,9 @@ typedef struct {
     int32_t n_hint;          /* expected catalogue size, for automatic choices */
     int32_t lut_log2;        /* log2 of the look-up table length target, 10..15 */
     int32_t group_waves;     /* wavefronts per counting workgroup, 1..16 (0: as many as fit) */
-    int32_t reserved[6];
+    int32_t shard_count;     /* 0 or 1: the whole work list; G > 1: count one of G shards */
+    int32_t shard_index;     /* the shard counted, 0..G-1: ordered items i with i % G == index */
+    int32_t reserved[4];
 } fcfc_tuning;
 
 /* Statistics of the last count on a plan (host copy; see fcfc_plan_stats). */

@@ -99,6 +99,7 @@ struct CountArgs {
     double wscale;
     int wpre;  // 1: staged A weights carry the scale 2^S (see prescale_ok)
     int copies;
+    uint32_t shard_count, shard_index;  // this launch takes items shard_index, + shard_count, ...
     // batched mode: chunks of items per catalogue
     const uint32_t* nchunks_dev;
     uint32_t* chunk_cursor;
@@ -766,11 +767,14 @@ __global__ __launch_bounds__(CT_MAX) void k_count(const CountArgs* argp) {
     };
     if (!BATCH) {
         const uint32_t nitems = __builtin_amdgcn_readfirstlane(*a.nitems_dev);
+        const uint32_t sc = a.shard_count, si = a.shard_index;
         process_items([&]() -> uint32_t {
             uint32_t v = 0;
             if (lane == 0) v = atomicAdd(a.cursor, 1u);
             v = __builtin_amdgcn_readfirstlane(v);
-            return v < nitems ? v : ~0u;
+            // one shard of the ordered list: items si, si + sc, si + 2 sc, ...
+            const uint64_t idx = (uint64_t)v * sc + si;
+            return idx < nitems ? (uint32_t)idx : ~0u;
         });
         drain_rechecks();
         __syncthreads();
@@ -1058,6 +1062,8 @@ static fcfc_status setup_launch(Plan* p, bool is_auto, bool weighted, bool batch
     a.mu_top_closed = 1;
     a.wscale = ldexp(1.0, S);
     a.ncat = 1;
+    a.shard_count = (p->tune.shard_count >= 1) ? (uint32_t)p->tune.shard_count : 1u;
+    a.shard_index = (p->tune.shard_count >= 1) ? (uint32_t)p->tune.shard_index : 0u;
     FCFC_HIP(hipFuncSetAttribute((const void*)L.kern, hipFuncAttributeMaxDynamicSharedMemorySize, a.lds_bytes));
     return FCFC_OK;
 }

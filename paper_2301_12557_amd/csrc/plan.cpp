@@ -366,6 +366,12 @@ extern "C" fcfc_status fcfc_plan_create(int32_t kind, int32_t los, const double*
     if (kind != FCFC_BIN_S) p->e2.assign(edges2, edges2 + n2 + 1);
     p->L = box_L;
     if (tune) p->tune = *tune;
+    if (p->tune.shard_count < 0 || (p->tune.shard_count > 1 &&
+                                    (p->tune.shard_index < 0 || p->tune.shard_index >= p->tune.shard_count))) {
+        delete p;
+        set_error("plan_create: shard_index must lie in [0, shard_count)");
+        return FCFC_EINVAL;
+    }
     if (kind == FCFC_BIN_SPERP_PI)
         p->rprune = sqrt(edges1[n1] * edges1[n1] + edges2[n2] * edges2[n2]) * (1.0 + 1e-12);
     else

@@ -38,7 +38,8 @@ class Tuning(ctypes.Structure):
                 ("hist_copies", ctypes.c_int32), ("order", ctypes.c_int32),
                 ("record_timing", ctypes.c_int32), ("n_hint", ctypes.c_int32),
                 ("lut_log2", ctypes.c_int32), ("group_waves", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 6)]
+                ("shard_count", ctypes.c_int32), ("shard_index", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 4)]
 
 
 class Stats(ctypes.Structure):
@@ -449,7 +450,7 @@ def diag_peaks(stream=None):
 
 
 TUNING_KEYS = ("cells_per_rmax", "tile_points", "seg_cells", "b_chunk", "hist_copies", "order",
-               "record_timing", "n_hint", "lut_log2", "group_waves")
+               "record_timing", "n_hint", "lut_log2", "group_waves", "shard_count", "shard_index")
 
 
 def autotune(x1, x2=None, *, model=None, kind="s", edges1, edges2=None, los="z", box=0.0, w1=None, w2=None,

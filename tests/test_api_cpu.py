@@ -177,3 +177,15 @@ def test_binding_rejects_host_tensors_and_bad_outputs():
         fcfc._out_tensor(torch.zeros(5, dtype=torch.int64), 5, torch.int64, "out")   # host tensor
     with pytest.raises(ValueError):
         fcfc._out_tensor(torch.zeros(5, dtype=torch.float64), 5, torch.int64, "out")  # wrong dtype
+
+
+def test_plan_rejects_bad_shard():
+    t = fcfc.Tuning()
+    t.shard_count = 4
+    t.shard_index = 4
+    assert _create(tune=t) == -1
+    t.shard_index = 3
+    assert _create(tune=t) == 0
+    t.shard_count = -1
+    t.shard_index = 0
+    assert _create(tune=t) == -1

@@ -377,3 +377,23 @@ def test_roofline_microbenchmarks_are_plausible():
     assert 10.0 < pk["fma_tflops"] <= 157.3 * 1.05
     assert pk["lds_u32_per_s"] > 1e12 and pk["lds_u64_per_s"] > 1e11
     assert 100.0 < pk["copy_gbps"] <= 8000.0 * 1.1
+
+
+def test_shards_sum_to_the_whole_count():
+    """The work-list shards (ordered items i % G == g) of G GPUs, each counted on its
+    own: the G histograms sum bit-exactly to the whole count, weighted sums to 1e-12."""
+    w = synth.workload(2, scale=0.03, weighted=True)
+    kw = dict(kind="smu", edges1=w["edges1"], edges2=w["edges2"], box=w["box"], w1=w["w1"])
+    whole, wwhole, st = gpu_count(w["x1"], **kw)
+    for G in (2, 3, 8):
+        tot = np.zeros_like(whole)
+        wtot = np.zeros_like(wwhole)
+        cand = 0
+        for g in range(G):
+            c, wc, sg = gpu_count(w["x1"], shard_count=G, shard_index=g, **kw)
+            tot += c
+            wtot += wc
+            cand += sg["candidates"]
+        assert np.array_equal(tot, whole), G
+        assert cand == st["candidates"]
+        assert np.allclose(wtot, wwhole, rtol=1e-12, atol=0)
