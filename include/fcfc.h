@@ -354,6 +354,46 @@ fcfc_status fcfc_diag_transcendental(double *rsq_max_rel, double *rcp_max_rel, d
 fcfc_status fcfc_diag_peaks(double *fma_tflops, double *lds_u32_per_s, double *lds_u64_per_s,
                             double *copy_gbps, void *stream);
 
+/*
+ * From pair counts to correlation functions (Sect. 1, App. D).  All arrays
+ * are device FP64; counts enter as FP64 (exact below 2^53).
+ *
+ * fcfc_xi -- any linear estimator over normalised pair counts:
+ *   xi[b] = (sum_t coef[t] X_t[b] / norm[t]) / (X_den[b] / norm[den]),
+ * with nterms (1..8) histograms d_terms[t] (host array of device pointers)
+ * and normalisations norm[t] > 0 (e.g. N_D (N_D - 1) / 2 for an auto DD,
+ * N_D N_R for DR).  Landy-Szalay: (DD, DR, RR), coef (1, -2, 1), den 2;
+ * Peebles-Hauser: (DD, RR), coef (1, -1), den 1; Szapudi-Szalay (cross):
+ * (D1D2, D1R2, R1D2, R1R2), coef (1, -1, -1, 1), den 3.  A bin with a zero
+ * denominator gets NaN.  Errors: FCFC_EINVAL.
+ */
+fcfc_status fcfc_xi(int32_t nterms, const double *const *d_terms, const double *coef,
+                    const double *norm, int32_t den, int64_t nbins, double *d_xi, void *stream);
+/*
+ * fcfc_analytic_rr -- the pair counts of a uniform periodic box for the plan's
+ * bins: npairs * V_bin / L^3 (npairs = N (N - 1) / 2 for an auto count, or
+ * ((sum w)^2 - sum w^2) / 2 weighted).  V_bin is the separation-space volume
+ * of the bin: a spherical shell for s; the shell times dmu for (s, mu)
+ * (line of sight z); a cylindrical annulus times 2 dpi for (s_perp, pi).
+ * Writes n1*n2 values.  Errors: FCFC_ESTATE (open plan), FCFC_EINVAL.
+ */
+fcfc_status fcfc_analytic_rr(fcfc_plan_t plan, double npairs, double *d_rr, void *stream);
+/*
+ * fcfc_multipoles -- Legendre multipoles of xi(s, mu) held constant within
+ * each mu bin: out[k*ns + i] = (2 l + 1) sum_j xi[i*nmu + j] * integral of
+ * P_l over [mu_j, mu_j+1], l = ells[k] (0..64).  mu_edges: host, nmu + 1
+ * values.  Errors: FCFC_EINVAL, FCFC_ENOMEM, FCFC_EHIP.
+ */
+fcfc_status fcfc_multipoles(const double *d_xi, int32_t ns, const double *mu_edges, int32_t nmu,
+                            const int32_t *ells, int32_t nell, double *d_out, void *stream);
+/*
+ * fcfc_wp -- projected correlation function w_p(s_perp_i) = 2 sum_j
+ * xi[i*npi + j] (pi_j+1 - pi_j) over all pi bins.  pi_edges: host, npi + 1
+ * values.  Errors: FCFC_EINVAL, FCFC_ENOMEM, FCFC_EHIP.
+ */
+fcfc_status fcfc_wp(const double *d_xi, int32_t nsp, const double *pi_edges, int32_t npi,
+                    double *d_out, void *stream);
+
 const char *fcfc_status_str(fcfc_status s);
 const char *fcfc_last_error(void);
 int32_t fcfc_version(void);

@@ -99,6 +99,10 @@ SIGNATURES = [
                              ctypes.POINTER(_I32)]),
     ("fcfc_diag_transcendental", _I32, [ctypes.POINTER(_D), ctypes.POINTER(_D), ctypes.POINTER(_D), _P]),
     ("fcfc_diag_peaks", _I32, [ctypes.POINTER(_D), ctypes.POINTER(_D), ctypes.POINTER(_D), ctypes.POINTER(_D), _P]),
+    ("fcfc_xi", _I32, [_I32, ctypes.POINTER(_P), ctypes.POINTER(_D), ctypes.POINTER(_D), _I32, _I64, _P, _P]),
+    ("fcfc_analytic_rr", _I32, [_P, _D, _P, _P]),
+    ("fcfc_multipoles", _I32, [_P, _I32, ctypes.POINTER(_D), _I32, ctypes.POINTER(_I32), _I32, _P, _P]),
+    ("fcfc_wp", _I32, [_P, _I32, ctypes.POINTER(_D), _I32, _P, _P]),
     ("fcfc_status_str", ctypes.c_char_p, [_I32]),
     ("fcfc_last_error", ctypes.c_char_p, []),
     ("fcfc_version", _I32, []),
@@ -447,6 +451,73 @@ def diag_peaks(stream=None):
     v = [ctypes.c_double() for _ in range(4)]
     check(load().fcfc_diag_peaks(*[ctypes.byref(x) for x in v], _stream_ptr(stream)))
     return dict(zip(("fma_tflops", "lds_u32_per_s", "lds_u64_per_s", "copy_gbps"), (x.value for x in v)))
+
+
+def _f64_dev(t, name):
+    import torch
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+        raise ValueError(f"{name} must be a contiguous CUDA float64 tensor")
+    return t
+
+
+def xi(terms, coef, norm, den, stream=None):
+    """Linear estimator: (sum_t coef_t X_t / norm_t) / (X_den / norm_den); terms are CUDA float64
+    tensors of one shape (counts: .double())."""
+    import torch
+    terms = [_f64_dev(t, "term") for t in terms]
+    n = terms[0].numel()
+    if any(t.numel() != n for t in terms):
+        raise ValueError("all terms need the same number of bins")
+    out = torch.empty_like(terms[0])
+    ptrs = (_P * len(terms))(*[t.data_ptr() for t in terms])
+    c = (_D * len(terms))(*[float(v) for v in coef])
+    nm = (_D * len(terms))(*[float(v) for v in norm])
+    check(load().fcfc_xi(len(terms), ptrs, c, nm, int(den), n, out.data_ptr(), _stream_ptr(stream)))
+    return out
+
+
+def landy_szalay(dd, dr, rr, n_d, n_r, stream=None):
+    """LS estimator for auto counts DD, RR and the cross DR of n_d data and n_r random points."""
+    return xi([dd.double(), dr.double(), rr.double()], [1.0, -2.0, 1.0],
+              [n_d * (n_d - 1) / 2.0, float(n_d) * n_r, n_r * (n_r - 1) / 2.0], 2, stream)
+
+
+def analytic_rr(plan, npairs, stream=None):
+    """Uniform periodic-box pair counts for the plan's bins (npairs = N (N - 1) / 2 for an auto count)."""
+    import torch
+    out = torch.empty(plan.n1 * plan.n2, dtype=torch.float64, device="cuda")
+    check(load().fcfc_analytic_rr(plan.h, float(npairs), out.data_ptr(), _stream_ptr(stream)))
+    return out.view(plan.shape)
+
+
+def multipoles(xi_smu, mu_edges, ells=(0, 2, 4), stream=None):
+    """Legendre multipoles of xi(s, mu) (shape (ns, nmu)): tensor (len(ells), ns)."""
+    import torch
+    x = _f64_dev(xi_smu, "xi")
+    ns, nmu = x.shape
+    mu = np.ascontiguousarray(np.asarray(mu_edges, dtype=np.float64))
+    if mu.size != nmu + 1:
+        raise ValueError("mu_edges needs nmu + 1 values")
+    ls = np.ascontiguousarray(np.asarray(ells, dtype=np.int32))
+    out = torch.empty((len(ls), ns), dtype=torch.float64, device=x.device)
+    check(load().fcfc_multipoles(x.data_ptr(), ns, mu.ctypes.data_as(ctypes.POINTER(_D)), nmu,
+                                 ls.ctypes.data_as(ctypes.POINTER(_I32)), len(ls), out.data_ptr(),
+                                 _stream_ptr(stream)))
+    return out
+
+
+def wp(xi_spi, pi_edges, stream=None):
+    """Projected correlation function of xi(s_perp, pi) (shape (nsp, npi))."""
+    import torch
+    x = _f64_dev(xi_spi, "xi")
+    nsp, npi = x.shape
+    pe = np.ascontiguousarray(np.asarray(pi_edges, dtype=np.float64))
+    if pe.size != npi + 1:
+        raise ValueError("pi_edges needs npi + 1 values")
+    out = torch.empty(nsp, dtype=torch.float64, device=x.device)
+    check(load().fcfc_wp(x.data_ptr(), nsp, pe.ctypes.data_as(ctypes.POINTER(_D)), npi, out.data_ptr(),
+                         _stream_ptr(stream)))
+    return out
 
 
 TUNING_KEYS = ("cells_per_rmax", "tile_points", "seg_cells", "b_chunk", "hist_copies", "order",

@@ -1,0 +1,94 @@
+"""Estimator kernels against the float64 oracle (oracle/estimators.py), and an
+end-to-end correlation function of a uniform periodic box.
+
+Tolerances: the estimators and w_p are short FP64 sums of the same terms in
+another order: 1e-13 relative (plus 1e-15 absolute near zero).  A multipole
+sums xi_j times the integral of P_l over the bin, and the two sides evaluate
+that integral differently (recursion at the edges vs an antiderivative
+polynomial); with |P_l| <= 1 every term is bounded by |xi_j| dmu_j, so the
+error is bounded relative to S = (2 l + 1) sum_j |xi_j| dmu_j: 1e-12 S."""
+import numpy as np
+import pytest
+
+from oracle import estimators as E
+from paper_2301_12557_amd import synth
+from helpers import note, to_dev, oracle_count
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _close(g, o):
+    g, o = np.asarray(g, dtype=np.float64), np.asarray(o, dtype=np.float64)
+    both_nan = np.isnan(g) & np.isnan(o)
+    assert np.array_equal(np.isnan(g), np.isnan(o))
+    ok = both_nan | (np.abs(g - o) <= 1e-13 * np.abs(o) + 1e-15)
+    assert np.all(ok), np.max(np.abs(g - o)[~both_nan])
+
+
+def test_linear_estimators():
+    from paper_2301_12557_amd import fcfc
+    rng = np.random.default_rng(1)
+    t = [rng.integers(0, 10**6, 4000).astype(np.float64) for _ in range(4)]
+    t[3][::97] = 0.0   # zero denominators
+    norm = [3.1e9, 7.7e11, 2.9e11, 1.3e12]
+    for terms, coef, den in ((t[:3], [1, -2, 1], 2), (t[:2], [1, -1], 1), (t, [1, -1, -1, 1], 3)):
+        g = fcfc.xi([to_dev(x) for x in terms], coef, norm[:len(terms)], den).cpu().numpy()
+        _close(g, E.xi_linear(terms, coef, norm[:len(terms)], den))
+
+
+@pytest.mark.parametrize("kind", ["s", "smu", "spi"])
+def test_analytic_rr(kind):
+    from paper_2301_12557_amd import fcfc
+    e1 = synth.linear_edges(0, 200, 40)
+    e2 = synth.mu_edges(100) if kind == "smu" else (synth.linear_edges(0, 150, 30) if kind == "spi" else None)
+    plan = fcfc.Plan(kind, e1, e2, box=1000.0)
+    npairs = 1e6 * (1e6 - 1) / 2
+    g = fcfc.analytic_rr(plan, npairs).cpu().numpy()
+    _close(g.reshape(E.bin_volumes(kind, e1, e2).shape), E.analytic_rr(kind, e1, e2, 1000.0, npairs))
+
+
+def test_multipoles_and_wp():
+    from paper_2301_12557_amd import fcfc
+    rng = np.random.default_rng(2)
+    x = rng.normal(0, 1, (40, 100))
+    mu = synth.mu_edges(100)
+    ells = (0, 2, 4, 6)
+    g = fcfc.multipoles(to_dev(x), mu, ells).cpu().numpy()
+    o = E.multipoles(x, mu, ells)
+    S = np.stack([(2 * l + 1) * (np.abs(x) @ np.diff(mu)) for l in ells])
+    assert np.all(np.abs(g - o) <= 1e-12 * S), np.max(np.abs(g - o) / S)
+    pe = synth.linear_edges(0, 80, 40)
+    y = rng.normal(0, 1, (25, 40))
+    _close(fcfc.wp(to_dev(y), pe).cpu().numpy(), E.wp(y, pe))
+
+
+def test_uniform_box_correlation_function_is_zero():
+    """xi(s, mu) of uniform periodic points from GPU pair counts and the analytic RR
+    (Peebles-Hauser) equals the oracle's, and its monopole is 0 within 5 sigma."""
+    from paper_2301_12557_amd import fcfc
+    n, L = 30000, 500.0
+    x = synth.uniform_box(n, L, 5)
+    e1 = synth.linear_edges(0, 60, 12)
+    e2 = synth.mu_edges(10)
+    plan = fcfc.Plan("smu", e1, e2, box=L, n_hint=n)
+    c = plan.build_cells(to_dev(x))
+    dd, _ = plan.count(c)
+    npairs = n * (n - 1) / 2.0
+    rr = fcfc.analytic_rr(plan, npairs)
+    xi = fcfc.xi([dd.double().reshape(-1), rr.reshape(-1)], [1, -1], [npairs, npairs], 1).view(plan.shape)
+    o, _ = oracle_count(x, kind="smu", edges1=e1, edges2=e2, box=L)
+    ref = E.xi_linear([o, E.analytic_rr("smu", e1, e2, L, npairs)], [1, -1], [npairs, npairs], 1)
+    _close(xi.cpu().numpy(), ref)
+    m = fcfc.multipoles(xi.contiguous(), e2, (0,)).cpu().numpy()[0]
+    # binomial error of the monopole: xi_0 = DD_s / RR_s - 1 over the whole shell
+    rr_s = E.analytic_rr("s", e1, None, L, npairs)
+    sig = np.sqrt(rr_s * (1 - rr_s / npairs)) / rr_s
+    note(f"monopole / sigma: {np.max(np.abs(m) / sig):.2f}")
+    assert np.all(np.abs(m[1:]) <= 5 * sig[1:])
