@@ -79,7 +79,7 @@ typedef struct fcfc_model_s *fcfc_model_t;
 typedef struct {
     const double *xyz;  /* n x 3, row-major float64 */
     const double *w;    /* n float64 weights, or NULL */
-    int64_t n;
+    int64_t n;          /* 0 .. 2^31 points (FCFC_EINVAL beyond) */
 } fcfc_catalog;
 
 /* Tuning knobs; zero means "choose".  Counts never depend on them. */

@@ -189,3 +189,23 @@ def test_plan_rejects_bad_shard():
     t.shard_count = -1
     t.shard_index = 0
     assert _create(tune=t) == -1
+
+
+def test_build_cells_rejects_oversized_catalogue():
+    """Catalogues hold at most 2^31 points (32-bit point indices in the work
+    list); beyond that, or with a negative size, build_cells refuses on the host."""
+    lib = fcfc.load()
+    e1 = np.asarray([0.0, 1.0, 2.0])
+    p = ctypes.c_void_p()
+    assert lib.fcfc_plan_create(0, 0, e1.ctypes.data_as(ctypes.c_void_p), 2, None, 0, 10.0, None,
+                                ctypes.byref(p)) == 0
+    out = ctypes.c_void_p()
+    for n in ((1 << 31) + 1, -1):
+        cat = fcfc.Catalog()
+        cat.xyz = ctypes.c_void_p(16)    # never dereferenced: the size check comes first
+        cat.w = None
+        cat.n = n
+        assert lib.fcfc_build_cells(p, ctypes.byref(cat), None, ctypes.byref(out)) == -1
+        assert b"2^31" in lib.fcfc_last_error()
+    assert not out.value
+    lib.fcfc_plan_free(p)
