@@ -43,6 +43,7 @@ def parse():
     ap.add_argument("--c4-repeats", type=int, default=5)
     ap.add_argument("--no-learned", action="store_true", help="skip training and the held-out C5 comparison")
     ap.add_argument("--no-peaks", action="store_true", help="skip the roofline microbenchmarks")
+    ap.add_argument("--no-pairs", action="store_true", help="skip the multi-tracer pair-list comparison")
     ap.add_argument("--shards", type=int, default=0,
                     help="also count each of G work-list shards (one GPU's share of a G-GPU run) and report "
                          "their kernel times")
@@ -291,6 +292,67 @@ def c5_section(fcfc, synth, model):
     return res
 
 
+# The multi-tracer pair list of the paper's quick guide (App. D): LRG data
+# and randoms (L, R), ELG data and randoms (E, S).
+TRACERS = (("L", 100_000), ("R", 500_000), ("E", 150_000), ("S", 750_000))
+TRACER_PAIRS = ("LL", "LR", "RR", "EE", "ES", "SS", "LE", "LS", "RE", "RS")
+
+
+def pairs_section(fcfc, synth, torch, repeats=3):
+    """Multi-tracer counts (S) per pair, each a separate count over cell sets
+    built once, against (M) one pair batch: one build, one work list, one
+    counting launch, replayed from a HIP graph.  Survey patch as C3 (open box,
+    mid-point line of sight, 40x40 (s_perp, pi) bins to 200), weights U[0.5, 2]."""
+    lab = [t for t, _ in TRACERS]
+    xs = [torch.from_numpy(synth.survey_shell(n, synth.config_seed(3) + 100 + i)).cuda()
+          for i, (_, n) in enumerate(TRACERS)]
+    ws = [torch.from_numpy(synth.uniform_weights(n, 0.5, 2.0, synth.config_seed(3) + 200 + i)).cuda()
+          for i, (_, n) in enumerate(TRACERS)]
+    pairs = [(lab.index(pq[0]), lab.index(pq[1])) for pq in TRACER_PAIRS]
+    e = synth.linear_edges(0, 200, 40)
+    plan = fcfc.Plan("spi", e, e, los="mid", box=0.0, n_hint=max(n for _, n in TRACERS))
+    plan.fit_bounds([(x, None) for x in xs])
+    nb = plan.n1 * plan.n2
+    outS = torch.empty(len(pairs) * nb, dtype=torch.int64, device="cuda")
+    woutS = torch.empty(len(pairs) * nb, dtype=torch.float64, device="cuda")
+
+    def separate():
+        cells = [plan.build_cells(x, w) for x, w in zip(xs, ws)]
+        for q, (a, b) in enumerate(pairs):
+            plan.count(cells[a], None if a == b else cells[b], weighted=True, out=outS[q * nb:(q + 1) * nb],
+                       wout=woutS[q * nb:(q + 1) * nb])
+        for c in cells:
+            c.close()
+
+    separate()
+    tS = [_sync_time(separate)[0] for _ in range(repeats)]
+    out = torch.empty_like(outS)
+    wout = torch.empty_like(woutS)
+    create_ms, b = _sync_time(lambda: fcfc.Batch(plan, list(zip(xs, ws)), pairs=pairs))
+    first_ms, _ = _sync_time(lambda: b.run(out, wout, use_graph=True))
+    tM = []
+    for _ in range(repeats):
+        ms, _ = _sync_time(lambda: b.run(out, wout, use_graph=True))
+        tM.append(ms)
+    n_items, gpu_ms = b.check()
+    equal = bool(torch.equal(out, outS) and torch.equal(wout, woutS))
+    b.close()
+    plan.close()
+    total = int(outS.sum().item())
+    return {
+        "workload": "multi-tracer survey patch (RA 60 deg, Dec +-15 deg, r 1000-2000, open box): "
+                    + ", ".join(f"{t} {n}" for t, n in TRACERS) + "; pairs " + " ".join(TRACER_PAIRS)
+                    + "; (s_perp, pi) 40x40 to 200, mid-point LOS, weights U[0.5, 2]",
+        "in_range_pairs": total,
+        "separate_ms": float(np.mean(tS)), "separate_ms_sd": float(np.std(tS)),
+        "batch_ms": float(np.mean(tM)), "batch_ms_sd": float(np.std(tM)), "runs": repeats,
+        "batch_create_ms": create_ms, "batch_first_run_ms": first_ms, "batch_items": n_items,
+        "batch_over_separate": float(np.mean(tS) / np.mean(tM)),
+        "in_range_pairs_per_s_batch": total / (np.mean(tM) * 1e-3),
+        "counts_equal": equal,
+    }
+
+
 def c3_main(args, fcfc, torch):
     """C3 (open box, mid-point line of sight): DD and DR (and RR) per step."""
     weighted = not args.unweighted
@@ -501,6 +563,11 @@ def main():
         if not args.no_learned:
             res["learned"]["c5_heldout"] = c5_section(fcfc, synth, model)
             log("C5 held-out comparison done")
+    if not args.no_pairs:
+        from paper_2301_12557_amd import synth
+        res["pairs"] = pairs_section(fcfc, synth, torch)
+        log(f"multi-tracer pairs: separate {res['pairs']['separate_ms']:.1f} ms, "
+            f"one batch {res['pairs']['batch_ms']:.1f} ms, equal {res['pairs']['counts_equal']}")
     if not args.no_cpu_baseline:
         log("timing the CPU oracle")
         res["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)

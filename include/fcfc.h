@@ -96,7 +96,8 @@ typedef struct {
     int32_t group_waves;     /* wavefronts per counting workgroup, 1..16 (0: as many as fit) */
     int32_t shard_count;     /* 0 or 1: the whole work list; G > 1: count one of G shards */
     int32_t shard_index;     /* the shard counted, 0..G-1: ordered items i with i % G == index */
-    int32_t reserved[4];
+    int32_t batch_chunk;     /* batches: work items per wavefront a workgroup takes at once, 1..1024 (0: 32) */
+    int32_t reserved[3];
 } fcfc_tuning;
 
 /* Statistics of the last count on a plan (host copy; see fcfc_plan_stats). */
@@ -188,20 +189,39 @@ fcfc_status fcfc_plan_stats(fcfc_plan_t plan, fcfc_stats *out);
 
 /*
  * fcfc_batch_create / fcfc_batch_run -- auto counts of many catalogues on one
- * periodic plan (line of sight z) in one pipeline: one cell build keyed by
- * (catalogue, cell), one work list, one persistent counting launch that
- * writes ncat histograms (d_counts: ncat x n1*n2 int64; d_wcounts likewise,
- * or NULL).  Each unordered pair of every catalogue is counted once, exactly
- * as fcfc_count_pairs does per catalogue.  fcfc_batch_create validates the
- * catalogues, sizes every buffer (synchronising `stream` once) and keeps the
- * catalogue pointers: they must stay valid and keep their sizes for the life
- * of the batch.  fcfc_batch_run enqueues the whole pipeline; with use_graph
- * it is captured into a HIP graph on the first run and replayed afterwards.
- * Errors: FCFC_ESTATE (open plan), FCFC_EINVAL (mixed weights, nulls),
- * FCFC_EBOX, FCFC_ENONFINITE, FCFC_ERANGE, FCFC_ENOMEM, FCFC_EHIP.
+ * plan in one pipeline: one cell build keyed by (catalogue, cell), one work
+ * list, one persistent counting launch that writes ncat histograms
+ * (d_counts: ncat x n1*n2 int64; d_wcounts likewise, or NULL).  Each
+ * unordered pair of every catalogue is counted once, exactly as
+ * fcfc_count_pairs does per catalogue.  Any plan works: periodic, or an open
+ * box whose bounds are set (fcfc_plan_fit_bounds over every catalogue, or
+ * fcfc_plan_set_bounds), with either line of sight.  fcfc_batch_create
+ * validates the catalogues, sizes every buffer (synchronising `stream` once)
+ * and keeps the catalogue pointers: they must stay valid and keep their sizes
+ * for the life of the batch.  fcfc_batch_run enqueues the whole pipeline;
+ * with use_graph it is captured into a HIP graph on the first run and
+ * replayed afterwards.
+ * Errors: FCFC_ESTATE (open plan without bounds), FCFC_EINVAL (mixed weights,
+ * nulls), FCFC_EBOX, FCFC_ENONFINITE, FCFC_ERANGE, FCFC_ENOMEM, FCFC_EHIP.
  */
 fcfc_status fcfc_batch_create(fcfc_plan_t plan, const fcfc_catalog *cats, int32_t ncat,
                               void *stream, fcfc_batch_t *out);
+/*
+ * fcfc_batch_create_pairs -- like fcfc_batch_create, for any list of
+ * catalogue pairs: pairs[2q] = a, pairs[2q+1] = b (0 <= a, b < ncat).  a == b
+ * is the auto count of catalogue a (unordered pairs, as fcfc_count_pairs with
+ * c2 = NULL); a != b the cross count of every ordered pair (i in a, j in b).
+ * This is the multi-tracer configuration of App. D (data, randoms and other
+ * tracers counted against each other, e.g. DD, DR, RR) with one shared cell
+ * build: fcfc_batch_run writes npairs histograms, d_counts[q * n1*n2 + bin]
+ * for pair q, in one counting launch whose work items of all pairs share the
+ * GPU (largest estimated pair first).  Weighted counts need weights in every
+ * catalogue.  Errors as fcfc_batch_create, plus FCFC_EINVAL for npairs < 1,
+ * npairs > 2^20 or a catalogue index outside [0, ncat).
+ */
+fcfc_status fcfc_batch_create_pairs(fcfc_plan_t plan, const fcfc_catalog *cats, int32_t ncat,
+                                    const int32_t *pairs, int32_t npairs, void *stream,
+                                    fcfc_batch_t *out);
 fcfc_status fcfc_batch_run(fcfc_batch_t batch, int64_t *d_counts, double *d_wcounts,
                            int32_t use_graph, void *stream);
 /*

@@ -1,14 +1,16 @@
-// batch.hip -- C ABI of the batched pipeline (many periodic catalogues).
+// batch.hip -- C ABI of the batched pipeline (many catalogues, one cell
+// build, one work list and one counting launch for a list of catalogue pairs).
+#include <vector>
+
 #include "internal.h"
 
 using namespace fcfc;
 
-extern "C" fcfc_status fcfc_batch_create(fcfc_plan_t plan, const fcfc_catalog* cats, int32_t ncat, void* stream,
-                                         fcfc_batch_t* out) {
-    clear_error();
+static fcfc_status batch_create(fcfc_plan_t plan, const fcfc_catalog* cats, int32_t ncat, const int32_t* pairs,
+                                int32_t npairs, void* stream, fcfc_batch_t* out) {
     Plan* p = (Plan*)plan;
-    if (!p || !cats || ncat < 1 || !out) {
-        set_error("batch_create: null plan, catalogues or output, or ncat < 1");
+    if (!p || !cats || ncat < 1 || !out || !pairs || npairs < 1) {
+        set_error("batch_create: null plan, catalogues, pairs or output, or no catalogue / pair");
         return FCFC_EINVAL;
     }
     for (int c = 0; c < ncat; c++) {
@@ -17,10 +19,39 @@ extern "C" fcfc_status fcfc_batch_create(fcfc_plan_t plan, const fcfc_catalog* c
             return FCFC_EINVAL;
         }
     }
+    for (int q = 0; q < npairs; q++) {
+        if (pairs[2 * q] < 0 || pairs[2 * q] >= ncat || pairs[2 * q + 1] < 0 || pairs[2 * q + 1] >= ncat) {
+            set_error("batch_create: pair %d names a catalogue outside [0, %d)", q, ncat);
+            return FCFC_EINVAL;
+        }
+    }
     BatchImpl* b = nullptr;
-    fcfc_status s = batch_create_impl(p, cats, ncat, (hipStream_t)stream, &b);
+    fcfc_status s = batch_create_impl(p, cats, ncat, pairs, npairs, (hipStream_t)stream, &b);
     if (s == FCFC_OK) *out = (fcfc_batch_t)b;
     return s;
+}
+
+extern "C" fcfc_status fcfc_batch_create(fcfc_plan_t plan, const fcfc_catalog* cats, int32_t ncat, void* stream,
+                                         fcfc_batch_t* out) {
+    clear_error();
+    if (ncat < 1 || ncat > (1 << 20)) {
+        set_error("batch_create: need 1 .. 2^20 catalogues");
+        return FCFC_EINVAL;
+    }
+    std::vector<int32_t> pairs(2 * (size_t)ncat);
+    for (int c = 0; c < ncat; c++) pairs[2 * c] = pairs[2 * c + 1] = c;  // the auto count of every catalogue
+    return batch_create(plan, cats, ncat, pairs.data(), ncat, stream, out);
+}
+
+extern "C" fcfc_status fcfc_batch_create_pairs(fcfc_plan_t plan, const fcfc_catalog* cats, int32_t ncat,
+                                               const int32_t* pairs, int32_t npairs, void* stream,
+                                               fcfc_batch_t* out) {
+    clear_error();
+    if (npairs > (1 << 20)) {
+        set_error("batch_create_pairs: at most 2^20 pairs");
+        return FCFC_EINVAL;
+    }
+    return batch_create(plan, cats, ncat, pairs, npairs, stream, out);
 }
 
 extern "C" fcfc_status fcfc_batch_run(fcfc_batch_t batch, int64_t* d_counts, double* d_wcounts, int32_t use_graph,

@@ -484,7 +484,7 @@ fcfc_status build_cells(Plan* p, const fcfc_catalog* cat, hipStream_t st, Cells*
     c->plan_id = p->id;
     c->grid = gr;
     c->n = n;
-    c->weighted = weighted;
+    c->weighted = weighted || n == 0;  // an empty set takes part in weighted counts (it adds nothing)
     c->has_abs = need_abs;
     c->pos32 = (float4*)(blk + o_pos32);
     c->abs32 = need_abs ? (float4*)(blk + o_abs32) : nullptr;
@@ -567,9 +567,10 @@ fcfc_status build_cells(Plan* p, const fcfc_catalog* cat, hipStream_t st, Cells*
 }
 
 // ---------------------------------------------------------------------------
-// batched build: many periodic catalogues on one grid, sorted by the
-// combined key (catalogue * ncell + cell) so that catalogue c occupies the
-// cells [c * ncell, (c+1) * ncell) of one stacked grid
+// batched build: many catalogues on one grid (periodic, or an open box
+// inside the plan bounds), sorted by the combined key (catalogue * ncell +
+// cell) so that catalogue c occupies the cells [c * ncell, (c+1) * ncell) of
+// one stacked grid
 // ---------------------------------------------------------------------------
 __device__ inline int find_cat(const int64_t* __restrict__ offs, int ncat, int64_t i) {
     int lo = 0, hi = ncat;  // offs[lo] <= i < offs[hi]
@@ -600,13 +601,18 @@ __global__ __launch_bounds__(256) void k_bkeys(const CatDesc* __restrict__ cats,
         const int64_t li = i - offs[c];
         double x = d.xyz[3 * li], y = d.xyz[3 * li + 1], z = d.xyz[3 * li + 2];
         uint32_t f = 0;
-        if (!isfinite(x) || !isfinite(y) || !isfinite(z)) f |= VF_NONFINITE;
-        else if (!(x >= 0.0 && x < g.L && y >= 0.0 && y < g.L && z >= 0.0 && z < g.L)) f |= VF_BOX;
+        if (!isfinite(x) || !isfinite(y) || !isfinite(z)) {
+            f |= VF_NONFINITE;
+        } else if (g.L > 0) {
+            if (!(x >= 0.0 && x < g.L && y >= 0.0 && y < g.L && z >= 0.0 && z < g.L)) f |= VF_BOX;
+        } else {
+            if (!(x >= g.lox && x <= g.hix && y >= g.loy && y <= g.hiy && z >= g.loz && z <= g.hiz)) f |= VF_BOX;
+        }
         uint32_t cx = 0, cy = 0, cz = 0;
         if (!f) {
-            cx = cell_of(x, 0.0, g.side, g.nx);
-            cy = cell_of(y, 0.0, g.side, g.ny);
-            cz = cell_of(z, 0.0, g.side, g.nz);
+            cx = cell_of(x, g.lox, g.side, g.nx);
+            cy = cell_of(y, g.loy, g.side, g.ny);
+            cz = cell_of(z, g.loz, g.side, g.nz);
         }
         key[i] = (((uint32_t)c * (uint32_t)g.nz + cz) * (uint32_t)g.ny + cy) * (uint32_t)g.nx + cx;
         idx[i] = (uint32_t)i;
@@ -634,8 +640,8 @@ __global__ __launch_bounds__(256) void k_bkeys(const CatDesc* __restrict__ cats,
 __global__ __launch_bounds__(256) void k_bgather(const CatDesc* __restrict__ cats, const int64_t* __restrict__ offs,
                                                  int ncat, const uint32_t* __restrict__ skey,
                                                  const uint32_t* __restrict__ sidx, int64_t n, GridArgs g,
-                                                 float4* __restrict__ pos32, double* __restrict__ pos64,
-                                                 double* __restrict__ wout) {
+                                                 float4* __restrict__ pos32, float4* __restrict__ abs32,
+                                                 double* __restrict__ pos64, double* __restrict__ wout) {
     int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= n) return;
     uint32_t i = sidx[p];
@@ -647,8 +653,11 @@ __global__ __launch_bounds__(256) void k_bgather(const CatDesc* __restrict__ cat
     uint32_t cy = (key / (uint32_t)g.nx) % (uint32_t)g.ny;
     uint32_t cz = (key / ((uint32_t)g.nx * (uint32_t)g.ny)) % (uint32_t)g.nz;
     double x = d.xyz[3 * li], y = d.xyz[3 * li + 1], z = d.xyz[3 * li + 2];
-    pos32[p] = make_float4((float)(x - (double)cx * g.side), (float)(y - (double)cy * g.side),
-                           (float)(z - (double)cz * g.side), __int_as_float((int)cx));
+    const double ox = g.lox + (double)cx * g.side;
+    const double oy = g.loy + (double)cy * g.side;
+    const double oz = g.loz + (double)cz * g.side;
+    pos32[p] = make_float4((float)(x - ox), (float)(y - oy), (float)(z - oz), __int_as_float((int)cx));
+    if (abs32) abs32[p] = make_float4((float)x, (float)y, (float)z, 0.f);
     pos64[3 * p] = x;
     pos64[3 * p + 1] = y;
     pos64[3 * p + 2] = z;
@@ -660,8 +669,8 @@ size_t batch_build_scratch(int64_t ntot) { return radix_scratch_bytes(ntot); }
 // Enqueue the batched build (no host synchronisation: capturable).
 void batch_build_enqueue(const Plan* p, const CatDesc* desc, const int64_t* offs, int ncat, int64_t ntot,
                          bool weighted, uint32_t** key, uint32_t** idx, uint32_t** tk, uint32_t** tv, void* sort_scr,
-                         uint32_t* flags, uint64_t* wst, float4* pos32, double* pos64, double* w, uint32_t* cs,
-                         hipStream_t st) {
+                         uint32_t* flags, uint64_t* wst, float4* pos32, float4* abs32, double* pos64, double* w,
+                         uint32_t* cs, hipStream_t st) {
     GridArgs g = make_grid_args(p);
     const int64_t ncell_all = p->grid.ncell() * (int64_t)ncat;
     fill_u32((uint32_t*)(pos32 + ntot), 0u, 8 * 4, st);
@@ -677,7 +686,7 @@ void batch_build_enqueue(const Plan* p, const CatDesc* desc, const int64_t* offs
         bits = (bits + 7) / 8 * 8;
         radix_sort_pairs(key, idx, tk, tv, ntot, bits, sort_scr, st);
         hipLaunchKernelGGL(k_bgather, dim3((unsigned)((ntot + 255) / 256)), dim3(256), 0, st, desc, offs, ncat, *key,
-                           *idx, ntot, g, pos32, pos64, weighted ? w : nullptr);
+                           *idx, ntot, g, pos32, abs32, pos64, weighted ? w : nullptr);
     }
     hipLaunchKernelGGL(k_cell_start, dim3((unsigned)((ntot + 1 + 255) / 256)), dim3(256), 0, st, *key, ntot, ncell_all,
                        cs);

@@ -100,13 +100,13 @@ struct CountArgs {
     int wpre;  // 1: staged A weights carry the scale 2^S (see prescale_ok)
     int copies;
     uint32_t shard_count, shard_index;  // this launch takes items shard_index, + shard_count, ...
-    // batched mode: chunks of items per catalogue
+    // batched mode: chunks of items per output histogram (one per catalogue pair)
     const uint32_t* nchunks_dev;
     uint32_t* chunk_cursor;
-    const uint32_t* chunk_prefix;  // ncat + 1, in catalogue order
-    const uint32_t* cat_order;     // catalogue index at each order position
-    const uint32_t* cat_items;     // ncat + 1: items of catalogue c are [cat_items[c], cat_items[c+1])
-    int ncat;
+    const uint32_t* chunk_prefix;  // ncat + 1, in histogram order
+    const uint32_t* cat_order;     // histogram index at each order position
+    const uint32_t* cat_items;     // ncat + 1: items of histogram c are [cat_items[c], cat_items[c+1])
+    int ncat;                      // histograms
     int chunk_items;
     // LDS layout (bytes)
     int off_lut1, off_lut2, off_band1, off_band2, off_hist, off_whist, off_q, off_qw, off_rb, off_astage,
@@ -879,15 +879,20 @@ static CountKernel pick_kernel(int kind, int los, bool is_auto, bool w, int P) {
     return los == FCFC_LOS_Z ? pick_aw<FCFC_BIN_SPERP_PI, FCFC_LOS_Z>(is_auto, w, P)
                              : pick_aw<FCFC_BIN_SPERP_PI, FCFC_LOS_MIDPOINT>(is_auto, w, P);
 }
-// batched auto counts in a periodic box (line of sight z)
-static CountKernel pick_batch_kernel(int kind, bool w, int P) {
-    if (kind == FCFC_BIN_S)
-        return w ? pick_p<FCFC_BIN_S, FCFC_LOS_Z, true, true, true>(P) : pick_p<FCFC_BIN_S, FCFC_LOS_Z, true, false, true>(P);
+// batched counts (auto and cross pairs of a stacked build): the auto
+// instantiation serves both, since only items of an auto pair carry the
+// same-row flag
+template <int KIND, int LOS>
+static CountKernel pick_bw(bool w, int P) {
+    return w ? pick_p<KIND, LOS, true, true, true>(P) : pick_p<KIND, LOS, true, false, true>(P);
+}
+static CountKernel pick_batch_kernel(int kind, int los, bool w, int P) {
+    if (kind == FCFC_BIN_S) return pick_bw<FCFC_BIN_S, FCFC_LOS_Z>(w, P);
     if (kind == FCFC_BIN_S_MU)
-        return w ? pick_p<FCFC_BIN_S_MU, FCFC_LOS_Z, true, true, true>(P)
-                 : pick_p<FCFC_BIN_S_MU, FCFC_LOS_Z, true, false, true>(P);
-    return w ? pick_p<FCFC_BIN_SPERP_PI, FCFC_LOS_Z, true, true, true>(P)
-             : pick_p<FCFC_BIN_SPERP_PI, FCFC_LOS_Z, true, false, true>(P);
+        return los == FCFC_LOS_Z ? pick_bw<FCFC_BIN_S_MU, FCFC_LOS_Z>(w, P)
+                                 : pick_bw<FCFC_BIN_S_MU, FCFC_LOS_MIDPOINT>(w, P);
+    return los == FCFC_LOS_Z ? pick_bw<FCFC_BIN_SPERP_PI, FCFC_LOS_Z>(w, P)
+                             : pick_bw<FCFC_BIN_SPERP_PI, FCFC_LOS_MIDPOINT>(w, P);
 }
 
 static int al16(int b) { return (b + 15) & ~15; }
@@ -933,15 +938,19 @@ static fcfc_status weight_scale(double wmin1, double wmax1, double wmin2, double
     return FCFC_OK;
 }
 
+// Most cells a tile may span: about T points' worth at ppc points per cell
+// (one cell when a cell holds half a tile or more), unless tuned.
+static int tile_seg(const Plan* p, int T, double ppc) {
+    if (p->tune.seg_cells > 0) return std::min(32, p->tune.seg_cells);
+    if (ppc >= T / 2) return 1;
+    return (int)std::max(1.0, std::min(16.0, floor((double)T / std::max(ppc, 1e-9))));
+}
+
 static fcfc_status setup_launch(Plan* p, bool is_auto, bool weighted, bool batch, double ppc, int S, LaunchSetup& L) {
     const Grid& g = p->grid;
     L.T = p->tune.tile_points == 64 ? 64 : 128;
     L.P = L.T / 64;
-    L.seg = p->tune.seg_cells > 0 ? std::min(32, p->tune.seg_cells) : 0;
-    if (L.seg == 0) {
-        L.seg = (int)std::max(1.0, std::min(16.0, floor((double)L.T / std::max(ppc, 1e-9))));
-        if (ppc >= L.T / 2) L.seg = 1;
-    }
+    L.seg = tile_seg(p, L.T, ppc);
     L.bchunk = p->tune.b_chunk >= 256 ? p->tune.b_chunk : 16384;
     L.copies = (p->tune.hist_copies == 2 || p->tune.hist_copies == 4) ? p->tune.hist_copies : 1;
     L.nrows = stencil_rows(p, is_auto, L.rows);
@@ -973,7 +982,8 @@ static fcfc_status setup_launch(Plan* p, bool is_auto, bool weighted, bool batch
     int dev = 0, maxlds = 65536;
     FCFC_HIP(hipGetDevice(&dev));
     if (hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) maxlds = 65536;
-    L.kern = batch ? pick_batch_kernel(p->kind, weighted, L.P) : pick_kernel(p->kind, p->los, is_auto, weighted, L.P);
+    L.kern = batch ? pick_batch_kernel(p->kind, p->los, weighted, L.P)
+                   : pick_kernel(p->kind, p->los, is_auto, weighted, L.P);
     FCFC_HIP(hipFuncSetAttribute((const void*)L.kern, hipFuncAttributeMaxDynamicSharedMemorySize, maxlds));
     auto lds_for = [&](int w) { return shared_bytes + w * per_wave + 64; };
     if (p->tune.group_waves >= 1 && p->tune.group_waves <= 16) {
@@ -1088,7 +1098,7 @@ static int4* bind_tables(const LaunchSetup& L, char* tab, CountArgs& a) {
 
 static WLArgs make_wl(const Plan* p, const LaunchSetup& L, bool is_auto, int ncat, int64_t npoints_a) {
     const Grid& g = p->grid;
-    WLArgs w;
+    WLArgs w{};
     w.nx = g.nx;
     w.ny = g.ny;
     w.nz = g.nz;
@@ -1098,6 +1108,7 @@ static WLArgs make_wl(const Plan* p, const LaunchSetup& L, bool is_auto, int nca
     w.nrows = std::max(1, L.nrows);
     w.periodic = g.L > 0;
     w.is_auto = is_auto;
+    w.full_rows = !is_auto;  // stencil_rows keeps the half stencil for auto counts
     w.ncat = ncat;
     // tiles end at `tile` points, at a span of `seg` cells, or at a row end
     const int64_t nrow = (int64_t)g.ny * g.nz * ncat;
@@ -1406,6 +1417,7 @@ __global__ void k_clamp_items(uint32_t* ctr, uint32_t cap) {
 struct BatchImpl {
     Plan* plan = nullptr;
     int ncat = 0;
+    int npairs = 0;  // histograms written: one per (A, B) catalogue pair
     int64_t ntot = 0;
     bool weighted = false;
     int S = 0;
@@ -1424,15 +1436,26 @@ struct BatchImpl {
     uint32_t* flags = nullptr;
     uint64_t* wst = nullptr;
     float4* pos32 = nullptr;
+    float4* abs32 = nullptr;  // absolute FP32 positions (mid-point line of sight only)
     double* pos64 = nullptr;
     double* w = nullptr;
     uint32_t* cs = nullptr;
+    int32_t* pairs = nullptr;  // 2 per pair
+    uint32_t *ptile_off = nullptr, *ptile_first = nullptr;
+    int* cat_seg = nullptr;    // tile span per catalogue (from its own density)
+    // largest-first order within each pair: keys, values, sort scratch, sorted items
+    uint32_t *sk0 = nullptr, *sv0 = nullptr, *sk1 = nullptr, *sv1 = nullptr;
+    void* isort_scr = nullptr;
+    Item* items2 = nullptr;
+    int sort_bits = 8;
+    uint32_t key_last = 0;
     uint32_t *tcount = nullptr, *toff = nullptr, *icount = nullptr, *ioff = nullptr;
     void* scan_scr = nullptr;
     Tile* tiles = nullptr;
     Item* items = nullptr;
     uint32_t* ctr = nullptr;  // [0] ntiles [1] nitems [2] cursor [3] nchunks [4] chunk cursor [5] overflow
-    uint32_t *cat_items = nullptr, *cat_order = nullptr, *chunk_prefix = nullptr;
+    // pair_items: npairs + 1 item offsets; pair_order: pairs by decreasing estimated cost
+    uint32_t *pair_items = nullptr, *pair_order = nullptr, *chunk_prefix = nullptr;
     unsigned long long* counts = nullptr;
     unsigned long long* wacc = nullptr;
     double* wout = nullptr;
@@ -1441,6 +1464,7 @@ struct BatchImpl {
     std::vector<void*> allocs;
     std::vector<char> host_args;
     std::vector<uint32_t> host_order;
+    std::vector<int32_t> host_pairs;
     std::vector<CatDesc> host_desc;
     std::vector<int64_t> host_offs;
     hipGraph_t graph = nullptr;
@@ -1475,7 +1499,7 @@ static void batch_enqueue_front(BatchImpl* b, hipStream_t st) {
     Plan* p = b->plan;
     uint32_t *k = b->key, *v = b->idx, *tk = b->tk, *tv = b->tv;
     batch_build_enqueue(p, b->desc, b->offs, b->ncat, b->ntot, b->weighted, &k, &v, &tk, &tv, b->sort_scr, b->flags,
-                        b->wst, b->pos32, b->pos64, b->w, b->cs, st);
+                        b->wst, b->pos32, b->abs32, b->pos64, b->w, b->cs, st);
     b->key_s = k;
     b->idx_s = v;
     int4* srows = (int4*)(b->tab + (b->L.tb_total - b->L.tb_rows));
@@ -1484,6 +1508,7 @@ static void batch_enqueue_front(BatchImpl* b, hipStream_t st) {
     scan_exclusive_u32(b->tcount, b->toff, b->nseg, &b->ctr[0], b->scan_scr, st);
     hipLaunchKernelGGL(k_tile_write, dim3((unsigned)((b->nseg + 255) / 256)), dim3(256), 0, st, b->cs, b->pos32, b->wl,
                        b->toff, b->tiles);
+    hipLaunchKernelGGL(k_pair_tiles, dim3(1), dim3(1), 0, st, b->toff, &b->ctr[0], b->wl, b->ptile_off, b->ptile_first);
     hipLaunchKernelGGL(k_item_count, dim3((unsigned)((b->npair_tr + 255) / 256)), dim3(256), 0, st, b->tiles, &b->ctr[0],
                        srows, b->cs, b->wl, b->icount);
     scan_exclusive_u32(b->icount, b->ioff, b->npair_tr, &b->ctr[1], b->scan_scr, st);
@@ -1496,38 +1521,49 @@ static void batch_enqueue_back(BatchImpl* b, hipStream_t st) {
     hipLaunchKernelGGL(k_clamp_items, dim3(1), dim3(1), 0, st, b->ctr, b->items_cap);
     hipLaunchKernelGGL(k_item_write, dim3((unsigned)((b->npair_tr + 255) / 256)), dim3(256), 0, st, b->tiles, &b->ctr[0],
                        srows, b->cs, b->wl, b->ioff, b->items, b->items_cap);
-    hipLaunchKernelGGL(k_cat_items, dim3((b->ncat + 1 + 255) / 256), dim3(256), 0, st, b->toff, b->ioff, &b->ctr[1], b->wl,
-                       b->cat_items);
-    hipLaunchKernelGGL(k_chunk_prefix, dim3(1), dim3(1), 0, st, b->cat_items, b->cat_order, b->ncat, b->L.a.chunk_items,
-                       b->chunk_prefix, &b->ctr[3]);
-    fill_u64((uint64_t*)b->counts, 0ull, (int64_t)b->ncat * p->nbins, st);
-    if (b->weighted) fill_u64((uint64_t*)b->wacc, 0ull, 2 * (int64_t)b->ncat * p->nbins, st);
+    hipLaunchKernelGGL(k_pair_items, dim3((b->npairs + 1 + 255) / 256), dim3(256), 0, st, b->ioff, &b->ctr[1], b->wl,
+                       b->pair_items);
+    // each pair's items largest first (pairs stay in place)
+    {
+        const unsigned nb = (b->items_cap + 255) / 256;
+        uint32_t *k0 = b->sk0, *v0 = b->sv0, *k1 = b->sk1, *v1 = b->sv1;
+        hipLaunchKernelGGL(k_pair_item_keys, dim3(nb), dim3(256), 0, st, b->items, &b->ctr[1], b->items_cap,
+                           b->pair_items, b->npairs, b->key_last, k0, v0);
+        radix_sort_pairs(&k0, &v0, &k1, &v1, b->items_cap, b->sort_bits, b->isort_scr, st);
+        hipLaunchKernelGGL(k_item_permute, dim3(nb), dim3(256), 0, st, b->items, v0, &b->ctr[1], b->items_cap,
+                           b->items2);
+    }
+    hipLaunchKernelGGL(k_chunk_prefix, dim3(1), dim3(1), 0, st, b->pair_items, b->pair_order, b->npairs,
+                       b->L.a.chunk_items, b->chunk_prefix, &b->ctr[3]);
+    fill_u64((uint64_t*)b->counts, 0ull, (int64_t)b->npairs * p->nbins, st);
+    if (b->weighted) fill_u64((uint64_t*)b->wacc, 0ull, 2 * (int64_t)b->npairs * p->nbins, st);
     hipLaunchKernelGGL(b->L.kern, dim3((unsigned)b->nblk), dim3(b->L.waves * 64), (size_t)b->L.a.lds_bytes, st,
                        (const CountArgs*)b->args_dev);
     if (b->weighted)
-        hipLaunchKernelGGL(k_finalize_w, dim3((b->ncat * p->nbins + 255) / 256), dim3(256), 0, st, b->wacc,
-                           b->ncat * p->nbins, b->S, b->wout);
+        hipLaunchKernelGGL(k_finalize_w, dim3((b->npairs * p->nbins + 255) / 256), dim3(256), 0, st, b->wacc,
+                           b->npairs * p->nbins, b->S, b->wout);
 }
 
-fcfc_status batch_create_impl(Plan* p, const fcfc_catalog* cats, int ncat, hipStream_t st, BatchImpl** out) {
-    if (p->L <= 0) {
-        set_error("batch_create: batched counts need a periodic plan");
+fcfc_status batch_create_impl(Plan* p, const fcfc_catalog* cats, int ncat, const int32_t* pairs, int npairs,
+                              hipStream_t st, BatchImpl** out) {
+    if (p->L <= 0 && !p->grid_set) {
+        set_error("batch_create: an open-box plan needs fcfc_plan_fit_bounds or fcfc_plan_set_bounds first");
         return FCFC_ESTATE;
-    }
-    if (p->los == FCFC_LOS_MIDPOINT && p->kind != FCFC_BIN_S) {
-        set_error("batch_create: batched counts use the z line of sight");
-        return FCFC_EINVAL;
     }
     BatchImpl* b = new (std::nothrow) BatchImpl();
     if (!b) return FCFC_ENOMEM;
     b->plan = p;
     b->ncat = ncat;
-    b->weighted = cats[0].w != nullptr;
+    b->npairs = npairs;
+    // weighted when any catalogue has weights; an empty catalogue has no weights to give
+    b->weighted = false;
+    for (int c = 0; c < ncat; c++) b->weighted = b->weighted || cats[c].w != nullptr;
     b->host_desc.resize(ncat);
     b->host_offs.resize(ncat + 1);
+    b->host_pairs.assign(pairs, pairs + 2 * (size_t)npairs);
     int64_t tot = 0;
     for (int c = 0; c < ncat; c++) {
-        if ((cats[c].w != nullptr) != b->weighted) {
+        if (cats[c].n > 0 && (cats[c].w != nullptr) != b->weighted) {
             delete b;
             set_error("batch_create: either every catalogue has weights or none");
             return FCFC_EINVAL;
@@ -1549,26 +1585,49 @@ fcfc_status batch_create_impl(Plan* p, const fcfc_catalog* cats, int ncat, hipSt
         set_error("batch_create: catalogues x cells exceeds 2^31");
         return FCFC_ERANGE;
     }
-    // catalogue order: longest first (cost ~ n^2)
-    b->host_order.resize(ncat);
-    for (int c = 0; c < ncat; c++) b->host_order[c] = (uint32_t)c;
+    bool all_auto = true;
+    for (int q = 0; q < npairs; q++) all_auto = all_auto && (pairs[2 * q] == pairs[2 * q + 1]);
+    // pair order: largest estimated cost first (n^2 / 2 for an auto count, n_a n_b for a cross count)
+    std::vector<double> cost(npairs);
+    for (int q = 0; q < npairs; q++) {
+        const double na = (double)cats[pairs[2 * q]].n, nb = (double)cats[pairs[2 * q + 1]].n;
+        cost[q] = (pairs[2 * q] == pairs[2 * q + 1]) ? 0.5 * na * na : na * nb;
+    }
+    b->host_order.resize(npairs);
+    for (int q = 0; q < npairs; q++) b->host_order[q] = (uint32_t)q;
     std::stable_sort(b->host_order.begin(), b->host_order.end(),
-                     [&](uint32_t x, uint32_t y) { return cats[x].n > cats[y].n; });
+                     [&](uint32_t x, uint32_t y) { return cost[x] > cost[y]; });
     const double ppc = (double)tot / std::max<int64_t>(1, g.ncell() * ncat);
-    fcfc_status s = setup_launch(p, true, b->weighted, true, ppc, 0, b->L);
+    fcfc_status s = setup_launch(p, all_auto, b->weighted, true, ppc, 0, b->L);
     if (s != FCFC_OK) {
         delete b;
         return s;
     }
-    b->wl = make_wl(p, b->L, true, ncat, tot);
+    b->wl = make_wl(p, b->L, all_auto, ncat, tot);
     b->nseg = (int64_t)g.ny * g.nz * ncat;  // A rows
-    b->npair_tr = (int64_t)b->wl.tiles_cap * b->wl.nrows;
-    if ((int64_t)b->wl.tiles_cap * b->wl.nrows >= 0xffffffffLL) {
+    // tiles of each catalogue span cells by its own density; pair-tiles: every
+    // pair takes the tiles of its A catalogue (each bounded as in make_wl)
+    std::vector<int> hseg(ncat);
+    std::vector<int64_t> cat_tiles(ncat);
+    int64_t tiles = 0;
+    for (int c = 0; c < ncat; c++) {
+        hseg[c] = tile_seg(p, b->L.T, (double)cats[c].n / std::max<int64_t>(1, g.ncell()));
+        cat_tiles[c] = (int64_t)g.ny * g.nz * ((g.nx + hseg[c] - 1) / hseg[c] + 1) + cats[c].n / b->L.T + 1;
+        tiles += cat_tiles[c];
+    }
+    int64_t ptiles = 0;
+    for (int q = 0; q < npairs; q++) ptiles += cat_tiles[pairs[2 * q]];
+    b->npair_tr = ptiles * b->wl.nrows;
+    if (tiles >= 0xffffffffLL || b->npair_tr >= 0xffffffffLL) {
         delete b;
         set_error("batch_create: work list too large");
         return FCFC_ERANGE;
     }
+    b->wl.npairs = npairs;
+    b->wl.ptiles_cap = (uint32_t)ptiles;
+    b->wl.tiles_cap = (uint32_t)tiles;
     const int nb = p->nbins;
+    const bool need_abs = (p->los == FCFC_LOS_MIDPOINT && p->kind != FCFC_BIN_S);
 #define BA(ptr, bytes)                                                         \
     do {                                                                       \
         fcfc_status s_ = balloc(b, (void**)&(ptr), (bytes));                   \
@@ -1587,6 +1646,7 @@ fcfc_status batch_create_impl(Plan* p, const fcfc_catalog* cats, int ncat, hipSt
     BA(b->flags, 64);
     BA(b->wst, 64);
     BA(b->pos32, 16 * (size_t)(tot + 8));
+    if (need_abs) BA(b->abs32, 16 * (size_t)(tot + 8));
     BA(b->pos64, 24 * (size_t)tot);
     if (b->weighted) BA(b->w, 8 * (size_t)(tot + 8));
     BA(b->cs, 4 * (size_t)(g.ncell() * ncat + 1));
@@ -1597,19 +1657,29 @@ fcfc_status batch_create_impl(Plan* p, const fcfc_catalog* cats, int ncat, hipSt
     BA(b->scan_scr, std::max(scan_scratch_bytes(b->nseg), scan_scratch_bytes(b->npair_tr)));
     BA(b->tiles, sizeof(Tile) * (size_t)b->wl.tiles_cap);
     BA(b->ctr, 256);
-    BA(b->cat_items, 4 * (size_t)(ncat + 1));
-    BA(b->cat_order, 4 * (size_t)ncat);
-    BA(b->chunk_prefix, 4 * (size_t)(ncat + 1));
-    BA(b->counts, 8 * (size_t)ncat * nb);
+    BA(b->pairs, 8 * (size_t)npairs);
+    BA(b->cat_seg, 4 * (size_t)ncat);
+    BA(b->ptile_off, 4 * (size_t)(npairs + 1));
+    BA(b->ptile_first, 4 * (size_t)npairs);
+    BA(b->pair_items, 4 * (size_t)(npairs + 1));
+    BA(b->pair_order, 4 * (size_t)npairs);
+    BA(b->chunk_prefix, 4 * (size_t)(npairs + 1));
+    BA(b->counts, 8 * (size_t)npairs * nb);
     if (b->weighted) {
-        BA(b->wacc, 16 * (size_t)ncat * nb);
-        BA(b->wout, 8 * (size_t)ncat * nb);
+        BA(b->wacc, 16 * (size_t)npairs * nb);
+        BA(b->wout, 8 * (size_t)npairs * nb);
     }
     BA(b->tab, b->L.tb_total);
     BA(b->args_dev, sizeof(CountArgs));
+    b->wl.pairs = b->pairs;
+    b->wl.cat_seg = b->cat_seg;
+    b->wl.ptile_off = b->ptile_off;
+    b->wl.ptile_first = b->ptile_first;
     FCFC_HIP(hipMemcpy(b->desc, b->host_desc.data(), sizeof(CatDesc) * ncat, hipMemcpyHostToDevice));
     FCFC_HIP(hipMemcpy(b->offs, b->host_offs.data(), sizeof(int64_t) * (ncat + 1), hipMemcpyHostToDevice));
-    FCFC_HIP(hipMemcpy(b->cat_order, b->host_order.data(), 4 * (size_t)ncat, hipMemcpyHostToDevice));
+    FCFC_HIP(hipMemcpy(b->pairs, b->host_pairs.data(), 8 * (size_t)npairs, hipMemcpyHostToDevice));
+    FCFC_HIP(hipMemcpy(b->cat_seg, hseg.data(), 4 * (size_t)ncat, hipMemcpyHostToDevice));
+    FCFC_HIP(hipMemcpy(b->pair_order, b->host_order.data(), 4 * (size_t)npairs, hipMemcpyHostToDevice));
     FCFC_HIP(hipMemcpy(b->tab, b->L.htab.data(), b->L.tb_total, hipMemcpyHostToDevice));
     FCFC_HIP(hipEventCreate(&b->ev0));
     FCFC_HIP(hipEventCreate(&b->ev1));
@@ -1629,7 +1699,8 @@ fcfc_status batch_create_impl(Plan* p, const fcfc_catalog* cats, int ncat, hipSt
     }
     if (hflags & 2u) {
         batch_free_impl(b);
-        set_error("batch_create: a point lies outside [0, L)");
+        set_error(p->L > 0 ? "batch_create: a point lies outside [0, L)"
+                           : "batch_create: a point lies outside the plan bounds");
         return FCFC_EBOX;
     }
     if (b->weighted) {
@@ -1645,18 +1716,28 @@ fcfc_status batch_create_impl(Plan* p, const fcfc_catalog* cats, int ncat, hipSt
     }
     b->items_cap = std::max<uint32_t>(hctr[1], 1);
     BA(b->items, sizeof(Item) * (size_t)b->items_cap);
+    BA(b->items2, sizeof(Item) * (size_t)b->items_cap);
+    BA(b->sk0, 4 * (size_t)b->items_cap);
+    BA(b->sv0, 4 * (size_t)b->items_cap);
+    BA(b->sk1, 4 * (size_t)b->items_cap);
+    BA(b->sv1, 4 * (size_t)b->items_cap);
+    BA(b->isort_scr, radix_scratch_bytes(b->items_cap));
 #undef BA
+    // pair keys (pair << 6 | cost key) sort in whole bytes; the end key is above them all
+    b->sort_bits = 8;
+    while (((uint64_t)npairs << 6) >= ((uint64_t)1 << b->sort_bits)) b->sort_bits += 8;
+    b->key_last = (uint32_t)(((uint64_t)1 << b->sort_bits) - 1);
     CountArgs& a = b->L.a;
     (void)bind_tables(b->L, b->tab, a);
     a.posA = b->pos32;
-    a.absA = nullptr;
+    a.absA = b->abs32;
     a.p64A = b->pos64;
     a.wA = b->weighted ? b->w : nullptr;
     a.posB = b->pos32;
     a.p64B = b->pos64;
     a.wB = a.wA;
     a.csB = b->cs;
-    a.items = b->items;
+    a.items = b->items2;
     a.nitems_dev = &b->ctr[1];
     a.cursor = &b->ctr[2];
     a.out_counts = b->counts;
@@ -1668,10 +1749,14 @@ fcfc_status batch_create_impl(Plan* p, const fcfc_catalog* cats, int ncat, hipSt
     a.nchunks_dev = &b->ctr[3];
     a.chunk_cursor = &b->ctr[4];
     a.chunk_prefix = b->chunk_prefix;
-    a.cat_order = b->cat_order;
-    a.cat_items = b->cat_items;
-    a.ncat = ncat;
-    a.chunk_items = std::max(16, b->L.waves * 8);
+    a.cat_order = b->pair_order;
+    a.cat_items = b->pair_items;
+    a.ncat = npairs;
+    // A workgroup takes chunks of 32 items per wavefront and waits for its
+    // slowest wave at the end of each; measured on MI355X, 8 lost 6 % to those
+    // waits and 128 or more left long tails (few chunks per pair).
+    const int per_wave = (p->tune.batch_chunk >= 1 && p->tune.batch_chunk <= 1024) ? p->tune.batch_chunk : 32;
+    a.chunk_items = std::max(16, b->L.waves * per_wave);
     b->host_args.resize(sizeof(CountArgs));
     memcpy(b->host_args.data(), &a, sizeof(CountArgs));
     FCFC_HIP(hipMemcpy(b->args_dev, b->host_args.data(), sizeof(CountArgs), hipMemcpyHostToDevice));
@@ -1707,7 +1792,7 @@ fcfc_status batch_run_impl(BatchImpl* b, int64_t* d_counts, double* d_wcounts, b
         batch_enqueue_back(b, st);
         FCFC_HIP(hipEventRecord(b->ev1, st));
     }
-    const size_t nbytes = (size_t)b->ncat * p->nbins * 8;
+    const size_t nbytes = (size_t)b->npairs * p->nbins * 8;
     FCFC_HIP(hipMemcpyAsync(d_counts, b->counts, nbytes, hipMemcpyDeviceToDevice, st));
     if (d_wcounts) FCFC_HIP(hipMemcpyAsync(d_wcounts, b->wout, nbytes, hipMemcpyDeviceToDevice, st));
     return FCFC_OK;

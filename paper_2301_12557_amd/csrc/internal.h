@@ -169,8 +169,8 @@ struct CatDesc {
 size_t batch_build_scratch(int64_t ntot);
 void batch_build_enqueue(const Plan* p, const CatDesc* desc, const int64_t* offs, int ncat, int64_t ntot,
                          bool weighted, uint32_t** key, uint32_t** idx, uint32_t** tk, uint32_t** tv, void* sort_scr,
-                         uint32_t* flags, uint64_t* wst, float4* pos32, double* pos64, double* w, uint32_t* cs,
-                         hipStream_t st);
+                         uint32_t* flags, uint64_t* wst, float4* pos32, float4* abs32, double* pos64, double* w,
+                         uint32_t* cs, hipStream_t st);
 
 // count (count.hip)
 // Learned cost model (mlp.hip): predicted log2(1 + ticks) of n work items
@@ -189,7 +189,9 @@ fcfc_status count_pairs(Plan* p, Cells* c1, Cells* c2, int64_t* d_counts, double
                         hipStream_t st, PredictReq* pr = nullptr);
 
 struct BatchImpl;
-fcfc_status batch_create_impl(Plan* p, const fcfc_catalog* cats, int ncat, hipStream_t st, BatchImpl** out);
+// pairs: 2 * npairs catalogue indices (A, B), A == B for an auto count
+fcfc_status batch_create_impl(Plan* p, const fcfc_catalog* cats, int ncat, const int32_t* pairs, int npairs,
+                              hipStream_t st, BatchImpl** out);
 fcfc_status batch_run_impl(BatchImpl* b, int64_t* d_counts, double* d_wcounts, bool use_graph, hipStream_t st);
 fcfc_status batch_check_impl(BatchImpl* b, hipStream_t st, uint32_t* nitems, float* ms);
 void batch_free_impl(BatchImpl* b);

@@ -22,6 +22,17 @@ struct WLArgs {
     int is_auto;
     uint32_t tiles_cap;
     int ncat;       // catalogues stacked along z (batched build); 1 otherwise
+    int full_rows;  // the stencil table holds every row (auto pairs then skip the lower half)
+    const int* cat_seg;  // per-catalogue seg of a batched build (null: seg for every row)
+    // pair mode (batched build, npairs > 0): items of every (A catalogue, B
+    // catalogue) pair; pair-tile t of pair p is tile ptile_first[p] + t -
+    // ptile_off[p], and index ranges of k_item_count / k_item_write run over
+    // pair-tiles (ptiles_cap of them) instead of tiles
+    const int32_t* pairs;         // 2 per pair: A catalogue, B catalogue (equal: auto count)
+    const uint32_t* ptile_off;    // npairs + 1
+    const uint32_t* ptile_first;  // npairs
+    int npairs;
+    uint32_t ptiles_cap;
 };
 
 __global__ void k_tile_count(const uint32_t* __restrict__ csA, WLArgs w, uint32_t* __restrict__ tcount);
@@ -33,12 +44,17 @@ __global__ void k_item_count(const Tile* __restrict__ tiles, const uint32_t* __r
 __global__ void k_item_write(const Tile* __restrict__ tiles, const uint32_t* __restrict__ ntiles_dev,
                              const int4* __restrict__ srows, const uint32_t* __restrict__ csB, WLArgs w,
                              const uint32_t* __restrict__ ioff, Item* __restrict__ items, uint32_t items_cap);
-__global__ void k_cat_items(const uint32_t* __restrict__ toff, const uint32_t* __restrict__ ioff,
-                            const uint32_t* __restrict__ nitems_dev, WLArgs w, uint32_t* __restrict__ cat_items);
+__global__ void k_pair_tiles(const uint32_t* __restrict__ toff, const uint32_t* __restrict__ ntiles_dev, WLArgs w,
+                             uint32_t* __restrict__ ptile_off, uint32_t* __restrict__ ptile_first);
+__global__ void k_pair_items(const uint32_t* __restrict__ ioff, const uint32_t* __restrict__ nitems_dev, WLArgs w,
+                             uint32_t* __restrict__ pair_items);
 __global__ void k_chunk_prefix(const uint32_t* __restrict__ cat_items, const uint32_t* __restrict__ cat_order,
                                int ncat, int chunk_items, uint32_t* __restrict__ prefix, uint32_t* __restrict__ nchunks);
 __global__ void k_item_keys(const Item* __restrict__ items, const uint32_t* __restrict__ nitems_dev,
                             uint32_t cap, uint32_t* __restrict__ key, uint32_t* __restrict__ val);
+__global__ void k_pair_item_keys(const Item* __restrict__ items, const uint32_t* __restrict__ nitems_dev,
+                                 uint32_t cap, const uint32_t* __restrict__ pair_items, int npairs, uint32_t last,
+                                 uint32_t* __restrict__ key, uint32_t* __restrict__ val);
 __global__ void k_item_permute(const Item* __restrict__ in, const uint32_t* __restrict__ perm,
                                const uint32_t* __restrict__ nitems_dev, uint32_t cap, Item* __restrict__ out);
 

@@ -11,6 +11,9 @@
 // use the half stencil (each unordered row pair once, Sect. 3.1) and, in the
 // A row itself, only B points after the A point (mask flag) plus the piece
 // wrapped from the right.
+// A batched build may list pairs of catalogues (auto or cross): the items of
+// pair (a, b) are those of the tiles of catalogue a against the rows of
+// catalogue b, and items come out grouped by pair.
 #include <algorithm>
 
 #include "internal.h"
@@ -29,13 +32,13 @@ __device__ inline int floor_div(int a, int n) {
 // of its first point.  Calls emit(first point, count, first cell, last cell)
 // in order.
 template <typename F>
-__device__ inline void row_tiles(const uint32_t* __restrict__ csA, int64_t rowcell, const WLArgs& w, F emit) {
+__device__ inline void row_tiles(const uint32_t* __restrict__ csA, int64_t rowcell, const WLArgs& w, int seg, F emit) {
     const uint32_t p1 = csA[rowcell + w.nx];
     uint32_t a = csA[rowcell];
     int c = 0;
     while (a < p1) {
         while (csA[rowcell + c + 1] <= a) c++;  // cell holding point a
-        const uint32_t lim = csA[rowcell + min(c + w.seg, w.nx)];
+        const uint32_t lim = csA[rowcell + min(c + seg, w.nx)];
         const uint32_t e = min(min(a + (uint32_t)w.tile, lim), p1);
         int c2 = c;
         while (csA[rowcell + c2 + 1] <= e - 1) c2++;  // cell holding the last point
@@ -44,12 +47,17 @@ __device__ inline void row_tiles(const uint32_t* __restrict__ csA, int64_t rowce
     }
 }
 
+// Largest cell span of a tile in row r (per catalogue in a batched build).
+__device__ inline int row_seg(const WLArgs& w, int64_t r) {
+    return w.cat_seg ? w.cat_seg[r / ((int64_t)w.ny * w.nz)] : w.seg;
+}
+
 __global__ void k_tile_count(const uint32_t* __restrict__ csA, WLArgs w, uint32_t* __restrict__ tcount) {
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t nrow = (int64_t)w.ny * w.nz * w.ncat;
     if (r >= nrow) return;
     uint32_t n = 0;
-    row_tiles(csA, r * w.nx, w, [&](uint32_t, uint32_t, int, int) { n++; });
+    row_tiles(csA, r * w.nx, w, row_seg(w, r), [&](uint32_t, uint32_t, int, int) { n++; });
     tcount[r] = n;
 }
 
@@ -59,7 +67,7 @@ __global__ void k_tile_write(const uint32_t* __restrict__ csA, const float4* __r
     const int64_t nrow = (int64_t)w.ny * w.nz * w.ncat;
     if (r >= nrow) return;
     uint32_t t = toff[r];
-    row_tiles(csA, r * w.nx, w, [&](uint32_t a, uint32_t cnt, int cxa, int cxb) {
+    row_tiles(csA, r * w.nx, w, row_seg(w, r), [&](uint32_t a, uint32_t cnt, int cxa, int cxb) {
         Tile tl;
         tl.a_begin = a;
         tl.a_count = cnt;
@@ -69,17 +77,21 @@ __global__ void k_tile_write(const uint32_t* __restrict__ csA, const float4* __r
     });
 }
 
-// Enumerate the pieces of (tile, stencil row); emit(item) is called for
+// Enumerate the pieces of (tile, stencil row) against the B rows of
+// catalogue bcat (< 0: the tile's own catalogue); emit(item) is called for
 // every work item, in a fixed order.
 template <typename F>
 __device__ inline void tile_row_items(const Tile& tl, int4 srow, const uint32_t* __restrict__ csB,
-                                      const WLArgs& w, uint32_t tile_id, F emit) {
+                                      const WLArgs& w, uint32_t tile_id, int bcat, bool is_auto, F emit) {
     // rows of a batched build are (catalogue, z, y); wrapping stays within the catalogue
     int cy = (int)(tl.row % (uint32_t)w.ny);
     int czc = (int)(tl.row / (uint32_t)w.ny);
     int cat = czc / w.nz;
     int cz = czc - cat * w.nz;
+    if (bcat < 0) bcat = cat;
     int dy = srow.x, dz = srow.y, kx = srow.z;
+    // an auto count takes each unordered pair of rows once (half stencil)
+    if (is_auto && w.full_rows && (dz < 0 || (dz == 0 && dy < 0))) return;
     int yu = cy + dy, zu = cz + dz;
     int sy = 0, sz = 0, yb = yu, zb = zu;
     if (w.periodic) {
@@ -91,10 +103,10 @@ __device__ inline void tile_row_items(const Tile& tl, int4 srow, const uint32_t*
     } else if (yu < 0 || yu >= w.ny || zu < 0 || zu >= w.nz) {
         return;
     }
-    bool same = w.is_auto && dy == 0 && dz == 0;
+    bool same = is_auto && dy == 0 && dz == 0;
     int x0 = (int)(tl.x01 & 0xffff), x1 = (int)(tl.x01 >> 16);
     int xlo = x0 - kx, xhi = x1 + kx;
-    uint32_t rowcell = (((uint32_t)cat * (uint32_t)w.nz + (uint32_t)zb) * (uint32_t)w.ny + (uint32_t)yb) * (uint32_t)w.nx;
+    uint32_t rowcell = (((uint32_t)bcat * (uint32_t)w.nz + (uint32_t)zb) * (uint32_t)w.ny + (uint32_t)yb) * (uint32_t)w.nx;
     // pieces: 0 = direct, 1 = wrapped from the left (sx = -1), 2 = wrapped from the right (sx = +1)
     for (int pc = 0; pc < 3; pc++) {
         int c0, c1, sx;
@@ -141,20 +153,48 @@ __device__ inline void tile_row_items(const Tile& tl, int4 srow, const uint32_t*
     }
 }
 
+// Pair-tile pt of a pair-mode list -> pair and tile; false past the last one.
+__device__ inline bool pair_tile(const WLArgs& w, int64_t pt, int& pr, uint32_t& ti) {
+    if (pt >= (int64_t)w.ptile_off[w.npairs]) return false;
+    int lo = 0, hi = w.npairs;  // ptile_off[lo] <= pt < ptile_off[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if ((int64_t)w.ptile_off[mid] <= pt) lo = mid;
+        else hi = mid;
+    }
+    pr = lo;
+    ti = w.ptile_first[lo] + (uint32_t)(pt - (int64_t)w.ptile_off[lo]);
+    return true;
+}
+
+// Items of index t = (tile or pair-tile) * nrows + stencil row.
+template <typename F>
+__device__ inline void index_items(const Tile* __restrict__ tiles, uint32_t ntiles, const int4* __restrict__ srows,
+                                   const uint32_t* __restrict__ csB, const WLArgs& w, int64_t t, F emit) {
+    const int64_t ti0 = t / w.nrows;
+    const int r = (int)(t % w.nrows);
+    if (w.npairs > 0) {
+        int pr;
+        uint32_t ti;
+        if (!pair_tile(w, ti0, pr, ti)) return;
+        const int ca = w.pairs[2 * pr], cb = w.pairs[2 * pr + 1];
+        tile_row_items(tiles[ti], srows[r], csB, w, ti, cb, ca == cb, emit);
+    } else if (ti0 < (int64_t)ntiles) {
+        tile_row_items(tiles[ti0], srows[r], csB, w, (uint32_t)ti0, -1, w.is_auto != 0, emit);
+    }
+}
+
+static __device__ inline int64_t index_total(const WLArgs& w) {
+    return (int64_t)(w.npairs > 0 ? w.ptiles_cap : w.tiles_cap) * w.nrows;
+}
+
 __global__ void k_item_count(const Tile* __restrict__ tiles, const uint32_t* __restrict__ ntiles_dev,
                              const int4* __restrict__ srows, const uint32_t* __restrict__ csB, WLArgs w,
                              uint32_t* __restrict__ icount) {
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int64_t total = (int64_t)w.tiles_cap * w.nrows;
-    if (t >= total) return;
-    uint32_t ntiles = *ntiles_dev;
-    int64_t ti = t / w.nrows;
-    int r = (int)(t % w.nrows);
+    if (t >= index_total(w)) return;
     uint32_t c = 0;
-    if (ti < (int64_t)ntiles) {
-        Tile tl = tiles[ti];
-        tile_row_items(tl, srows[r], csB, w, (uint32_t)ti, [&](const Item&) { c++; });
-    }
+    index_items(tiles, *ntiles_dev, srows, csB, w, t, [&](const Item&) { c++; });
     icount[t] = c;
 }
 
@@ -163,34 +203,44 @@ __global__ void k_item_write(const Tile* __restrict__ tiles, const uint32_t* __r
                              const uint32_t* __restrict__ ioff, Item* __restrict__ items,
                              uint32_t items_cap) {
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int64_t total = (int64_t)w.tiles_cap * w.nrows;
-    if (t >= total) return;
-    uint32_t ntiles = *ntiles_dev;
-    int64_t ti = t / w.nrows;
-    int r = (int)(t % w.nrows);
-    if (ti >= (int64_t)ntiles) return;
-    Tile tl = tiles[ti];
+    if (t >= index_total(w)) return;
     uint32_t o = ioff[t];
-    tile_row_items(tl, srows[r], csB, w, (uint32_t)ti, [&](const Item& it) {
+    index_items(tiles, *ntiles_dev, srows, csB, w, t, [&](const Item& it) {
         if (o < items_cap) items[o] = it;
         o++;
     });
 }
 
-// First work item of each catalogue of a batched build: tiles (and hence
-// items) are ordered by catalogue, so catalogue c starts at the first
-// (tile, row) pair of its first segment.
-__global__ void k_cat_items(const uint32_t* __restrict__ toff, const uint32_t* __restrict__ ioff,
-                            const uint32_t* __restrict__ nitems_dev, WLArgs w, uint32_t* __restrict__ cat_items) {
-    int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c > w.ncat) return;
-    if (c == w.ncat) {
-        cat_items[c] = *nitems_dev;
-        return;
+// Pair-tile ranges: the tiles of catalogue c are those of its rows
+// [c ny nz, (c+1) ny nz), consecutive in the tile list.  One thread (a few
+// hundred pairs at most).
+__global__ void k_pair_tiles(const uint32_t* __restrict__ toff, const uint32_t* __restrict__ ntiles_dev, WLArgs w,
+                             uint32_t* __restrict__ ptile_off, uint32_t* __restrict__ ptile_first) {
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    const int64_t rows = (int64_t)w.ny * w.nz;
+    const uint32_t ntiles = *ntiles_dev;
+    uint32_t acc = 0;
+    for (int p = 0; p < w.npairs; p++) {
+        const int c = w.pairs[2 * p];
+        const uint32_t t0 = toff[(int64_t)c * rows];
+        const uint32_t t1 = (c + 1 < w.ncat) ? toff[(int64_t)(c + 1) * rows] : ntiles;
+        ptile_first[p] = t0;
+        ptile_off[p] = acc;
+        acc += t1 - t0;
     }
-    const int64_t row0 = (int64_t)c * w.ny * w.nz;  // first A row of the catalogue
-    uint32_t t0 = toff[row0];
-    cat_items[c] = ioff[(int64_t)t0 * w.nrows];
+    ptile_off[w.npairs] = acc;
+}
+
+// First work item of each pair (items come out grouped by pair), clamped to
+// the item count so that a clamped list never sends a reader past it.
+__global__ void k_pair_items(const uint32_t* __restrict__ ioff, const uint32_t* __restrict__ nitems_dev, WLArgs w,
+                             uint32_t* __restrict__ pair_items) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p > w.npairs) return;
+    const uint32_t n = *nitems_dev;
+    const int64_t idx = (int64_t)w.ptile_off[p] * w.nrows;
+    const uint32_t v = (p < w.npairs && idx < index_total(w)) ? ioff[idx] : n;
+    pair_items[p] = v < n ? v : n;
 }
 
 // Chunks of `chunk_items` items per catalogue, catalogues in the given order
@@ -213,17 +263,39 @@ __global__ void k_chunk_prefix(const uint32_t* __restrict__ cat_items, const uin
 // reversed so that an ascending stable sort puts the largest first while
 // items of one bucket keep their enumeration order (A tiles and B rows stay
 // close together in memory).
+__device__ inline uint32_t cost_key(uint32_t c) {
+    uint32_t lg = c ? 31u - (uint32_t)__clz(c) : 0u;  // floor(log2 c)
+    uint32_t half = (lg >= 1 && ((c >> (lg - 1)) & 1u)) ? 1u : 0u;
+    return 63u - min(63u, 2u * lg + half);
+}
+
 __global__ void k_item_keys(const Item* __restrict__ items, const uint32_t* __restrict__ nitems_dev,
                             uint32_t cap, uint32_t* __restrict__ key, uint32_t* __restrict__ val) {
     uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= cap) return;
     uint32_t n = *nitems_dev;
-    uint32_t k = 255u;
-    if (i < n) {
-        uint32_t c = items[i].cost;
-        uint32_t lg = c ? 31u - (uint32_t)__clz(c) : 0u;  // floor(log2 c)
-        uint32_t half = (lg >= 1 && ((c >> (lg - 1)) & 1u)) ? 1u : 0u;
-        k = 63u - min(63u, 2u * lg + half);
+    key[i] = (i < n) ? cost_key(items[i].cost) : 255u;
+    val[i] = i;
+}
+
+// The same key within each pair of a pair-mode list: (pair << 6) | cost key,
+// so that a stable sort keeps the pairs where they are (items are grouped by
+// pair) and puts each pair's largest items first.  Items past the end get
+// `last`, above every other key.
+__global__ void k_pair_item_keys(const Item* __restrict__ items, const uint32_t* __restrict__ nitems_dev,
+                                 uint32_t cap, const uint32_t* __restrict__ pair_items, int npairs, uint32_t last,
+                                 uint32_t* __restrict__ key, uint32_t* __restrict__ val) {
+    uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= cap) return;
+    uint32_t k = last;
+    if (i < *nitems_dev) {
+        int lo = 0, hi = npairs;  // pair_items[lo] <= i < pair_items[hi]
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (pair_items[mid] <= i) lo = mid;
+            else hi = mid;
+        }
+        k = ((uint32_t)lo << 6) | cost_key(items[i].cost);
     }
     key[i] = k;
     val[i] = i;

@@ -39,7 +39,7 @@ class Tuning(ctypes.Structure):
                 ("record_timing", ctypes.c_int32), ("n_hint", ctypes.c_int32),
                 ("lut_log2", ctypes.c_int32), ("group_waves", ctypes.c_int32),
                 ("shard_count", ctypes.c_int32), ("shard_index", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 4)]
+                ("batch_chunk", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
 
 
 class Stats(ctypes.Structure):
@@ -70,6 +70,7 @@ SIGNATURES = [
     ("fcfc_count_pairs", _I32, [_P, _P, _P, _P, _P, _P]),
     ("fcfc_plan_stats", _I32, [_P, ctypes.POINTER(Stats)]),
     ("fcfc_batch_create", _I32, [_P, ctypes.POINTER(Catalog), _I32, _P, ctypes.POINTER(_P)]),
+    ("fcfc_batch_create_pairs", _I32, [_P, ctypes.POINTER(Catalog), _I32, _P, _I32, _P, ctypes.POINTER(_P)]),
     ("fcfc_batch_run", _I32, [_P, _P, _P, _I32, _P]),
     ("fcfc_batch_check", _I32, [_P, _P, ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_float)]),
     ("fcfc_batch_free", None, [_P]),
@@ -297,20 +298,32 @@ class Cells:
 
 
 class Batch:
-    """Owns an fcfc_batch_t: auto counts of many periodic catalogues in one pipeline."""
+    """Owns an fcfc_batch_t: counts of many catalogues in one pipeline.
 
-    def __init__(self, plan, catalogs, stream=None):
+    catalogs: list of (xyz, w or None) device tensors.  pairs: None for the
+    auto count of every catalogue, else a list of (a, b) catalogue indices,
+    a == b for the auto count of a and a != b for the cross count of a with b;
+    run() writes one histogram per pair, in the order given."""
+
+    def __init__(self, plan, catalogs, pairs=None, stream=None):
         self._keep = catalogs
         arr = (Catalog * len(catalogs))(*[_catalog(x, w) for (x, w) in catalogs])
         h = ctypes.c_void_p()
-        check(load().fcfc_batch_create(plan.h, arr, len(catalogs), _stream_ptr(stream), ctypes.byref(h)))
+        if pairs is None:
+            check(load().fcfc_batch_create(plan.h, arr, len(catalogs), _stream_ptr(stream), ctypes.byref(h)))
+            self.nhist = len(catalogs)
+        else:
+            pr = np.ascontiguousarray(np.asarray(pairs, dtype=np.int32).reshape(-1, 2))
+            check(load().fcfc_batch_create_pairs(plan.h, arr, len(catalogs), pr.ctypes.data_as(_P), len(pr),
+                                                 _stream_ptr(stream), ctypes.byref(h)))
+            self.nhist = len(pr)
         self.h = h
         self.plan = plan
         self.ncat = len(catalogs)
 
     def run(self, out, wout=None, use_graph=True, stream=None):
         import torch
-        nb = self.ncat * self.plan.n1 * self.plan.n2
+        nb = self.nhist * self.plan.n1 * self.plan.n2
         _out_tensor(out, nb, torch.int64, "out")
         if wout is not None:
             _out_tensor(wout, nb, torch.float64, "wout")
@@ -521,7 +534,7 @@ def wp(xi_spi, pi_edges, stream=None):
 
 
 TUNING_KEYS = ("cells_per_rmax", "tile_points", "seg_cells", "b_chunk", "hist_copies", "order",
-               "record_timing", "n_hint", "lut_log2", "group_waves", "shard_count", "shard_index")
+               "record_timing", "n_hint", "lut_log2", "group_waves", "shard_count", "shard_index", "batch_chunk")
 
 
 def autotune(x1, x2=None, *, model=None, kind="s", edges1, edges2=None, los="z", box=0.0, w1=None, w2=None,

@@ -209,3 +209,30 @@ def test_build_cells_rejects_oversized_catalogue():
         assert b"2^31" in lib.fcfc_last_error()
     assert not out.value
     lib.fcfc_plan_free(p)
+
+
+def test_batch_pairs_rejected_on_the_host():
+    """A pair naming a catalogue outside [0, ncat), or an empty pair list, is
+    FCFC_EINVAL before any GPU work."""
+    lib = fcfc.load()
+    e1 = np.asarray([0.0, 1.0, 2.0])
+    p = ctypes.c_void_p()
+    assert lib.fcfc_plan_create(0, 0, e1.ctypes.data_as(ctypes.c_void_p), 2, None, 0, 10.0, None,
+                                ctypes.byref(p)) == 0
+    cats = (fcfc.Catalog * 2)()
+    for c in cats:
+        c.xyz = ctypes.c_void_p(16)    # never dereferenced: the checks come first
+        c.w = None
+        c.n = 10
+    out = ctypes.c_void_p()
+    for pairs in ([0, 2], [-1, 0], [1, 0, 0, 5]):
+        pr = np.asarray(pairs, dtype=np.int32)
+        assert lib.fcfc_batch_create_pairs(p, cats, 2, pr.ctypes.data_as(ctypes.c_void_p), len(pr) // 2, None,
+                                           ctypes.byref(out)) == -1, pairs
+        assert b"pair" in lib.fcfc_last_error()
+    pr = np.asarray([0, 0], dtype=np.int32)
+    assert lib.fcfc_batch_create_pairs(p, cats, 2, pr.ctypes.data_as(ctypes.c_void_p), 0, None,
+                                       ctypes.byref(out)) == -1
+    assert lib.fcfc_batch_create_pairs(p, cats, 2, None, 1, None, ctypes.byref(out)) == -1
+    assert not out.value
+    lib.fcfc_plan_free(p)

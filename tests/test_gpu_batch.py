@@ -86,7 +86,7 @@ def test_batch_graph_replays_equal_individual_counts():
     b.close()
 
 
-def test_batch_rejects_open_plan():
+def test_batch_rejects_open_plan_without_bounds():
     from paper_2301_12557_amd import fcfc
     plan = fcfc.Plan("s", [0.0, 1.0, 2.0], box=0.0)
     x = to_dev(np.random.default_rng(0).random((10, 3)))
