@@ -86,7 +86,7 @@ typedef struct {
 typedef struct {
     int32_t cells_per_rmax;  /* k: cell side = r_prune / k, 1..8 */
     int32_t tile_points;     /* A points per wavefront tile: 64 or 128 */
-    int32_t seg_cells;       /* consecutive A cells a tile may span, 1..64 */
+    int32_t seg_cells;       /* consecutive A cells a tile may span, 1..32 (0: 32) */
     int32_t b_chunk;         /* max B points per work item, >= 256 */
     int32_t hist_copies;     /* LDS histogram copies per workgroup: 1, 2 or 4 */
     int32_t order;           /* FCFC_ORDER_* */

@@ -24,6 +24,13 @@ __global__ void k_fill_u64(uint64_t* p, uint64_t v, int64_t n) {
     for (; i < n; i += stride) p[i] = v;
 }
 
+int key_xbits(int64_t ncells) {
+    int cb = 0;
+    while (cb < 31 && ((int64_t)1 << cb) < ncells) cb++;
+    const int total = std::min(32, (cb + 8 + 7) / 8 * 8);
+    return total - cb;
+}
+
 static int grid_for(int64_t n, int block = 256, int cap = 65536) {
     int64_t g = (n + block - 1) / block;
     if (g < 1) g = 1;
@@ -347,9 +354,15 @@ __device__ inline int cell_of(double x, double lo, double side, int n) {
     int c = (f < 0.0) ? 0 : ((f > (double)(n - 1)) ? n - 1 : (int)f);
     return c;
 }
+// position of x within cell c on 2^xbits steps, clamped to the cell
+__device__ inline uint32_t subcell_of(double x, double lo, double side, int c, int xbits) {
+    const double f = ((x - lo) / side - (double)c) * (double)(1u << xbits);
+    const double top = (double)((1u << xbits) - 1u);
+    return (uint32_t)((f < 0.0) ? 0.0 : ((f > top) ? top : floor(f)));
+}
 
 __global__ __launch_bounds__(256) void k_keys(const double* __restrict__ xyz, const double* __restrict__ w,
-                                              int64_t n, GridArgs g, uint32_t* __restrict__ key,
+                                              int64_t n, GridArgs g, int xbits, uint32_t* __restrict__ key,
                                               uint32_t* __restrict__ idx, uint32_t* __restrict__ flags,
                                               uint64_t* __restrict__ wst /*[0] min nonzero |w|, [1] max*/) {
     __shared__ uint32_t sflag;
@@ -371,13 +384,14 @@ __global__ __launch_bounds__(256) void k_keys(const double* __restrict__ xyz, co
         } else {
             if (!(x >= g.lox && x <= g.hix && y >= g.loy && y <= g.hiy && z >= g.loz && z <= g.hiz)) f |= VF_BOX;
         }
-        uint32_t cx = 0, cy = 0, cz = 0;
+        uint32_t cx = 0, cy = 0, cz = 0, q = 0;
         if (!f) {
             cx = cell_of(x, g.lox, g.side, g.nx);
             cy = cell_of(y, g.loy, g.side, g.ny);
             cz = cell_of(z, g.loz, g.side, g.nz);
+            q = subcell_of(x, g.lox, g.side, (int)cx, xbits);
         }
-        key[i] = (cz * (uint32_t)g.ny + cy) * (uint32_t)g.nx + cx;
+        key[i] = (((cz * (uint32_t)g.ny + cy) * (uint32_t)g.nx + cx) << xbits) | q;
         idx[i] = (uint32_t)i;
         if (w) {
             double wv = w[i];
@@ -407,13 +421,13 @@ __global__ __launch_bounds__(256) void k_keys(const double* __restrict__ xyz, co
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_gather(const double* __restrict__ xyz, const double* __restrict__ w,
                                                 const uint32_t* __restrict__ skey,
-                                                const uint32_t* __restrict__ sidx, int64_t n, GridArgs g,
+                                                const uint32_t* __restrict__ sidx, int64_t n, GridArgs g, int xbits,
                                                 float4* __restrict__ pos32, float4* __restrict__ abs32,
                                                 double* __restrict__ pos64, double* __restrict__ wout) {
     int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= n) return;
     uint32_t i = sidx[p];
-    uint32_t key = skey[p];
+    uint32_t key = skey[p] >> xbits;
     uint32_t cx = key % (uint32_t)g.nx;
     uint32_t cy = (key / (uint32_t)g.nx) % (uint32_t)g.ny;
     uint32_t cz = key / ((uint32_t)g.nx * (uint32_t)g.ny);
@@ -429,12 +443,12 @@ __global__ __launch_bounds__(256) void k_gather(const double* __restrict__ xyz, 
     if (wout) wout[p] = w[i];
 }
 
-__global__ void k_cell_start(const uint32_t* __restrict__ skey, int64_t n, int64_t ncell,
+__global__ void k_cell_start(const uint32_t* __restrict__ skey, int64_t n, int64_t ncell, int xbits,
                              uint32_t* __restrict__ cs) {
     int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p > n) return;
-    int64_t kprev = (p == 0) ? -1 : (int64_t)skey[p - 1];
-    int64_t kcur = (p == n) ? ncell : (int64_t)skey[p];
+    int64_t kprev = (p == 0) ? -1 : (int64_t)(skey[p - 1] >> xbits);
+    int64_t kcur = (p == n) ? ncell : (int64_t)(skey[p] >> xbits);
     for (int64_t c = kprev + 1; c <= kcur; c++) cs[c] = (uint32_t)p;
 }
 
@@ -471,7 +485,8 @@ fcfc_status build_cells(Plan* p, const fcfc_catalog* cat, hipStream_t st, Cells*
     size_t o_pos64 = o_abs32 + (need_abs ? align256((size_t)n * 16) : 0);
     size_t o_w = o_pos64 + align256((size_t)n * 24);
     size_t o_cs = o_w + (weighted ? align256((size_t)(n + PAD) * 8) : 0);
-    size_t total = o_cs + align256((size_t)(ncell + 1) * 4);
+    size_t o_key = o_cs + align256((size_t)(ncell + 1) * 4);
+    size_t total = o_key + align256((size_t)std::max<int64_t>(n, 1) * 4);
     Cells* c = new (std::nothrow) Cells();
     if (!c) return FCFC_ENOMEM;
     char* blk = nullptr;
@@ -491,6 +506,8 @@ fcfc_status build_cells(Plan* p, const fcfc_catalog* cat, hipStream_t st, Cells*
     c->pos64 = (double*)(blk + o_pos64);
     c->w = weighted ? (double*)(blk + o_w) : nullptr;
     c->cell_start = (uint32_t*)(blk + o_cs);
+    c->xkey = (uint32_t*)(blk + o_key);
+    c->xbits = key_xbits(ncell);
 
     // scratch: keys, idx, tmp keys, tmp idx, flags + weight stats, sort scratch
     size_t s_keys = align256((size_t)std::max<int64_t>(n, 1) * 4);
@@ -520,15 +537,22 @@ fcfc_status build_cells(Plan* p, const fcfc_catalog* cat, hipStream_t st, Cells*
     fill_u64(wst + 1, 0ull, 1, st);
     if (n > 0) {
         hipLaunchKernelGGL(k_keys, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, cat->xyz, cat->w, n, g,
-                           key, idx, flags, wst);
+                           c->xbits, key, idx, flags, wst);
         int bits = 0;
         while (bits < 32 && ((int64_t)1 << bits) < ncell) bits++;
-        bits = (bits + 7) / 8 * 8;
+        bits = std::min(32, bits + c->xbits);
         radix_sort_pairs(&key, &idx, &tk, &tv, n, bits, sort_scr, st);
         hipLaunchKernelGGL(k_gather, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, cat->xyz, cat->w, key,
-                           idx, n, g, c->pos32, c->abs32, c->pos64, c->w);
+                           idx, n, g, c->xbits, c->pos32, c->abs32, c->pos64, c->w);
+        if (hipMemcpyAsync(c->xkey, key, (size_t)n * 4, hipMemcpyDeviceToDevice, st) != hipSuccess) {
+            (void)hipFreeAsync(scr, st);
+            (void)hipFree(blk);
+            delete c;
+            set_error("build_cells: HIP copy failed");
+            return FCFC_EHIP;
+        }
     }
-    hipLaunchKernelGGL(k_cell_start, dim3((unsigned)((n + 1 + 255) / 256)), dim3(256), 0, st, key, n, ncell,
+    hipLaunchKernelGGL(k_cell_start, dim3((unsigned)((n + 1 + 255) / 256)), dim3(256), 0, st, key, n, ncell, c->xbits,
                        c->cell_start);
     uint64_t h[3] = {0, 0, 0};
     hipError_t e1 = hipMemcpyAsync(h, flags, 8, hipMemcpyDeviceToHost, st);
@@ -583,7 +607,7 @@ __device__ inline int find_cat(const int64_t* __restrict__ offs, int ncat, int64
 }
 
 __global__ __launch_bounds__(256) void k_bkeys(const CatDesc* __restrict__ cats, const int64_t* __restrict__ offs,
-                                               int ncat, int64_t ntot, GridArgs g, uint32_t* __restrict__ key,
+                                               int ncat, int64_t ntot, GridArgs g, int xbits, uint32_t* __restrict__ key,
                                                uint32_t* __restrict__ idx, uint32_t* __restrict__ flags,
                                                uint64_t* __restrict__ wst) {
     __shared__ uint32_t sflag;
@@ -608,13 +632,14 @@ __global__ __launch_bounds__(256) void k_bkeys(const CatDesc* __restrict__ cats,
         } else {
             if (!(x >= g.lox && x <= g.hix && y >= g.loy && y <= g.hiy && z >= g.loz && z <= g.hiz)) f |= VF_BOX;
         }
-        uint32_t cx = 0, cy = 0, cz = 0;
+        uint32_t cx = 0, cy = 0, cz = 0, q = 0;
         if (!f) {
             cx = cell_of(x, g.lox, g.side, g.nx);
             cy = cell_of(y, g.loy, g.side, g.ny);
             cz = cell_of(z, g.loz, g.side, g.nz);
+            q = subcell_of(x, g.lox, g.side, (int)cx, xbits);
         }
-        key[i] = (((uint32_t)c * (uint32_t)g.nz + cz) * (uint32_t)g.ny + cy) * (uint32_t)g.nx + cx;
+        key[i] = (((((uint32_t)c * (uint32_t)g.nz + cz) * (uint32_t)g.ny + cy) * (uint32_t)g.nx + cx) << xbits) | q;
         idx[i] = (uint32_t)i;
         if (d.w) {
             double wv = d.w[li];
@@ -639,7 +664,7 @@ __global__ __launch_bounds__(256) void k_bkeys(const CatDesc* __restrict__ cats,
 
 __global__ __launch_bounds__(256) void k_bgather(const CatDesc* __restrict__ cats, const int64_t* __restrict__ offs,
                                                  int ncat, const uint32_t* __restrict__ skey,
-                                                 const uint32_t* __restrict__ sidx, int64_t n, GridArgs g,
+                                                 const uint32_t* __restrict__ sidx, int64_t n, GridArgs g, int xbits,
                                                  float4* __restrict__ pos32, float4* __restrict__ abs32,
                                                  double* __restrict__ pos64, double* __restrict__ wout) {
     int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -648,7 +673,7 @@ __global__ __launch_bounds__(256) void k_bgather(const CatDesc* __restrict__ cat
     const int c = find_cat(offs, ncat, i);
     const CatDesc d = cats[c];
     const int64_t li = (int64_t)i - offs[c];
-    uint32_t key = skey[p];
+    uint32_t key = skey[p] >> xbits;
     uint32_t cx = key % (uint32_t)g.nx;
     uint32_t cy = (key / (uint32_t)g.nx) % (uint32_t)g.ny;
     uint32_t cz = (key / ((uint32_t)g.nx * (uint32_t)g.ny)) % (uint32_t)g.nz;
@@ -667,7 +692,7 @@ __global__ __launch_bounds__(256) void k_bgather(const CatDesc* __restrict__ cat
 size_t batch_build_scratch(int64_t ntot) { return radix_scratch_bytes(ntot); }
 
 // Enqueue the batched build (no host synchronisation: capturable).
-void batch_build_enqueue(const Plan* p, const CatDesc* desc, const int64_t* offs, int ncat, int64_t ntot,
+void batch_build_enqueue(const Plan* p, int xbits, const CatDesc* desc, const int64_t* offs, int ncat, int64_t ntot,
                          bool weighted, uint32_t** key, uint32_t** idx, uint32_t** tk, uint32_t** tv, void* sort_scr,
                          uint32_t* flags, uint64_t* wst, float4* pos32, float4* abs32, double* pos64, double* w,
                          uint32_t* cs, hipStream_t st) {
@@ -680,16 +705,16 @@ void batch_build_enqueue(const Plan* p, const CatDesc* desc, const int64_t* offs
     fill_u64(wst + 1, 0ull, 1, st);
     if (ntot > 0) {
         hipLaunchKernelGGL(k_bkeys, dim3((unsigned)((ntot + 255) / 256)), dim3(256), 0, st, desc, offs, ncat, ntot, g,
-                           *key, *idx, flags, wst);
+                           xbits, *key, *idx, flags, wst);
         int bits = 0;
         while (bits < 32 && ((int64_t)1 << bits) < ncell_all) bits++;
-        bits = (bits + 7) / 8 * 8;
+        bits = std::min(32, bits + xbits);
         radix_sort_pairs(key, idx, tk, tv, ntot, bits, sort_scr, st);
         hipLaunchKernelGGL(k_bgather, dim3((unsigned)((ntot + 255) / 256)), dim3(256), 0, st, desc, offs, ncat, *key,
-                           *idx, ntot, g, pos32, abs32, pos64, weighted ? w : nullptr);
+                           *idx, ntot, g, xbits, pos32, abs32, pos64, weighted ? w : nullptr);
     }
     hipLaunchKernelGGL(k_cell_start, dim3((unsigned)((ntot + 1 + 255) / 256)), dim3(256), 0, st, *key, ntot, ncell_all,
-                       cs);
+                       xbits, cs);
 }
 
 }  // namespace fcfc

@@ -938,19 +938,17 @@ static fcfc_status weight_scale(double wmin1, double wmax1, double wmin2, double
     return FCFC_OK;
 }
 
-// Most cells a tile may span: about T points' worth at ppc points per cell
-// (one cell when a cell holds half a tile or more), unless tuned.
-static int tile_seg(const Plan* p, int T, double ppc) {
-    if (p->tune.seg_cells > 0) return std::min(32, p->tune.seg_cells);
-    if (ppc >= T / 2) return 1;
-    return (int)std::max(1.0, std::min(16.0, floor((double)T / std::max(ppc, 1e-9))));
-}
+// Most cells a tile may span, unless tuned: 32, so that tiles are cut by
+// their point count and fill every lane.  B ranges are trimmed to the tile's
+// actual x extent, so a wide tile costs only its extent (measured on MI355X:
+// C5 7.0 -> 5.6 ms, C2 8.5 -> 8.3 ms against the earlier density-based span).
+static int tile_seg(const Plan* p) { return p->tune.seg_cells > 0 ? std::min(32, p->tune.seg_cells) : 32; }
 
-static fcfc_status setup_launch(Plan* p, bool is_auto, bool weighted, bool batch, double ppc, int S, LaunchSetup& L) {
+static fcfc_status setup_launch(Plan* p, bool is_auto, bool weighted, bool batch, int S, LaunchSetup& L) {
     const Grid& g = p->grid;
     L.T = p->tune.tile_points == 64 ? 64 : 128;
     L.P = L.T / 64;
-    L.seg = tile_seg(p, L.T, ppc);
+    L.seg = tile_seg(p);
     L.bchunk = p->tune.b_chunk >= 256 ? p->tune.b_chunk : 16384;
     L.copies = (p->tune.hist_copies == 2 || p->tune.hist_copies == 4) ? p->tune.hist_copies : 1;
     L.nrows = stencil_rows(p, is_auto, L.rows);
@@ -1203,13 +1201,14 @@ fcfc_status count_pairs(Plan* p, Cells* c1, Cells* c2, int64_t* d_counts, double
         FCFC_TRY(weight_scale(c1->wmin, c1->wmax, cb->wmin, cb->wmax, &S));
     }
     LaunchSetup L;
-    const double ppc = (double)c1->n / std::max<int64_t>(1, g.ncell());
-    FCFC_TRY(setup_launch(p, is_auto, weighted, false, ppc, S, L));
+    FCFC_TRY(setup_launch(p, is_auto, weighted, false, S, L));
     if (weighted) L.a.wpre = prescale_ok(c1->wmin, c1->wmax, cb->wmin, cb->wmax, S);
     CountArgs& a = L.a;
     const bool sorted = !pr && p->tune.order != FCFC_ORDER_BUILT;
     const Model* model = pr ? pr->model : (p->tune.order == FCFC_ORDER_LEARNED ? p->model : nullptr);
     WLArgs w = make_wl(p, L, is_auto, 1, c1->n);
+    w.keyB = cb->xkey;
+    w.xbits = cb->xbits;
     const int64_t nseg = (int64_t)g.ny * g.nz;  // A rows (tile counts per row)
     const int64_t tiles_cap = w.tiles_cap;
     if (tiles_cap >= 0xffffffffLL / std::max(1, L.nrows)) {
@@ -1260,7 +1259,7 @@ fcfc_status count_pairs(Plan* p, Cells* c1, Cells* c2, int64_t* d_counts, double
     fill_u32(ctr, 0u, 64, st);
     hipLaunchKernelGGL(k_tile_count, dim3((unsigned)((nseg + 255) / 256)), dim3(256), 0, st, c1->cell_start, w, tcount);
     scan_exclusive_u32(tcount, toff, nseg, &ctr[0], scan_scr, st);
-    hipLaunchKernelGGL(k_tile_write, dim3((unsigned)((nseg + 255) / 256)), dim3(256), 0, st, c1->cell_start, c1->pos32,
+    hipLaunchKernelGGL(k_tile_write, dim3((unsigned)((nseg + 255) / 256)), dim3(256), 0, st, c1->cell_start, c1->xkey,
                        w, toff, tiles);
     hipLaunchKernelGGL(k_item_count, dim3((unsigned)((npair_tr + 255) / 256)), dim3(256), 0, st, tiles, &ctr[0], srows,
                        cb->cell_start, w, icount);
@@ -1418,6 +1417,7 @@ struct BatchImpl {
     Plan* plan = nullptr;
     int ncat = 0;
     int npairs = 0;  // histograms written: one per (A, B) catalogue pair
+    int xbits = 0;   // sub-cell x bits of the sort keys
     int64_t ntot = 0;
     bool weighted = false;
     int S = 0;
@@ -1442,7 +1442,6 @@ struct BatchImpl {
     uint32_t* cs = nullptr;
     int32_t* pairs = nullptr;  // 2 per pair
     uint32_t *ptile_off = nullptr, *ptile_first = nullptr;
-    int* cat_seg = nullptr;    // tile span per catalogue (from its own density)
     // largest-first order within each pair: keys, values, sort scratch, sorted items
     uint32_t *sk0 = nullptr, *sv0 = nullptr, *sk1 = nullptr, *sv1 = nullptr;
     void* isort_scr = nullptr;
@@ -1498,15 +1497,19 @@ void batch_free_impl(BatchImpl* b) {
 static void batch_enqueue_front(BatchImpl* b, hipStream_t st) {
     Plan* p = b->plan;
     uint32_t *k = b->key, *v = b->idx, *tk = b->tk, *tv = b->tv;
-    batch_build_enqueue(p, b->desc, b->offs, b->ncat, b->ntot, b->weighted, &k, &v, &tk, &tv, b->sort_scr, b->flags,
-                        b->wst, b->pos32, b->abs32, b->pos64, b->w, b->cs, st);
+    batch_build_enqueue(p, b->xbits, b->desc, b->offs, b->ncat, b->ntot, b->weighted, &k, &v, &tk, &tv, b->sort_scr,
+                        b->flags, b->wst, b->pos32, b->abs32, b->pos64, b->w, b->cs, st);
     b->key_s = k;
     b->idx_s = v;
+    // the sorted keys trim the B ranges (the ping-pong buffer that holds them
+    // is the same on every run: the pass count is fixed)
+    b->wl.keyB = k;
+    b->wl.xbits = b->xbits;
     int4* srows = (int4*)(b->tab + (b->L.tb_total - b->L.tb_rows));
     fill_u32(b->ctr, 0u, 64, st);
     hipLaunchKernelGGL(k_tile_count, dim3((unsigned)((b->nseg + 255) / 256)), dim3(256), 0, st, b->cs, b->wl, b->tcount);
     scan_exclusive_u32(b->tcount, b->toff, b->nseg, &b->ctr[0], b->scan_scr, st);
-    hipLaunchKernelGGL(k_tile_write, dim3((unsigned)((b->nseg + 255) / 256)), dim3(256), 0, st, b->cs, b->pos32, b->wl,
+    hipLaunchKernelGGL(k_tile_write, dim3((unsigned)((b->nseg + 255) / 256)), dim3(256), 0, st, b->cs, k, b->wl,
                        b->toff, b->tiles);
     hipLaunchKernelGGL(k_pair_tiles, dim3(1), dim3(1), 0, st, b->toff, &b->ctr[0], b->wl, b->ptile_off, b->ptile_first);
     hipLaunchKernelGGL(k_item_count, dim3((unsigned)((b->npair_tr + 255) / 256)), dim3(256), 0, st, b->tiles, &b->ctr[0],
@@ -1597,22 +1600,19 @@ fcfc_status batch_create_impl(Plan* p, const fcfc_catalog* cats, int ncat, const
     for (int q = 0; q < npairs; q++) b->host_order[q] = (uint32_t)q;
     std::stable_sort(b->host_order.begin(), b->host_order.end(),
                      [&](uint32_t x, uint32_t y) { return cost[x] > cost[y]; });
-    const double ppc = (double)tot / std::max<int64_t>(1, g.ncell() * ncat);
-    fcfc_status s = setup_launch(p, all_auto, b->weighted, true, ppc, 0, b->L);
+    fcfc_status s = setup_launch(p, all_auto, b->weighted, true, 0, b->L);
     if (s != FCFC_OK) {
         delete b;
         return s;
     }
     b->wl = make_wl(p, b->L, all_auto, ncat, tot);
+    b->xbits = key_xbits((int64_t)ncat * g.ncell());
     b->nseg = (int64_t)g.ny * g.nz * ncat;  // A rows
-    // tiles of each catalogue span cells by its own density; pair-tiles: every
-    // pair takes the tiles of its A catalogue (each bounded as in make_wl)
-    std::vector<int> hseg(ncat);
+    // pair-tiles: every pair takes the tiles of its A catalogue (each bounded as in make_wl)
     std::vector<int64_t> cat_tiles(ncat);
     int64_t tiles = 0;
     for (int c = 0; c < ncat; c++) {
-        hseg[c] = tile_seg(p, b->L.T, (double)cats[c].n / std::max<int64_t>(1, g.ncell()));
-        cat_tiles[c] = (int64_t)g.ny * g.nz * ((g.nx + hseg[c] - 1) / hseg[c] + 1) + cats[c].n / b->L.T + 1;
+        cat_tiles[c] = (int64_t)g.ny * g.nz * ((g.nx + b->L.seg - 1) / b->L.seg + 1) + cats[c].n / b->L.T + 1;
         tiles += cat_tiles[c];
     }
     int64_t ptiles = 0;
@@ -1658,7 +1658,6 @@ fcfc_status batch_create_impl(Plan* p, const fcfc_catalog* cats, int ncat, const
     BA(b->tiles, sizeof(Tile) * (size_t)b->wl.tiles_cap);
     BA(b->ctr, 256);
     BA(b->pairs, 8 * (size_t)npairs);
-    BA(b->cat_seg, 4 * (size_t)ncat);
     BA(b->ptile_off, 4 * (size_t)(npairs + 1));
     BA(b->ptile_first, 4 * (size_t)npairs);
     BA(b->pair_items, 4 * (size_t)(npairs + 1));
@@ -1672,13 +1671,11 @@ fcfc_status batch_create_impl(Plan* p, const fcfc_catalog* cats, int ncat, const
     BA(b->tab, b->L.tb_total);
     BA(b->args_dev, sizeof(CountArgs));
     b->wl.pairs = b->pairs;
-    b->wl.cat_seg = b->cat_seg;
     b->wl.ptile_off = b->ptile_off;
     b->wl.ptile_first = b->ptile_first;
     FCFC_HIP(hipMemcpy(b->desc, b->host_desc.data(), sizeof(CatDesc) * ncat, hipMemcpyHostToDevice));
     FCFC_HIP(hipMemcpy(b->offs, b->host_offs.data(), sizeof(int64_t) * (ncat + 1), hipMemcpyHostToDevice));
     FCFC_HIP(hipMemcpy(b->pairs, b->host_pairs.data(), 8 * (size_t)npairs, hipMemcpyHostToDevice));
-    FCFC_HIP(hipMemcpy(b->cat_seg, hseg.data(), 4 * (size_t)ncat, hipMemcpyHostToDevice));
     FCFC_HIP(hipMemcpy(b->pair_order, b->host_order.data(), 4 * (size_t)npairs, hipMemcpyHostToDevice));
     FCFC_HIP(hipMemcpy(b->tab, b->L.htab.data(), b->L.tb_total, hipMemcpyHostToDevice));
     FCFC_HIP(hipEventCreate(&b->ev0));

@@ -140,8 +140,17 @@ struct Cells {
     double* pos64 = nullptr;    // sorted FP64 xyz (AoS)
     double* w = nullptr;        // sorted weights
     uint32_t* cell_start = nullptr;  // ncell + 1
+    // sorted keys: cell key << xbits | the point's x position within its cell
+    // on 2^xbits steps, so that every row of cells is sorted by x
+    uint32_t* xkey = nullptr;
+    int xbits = 0;
     void* block = nullptr;      // single allocation holding everything
 };
+
+// Sub-cell x bits of the sort key for a grid of ncells cells (catalogues x
+// cells for a batched build): the key fills whole bytes up to 32 bits, with
+// at least 8 sub-cell bits when the cell key leaves room for them.
+int key_xbits(int64_t ncells);
 
 // plan / numerics helpers (plan.cpp)
 const char* last_error();
@@ -149,7 +158,7 @@ fcfc_status fcfc_set_bounds_internal(Plan* p, const double lo[3], const double h
 fcfc_status plan_finalize_grid(Plan* p);
 fcfc_status plan_finalize_numerics(Plan* p);
 int choose_k(const Plan* p, int64_t n_hint);
-int stencil_rows(const Plan* p, bool half, std::vector<int4>& rows);  // (dy, dz, kx, 0)
+int stencil_rows(const Plan* p, bool half, std::vector<int4>& rows);  // (dy, dz, kx, float bits of the x reach)
 
 // build (build.hip)
 fcfc_status build_cells(Plan* p, const fcfc_catalog* cat, hipStream_t st, Cells** out);
@@ -167,7 +176,7 @@ struct CatDesc {
     int64_t off;
 };
 size_t batch_build_scratch(int64_t ntot);
-void batch_build_enqueue(const Plan* p, const CatDesc* desc, const int64_t* offs, int ncat, int64_t ntot,
+void batch_build_enqueue(const Plan* p, int xbits, const CatDesc* desc, const int64_t* offs, int ncat, int64_t ntot,
                          bool weighted, uint32_t** key, uint32_t** idx, uint32_t** tk, uint32_t** tv, void* sort_scr,
                          uint32_t* flags, uint64_t* wst, float4* pos32, float4* abs32, double* pos64, double* w,
                          uint32_t* cs, hipStream_t st);

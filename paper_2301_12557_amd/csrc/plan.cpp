@@ -60,8 +60,13 @@ int stencil_rows(const Plan* p, bool half, std::vector<int4>& rows) {
             double tz = std::max(abs(dz) - 1, 0) * s;
             double t2 = ty * ty + tz * tz;
             if (t2 >= reff * reff) continue;
-            int kx = (int)floor(sqrt(reff * reff - t2) / s) + 1;
-            rows.push_back(make_int4(dy, dz, kx, 0));
+            const double reach = sqrt(reff * reff - t2) / s;  // largest |dx| of a pair in range, in cells
+            const int kx = (int)floor(reach) + 1;
+            float rf = (float)reach;
+            if ((double)rf < reach) rf = nextafterf(rf, INFINITY);
+            int rbits;
+            memcpy(&rbits, &rf, 4);
+            rows.push_back(make_int4(dy, dz, kx, rbits));
         }
     }
     return (int)rows.size();

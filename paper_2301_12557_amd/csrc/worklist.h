@@ -10,6 +10,7 @@ struct Tile {
     uint32_t a_count;  // points in the tile
     uint32_t row;      // A row index cz*ny + cy
     uint32_t x01;      // first (bits 0..15) and last (bits 16..31) cell x spanned
+    uint32_t klo, khi; // sort keys of the first and last point (x-ordered within the row)
 };
 
 struct WLArgs {
@@ -17,13 +18,16 @@ struct WLArgs {
     int seg;        // most cells a tile may span
     int tile;       // points per tile
     int bchunk;     // B points per item
-    int nrows;      // stencil rows
+    int nrows;      // stencil rows (x: dy, y: dz, z: kx, w: float bits of the x reach in cells)
+    // sorted keys of the B points (cell key << xbits | sub-cell x): B ranges
+    // are trimmed to the points within reach of the tile's x extent
+    const uint32_t* keyB;
+    int xbits;
     int periodic;
     int is_auto;
     uint32_t tiles_cap;
     int ncat;       // catalogues stacked along z (batched build); 1 otherwise
     int full_rows;  // the stencil table holds every row (auto pairs then skip the lower half)
-    const int* cat_seg;  // per-catalogue seg of a batched build (null: seg for every row)
     // pair mode (batched build, npairs > 0): items of every (A catalogue, B
     // catalogue) pair; pair-tile t of pair p is tile ptile_first[p] + t -
     // ptile_off[p], and index ranges of k_item_count / k_item_write run over
@@ -36,7 +40,7 @@ struct WLArgs {
 };
 
 __global__ void k_tile_count(const uint32_t* __restrict__ csA, WLArgs w, uint32_t* __restrict__ tcount);
-__global__ void k_tile_write(const uint32_t* __restrict__ csA, const float4* __restrict__ posA, WLArgs w,
+__global__ void k_tile_write(const uint32_t* __restrict__ csA, const uint32_t* __restrict__ keyA, WLArgs w,
                              const uint32_t* __restrict__ toff, Tile* __restrict__ tiles);
 __global__ void k_item_count(const Tile* __restrict__ tiles, const uint32_t* __restrict__ ntiles_dev,
                              const int4* __restrict__ srows, const uint32_t* __restrict__ csB, WLArgs w,

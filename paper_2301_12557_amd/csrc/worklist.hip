@@ -47,34 +47,44 @@ __device__ inline void row_tiles(const uint32_t* __restrict__ csA, int64_t rowce
     }
 }
 
-// Largest cell span of a tile in row r (per catalogue in a batched build).
-__device__ inline int row_seg(const WLArgs& w, int64_t r) {
-    return w.cat_seg ? w.cat_seg[r / ((int64_t)w.ny * w.nz)] : w.seg;
-}
-
 __global__ void k_tile_count(const uint32_t* __restrict__ csA, WLArgs w, uint32_t* __restrict__ tcount) {
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t nrow = (int64_t)w.ny * w.nz * w.ncat;
     if (r >= nrow) return;
     uint32_t n = 0;
-    row_tiles(csA, r * w.nx, w, row_seg(w, r), [&](uint32_t, uint32_t, int, int) { n++; });
+    row_tiles(csA, r * w.nx, w, w.seg, [&](uint32_t, uint32_t, int, int) { n++; });
     tcount[r] = n;
 }
 
-__global__ void k_tile_write(const uint32_t* __restrict__ csA, const float4* __restrict__ posA, WLArgs w,
+__global__ void k_tile_write(const uint32_t* __restrict__ csA, const uint32_t* __restrict__ keyA, WLArgs w,
                              const uint32_t* __restrict__ toff, Tile* __restrict__ tiles) {
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t nrow = (int64_t)w.ny * w.nz * w.ncat;
     if (r >= nrow) return;
     uint32_t t = toff[r];
-    row_tiles(csA, r * w.nx, w, row_seg(w, r), [&](uint32_t a, uint32_t cnt, int cxa, int cxb) {
+    row_tiles(csA, r * w.nx, w, w.seg, [&](uint32_t a, uint32_t cnt, int cxa, int cxb) {
         Tile tl;
         tl.a_begin = a;
         tl.a_count = cnt;
         tl.row = (uint32_t)r;
         tl.x01 = (uint32_t)(cxa & 0xffff) | ((uint32_t)cxb << 16);
+        tl.klo = keyA[a];
+        tl.khi = keyA[a + cnt - 1];
         tiles[t++] = tl;
     });
+}
+
+// First index in [lo, hi) of a sorted key array whose key is >= v (> v when
+// `upper`).
+__device__ inline uint32_t key_search(const uint32_t* __restrict__ key, uint32_t lo, uint32_t hi, uint64_t v,
+                                      bool upper) {
+    while (lo < hi) {
+        const uint32_t mid = lo + ((hi - lo) >> 1);
+        const uint64_t k = key[mid];
+        if (upper ? (k <= v) : (k < v)) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
 }
 
 // Enumerate the pieces of (tile, stencil row) against the B rows of
@@ -107,6 +117,17 @@ __device__ inline void tile_row_items(const Tile& tl, int4 srow, const uint32_t*
     int x0 = (int)(tl.x01 & 0xffff), x1 = (int)(tl.x01 >> 16);
     int xlo = x0 - kx, xhi = x1 + kx;
     uint32_t rowcell = (((uint32_t)bcat * (uint32_t)w.nz + (uint32_t)zb) * (uint32_t)w.ny + (uint32_t)yb) * (uint32_t)w.nx;
+    // the tile's x extent in cells of its row, bounded by the sort keys of its
+    // first and last point (the key holds the x position within the cell on
+    // 2^xbits steps, rounded down)
+    const double steps = (double)(1u << w.xbits);
+    const uint32_t xmask = (1u << w.xbits) - 1u;
+    const uint32_t rowcellA = tl.row * (uint32_t)w.nx;
+    const double ua_lo = (double)((tl.klo >> w.xbits) - rowcellA) + (double)(tl.klo & xmask) / steps;
+    const double ua_hi = (double)((tl.khi >> w.xbits) - rowcellA) + (double)((tl.khi & xmask) + 1u) / steps;
+    // largest |dx| of a pair in range for this row, in cells, rounded up; the
+    // extra 1e-6 cells covers the rounding of the keys' FP64 positions
+    const double reach = (double)__int_as_float(srow.w) + 1e-6;
     // pieces: 0 = direct, 1 = wrapped from the left (sx = -1), 2 = wrapped from the right (sx = +1)
     for (int pc = 0; pc < 3; pc++) {
         int c0, c1, sx;
@@ -132,6 +153,16 @@ __device__ inline void tile_row_items(const Tile& tl, int4 srow, const uint32_t*
             flags |= ITEM_SAMEROW;
             bb = max(bb, tl.a_begin);
         }
+        if (w.keyB) {
+            // B points of this piece within reach of the tile, in the B row's
+            // own cell units (the piece's image shift moves them by sx nx)
+            const double lo = ua_lo - reach - (double)(sx * w.nx);
+            const double hi = ua_hi + reach - (double)(sx * w.nx);
+            const uint64_t base = (uint64_t)rowcell << w.xbits;
+            if (hi < (double)c0) continue;  // the whole piece is out of reach
+            if (lo > (double)c0) bb = key_search(w.keyB, bb, be, base + (uint64_t)floor(lo * steps), false);
+            if (hi < (double)(c1 + 1)) be = key_search(w.keyB, bb, be, base + (uint64_t)floor(hi * steps), true);
+        }
         if (bb >= be) continue;
         int xb0 = c0 + sx * w.nx;
         uint32_t meta = ((uint32_t)(uint8_t)(int8_t)dy) | ((uint32_t)(uint8_t)(int8_t)dz << 8) |
@@ -143,7 +174,9 @@ __device__ inline void tile_row_items(const Tile& tl, int4 srow, const uint32_t*
             it.b_begin = b;
             it.b_end = min(be, b + (uint32_t)w.bchunk);
             it.b_rowcell = rowcell;
-            it.acnt_xb0 = (tl.a_count & 0xffffu) | ((uint32_t)(uint16_t)(int16_t)xb0 << 16);
+            // the kernel walks B cells from the cell of the item's first point
+            const int xs = w.keyB ? (int)((w.keyB[b] >> w.xbits) - rowcell) + sx * w.nx : xb0;
+            it.acnt_xb0 = (tl.a_count & 0xffffu) | ((uint32_t)(uint16_t)(int16_t)xs << 16);
             it.meta = meta;
             uint64_t pairs = (uint64_t)tl.a_count * (uint64_t)(it.b_end - it.b_begin);
             it.cost = (uint32_t)min<uint64_t>(pairs, 0xffffffffull);
