@@ -100,7 +100,15 @@ extern "C" fcfc_status fcfc_plan_stats(fcfc_plan_t plan, fcfc_stats* out) {
 extern "C" void fcfc_cells_free(fcfc_cells_t cells) {
     Cells* c = (Cells*)cells;
     if (!c) return;
-    if (c->block) (void)hipFree(c->block);
+    if (c->block) {
+        // as hipFree would, wait for all work on the device (counts that read
+        // the cell set may still be in flight), then hand the block back to
+        // the library's pool; the free completes before this returns, so any
+        // stream may reuse the memory
+        (void)hipDeviceSynchronize();
+        dev_free(c->block, nullptr);
+        (void)hipStreamSynchronize(nullptr);
+    }
     delete c;
 }
 

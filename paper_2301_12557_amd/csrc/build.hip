@@ -5,6 +5,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <vector>
 
 #include "internal.h"
 
@@ -29,6 +30,16 @@ int key_xbits(int64_t ncells) {
     while (cb < 31 && ((int64_t)1 << cb) < ncells) cb++;
     const int total = std::min(32, (cb + 8 + 7) / 8 * 8);
     return total - cb;
+}
+
+void weight_stats_reduce(const uint64_t* slots, uint64_t* bmin, uint64_t* bmax) {
+    uint64_t m = 0, x = 0;
+    for (int sl = 0; sl < STAT_SLOTS; sl++) {
+        m = std::max(m, slots[(size_t)sl * STAT_STRIDE]);
+        x = std::max(x, slots[(size_t)sl * STAT_STRIDE + 1]);
+    }
+    *bmin = ~m;  // ~0 when no slot saw a non-zero weight
+    *bmax = x;
 }
 
 static int grid_for(int64_t n, int block = 256, int cap = 65536) {
@@ -245,7 +256,7 @@ void radix_sort_pairs(uint32_t** k, uint32_t** v, uint32_t** tk, uint32_t** tv, 
 // bounding box over catalogues
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_aabb(const double* __restrict__ xyz, int64_t n,
-                                              uint64_t* __restrict__ mm /*lo[3], hi[3] ord bits*/,
+                                              uint64_t* __restrict__ mm /*slots: ~lo[3], hi[3] ord bits*/,
                                               uint32_t* __restrict__ flags) {
     __shared__ uint64_t smin[3][256], smax[3][256];
     __shared__ uint32_t sflag;
@@ -282,9 +293,10 @@ __global__ __launch_bounds__(256) void k_aabb(const double* __restrict__ xyz, in
         __syncthreads();
     }
     if (threadIdx.x == 0) {
+        unsigned long long* slot = (unsigned long long*)mm + (size_t)(blockIdx.x % STAT_SLOTS) * STAT_STRIDE;
         for (int a = 0; a < 3; a++) {
-            atomicMin((unsigned long long*)&mm[a], (unsigned long long)smin[a][0]);
-            atomicMax((unsigned long long*)&mm[3 + a], (unsigned long long)smax[a][0]);
+            atomicMax(&slot[a], ~(unsigned long long)smin[a][0]);
+            atomicMax(&slot[3 + a], (unsigned long long)smax[a][0]);
         }
         if (sflag) atomicOr(flags, sflag);
     }
@@ -292,32 +304,25 @@ __global__ __launch_bounds__(256) void k_aabb(const double* __restrict__ xyz, in
 
 fcfc_status fit_bounds(Plan* p, const fcfc_catalog* cats, int ncat, hipStream_t st) {
     uint64_t* d = nullptr;
-    FCFC_HIP(hipMallocAsync((void**)&d, 64, st));
-    uint32_t* flags = (uint32_t*)(d + 6);
-    uint64_t init[7];
-    for (int a = 0; a < 3; a++) {
-        init[a] = ~0ull;
-        init[3 + a] = 0ull;
-    }
-    init[6] = 0;
+    FCFC_TRY(dev_alloc((void**)&d, STAT_BYTES + 64, st));
+    uint32_t* flags = (uint32_t*)(d + STAT_SLOTS * STAT_STRIDE);
     int64_t total = 0;
-    fill_u64(d, ~0ull, 3, st);
-    fill_u64(d + 3, 0ull, 4, st);
+    fill_u64(d, 0ull, STAT_SLOTS * STAT_STRIDE + 8, st);
     for (int c = 0; c < ncat; c++) {
         if (cats[c].n <= 0) continue;
         total += cats[c].n;
         int g = grid_for(cats[c].n, 256, 4096);
         hipLaunchKernelGGL(k_aabb, dim3(g), dim3(256), 0, st, cats[c].xyz, cats[c].n, d, flags);
     }
-    uint64_t h[7];
-    hipError_t e1 = hipMemcpyAsync(h, d, 56, hipMemcpyDeviceToHost, st);
+    std::vector<uint64_t> h(STAT_SLOTS * STAT_STRIDE + 8);
+    hipError_t e1 = hipMemcpyAsync(h.data(), d, STAT_BYTES + 64, hipMemcpyDeviceToHost, st);
     hipError_t e2 = hipStreamSynchronize(st);
-    (void)hipFreeAsync(d, st);
+    dev_free(d, st);
     if (e1 != hipSuccess || e2 != hipSuccess) {
         set_error("fit_bounds: %s", hipGetErrorString(e1 != hipSuccess ? e1 : e2));
         return FCFC_EHIP;
     }
-    if ((uint32_t)h[6] & 1u) {
+    if (h[STAT_SLOTS * STAT_STRIDE] & 1u) {
         set_error("fit_bounds: non-finite coordinate");
         return FCFC_ENONFINITE;
     }
@@ -329,8 +334,13 @@ fcfc_status fit_bounds(Plan* p, const fcfc_catalog* cats, int ncat, hipStream_t 
         }
     } else {
         for (int a = 0; a < 3; a++) {
-            lo[a] = ord_value(h[a]);
-            hi[a] = ord_value(h[3 + a]);
+            uint64_t l = 0, u = 0;  // max of ~lo bits, max of hi bits
+            for (int sl = 0; sl < STAT_SLOTS; sl++) {
+                l = std::max(l, h[(size_t)sl * STAT_STRIDE + a]);
+                u = std::max(u, h[(size_t)sl * STAT_STRIDE + 3 + a]);
+            }
+            lo[a] = ord_value(~l);
+            hi[a] = ord_value(u);
         }
     }
     return fcfc_set_bounds_internal(p, lo, hi);
@@ -349,6 +359,23 @@ struct GridArgs {
 
 enum : uint32_t { VF_NONFINITE = 1u, VF_BOX = 2u, VF_WNONFINITE = 4u };
 
+// Weight statistics of a workgroup: smallest non-zero and largest |w| as
+// ordered bits.  Each wave reduces its lanes with shuffles and one lane
+// updates the workgroup's LDS words (all 256 lanes contending for one LDS
+// word made the key pass four times slower).
+__device__ inline void wave_weight_stats(unsigned long long bmin, unsigned long long bmax, unsigned long long* swmin,
+                                         unsigned long long* swmax) {
+    for (int o = 32; o > 0; o >>= 1) {
+        const unsigned long long a = __shfl_xor(bmin, o), b = __shfl_xor(bmax, o);
+        bmin = a < bmin ? a : bmin;
+        bmax = b > bmax ? b : bmax;
+    }
+    if ((threadIdx.x & 63) == 0) {
+        if (bmin != ~0ull) atomicMin(swmin, bmin);
+        if (bmax) atomicMax(swmax, bmax);
+    }
+}
+
 __device__ inline int cell_of(double x, double lo, double side, int n) {
     double f = floor((x - lo) / side);
     int c = (f < 0.0) ? 0 : ((f > (double)(n - 1)) ? n - 1 : (int)f);
@@ -364,7 +391,7 @@ __device__ inline uint32_t subcell_of(double x, double lo, double side, int c, i
 __global__ __launch_bounds__(256) void k_keys(const double* __restrict__ xyz, const double* __restrict__ w,
                                               int64_t n, GridArgs g, int xbits, uint32_t* __restrict__ key,
                                               uint32_t* __restrict__ idx, uint32_t* __restrict__ flags,
-                                              uint64_t* __restrict__ wst /*[0] min nonzero |w|, [1] max*/) {
+                                              uint64_t* __restrict__ wst /*slots: ~min nonzero |w|, max |w| bits*/) {
     __shared__ uint32_t sflag;
     __shared__ uint64_t swmin, swmax;
     if (threadIdx.x == 0) {
@@ -375,6 +402,7 @@ __global__ __launch_bounds__(256) void k_keys(const double* __restrict__ xyz, co
     __syncthreads();
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     uint32_t f = 0;
+    unsigned long long bmin = ~0ull, bmax = 0ull;
     if (i < n) {
         double x = xyz[3 * i], y = xyz[3 * i + 1], z = xyz[3 * i + 2];
         if (!isfinite(x) || !isfinite(y) || !isfinite(z)) {
@@ -399,19 +427,21 @@ __global__ __launch_bounds__(256) void k_keys(const double* __restrict__ xyz, co
                 f |= VF_WNONFINITE;
             } else {
                 double a = fabs(wv);
-                uint64_t b = (uint64_t)__double_as_longlong(a);  // positive: bits are ordered
-                if (a > 0.0) atomicMin((unsigned long long*)&swmin, (unsigned long long)b);
-                atomicMax((unsigned long long*)&swmax, (unsigned long long)b);
+                unsigned long long b = (unsigned long long)__double_as_longlong(a);  // positive: bits are ordered
+                if (a > 0.0) bmin = b;
+                bmax = b;
             }
         }
         if (f) atomicOr(&sflag, f);
     }
+    if (w) wave_weight_stats(bmin, bmax, (unsigned long long*)&swmin, (unsigned long long*)&swmax);
     __syncthreads();
     if (threadIdx.x == 0) {
         if (sflag) atomicOr(flags, sflag);
         if (w) {
-            if (swmin != ~0ull) atomicMin((unsigned long long*)&wst[0], (unsigned long long)swmin);
-            atomicMax((unsigned long long*)&wst[1], (unsigned long long)swmax);
+            unsigned long long* slot = (unsigned long long*)wst + (size_t)(blockIdx.x % STAT_SLOTS) * STAT_STRIDE;
+            if (swmin != ~0ull) atomicMax(&slot[0], ~(unsigned long long)swmin);
+            if (swmax) atomicMax(&slot[1], (unsigned long long)swmax);
         }
     }
 }
@@ -490,7 +520,7 @@ fcfc_status build_cells(Plan* p, const fcfc_catalog* cat, hipStream_t st, Cells*
     Cells* c = new (std::nothrow) Cells();
     if (!c) return FCFC_ENOMEM;
     char* blk = nullptr;
-    if (hipMalloc((void**)&blk, total) != hipSuccess) {
+    if (dev_alloc((void**)&blk, total, st) != FCFC_OK) {
         delete c;
         set_error("build_cells: cannot allocate %zu bytes", total);
         return FCFC_ENOMEM;
@@ -511,12 +541,12 @@ fcfc_status build_cells(Plan* p, const fcfc_catalog* cat, hipStream_t st, Cells*
 
     // scratch: keys, idx, tmp keys, tmp idx, flags + weight stats, sort scratch
     size_t s_keys = align256((size_t)std::max<int64_t>(n, 1) * 4);
-    size_t s_misc = 256;
+    size_t s_misc = 256 + STAT_BYTES;
     size_t s_sort = align256(radix_scratch_bytes(n));
     size_t stotal = 4 * s_keys + s_misc + s_sort;
     char* scr = nullptr;
-    if (hipMallocAsync((void**)&scr, stotal, st) != hipSuccess) {
-        (void)hipFree(blk);
+    if (dev_alloc((void**)&scr, stotal, st) != FCFC_OK) {
+        dev_free(blk, st);
         delete c;
         set_error("build_cells: cannot allocate scratch");
         return FCFC_ENOMEM;
@@ -526,15 +556,14 @@ fcfc_status build_cells(Plan* p, const fcfc_catalog* cat, hipStream_t st, Cells*
     uint32_t* tk = (uint32_t*)(scr + 2 * s_keys);
     uint32_t* tv = (uint32_t*)(scr + 3 * s_keys);
     uint32_t* flags = (uint32_t*)(scr + 4 * s_keys);
-    uint64_t* wst = (uint64_t*)(scr + 4 * s_keys + 64);
+    uint64_t* wst = (uint64_t*)(scr + 4 * s_keys + 256);
     void* sort_scr = scr + 4 * s_keys + s_misc;
 
     GridArgs g = make_grid_args(p);
     fill_u32((uint32_t*)(c->pos32 + n), 0u, PAD * 4, st);
     if (weighted) fill_u64((uint64_t*)(c->w + n), 0ull, PAD, st);
     fill_u32(flags, 0u, 1, st);
-    fill_u64(wst, ~0ull, 1, st);
-    fill_u64(wst + 1, 0ull, 1, st);
+    fill_u64(wst, 0ull, STAT_SLOTS * STAT_STRIDE, st);
     if (n > 0) {
         hipLaunchKernelGGL(k_keys, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, cat->xyz, cat->w, n, g,
                            c->xbits, key, idx, flags, wst);
@@ -545,8 +574,8 @@ fcfc_status build_cells(Plan* p, const fcfc_catalog* cat, hipStream_t st, Cells*
         hipLaunchKernelGGL(k_gather, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, cat->xyz, cat->w, key,
                            idx, n, g, c->xbits, c->pos32, c->abs32, c->pos64, c->w);
         if (hipMemcpyAsync(c->xkey, key, (size_t)n * 4, hipMemcpyDeviceToDevice, st) != hipSuccess) {
-            (void)hipFreeAsync(scr, st);
-            (void)hipFree(blk);
+            dev_free(scr, st);
+            dev_free(blk, st);
             delete c;
             set_error("build_cells: HIP copy failed");
             return FCFC_EHIP;
@@ -555,12 +584,13 @@ fcfc_status build_cells(Plan* p, const fcfc_catalog* cat, hipStream_t st, Cells*
     hipLaunchKernelGGL(k_cell_start, dim3((unsigned)((n + 1 + 255) / 256)), dim3(256), 0, st, key, n, ncell, c->xbits,
                        c->cell_start);
     uint64_t h[3] = {0, 0, 0};
+    std::vector<uint64_t> hws(STAT_SLOTS * STAT_STRIDE);
     hipError_t e1 = hipMemcpyAsync(h, flags, 8, hipMemcpyDeviceToHost, st);
-    hipError_t e2 = hipMemcpyAsync(h + 1, wst, 16, hipMemcpyDeviceToHost, st);
+    hipError_t e2 = hipMemcpyAsync(hws.data(), wst, STAT_BYTES, hipMemcpyDeviceToHost, st);
     hipError_t e3 = hipStreamSynchronize(st);
-    (void)hipFreeAsync(scr, st);
+    dev_free(scr, st);
     if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
-        (void)hipFree(blk);
+        dev_free(blk, st);
         delete c;
         set_error("build_cells: HIP error %s", hipGetErrorString(e3 != hipSuccess ? e3 : (e2 != hipSuccess ? e2 : e1)));
         return FCFC_EHIP;
@@ -575,11 +605,12 @@ fcfc_status build_cells(Plan* p, const fcfc_catalog* cat, hipStream_t st, Cells*
         s = FCFC_EBOX;
     }
     if (s != FCFC_OK) {
-        (void)hipFree(blk);
+        dev_free(blk, st);
         delete c;
         return s;
     }
     if (weighted) {
+        weight_stats_reduce(hws.data(), &h[1], &h[2]);
         double a, b;
         memcpy(&a, &h[1], 8);
         memcpy(&b, &h[2], 8);
@@ -619,6 +650,7 @@ __global__ __launch_bounds__(256) void k_bkeys(const CatDesc* __restrict__ cats,
     }
     __syncthreads();
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    unsigned long long bmin = ~0ull, bmax = 0ull;
     if (i < ntot) {
         const int c = find_cat(offs, ncat, i);
         const CatDesc d = cats[c];
@@ -647,18 +679,20 @@ __global__ __launch_bounds__(256) void k_bkeys(const CatDesc* __restrict__ cats,
                 f |= VF_WNONFINITE;
             } else {
                 double a = fabs(wv);
-                uint64_t b = (uint64_t)__double_as_longlong(a);
-                if (a > 0.0) atomicMin((unsigned long long*)&swmin, (unsigned long long)b);
-                atomicMax((unsigned long long*)&swmax, (unsigned long long)b);
+                unsigned long long b = (unsigned long long)__double_as_longlong(a);
+                if (a > 0.0) bmin = b;
+                bmax = b;
             }
         }
         if (f) atomicOr(&sflag, f);
     }
+    wave_weight_stats(bmin, bmax, (unsigned long long*)&swmin, (unsigned long long*)&swmax);
     __syncthreads();
     if (threadIdx.x == 0) {
         if (sflag) atomicOr(flags, sflag);
-        if (swmin != ~0ull) atomicMin((unsigned long long*)&wst[0], (unsigned long long)swmin);
-        if (swmax) atomicMax((unsigned long long*)&wst[1], (unsigned long long)swmax);
+        unsigned long long* slot = (unsigned long long*)wst + (size_t)(blockIdx.x % STAT_SLOTS) * STAT_STRIDE;
+        if (swmin != ~0ull) atomicMax(&slot[0], ~(unsigned long long)swmin);
+        if (swmax) atomicMax(&slot[1], (unsigned long long)swmax);
     }
 }
 
@@ -701,8 +735,7 @@ void batch_build_enqueue(const Plan* p, int xbits, const CatDesc* desc, const in
     fill_u32((uint32_t*)(pos32 + ntot), 0u, 8 * 4, st);
     if (weighted) fill_u64((uint64_t*)(w + ntot), 0ull, 8, st);
     fill_u32(flags, 0u, 1, st);
-    fill_u64(wst, ~0ull, 1, st);
-    fill_u64(wst + 1, 0ull, 1, st);
+    fill_u64(wst, 0ull, STAT_SLOTS * STAT_STRIDE, st);
     if (ntot > 0) {
         hipLaunchKernelGGL(k_bkeys, dim3((unsigned)((ntot + 255) / 256)), dim3(256), 0, st, desc, offs, ncat, ntot, g,
                            xbits, *key, *idx, flags, wst);

@@ -1228,7 +1228,7 @@ fcfc_status count_pairs(Plan* p, Cells* c1, Cells* c2, int64_t* d_counts, double
     size_t s_acc = weighted ? al256((size_t)p->nbins * 16) : 0;
     size_t s1 = s_tab + 2 * s_tc + s_tiles + 2 * s_ic + s_scan + s_ctr + s_args + s_acc;
     char* scr = nullptr;
-    if (hipMallocAsync((void**)&scr, s1, st) != hipSuccess) {
+    if (dev_alloc((void**)&scr, s1, st) != FCFC_OK) {
         set_error("count_pairs: cannot allocate %zu bytes of scratch", s1);
         return FCFC_ENOMEM;
     }
@@ -1275,8 +1275,8 @@ fcfc_status count_pairs(Plan* p, Cells* c1, Cells* c2, int64_t* d_counts, double
     size_t s_pred = model ? al256((size_t)std::max<uint32_t>(nitems, 1) * 20) : 0;
     size_t s2 = 2 * s_items + 4 * s_sort + s_rs + s_times + s_pred;
     char* scr2 = nullptr;
-    if (hipMallocAsync((void**)&scr2, s2, st) != hipSuccess) {
-        (void)hipFreeAsync(scr, st);
+    if (dev_alloc((void**)&scr2, s2, st) != FCFC_OK) {
+        dev_free(scr, st);
         set_error("count_pairs: cannot allocate %zu bytes for %u work items", s2, nitems);
         return FCFC_ENOMEM;
     }
@@ -1300,8 +1300,8 @@ fcfc_status count_pairs(Plan* p, Cells* c1, Cells* c2, int64_t* d_counts, double
             FCFC_HIP(hipMemcpyAsync(tk, dsum, 16, hipMemcpyDeviceToHost, st));
         }
         FCFC_HIP(hipStreamSynchronize(st));
-        (void)hipFreeAsync(scr2, st);
-        (void)hipFreeAsync(scr, st);
+        dev_free(scr2, st);
+        dev_free(scr, st);
         int khz = 0;
         if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, 0) != hipSuccess || khz <= 0) khz = 100000;
         pr->items = nitems;
@@ -1385,8 +1385,8 @@ fcfc_status count_pairs(Plan* p, Cells* c1, Cells* c2, int64_t* d_counts, double
             p->timing_n = nitems;
         }
     }
-    (void)hipFreeAsync(scr2, st);
-    (void)hipFreeAsync(scr, st);
+    dev_free(scr2, st);
+    dev_free(scr, st);
     p->last_stream = st;
     p->have_stats = true;
     p->stats.items = nitems;
@@ -1644,7 +1644,7 @@ fcfc_status batch_create_impl(Plan* p, const fcfc_catalog* cats, int ncat, const
     BA(b->tv, 4 * (size_t)tot);
     BA(b->sort_scr, batch_build_scratch(tot));
     BA(b->flags, 64);
-    BA(b->wst, 64);
+    BA(b->wst, STAT_BYTES);
     BA(b->pos32, 16 * (size_t)(tot + 8));
     if (need_abs) BA(b->abs32, 16 * (size_t)(tot + 8));
     BA(b->pos64, 24 * (size_t)tot);
@@ -1684,9 +1684,10 @@ fcfc_status batch_create_impl(Plan* p, const fcfc_catalog* cats, int ncat, const
     batch_enqueue_front(b, st);
     uint32_t hctr[2] = {0, 0};
     uint64_t hw[2] = {0, 0};
+    std::vector<uint64_t> hws(STAT_SLOTS * STAT_STRIDE);
     uint32_t hflags = 0;
     FCFC_HIP(hipMemcpyAsync(hctr, b->ctr, 8, hipMemcpyDeviceToHost, st));
-    FCFC_HIP(hipMemcpyAsync(hw, b->wst, 16, hipMemcpyDeviceToHost, st));
+    FCFC_HIP(hipMemcpyAsync(hws.data(), b->wst, STAT_BYTES, hipMemcpyDeviceToHost, st));
     FCFC_HIP(hipMemcpyAsync(&hflags, b->flags, 4, hipMemcpyDeviceToHost, st));
     FCFC_HIP(hipStreamSynchronize(st));
     if (hflags & 5u) {
@@ -1701,6 +1702,7 @@ fcfc_status batch_create_impl(Plan* p, const fcfc_catalog* cats, int ncat, const
         return FCFC_EBOX;
     }
     if (b->weighted) {
+        weight_stats_reduce(hws.data(), &hw[0], &hw[1]);
         double wmin = 0, wmax = 0;
         if (hw[0] != ~0ull) memcpy(&wmin, &hw[0], 8);
         memcpy(&wmax, &hw[1], 8);

@@ -104,7 +104,7 @@ __global__ void k_wp(const double* __restrict__ xi, int nsp, int npi, const doub
 }
 
 static fcfc_status upload_edges(const double* h, int n, double** d, hipStream_t st) {
-    if (hipMallocAsync((void**)d, sizeof(double) * (size_t)(n + 1), st) != hipSuccess) {
+    if (dev_alloc((void**)d, sizeof(double) * (size_t)(n + 1), st) != FCFC_OK) {
         set_error("estimators: cannot allocate %d edges", n + 1);
         return FCFC_ENOMEM;
     }
@@ -160,7 +160,7 @@ extern "C" fcfc_status fcfc_analytic_rr(fcfc_plan_t plan, double npairs, double*
     if (p->kind != FCFC_BIN_S) {
         fcfc_status s = upload_edges(p->e2.data(), p->n2, &e2, st);
         if (s != FCFC_OK) {
-            (void)hipFreeAsync(e1, st);
+            dev_free(e1, st);
             return s;
         }
     }
@@ -168,8 +168,8 @@ extern "C" fcfc_status fcfc_analytic_rr(fcfc_plan_t plan, double npairs, double*
     hipLaunchKernelGGL(k_analytic_rr, dim3((p->nbins + 255) / 256), dim3(256), 0, st, p->kind, e1, p->n1, e2, p->n2,
                        scale, d_rr);
     fcfc_status s = (hipGetLastError() == hipSuccess) ? FCFC_OK : FCFC_EHIP;
-    (void)hipFreeAsync(e1, st);
-    if (e2) (void)hipFreeAsync(e2, st);
+    dev_free(e1, st);
+    if (e2) dev_free(e2, st);
     if (s != FCFC_OK) set_error("analytic_rr: launch failed");
     return s;
 }
@@ -187,8 +187,8 @@ extern "C" fcfc_status fcfc_multipoles(const double* d_xi, int32_t ns, const dou
     double* mu = nullptr;
     FCFC_TRY(upload_edges(mu_edges, nmu, &mu, st));
     int* dl = nullptr;
-    if (hipMallocAsync((void**)&dl, sizeof(int) * (size_t)nell, st) != hipSuccess) {
-        (void)hipFreeAsync(mu, st);
+    if (dev_alloc((void**)&dl, sizeof(int) * (size_t)nell, st) != FCFC_OK) {
+        dev_free(mu, st);
         set_error("multipoles: cannot allocate");
         return FCFC_ENOMEM;
     }
@@ -199,8 +199,8 @@ extern "C" fcfc_status fcfc_multipoles(const double* d_xi, int32_t ns, const dou
                            d_out);
         if (hipGetLastError() != hipSuccess) s = FCFC_EHIP;
     }
-    (void)hipFreeAsync(mu, st);
-    (void)hipFreeAsync(dl, st);
+    dev_free(mu, st);
+    dev_free(dl, st);
     if (s != FCFC_OK) set_error("multipoles: HIP failure");
     return s;
 }
@@ -214,7 +214,7 @@ extern "C" fcfc_status fcfc_wp(const double* d_xi, int32_t nsp, const double* pi
     FCFC_TRY(upload_edges(pi_edges, npi, &pe, st));
     hipLaunchKernelGGL(k_wp, dim3((nsp + 255) / 256), dim3(256), 0, st, d_xi, nsp, npi, pe, d_out);
     fcfc_status s = (hipGetLastError() == hipSuccess) ? FCFC_OK : FCFC_EHIP;
-    (void)hipFreeAsync(pe, st);
+    dev_free(pe, st);
     if (s != FCFC_OK) set_error("wp: launch failed");
     return s;
 }

@@ -168,6 +168,19 @@ void fill_u64(uint64_t* p, uint64_t v, int64_t n, hipStream_t st);
 // relative error bound assumed for the hardware FP32 rsq and rcp (plan.cpp)
 double trans_rel_bound();
 
+// Per-launch statistics (weight range, bounding box) are gathered in
+// STAT_SLOTS slots of one 128-byte line each, workgroup b updating slot
+// b % STAT_SLOTS: one address taking an atomic from every workgroup
+// serialised them (about 11 ns each).  Minima are kept as maxima of the
+// complemented bits, so that a zero fill initialises every slot; the host
+// reduces the slots after its read-back.
+constexpr int STAT_SLOTS = 64;
+constexpr int STAT_STRIDE = 16;  // u64 per slot
+constexpr size_t STAT_BYTES = (size_t)STAT_SLOTS * STAT_STRIDE * 8;
+// weight statistics of a build: bits of the smallest non-zero |w| (~0 when
+// there is none) and of the largest |w|
+void weight_stats_reduce(const uint64_t* slots, uint64_t* bmin, uint64_t* bmax);
+
 // batched build (build.hip)
 struct CatDesc {
     const double* xyz;
@@ -206,5 +219,11 @@ fcfc_status batch_check_impl(BatchImpl* b, hipStream_t st, uint32_t* nitems, flo
 void batch_free_impl(BatchImpl* b);
 
 int device_cu_count();
+
+// Stream-ordered device memory from the library's pool (mem.cpp): dev_alloc
+// returns FCFC_ENOMEM (with the error text set) on failure; dev_free returns
+// the memory on stream `st`.
+fcfc_status dev_alloc(void** ptr, size_t bytes, hipStream_t st);
+void dev_free(void* ptr, hipStream_t st);
 
 }  // namespace fcfc
