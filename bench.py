@@ -40,7 +40,7 @@ def parse():
     ap.add_argument("--tune", default="", help="tuning overrides, e.g. cells_per_rmax=3,tile_points=128")
     ap.add_argument("--no-c4", action="store_true", help="skip the batched-mocks comparison")
     ap.add_argument("--c4-mocks", type=int, default=200)
-    ap.add_argument("--c4-repeats", type=int, default=5)
+    ap.add_argument("--c4-repeats", type=int, default=12)
     ap.add_argument("--no-learned", action="store_true", help="skip training and the held-out C5 comparison")
     ap.add_argument("--no-peaks", action="store_true", help="skip the roofline microbenchmarks")
     ap.add_argument("--no-pairs", action="store_true", help="skip the multi-tracer pair-list comparison")
@@ -114,7 +114,16 @@ def cpu_baseline(w, target_s):
         pass
     omp = os.environ.get("OMP_NUM_THREADS")
     threads = int(omp) if omp else cores
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
     return {"value": float(c.sum()) / dt, "unit": "pairs/s", "cores": threads, "kind": "oracle",
+            "nproc": os.cpu_count(), "cpus_available": cores, "cpu_model": model,
             "sample": f"FP64 cell-list oracle, cross count of {s} random points of the catalogue against all "
                       f"{len(x)} points: {int(c.sum())} in-range pairs in {dt:.2f} s"}
 
@@ -507,6 +516,29 @@ def main():
                    "lut_entries": stats["lut_entries"],
                    "band_d2_rel": stats["band_d2_rel"], "device": torch.cuda.get_device_name(0)},
     }
+    # the build (a1-a5) is HBM-bound: its algorithmic bytes are the inputs read
+    # once and the sorted outputs written once, over HIP events on its stream
+    # (which include the one synchronisation the build makes)
+    bms = []
+    for _ in range(3):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        cb = plan.build_cells(x, wt)
+        e1.record()
+        torch.cuda.synchronize()
+        bms.append(e0.elapsed_time(e1))
+        cb.close()
+    per_point = 24 + 16 + 24 + 4 + (16 if weighted else 0)
+    build_bytes = per_point * len(x) + 4 * (int(np.prod(stats["grid"])) + 1)
+    build_ms = float(min(bms))
+    res["build_roofline"] = {"bound": "hbm", "achieved": build_bytes / (build_ms * 1e-3) / 1e9, "peak": 8000.0,
+                             "unit": "GB/s", "frac": build_bytes / (build_ms * 1e-3) / 8e12, "ms": build_ms,
+                             "algorithmic_bytes": build_bytes,
+                             "per_unit": f"{per_point} B per point (positions{' and weights' if weighted else ''} "
+                                         "read once; FP32 cell-local, FP64, key"
+                                         f"{', weights' if weighted else ''} written once) + 4 B per cell"}
+    log(f"build: {build_ms:.3f} ms, {res['build_roofline']['achieved']:.0f} GB/s")
     if args.shards > 1:
         G = args.shards
         cells = plan.build_cells(x, wt)
