@@ -243,16 +243,28 @@ fcfc_status plan_finalize_numerics(Plan* p) {
     } else {
         ErrModel m1 = d2m, m2 = d2m;
         if (p->los == FCFC_LOS_MIDPOINT) {
-            // absolute FP32 coordinates: error u*R; l = 2a + d per axis
+            // Kernel: l = fl(2a) + d per axis from FP32 absolute coordinates (error
+            // el per axis), dot = d.l and ll = |l|^2 by fma chains, pi^2 =
+            // dot^2 rcp(ll).  With |d| <= r and |l| >= lmin (twice the distance from
+            // the observer to the box):
+            //   |dot32 - dot| / |l| <= dpi = sqrt3 e + sqrt3 el |d| / lmin + 3 u |d|
+            //   (taken with twice the middle term),
+            //   rcp(ll32) = (1 / ll)(1 + eps), |eps| <= rel = 2 sqrt3 el / lmin + 6 u + TRANS_REL,
+            // so |pi^2_32 - pi^2| <= (2 dpi |pi| + dpi^2)(1 + rel) + rel pi^2: a term in
+            // sqrt(E), a constant and a term in E at an edge E = pi^2.  Everything is
+            // doubled for margin.
             double R = p->coord_max;
             double el = 2.0 * (2.0 * u * R + e + u * (2.0 * R + r)) * 2.0;
             double lmin = 2.0 * p->obs_dist;
             double dpi = sqrt(3.0) * e + 2.0 * sqrt(3.0) * el * r / lmin + 3.0 * u * r;
-            double bmid = 2.0 * r * dpi + dpi * dpi +
-                          r * r * (2.0 * sqrt(3.0) * el / lmin + 6.0 * u + TRANS_REL);
-            bmid *= 2.0;
-            m2.B += bmid;          // pi^2
-            m1.B += bmid + u * r * r * 2.0;  // s_perp^2 = d2 - pi^2
+            double rel = 2.0 * sqrt(3.0) * el / lmin + 6.0 * u + TRANS_REL;
+            m2.A += 2.0 * 2.0 * dpi * (1.0 + rel);
+            m2.B += 2.0 * dpi * dpi * (1.0 + rel);
+            m2.C += 2.0 * rel;
+            // s_perp^2 = d2 - pi^2 carries the pi^2 error of any pi in range (up to
+            // just above the top pi edge) and the rounding of the difference
+            const double P2 = p->e2.back() * p->e2.back() * (1.0 + 1e-3) + 1.0;
+            m1.B += 2.0 * ((2.0 * dpi * sqrt(P2) + dpi * dpi) * (1.0 + rel) + rel * P2) + u * r * r * 2.0;
         }
         FCFC_TRY(build_lut(p->lut1, p->e1, m1, std::max(8, lg - 1)));
         FCFC_TRY(build_lut(p->lut2, p->e2, m2, std::max(8, lg - 1)));

@@ -397,3 +397,50 @@ def test_shards_sum_to_the_whole_count():
         assert np.array_equal(tot, whole), G
         assert cand == st["candidates"]
         assert np.allclose(wtot, wwhole, rtol=1e-12, atol=0)
+
+
+def _midpoint_pairs(edges_sp, edges_pi, n_per, seed, rmin=1000.0, rmax=2000.0):
+    """Pairs (a_i, b_i) of a survey shell placed so that the FP64 mid-point pi^2
+    or s_perp^2 of the pair lies at a chosen relative offset (1e-11 .. 1e-1, both
+    signs) from an edge.  b = a + pi l_hat + s_perp p_hat, with l_hat the
+    mid-point line of sight of the pair itself, found by fixed-point iteration."""
+    rng = np.random.default_rng(seed)
+    offs = np.concatenate([-np.logspace(-11, -1, 21), np.logspace(-11, -1, 21)])
+    A, B = [], []
+
+    def place(pi_t, sp_t):
+        a = synth.survey_shell(1, int(rng.integers(1 << 30)), rmin=rmin + 300.0, rmax=rmax - 300.0)[0]
+        t = rng.normal(size=3)
+        lh = a / np.linalg.norm(a)
+        for _ in range(60):
+            p = t - (t @ lh) * lh
+            p /= np.linalg.norm(p)
+            b = a + pi_t * lh + sp_t * p
+            l2 = (a + b) / np.linalg.norm(a + b)
+            if np.allclose(l2, lh, rtol=0, atol=1e-17):
+                break
+            lh = l2
+        A.append(a)
+        B.append(b)
+
+    for k, e in enumerate(edges_pi[1:], 1):
+        for d in offs[rng.permutation(len(offs))[:n_per]]:
+            place(np.sqrt(e * e * (1.0 + d)), rng.uniform(0.0, edges_sp[-1] * 0.9))
+    for k, e in enumerate(edges_sp[1:], 1):
+        for d in offs[rng.permutation(len(offs))[:n_per]]:
+            place(rng.uniform(0.0, edges_pi[-1] * 0.9) * rng.choice([-1.0, 1.0]), np.sqrt(e * e * (1.0 + d)))
+    return np.array(A), np.array(B)
+
+
+def test_midpoint_knife_edges():
+    """Pairs at every distance from 1e-11 to 1e-1 (relative, both sides) of each
+    pi and s_perp edge, mid-point line of sight: the FP32 bands must send every
+    pair whose FP32 value could fall on the wrong side to the FP64 recheck, so the
+    counts equal the oracle's bit for bit."""
+    e = synth.linear_edges(0, 200, 40)
+    a, b = _midpoint_pairs(e, e, 16, 5)
+    note(f"mid-point knife edges: {len(a)} constructed pairs")
+    check_case("mid knife spi", a, b, kind="spi", los="mid", edges1=e, edges2=e, box=0.0)
+    # (s, mu) with the same pairs: mu edges meet pairs at every angle
+    check_case("mid knife smu", a, b, kind="smu", los="mid", edges1=synth.linear_edges(0, 282, 47),
+               edges2=synth.mu_edges(20), box=0.0)
