@@ -375,6 +375,39 @@ fcfc_status fcfc_diag_peaks(double *fma_tflops, double *lds_u32_per_s, double *l
                             double *copy_gbps, void *stream);
 
 /*
+ * Angular pair counts.  The method applies to points on the sky directly
+ * (Sect. 3.1; angular statistics are the future work of Sect. 6): a sky
+ * position is a unit vector, and the angle theta between two positions maps
+ * one to one onto their chord 2 sin(theta / 2), so angular bins are chord
+ * bins of the unit vectors, counted by the s path of this library.
+ *
+ * fcfc_radec_to_unit -- d_xyz[3i..3i+2] = (cos d cos a, cos d sin a, sin d)
+ * for right ascension a = d_ra_deg[i] and declination d = d_dec_deg[i] in
+ * degrees (device arrays of n values; d_xyz n x 3 row-major, written).  The
+ * vectors are unit length to FP64 rounding.  Enqueued on `stream`; non-finite
+ * angles give non-finite vectors, which fcfc_build_cells rejects.
+ * Errors: FCFC_EINVAL (null arrays, n < 0).
+ */
+fcfc_status fcfc_radec_to_unit(const double *d_ra_deg, const double *d_dec_deg, int64_t n,
+                               double *d_xyz, void *stream);
+/*
+ * fcfc_angular_plan -- a plan counting pairs of unit vectors in the angular
+ * bins theta_deg[0..n] (host array, degrees, strictly increasing in [0, 180]):
+ * an s plan (FCFC_BIN_S) over the chord edges c_k = 2 sin(theta_k / 2),
+ * computed once in FP64, in an open box holding the unit sphere.  The
+ * counted quantity is the chord of the FP64 unit vectors against these
+ * edges (half-open bins of the squared chord, as every separation here); it
+ * equals the angular bin except for pairs within rounding of an edge.
+ * chord_out (host, n + 1 values, or NULL) receives the edges used.  Cells
+ * are built and counted as with any plan (fcfc_build_cells, fcfc_count_pairs,
+ * batches); positions must be unit vectors (any point outside [-1, 1]^3 is
+ * FCFC_EBOX).  Errors: FCFC_EINVAL, FCFC_EEDGES (an edge outside [0, 180],
+ * or chords not strictly increasing), and those of fcfc_plan_create.
+ */
+fcfc_status fcfc_angular_plan(const double *theta_deg, int32_t n, const fcfc_tuning *tune,
+                              double *chord_out, fcfc_plan_t *out);
+
+/*
  * From pair counts to correlation functions (Sect. 1, App. D).  All arrays
  * are device FP64; counts enter as FP64 (exact below 2^53).
  *

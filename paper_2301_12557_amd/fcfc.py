@@ -104,6 +104,9 @@ SIGNATURES = [
     ("fcfc_analytic_rr", _I32, [_P, _D, _P, _P]),
     ("fcfc_multipoles", _I32, [_P, _I32, ctypes.POINTER(_D), _I32, ctypes.POINTER(_I32), _I32, _P, _P]),
     ("fcfc_wp", _I32, [_P, _I32, ctypes.POINTER(_D), _I32, _P, _P]),
+    ("fcfc_radec_to_unit", _I32, [_P, _P, _I64, _P, _P]),
+    ("fcfc_angular_plan", _I32, [ctypes.POINTER(_D), _I32, ctypes.POINTER(Tuning), ctypes.POINTER(_D),
+                                 ctypes.POINTER(_P)]),
     ("fcfc_status_str", ctypes.c_char_p, [_I32]),
     ("fcfc_last_error", ctypes.c_char_p, []),
     ("fcfc_version", _I32, []),
@@ -193,6 +196,19 @@ class Plan:
                                    self.n2 if e2 is not None else 0, float(box), ctypes.byref(self.tuning),
                                    ctypes.byref(h)))
         self.h = h
+
+    @classmethod
+    def _wrap(cls, h, kind, e1, e2, tuning):
+        """A Plan object owning an fcfc_plan_t made by another entry point."""
+        self = cls.__new__(cls)
+        self.kind = kind
+        self._e1 = np.ascontiguousarray(e1, dtype=np.float64)
+        self._e2 = None if e2 is None else np.ascontiguousarray(e2, dtype=np.float64)
+        self.n1 = len(self._e1) - 1
+        self.n2 = 1 if e2 is None else len(self._e2) - 1
+        self.tuning = tuning
+        self.h = h
+        return self
 
     @property
     def shape(self):
@@ -560,6 +576,53 @@ def autotune(x1, x2=None, *, model=None, kind="s", edges1, edges2=None, los="z",
                                os.fsencode(cache) if cache else None, _stream_ptr(stream), ctypes.byref(best),
                                ctypes.byref(bms), ctypes.byref(hms), ctypes.byref(ntr)))
     return {k: int(getattr(best, k)) for k in TUNING_KEYS}, bms.value, hms.value, ntr.value
+
+
+def radec_to_unit(ra_deg, dec_deg, out=None, stream=None):
+    """Unit vectors (N x 3 CUDA float64) of sky positions in degrees (CUDA float64 tensors)."""
+    import torch
+    for t, name in ((ra_deg, "ra"), (dec_deg, "dec")):
+        if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64 and t.dim() == 1
+                and t.is_contiguous()):
+            raise ValueError(f"{name} must be a contiguous 1-D CUDA float64 tensor")
+    if ra_deg.shape != dec_deg.shape:
+        raise ValueError("ra and dec must have the same length")
+    n = int(ra_deg.shape[0])
+    if out is None:
+        out = torch.empty((n, 3), dtype=torch.float64, device=ra_deg.device)
+    _out_tensor(out, 3 * n, torch.float64, "out")
+    check(load().fcfc_radec_to_unit(ra_deg.data_ptr(), dec_deg.data_ptr(), n, out.data_ptr(), _stream_ptr(stream)))
+    return out
+
+
+def angular_plan(theta_deg, **tuning):
+    """Plan of angular bins (degrees) over unit vectors; returns (Plan, chord edges used)."""
+    th = np.ascontiguousarray(np.asarray(theta_deg, dtype=np.float64))
+    chord = np.empty(len(th), dtype=np.float64)
+    t = make_tuning(**tuning)
+    h = ctypes.c_void_p()
+    check(load().fcfc_angular_plan(th.ctypes.data_as(ctypes.POINTER(_D)), len(th) - 1, ctypes.byref(t),
+                                   chord.ctypes.data_as(ctypes.POINTER(_D)), ctypes.byref(h)))
+    return Plan._wrap(h, "s", chord, None, t), chord
+
+
+def angular_count(u1, u2=None, *, theta_deg, w1=None, w2=None, stream=None, **tuning):
+    """Angular pair counts of unit vectors (CUDA float64 N x 3): auto when u2 is None.
+    Returns (counts, wcounts or None, chord edges used)."""
+    weighted = w1 is not None
+    if "n_hint" not in tuning:
+        tuning["n_hint"] = int(max(u1.shape[0], 0 if u2 is None else u2.shape[0]))
+    plan, chord = angular_plan(theta_deg, **tuning)
+    try:
+        c1 = plan.build_cells(u1, w1 if weighted else None, stream)
+        c2 = plan.build_cells(u2, w2 if weighted else None, stream) if u2 is not None else None
+        counts, wcounts = plan.count(c1, c2, weighted=weighted, stream=stream)
+        c1.close()
+        if c2 is not None:
+            c2.close()
+    finally:
+        plan.close()
+    return counts, wcounts, chord
 
 
 def count_pairs(x1, x2=None, *, kind="s", edges1, edges2=None, los="z", box=0.0, w1=None, w2=None,

@@ -236,3 +236,21 @@ def test_batch_pairs_rejected_on_the_host():
     assert lib.fcfc_batch_create_pairs(p, cats, 2, None, 1, None, ctypes.byref(out)) == -1
     assert not out.value
     lib.fcfc_plan_free(p)
+
+
+def test_angular_plan_on_the_host():
+    """fcfc_angular_plan returns the FP64 chord edges 2 sin(theta/2) it counts with
+    (within an ulp of the oracle's), and refuses edges outside [0, 180] degrees."""
+    from oracle import angular as A
+    lib = fcfc.load()
+    th = np.array([0.0, 0.5, 1.0, 10.0, 60.0, 179.0])
+    chord = np.empty(len(th))
+    h = ctypes.c_void_p()
+    assert lib.fcfc_angular_plan(th.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), len(th) - 1, None,
+                                 chord.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.byref(h)) == 0
+    assert np.allclose(chord, A.chord_edges(th), rtol=2.3e-16, atol=0)
+    lib.fcfc_plan_free(h)
+    for bad in ([0.0, 10.0, 190.0], [0.0, -1.0, 5.0], [0.0, 5.0, 5.0]):
+        b = np.asarray(bad)
+        assert lib.fcfc_angular_plan(b.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), 2, None, None,
+                                     ctypes.byref(h)) == -6, bad
