@@ -444,3 +444,40 @@ def test_midpoint_knife_edges():
     # (s, mu) with the same pairs: mu edges meet pairs at every angle
     check_case("mid knife smu", a, b, kind="smu", los="mid", edges1=synth.linear_edges(0, 282, 47),
                edges2=synth.mu_edges(20), box=0.0)
+
+
+def test_c4_full_size_batch_sampled():
+    """C4 at full size, as the benchmark counts it (batched pipeline replayed from
+    a HIP graph): six mocks of the 200 (the largest, the smallest and four
+    others, 100k-500k points, L = 1000, (s, mu) 40 x 100).  Each batched histogram
+    equals that mock counted alone, bit for bit, and a sampled cross of each mock
+    equals the oracle's."""
+    import torch
+    from paper_2301_12557_amd import fcfc
+    sizes = synth.mock_sizes(200)
+    pick = sorted({int(np.argmax(sizes)), int(np.argmin(sizes)), 3, 50, 120, 199})
+    e1 = synth.linear_edges(0, 200, 40)
+    e2 = synth.mu_edges(100)
+    xs = [synth.lognormal_box_torch(int(sizes[m]), 1000.0, synth.MOCK_SEED_BASE + m, device="cuda") for m in pick]
+    note(f"C4 batch of mocks {pick}, sizes {[int(sizes[m]) for m in pick]}")
+    plan = fcfc.Plan("smu", e1, e2, box=1000.0, n_hint=int(np.median(sizes)))
+    b = fcfc.Batch(plan, [(x, None) for x in xs])
+    nb = 40 * 100
+    out = torch.empty(len(xs) * nb, dtype=torch.int64, device="cuda")
+    for _ in range(2):
+        b.run(out, use_graph=True)
+        b.check()
+    got = out.cpu().numpy().reshape(len(xs), nb)
+    rng = np.random.default_rng(17)
+    for i, x in enumerate(xs):
+        c = plan.build_cells(x)
+        alone, _ = plan.count(c)
+        c.close()
+        assert np.array_equal(got[i], alone.cpu().numpy().reshape(-1)), f"mock {pick[i]}"
+        xh = x.cpu().numpy()
+        s = xh[rng.choice(len(xh), 1000, replace=False)]
+        g, _, _ = gpu_count(s, xh, kind="smu", edges1=e1, edges2=e2, box=1000.0)
+        o, _ = oracle_count(s, xh, kind="smu", edges1=e1, edges2=e2, box=1000.0, method="grid")
+        assert_same(g, o, what=f"C4 mock {pick[i]} sample x full")
+    b.close()
+    plan.close()
