@@ -54,7 +54,10 @@ __device__ inline Item ldc_item(const Item* p, uint32_t i) {
 
 constexpr int CT_MAX = 1024;        // threads per workgroup (16 waves: 4 per SIMD, one workgroup per CU)
 constexpr int QCAP = 192;           // compaction queue entries per wave (63 + 64 P), plus one dump entry
-constexpr int RB_CAP = 128;         // recheck entries per wave
+// recheck entries per wave: RB_FLUSH - 1 waiting plus the up to 64 of one
+// binning pass (rechecks are rare; a small buffer leaves LDS for more waves)
+constexpr int RB_FLUSH = 32;
+constexpr int RB_CAP = RB_FLUSH + 64;
 constexpr int ASTAGE = 128;         // staged A points per wave (mid-point line of sight)
 
 // queue entry size in floats: (v1, v2, ids), or (dx, dy, dz, ids) for the
@@ -438,11 +441,12 @@ __device__ __attribute__((always_inline)) inline void bin_queue(ArgsRef a, const
             r[2] = c.it;
         }
         c.rcount += (int)__popcll(m);
-        if (c.rcount >= 64) {
+        if (c.rcount >= RB_FLUSH) {
+            const int n = c.rcount < 64 ? c.rcount : 64;
             wave_sync_lds();
-            process_rechecks<KIND, LOS, W>(a, s, c.rcount - 64, 64, lane, c.nrechk);
+            process_rechecks<KIND, LOS, W>(a, s, c.rcount - n, n, lane, c.nrechk);
             wave_sync_lds();
-            c.rcount -= 64;
+            c.rcount -= n;
         }
     }
 }
