@@ -911,6 +911,7 @@ struct LaunchSetup {
     std::vector<int4> rows;
     int nrows = 0;
     std::vector<char> htab;  // tables blob: lut1, lut2, band1, band2, E1, E2, stencil rows
+    int lut_entries = 0;     // entries of the look-up table used for s (or s_perp)
     size_t tb_l1 = 0, tb_l2 = 0, tb_b1 = 0, tb_b2 = 0, tb_e1 = 0, tb_e2 = 0, tb_rows = 0, tb_total = 0;
     CountKernel kern = nullptr;
 };
@@ -956,13 +957,82 @@ static fcfc_status setup_launch(Plan* p, bool is_auto, bool weighted, bool batch
     L.bchunk = p->tune.b_chunk >= 256 ? p->tune.b_chunk : 16384;
     L.copies = (p->tune.hist_copies == 2 || p->tune.hist_copies == 4) ? p->tune.hist_copies : 1;
     L.nrows = stencil_rows(p, is_auto, L.rows);
-    const Lut1D& L1 = p->lut1;
-    const Lut1D& L2 = p->lut2;
     const bool two = (p->kind == FCFC_BIN_SPERP_PI);
+    const bool mid = (p->los == FCFC_LOS_MIDPOINT && p->kind != FCFC_BIN_S);
+    const int qbytes = (QCAP + 1) * (mid ? 16 : 12);
+    const int per_wave = qbytes + (weighted ? ASTAGE * 8 : 0) + RB_CAP * 12 + (mid ? ASTAGE * 16 : 0);
+    int dev = 0, maxlds = 65536;
+    FCFC_HIP(hipGetDevice(&dev));
+    if (hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) maxlds = 65536;
+    L.kern = batch ? pick_batch_kernel(p->kind, p->los, weighted, L.P)
+                   : pick_kernel(p->kind, p->los, is_auto, weighted, L.P);
+    FCFC_HIP(hipFuncSetAttribute((const void*)L.kern, hipFuncAttributeMaxDynamicSharedMemorySize, maxlds));
+    // LDS shared by the workgroup's waves for tables of n1t and n2t entries
+    auto shared_for = [&](int n1t, int n2t) {
+        return al16(n1t * 2 + 4) + al16(n2t * 2 + 4) + al16(2 * (p->n1 + 1) * 4) +
+               al16(two ? 2 * (p->n2 + 1) * 4 : 0) + al16(p->nbins * 4 * L.copies) +
+               (weighted ? al16(p->nbins * 16) : 0);
+    };
+    // Workgroup size for a given shared part, and the waves resident per CU.
+    // Default, from timings on MI355X: two 12-wave workgroups per CU (three
+    // waves per SIMD each) when they fit, else one workgroup of the largest
+    // even wave count that fits (odd counts leave the SIMDs unevenly loaded
+    // and ran measurably slower).
+    auto choose_waves = [&](int shared, int& waves, int& resident) {
+        auto lds_for = [&](int w) { return shared + w * per_wave + 64; };
+        if (p->tune.group_waves >= 1 && p->tune.group_waves <= 16) {
+            waves = p->tune.group_waves;
+            while (waves > 1 && lds_for(waves) > maxlds) waves--;
+        } else {
+            waves = 16;
+            while (waves > 1 && lds_for(waves) > maxlds) waves--;
+            int occ12 = 0;
+            if (lds_for(12) <= maxlds &&
+                hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ12, (const void*)L.kern, 12 * 64, lds_for(12)) ==
+                    hipSuccess &&
+                occ12 >= 2)
+                waves = 12;
+            else if (waves > 2)
+                waves &= ~1;
+        }
+        int occ = 0;
+        if (lds_for(waves) > maxlds ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)L.kern, waves * 64, lds_for(waves)) !=
+                hipSuccess)
+            occ = 0;
+        resident = waves * occ;
+        return lds_for(waves) <= maxlds;
+    };
+    // The larger look-up tables (fewer entries that meet a band) are used
+    // whenever they keep as many waves resident: on MI355X they ran C1 0.34
+    // -> 0.26 ms and unweighted C2 5.6 -> 5.3 ms, while costing the weighted
+    // C2 kernel two of its 16 waves (7.5 -> 7.8 ms) where they are not used.
+    const Lut1D* T1 = &p->lut1;
+    const Lut1D* T2 = &p->lut2;
+    int shared_bytes = shared_for((int)T1->tab.size(), two ? (int)T2->tab.size() : 0);
+    int waves = 1, resident = 0;
+    const bool fits = choose_waves(shared_bytes, waves, resident);
+    if (p->has_big) {
+        const int sb = shared_for((int)p->lut1b.tab.size(), two ? (int)p->lut2b.tab.size() : 0);
+        int wb = 1, rb = 0;
+        if (choose_waves(sb, wb, rb) && rb >= resident && rb > 0) {
+            T1 = &p->lut1b;
+            T2 = &p->lut2b;
+            shared_bytes = sb;
+            waves = wb;
+        }
+    }
+    if (!fits && T1 == &p->lut1) {
+        set_error("count: %d bytes of LDS needed (tables + histogram), device allows %d", shared_bytes + per_wave + 64,
+                  maxlds);
+        return FCFC_ERANGE;
+    }
+    L.waves = waves;
+    L.lut_entries = (int)T1->tab.size();
     CountArgs& a = L.a;
     memset(&a, 0, sizeof(a));
-    a.nlut1 = (int)L1.tab.size();
-    a.nlut2 = two ? (int)L2.tab.size() : 0;
+    a.nlut1 = (int)T1->tab.size();
+    a.nlut2 = two ? (int)T2->tab.size() : 0;
     a.copies = L.copies;
     int off = 0;
     a.off_lut1 = off;
@@ -977,41 +1047,6 @@ static fcfc_status setup_launch(Plan* p, bool is_auto, bool weighted, bool batch
     off += al16(p->nbins * 4 * L.copies);
     a.off_whist = off;
     off += weighted ? al16(p->nbins * 16) : 0;
-    const int shared_bytes = off;
-    const bool mid = (p->los == FCFC_LOS_MIDPOINT && p->kind != FCFC_BIN_S);
-    const int qbytes = (QCAP + 1) * (mid ? 16 : 12);
-    const int per_wave = qbytes + (weighted ? ASTAGE * 8 : 0) + RB_CAP * 12 + (mid ? ASTAGE * 16 : 0);
-    int dev = 0, maxlds = 65536;
-    FCFC_HIP(hipGetDevice(&dev));
-    if (hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) maxlds = 65536;
-    L.kern = batch ? pick_batch_kernel(p->kind, p->los, weighted, L.P)
-                   : pick_kernel(p->kind, p->los, is_auto, weighted, L.P);
-    FCFC_HIP(hipFuncSetAttribute((const void*)L.kern, hipFuncAttributeMaxDynamicSharedMemorySize, maxlds));
-    auto lds_for = [&](int w) { return shared_bytes + w * per_wave + 64; };
-    if (p->tune.group_waves >= 1 && p->tune.group_waves <= 16) {
-        L.waves = p->tune.group_waves;
-        while (L.waves > 1 && lds_for(L.waves) > maxlds) L.waves--;
-    } else {
-        // Default workgroup size, from timings on MI355X: two 12-wave workgroups
-        // per CU (three waves per SIMD each) when they fit, else one workgroup of
-        // the largest even wave count that fits (odd counts leave the SIMDs
-        // unevenly loaded and ran measurably slower).
-        L.waves = 16;
-        while (L.waves > 1 && lds_for(L.waves) > maxlds) L.waves--;
-        int occ12 = 0;
-        if (lds_for(12) <= maxlds &&
-            hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ12, (const void*)L.kern, 12 * 64, lds_for(12)) ==
-                hipSuccess &&
-            occ12 >= 2)
-            L.waves = 12;
-        else if (L.waves > 2)
-            L.waves &= ~1;
-    }
-    if (lds_for(L.waves) > maxlds) {
-        set_error("count: %d bytes of LDS needed (tables + histogram), device allows %d", shared_bytes + per_wave + 64,
-                  maxlds);
-        return FCFC_ERANGE;
-    }
     a.off_q = off;
     off += L.waves * qbytes;
     a.off_qw = off;
@@ -1035,29 +1070,29 @@ static fcfc_status setup_launch(Plan* p, bool is_auto, bool weighted, bool batch
     L.htab.assign(L.tb_total, 0);
     {
         size_t o = 0;
-        memcpy(&L.htab[o], L1.tab.data(), L1.tab.size() * 2);
+        memcpy(&L.htab[o], T1->tab.data(), T1->tab.size() * 2);
         o += L.tb_l1;
-        if (two) memcpy(&L.htab[o], L2.tab.data(), L2.tab.size() * 2);
+        if (two) memcpy(&L.htab[o], T2->tab.data(), T2->tab.size() * 2);
         o += L.tb_l2;
-        memcpy(&L.htab[o], L1.lo.data(), (p->n1 + 1) * 4);
-        memcpy(&L.htab[o + (p->n1 + 1) * 4], L1.hi.data(), (p->n1 + 1) * 4);
+        memcpy(&L.htab[o], T1->lo.data(), (p->n1 + 1) * 4);
+        memcpy(&L.htab[o + (p->n1 + 1) * 4], T1->hi.data(), (p->n1 + 1) * 4);
         o += L.tb_b1;
         if (two) {
-            memcpy(&L.htab[o], L2.lo.data(), (p->n2 + 1) * 4);
-            memcpy(&L.htab[o + (p->n2 + 1) * 4], L2.hi.data(), (p->n2 + 1) * 4);
+            memcpy(&L.htab[o], T2->lo.data(), (p->n2 + 1) * 4);
+            memcpy(&L.htab[o + (p->n2 + 1) * 4], T2->hi.data(), (p->n2 + 1) * 4);
         }
         o += L.tb_b2;
-        memcpy(&L.htab[o], L1.E.data(), (p->n1 + 1) * 8);
+        memcpy(&L.htab[o], T1->E.data(), (p->n1 + 1) * 8);
         o += L.tb_e1;
-        if (two) memcpy(&L.htab[o], L2.E.data(), (p->n2 + 1) * 8);
+        if (two) memcpy(&L.htab[o], T2->E.data(), (p->n2 + 1) * 8);
         o += L.tb_e2;
         if (L.nrows) memcpy(&L.htab[o], L.rows.data(), L.nrows * 16);
     }
     // numeric constants
-    a.scale1 = L1.scale;
-    a.scale2 = two ? L2.scale : 1.f;
-    a.vmax1 = L1.vmax;
-    a.vmax2 = two ? L2.vmax : 0.f;
+    a.scale1 = T1->scale;
+    a.scale2 = two ? T2->scale : 1.f;
+    a.vmax1 = T1->vmax;
+    a.vmax2 = two ? T2->vmax : 0.f;
     a.n1 = p->n1;
     a.n2 = p->n2;
     a.nbins = p->nbins;
@@ -1402,6 +1437,7 @@ fcfc_status count_pairs(Plan* p, Cells* c1, Cells* c2, int64_t* d_counts, double
     p->stats.cell_side = g.side;
     p->stats.wg_per_cu = occ;
     p->stats.group_waves = L.waves;
+    p->stats.lut_entries = L.lut_entries;
     p->stats.order_used = model ? FCFC_ORDER_LEARNED : (sorted ? FCFC_ORDER_HEURISTIC : FCFC_ORDER_BUILT);
     p->last_pts = L.P;
     return FCFC_OK;

@@ -107,6 +107,8 @@ struct Plan {
     bool numerics_ready = false;
     double e_axis = 0;          // bound on the FP32 error of one displacement component
     Lut1D lut1, lut2;           // s (or s_perp) and pi tables
+    Lut1D lut1b, lut2b;         // the same with twice the entries (has_big)
+    bool has_big = false;       // counts may use the larger tables where LDS allows
     float r2prune32 = 0;        // FP32 candidate threshold (>= every relevant value)
     float d2small = 0;          // pairs closer than this are always rechecked (mu)
     float mu_tolA = 0, mu_tolB = 0, mu_tolC = 0;  // mu band: n*(A*rs + B*rs^2 + C)

@@ -236,8 +236,15 @@ fcfc_status plan_finalize_numerics(Plan* p) {
     d2m.C = 3.3 * u + 1e-15;
     int lg = p->tune.lut_log2 > 0 ? std::min(14, std::max(8, p->tune.lut_log2)) : 13;
 
+    // With the default size, tables with twice the entries are built too; a
+    // count uses them when they leave as many waves resident.
+    const bool big = p->tune.lut_log2 <= 0;
+    p->has_big = false;
+    p->lut1b = Lut1D();
+    p->lut2b = Lut1D();
     if (p->kind == FCFC_BIN_S || p->kind == FCFC_BIN_S_MU) {
         FCFC_TRY(build_lut(p->lut1, p->e1, d2m, lg));
+        if (big) FCFC_TRY(build_lut(p->lut1b, p->e1, d2m, lg + 1));
         p->r2prune32 = p->lut1.vmax;
         p->lut2 = Lut1D();
     } else {
@@ -268,6 +275,10 @@ fcfc_status plan_finalize_numerics(Plan* p) {
         }
         FCFC_TRY(build_lut(p->lut1, p->e1, m1, std::max(8, lg - 1)));
         FCFC_TRY(build_lut(p->lut2, p->e2, m2, std::max(8, lg - 1)));
+        if (big) {
+            FCFC_TRY(build_lut(p->lut1b, p->e1, m1, lg));
+            FCFC_TRY(build_lut(p->lut2b, p->e2, m2, lg));
+        }
         double S = p->lut1.E[p->n1] + p->lut2.E[p->n2];
         p->r2prune32 = f32_up(S + 1.5 * d2m(S) + 2.0 * S * 1.2e-7);
     }
@@ -291,6 +302,7 @@ fcfc_status plan_finalize_numerics(Plan* p) {
     } else {
         p->d2small = 0.f;
     }
+    p->has_big = big;
     p->numerics_ready = true;
     p->stats.band_d2_rel = std::max(p->lut1.band_rel, p->lut2.band_rel);
     p->stats.lut_entries = (int32_t)p->lut1.tab.size();
