@@ -230,8 +230,26 @@ def c4_section(fcfc, synth, mocks, model, repeats):
     tune_ms, tuned = _sync_time(lambda: fcfc.autotune(mocks[med], model=model, kind="smu", edges1=e1, edges2=e2,
                                                       box=1000.0, n_hint=nhint))
     tk = {k: v for k, v in tuned[0].items() if k not in ("record_timing", "order")}
-    planL = fcfc.Plan("smu", e1, e2, box=1000.0, **tk)
-    tL, cL, fL, iL, eqL = batch_arm(planL)
+
+    # The proposal was measured on single counts of one mock; it is kept only if
+    # it also beats the default on a batch of 20 mocks (best of 3 replays each).
+    def sub_batch_ms(pl):
+        sub = [(x, None) for x in mocks[:20]]
+        out = torch.empty(len(sub) * nb, dtype=torch.int64, device="cuda")
+        b = fcfc.Batch(pl, sub)
+        b.run(out, use_graph=True)
+        ms = min(_sync_time(lambda: b.run(out, use_graph=True))[0] for _ in range(3))
+        b.close()
+        return ms
+
+    planT = fcfc.Plan("smu", e1, e2, box=1000.0, **tk)
+    sub_tuned, sub_default = sub_batch_ms(planT), sub_batch_ms(plan)
+    kept = sub_tuned < sub_default
+    if not kept:
+        tk = {"n_hint": nhint}
+        planT.close()
+        planT = plan
+    tL, cL, fL, iL, eqL = batch_arm(planT)
 
     def arm(ts, extra=None):
         ts = np.asarray(ts)
@@ -249,9 +267,12 @@ def c4_section(fcfc, synth, mocks, model, repeats):
                           "cells_per_rmax": st["cells_per_rmax"]}),
             "B": arm(tB, {"what": "batched pipeline replayed from a HIP graph, analytic tuning",
                           "create_ms": cB, "first_run_ms": fB, "items": iB, "counts_equal_P": eqB}),
-            "BL": arm(tL, {"what": "batched pipeline (HIP graph) with the autotuned tuning, cell sizes proposed by "
-                                   "the learned model, tuned on the median-size mock",
+            "BL": arm(tL, {"what": "batched pipeline (HIP graph) with the autotuned tuning (cell sizes proposed by "
+                                   "the learned model, tuned on the median-size mock), kept only if it also beats "
+                                   "the default on a 20-mock sub-batch",
                            "tuning": tk, "autotune_ms": tune_ms, "autotune_trials": tuned[3],
+                           "proposal": {k: v for k, v in tuned[0].items() if k not in ("record_timing", "order")},
+                           "sub_batch_ms": {"proposal": sub_tuned, "default": sub_default}, "proposal_kept": kept,
                            "create_ms": cL, "first_run_ms": fL, "items": iL, "counts_equal_P": eqL}),
         },
         "BL_over_P": float(np.mean(tP) / np.mean(tL)),

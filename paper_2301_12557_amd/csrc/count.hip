@@ -100,7 +100,6 @@ struct CountArgs {
     float mu_n, tolA, tolB, tolC;
     int mu_top_closed;
     double wscale;
-    int wpre;  // 1: staged A weights carry the scale 2^S (see prescale_ok)
     int copies;
     uint32_t shard_count, shard_index;  // this launch takes items shard_index, + shard_count, ...
     // batched mode: chunks of items per output histogram (one per catalogue pair)
@@ -112,7 +111,7 @@ struct CountArgs {
     int ncat;                      // histograms
     int chunk_items;
     // LDS layout (bytes)
-    int off_lut1, off_lut2, off_band1, off_band2, off_hist, off_whist, off_q, off_qw, off_rb, off_astage,
+    int off_lut1, off_lut2, off_band1, off_band2, off_hist, off_whist, off_q, off_rb, off_astage,
         off_misc, lds_bytes;
 };
 
@@ -130,7 +129,6 @@ struct Smem {
     unsigned long long* wlo;
     unsigned long long* whi;
     float* qf;        // this wave's compaction queue (entries of QStride floats)
-    double* aw;       // this wave's A point weights, by tile slot
     uint32_t* rb;     // this wave's recheck entries (a, b, item)
     float4* astage;   // this wave's A points in absolute FP32 (mid-point line of sight)
     unsigned long long* misc;
@@ -262,7 +260,6 @@ struct KConst {
     float scale1, scale2, vmax1, vmax2, r2prune, d2small, mu_n, mu_nm1, tolA, tolB, tolC, side32;
     int n1, n2, nbins, nx, copies;
     double wscale;
-    int wpre;
 };
 
 // q: the pair weight times 2^S, an integer below 2^62 in magnitude
@@ -346,9 +343,12 @@ __device__ __attribute__((always_inline)) inline void bin_queue(ArgsRef a, const
             ids = __float_as_uint(qe[2]);
         }
     }
-    // the B weight of the pair, fetched early (product formed only for pairs in range)
-    double wb = 0.0;
-    if (W && valid) wb = a.wB[c.b_begin + (ids >> 7)];
+    // the weights of the pair, fetched early (product formed only for pairs in range)
+    double wa = 0.0, wb = 0.0;
+    if (W && valid) {
+        wb = a.wB[c.b_begin + (ids >> 7)];
+        wa = a.wA[c.a_begin + (ids & 127u)];
+    }
     bool amb = false;
     bool okb;  // a bin was found (flat is meaningful)
     int flat;
@@ -426,10 +426,9 @@ __device__ __attribute__((always_inline)) inline void bin_queue(ArgsRef a, const
     if (valid & okb & !amb) {
         atomicAdd(&hist_l[flat], 1u);
         if (W) {
-            // fl(wa * 2^S * wb) == fl(wa * wb) * 2^S when nothing overflows or
-            // underflows, which the host checked before setting wpre
-            const double q = s.aw[ids & 127u] * wb;
-            add_weight(s, flat, k.wpre ? q : q * k.wscale);
+            // fl(wa * wb) * 2^S is exact: the scale only moves the exponent, and
+            // the host chose S so that the largest scaled product stays below 2^62
+            add_weight(s, flat, (wa * wb) * k.wscale);
         }
     }
     if (m) {
@@ -469,7 +468,6 @@ __global__ __launch_bounds__(CT_MAX) void k_count(const CountArgs* argp) {
     s.whi = s.wlo + a.nbins;
     constexpr int QS = QStride<KIND, LOS>::value;
     s.qf = (float*)(smem + a.off_q) + (size_t)wave * (QCAP + 1) * QS;
-    s.aw = (double*)(smem + a.off_qw) + (size_t)wave * ASTAGE;
     s.rb = (uint32_t*)(smem + a.off_rb) + (size_t)wave * RB_CAP * 3;
     s.astage = (float4*)(smem + a.off_astage) + (size_t)wave * ASTAGE;
     s.misc = (unsigned long long*)(smem + a.off_misc);
@@ -516,7 +514,6 @@ __global__ __launch_bounds__(CT_MAX) void k_count(const CountArgs* argp) {
     k.nx = a.nx;
     k.copies = a.copies;
     k.wscale = a.wscale;
-    k.wpre = a.wpre;
     uint32_t* hist_l = s.hist + (size_t)(lane % k.copies) * k.nbins;
     WaveCtx c;
     c.rcount = 0;
@@ -531,7 +528,6 @@ __global__ __launch_bounds__(CT_MAX) void k_count(const CountArgs* argp) {
         Item item;
         float4 av[P];
         float4 aabs[P];
-        double aw[P];
         uint32_t csv;  // lane t: start of B cell xw0 + t of the item's row
     };
     auto load_in = [&](uint32_t itx, ItemIn& in) __attribute__((always_inline)) {
@@ -547,7 +543,6 @@ __global__ __launch_bounds__(CT_MAX) void k_count(const CountArgs* argp) {
                 in.aabs[p] = make_float4(far, far, far, 0.f);
                 if (i < acnt) in.aabs[p] = a.absA[a_begin + i];
             }
-            if (W) in.aw[p] = (i < acnt) ? a.wA[a_begin + i] : 0.0;
         }
         const int xb0 = (int)(int16_t)(in.item.acnt_xb0 >> 16);
         const int sxi = (int)((in.item.meta >> 16) & 3u) - 1;
@@ -671,7 +666,6 @@ __global__ __launch_bounds__(CT_MAX) void k_count(const CountArgs* argp) {
                 const float4 q = cur.aabs[p];
                 s.astage[i] = make_float4(2.0f * q.x, 2.0f * q.y, 2.0f * q.z, 0.f);
             }
-            if (W) s.aw[i] = k.wpre ? cur.aw[p] * k.wscale : cur.aw[p];
         }
         int qn = 0;
         int xu = xb0;
@@ -692,7 +686,6 @@ __global__ __launch_bounds__(CT_MAX) void k_count(const CountArgs* argp) {
                     const float FCFC_CONST* bp = (const float FCFC_CONST*)a.posB + 4 * (size_t)j;
                     uint32_t jbits = (j - b_begin) << 7;
                     float3 nb = make_float3(bp[0], bp[1], bp[2]);
-#pragma unroll 2
                     for (; j < cell_end; j++, jbits += 128u) {
                         const float3 b = nb;
                         // prefetch the next B point (arrays carry padding past the last point)
@@ -917,16 +910,6 @@ struct LaunchSetup {
 };
 
 // Common fixed-point scale 2^S making every weight product an integer.
-// Whether A weights may carry the scale 2^S before the product is formed:
-// fl(wa 2^S wb) equals fl(wa wb) 2^S exactly when wa 2^S, wa wb and the scaled
-// product all stay normal and finite.
-static int prescale_ok(double wminA, double wmaxA, double wminB, double wmaxB, int S) {
-    if (!(wminA > 0) || !(wminB > 0)) return 0;
-    const double lo = ldexp(1.0, -1000), hi = ldexp(1.0, 1000);
-    const double s = ldexp(1.0, S);
-    return (wminA * wminB >= lo && wmaxA * s < hi && wminA * s >= lo && wmaxA * wmaxB * s < hi) ? 1 : 0;
-}
-
 static fcfc_status weight_scale(double wmin1, double wmax1, double wmin2, double wmax2, int* S) {
     *S = 0;
     if (wmin1 > 0 && wmin2 > 0) {
@@ -960,7 +943,7 @@ static fcfc_status setup_launch(Plan* p, bool is_auto, bool weighted, bool batch
     const bool two = (p->kind == FCFC_BIN_SPERP_PI);
     const bool mid = (p->los == FCFC_LOS_MIDPOINT && p->kind != FCFC_BIN_S);
     const int qbytes = (QCAP + 1) * (mid ? 16 : 12);
-    const int per_wave = qbytes + (weighted ? ASTAGE * 8 : 0) + RB_CAP * 12 + (mid ? ASTAGE * 16 : 0);
+    const int per_wave = qbytes + RB_CAP * 12 + (mid ? ASTAGE * 16 : 0);
     int dev = 0, maxlds = 65536;
     FCFC_HIP(hipGetDevice(&dev));
     if (hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) maxlds = 65536;
@@ -1049,8 +1032,6 @@ static fcfc_status setup_launch(Plan* p, bool is_auto, bool weighted, bool batch
     off += weighted ? al16(p->nbins * 16) : 0;
     a.off_q = off;
     off += L.waves * qbytes;
-    a.off_qw = off;
-    off += weighted ? L.waves * ASTAGE * 8 : 0;
     a.off_rb = off;
     off += L.waves * RB_CAP * 12;
     a.off_astage = off;
@@ -1241,7 +1222,6 @@ fcfc_status count_pairs(Plan* p, Cells* c1, Cells* c2, int64_t* d_counts, double
     }
     LaunchSetup L;
     FCFC_TRY(setup_launch(p, is_auto, weighted, false, S, L));
-    if (weighted) L.a.wpre = prescale_ok(c1->wmin, c1->wmax, cb->wmin, cb->wmax, S);
     CountArgs& a = L.a;
     const bool sorted = !pr && p->tune.order != FCFC_ORDER_BUILT;
     const Model* model = pr ? pr->model : (p->tune.order == FCFC_ORDER_LEARNED ? p->model : nullptr);
@@ -1461,7 +1441,6 @@ struct BatchImpl {
     int64_t ntot = 0;
     bool weighted = false;
     int S = 0;
-    int wpre = 0;
     LaunchSetup L;
     WLArgs wl;
     int64_t nseg = 0, npair_tr = 0;
@@ -1747,7 +1726,6 @@ fcfc_status batch_create_impl(Plan* p, const fcfc_catalog* cats, int ncat, const
         if (hw[0] != ~0ull) memcpy(&wmin, &hw[0], 8);
         memcpy(&wmax, &hw[1], 8);
         fcfc_status ws = weight_scale(wmin, wmax, wmin, wmax, &b->S);
-        b->wpre = prescale_ok(wmin, wmax, wmin, wmax, b->S);
         if (ws != FCFC_OK) {
             batch_free_impl(b);
             return ws;
@@ -1784,7 +1762,6 @@ fcfc_status batch_create_impl(Plan* p, const fcfc_catalog* cats, int ncat, const
     a.stats = nullptr;
     a.times = nullptr;
     a.wscale = ldexp(1.0, b->S);
-    a.wpre = b->wpre;
     a.nchunks_dev = &b->ctr[3];
     a.chunk_cursor = &b->ctr[4];
     a.chunk_prefix = b->chunk_prefix;
