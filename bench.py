@@ -250,6 +250,14 @@ def c4_section(fcfc, synth, mocks, model, repeats):
         planT.close()
         planT = plan
     tL, cL, fL, iL, eqL = batch_arm(planT)
+    # the network's own gain on the work order: default tuning, items of each
+    # mock ordered by the model's predicted time instead of the heuristic cost
+    order_arm = None
+    if model is not None:
+        planO = fcfc.Plan("smu", e1, e2, box=1000.0, n_hint=nhint, order="learned")
+        planO.set_model(model)
+        tO, cO, fO, iO, eqO = batch_arm(planO)
+        order_arm = (tO, cO, fO, iO, eqO)
 
     def arm(ts, extra=None):
         ts = np.asarray(ts)
@@ -274,7 +282,13 @@ def c4_section(fcfc, synth, mocks, model, repeats):
                            "proposal": {k: v for k, v in tuned[0].items() if k not in ("record_timing", "order")},
                            "sub_batch_ms": {"proposal": sub_tuned, "default": sub_default}, "proposal_kept": kept,
                            "create_ms": cL, "first_run_ms": fL, "items": iL, "counts_equal_P": eqL}),
+            **({"BO": arm(order_arm[0], {"what": "batched pipeline (HIP graph), default tuning, each mock's items in "
+                                                "the order of the learned cost model's predicted time",
+                                        "create_ms": order_arm[1], "first_run_ms": order_arm[2],
+                                        "items": order_arm[3], "counts_equal_P": order_arm[4]})}
+               if order_arm else {}),
         },
+        **({"BO_over_B": float(np.mean(tB) / np.mean(order_arm[0]))} if order_arm else {}),
         "BL_over_P": float(np.mean(tP) / np.mean(tL)),
         "B_over_P": float(np.mean(tP) / np.mean(tB)),
         "BL_over_B": float(np.mean(tB) / np.mean(tL)),
@@ -609,8 +623,7 @@ def main():
             log(f"cost model trained on {train['samples']} items, loss {train['final_loss']:.3f}")
         if not args.no_c4:
             res["c4"] = c4_section(fcfc, synth, mocks, model, args.c4_repeats)
-            log(f"C4 mocks/s: P {res['c4']['arms']['P']['mocks_per_s']:.1f} B {res['c4']['arms']['B']['mocks_per_s']:.1f}"
-                f" BL {res['c4']['arms']['BL']['mocks_per_s']:.1f}")
+            log(f"C4 mocks/s: " + " ".join(f"{k} {v['mocks_per_s']:.1f}" for k, v in res['c4']['arms'].items()))
         del mocks
         torch.cuda.empty_cache()
         if not args.no_learned:

@@ -200,7 +200,12 @@ fcfc_status fcfc_plan_stats(fcfc_plan_t plan, fcfc_stats *out);
  * and keeps the catalogue pointers: they must stay valid and keep their sizes
  * for the life of the batch.  fcfc_batch_run enqueues the whole pipeline;
  * with use_graph it is captured into a HIP graph on the first run and
- * replayed afterwards.
+ * replayed afterwards.  The items of each catalogue (pair) run largest
+ * first: by the heuristic cost (A points x B points), or, when the plan's
+ * order is FCFC_ORDER_LEARNED and a model is attached (fcfc_plan_set_model),
+ * by the model's predicted time, using a copy of the model taken here (later
+ * training does not change the batch; a non-finite prediction sends the
+ * whole list back to the heuristic key).  The order never changes a count.
  * Errors: FCFC_ESTATE (open plan without bounds), FCFC_EINVAL (mixed weights,
  * nulls), FCFC_EBOX, FCFC_ENONFINITE, FCFC_ERANGE, FCFC_ENOMEM, FCFC_EHIP.
  */

@@ -1182,6 +1182,15 @@ __global__ __launch_bounds__(256) void k_pred_check(const float* __restrict__ pr
     if (__any(b) && (threadIdx.x & 63) == 0) atomicOr(bad, 1ull);
 }
 
+// k_pred_check over the first *n_dev predictions (a batched list sized on the device)
+__global__ __launch_bounds__(256) void k_pred_check_dev(const float* __restrict__ pred, const uint32_t* n_dev,
+                                                        unsigned long long* bad) {
+    const uint32_t n = *n_dev;
+    bool b = false;
+    for (uint32_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) b |= !isfinite(pred[i]);
+    if (__any(b) && (threadIdx.x & 63) == 0) atomicOr(bad, 1ull);
+}
+
 // learned sort key: half-octave buckets of the predicted time, longest first;
 // the heuristic key (cost = A points x B points) if any prediction was bad
 __global__ void k_pred_keys(const Item* __restrict__ items, const float* __restrict__ pred,
@@ -1463,6 +1472,13 @@ struct BatchImpl {
     uint32_t *ptile_off = nullptr, *ptile_first = nullptr;
     // largest-first order within each pair: keys, values, sort scratch, sorted items
     uint32_t *sk0 = nullptr, *sv0 = nullptr, *sk1 = nullptr, *sv1 = nullptr;
+    // learned order (plan order FCFC_ORDER_LEARNED with a model attached): a
+    // frozen copy of the model, item features, predictions, non-finite flag
+    Model* msnap = nullptr;
+    float* mparams = nullptr;
+    float *feat = nullptr, *pred = nullptr;
+    unsigned long long* bad = nullptr;
+    float kcells = 1.f;
     void* isort_scr = nullptr;
     Item* items2 = nullptr;
     int sort_bits = 8;
@@ -1502,6 +1518,7 @@ static fcfc_status balloc(BatchImpl* b, void** p, size_t bytes) {
 
 void batch_free_impl(BatchImpl* b) {
     if (!b) return;
+    model_snapshot_free(b->msnap);
     if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
     if (b->ev0) (void)hipEventDestroy(b->ev0);
@@ -1549,8 +1566,17 @@ static void batch_enqueue_back(BatchImpl* b, hipStream_t st) {
     {
         const unsigned nb = (b->items_cap + 255) / 256;
         uint32_t *k0 = b->sk0, *v0 = b->sv0, *k1 = b->sk1, *v1 = b->sv1;
-        hipLaunchKernelGGL(k_pair_item_keys, dim3(nb), dim3(256), 0, st, b->items, &b->ctr[1], b->items_cap,
-                           b->pair_items, b->npairs, b->key_last, k0, v0);
+        if (b->msnap) {
+            model_item_costs(b->msnap, b->items, b->items_cap, b->kcells, b->feat, b->pred, st);
+            fill_u64((uint64_t*)b->bad, 0ull, 1, st);
+            hipLaunchKernelGGL(k_pred_check_dev, dim3(std::min<uint32_t>(nb, 1024)), dim3(256), 0, st, b->pred,
+                               &b->ctr[1], b->bad);
+            hipLaunchKernelGGL(k_pair_pred_keys, dim3(nb), dim3(256), 0, st, b->items, &b->ctr[1], b->items_cap,
+                               b->pair_items, b->npairs, b->key_last, b->pred, b->bad, k0, v0);
+        } else {
+            hipLaunchKernelGGL(k_pair_item_keys, dim3(nb), dim3(256), 0, st, b->items, &b->ctr[1], b->items_cap,
+                               b->pair_items, b->npairs, b->key_last, k0, v0);
+        }
         radix_sort_pairs(&k0, &v0, &k1, &v1, b->items_cap, b->sort_bits, b->isort_scr, st);
         hipLaunchKernelGGL(k_item_permute, dim3(nb), dim3(256), 0, st, b->items, v0, &b->ctr[1], b->items_cap,
                            b->items2);
@@ -1739,6 +1765,20 @@ fcfc_status batch_create_impl(Plan* p, const fcfc_catalog* cats, int ncat, const
     BA(b->sk1, 4 * (size_t)b->items_cap);
     BA(b->sv1, 4 * (size_t)b->items_cap);
     BA(b->isort_scr, radix_scratch_bytes(b->items_cap));
+    if (p->tune.order == FCFC_ORDER_LEARNED && p->model) {
+        BA(b->mparams, model_param_bytes());
+        BA(b->feat, 16 * (size_t)b->items_cap);
+        BA(b->pred, 4 * (size_t)b->items_cap);
+        BA(b->bad, 64);
+        b->msnap = model_snapshot(p->model, b->mparams, st);
+        if (!b->msnap) {
+            batch_free_impl(b);
+            set_error("batch_create: cannot copy the cost model");
+            return FCFC_EHIP;
+        }
+        b->kcells = (float)(p->rprune / g.side);
+        FCFC_HIP(hipStreamSynchronize(st));
+    }
 #undef BA
     // pair keys (pair << 6 | cost key) sort in whole bytes; the end key is above them all
     b->sort_bits = 8;

@@ -202,6 +202,13 @@ void batch_build_enqueue(const Plan* p, int xbits, const CatDesc* desc, const in
 struct Model;
 void model_item_costs(const Model* md, const Item* items, uint32_t n, float kcells, float* feat, float* pred,
                       hipStream_t st);
+// A frozen copy of a model for a pipeline that outlives later training: the
+// parameters are copied on `st` into `params` (model_param_bytes(), owned by
+// the caller), the normalisation with them; free with model_snapshot_free
+// (the host object only).
+size_t model_param_bytes();
+Model* model_snapshot(const Model* src, float* params, hipStream_t st);
+void model_snapshot_free(Model* m);
 // Predict-only count: with `predict` set, count_pairs builds the work list,
 // scores it with the model and returns the predicted time (ms) without counting.
 struct PredictReq {

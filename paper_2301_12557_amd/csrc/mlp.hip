@@ -265,6 +265,23 @@ void model_item_costs(const Model* md, const Item* items, uint32_t n, float kcel
                        (int64_t)n, nrm, pred);
 }
 
+size_t model_param_bytes() { return sizeof(float) * (NPARAM + 1); }
+
+Model* model_snapshot(const Model* src, float* params, hipStream_t st) {
+    Model* m = new (std::nothrow) Model();
+    if (!m) return nullptr;
+    if (hipMemcpyAsync(params, src->params, model_param_bytes(), hipMemcpyDeviceToDevice, st) != hipSuccess) {
+        delete m;
+        return nullptr;
+    }
+    m->params = params;
+    for (int i = 0; i < 10; i++) m->norm[i] = src->norm[i];
+    m->step = src->step;
+    return m;
+}
+
+void model_snapshot_free(Model* m) { delete m; }
+
 static fcfc_status model_alloc(Model* md) {
     float* blk = nullptr;
     if (hipMalloc((void**)&blk, sizeof(float) * (4 * (NPARAM + 1) + 64)) != hipSuccess) {

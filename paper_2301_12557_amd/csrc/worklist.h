@@ -59,6 +59,10 @@ __global__ void k_item_keys(const Item* __restrict__ items, const uint32_t* __re
 __global__ void k_pair_item_keys(const Item* __restrict__ items, const uint32_t* __restrict__ nitems_dev,
                                  uint32_t cap, const uint32_t* __restrict__ pair_items, int npairs, uint32_t last,
                                  uint32_t* __restrict__ key, uint32_t* __restrict__ val);
+__global__ void k_pair_pred_keys(const Item* __restrict__ items, const uint32_t* __restrict__ nitems_dev,
+                                 uint32_t cap, const uint32_t* __restrict__ pair_items, int npairs, uint32_t last,
+                                 const float* __restrict__ pred, const unsigned long long* __restrict__ bad,
+                                 uint32_t* __restrict__ key, uint32_t* __restrict__ val);
 __global__ void k_item_permute(const Item* __restrict__ in, const uint32_t* __restrict__ perm,
                                const uint32_t* __restrict__ nitems_dev, uint32_t cap, Item* __restrict__ out);
 

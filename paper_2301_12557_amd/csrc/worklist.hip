@@ -334,6 +334,36 @@ __global__ void k_pair_item_keys(const Item* __restrict__ items, const uint32_t*
     val[i] = i;
 }
 
+// The same with the learned key: half-octave buckets of the predicted time
+// (log2 of ticks), longest first; the cost key for every item if any
+// prediction was not finite (*bad).
+__global__ void k_pair_pred_keys(const Item* __restrict__ items, const uint32_t* __restrict__ nitems_dev,
+                                 uint32_t cap, const uint32_t* __restrict__ pair_items, int npairs, uint32_t last,
+                                 const float* __restrict__ pred, const unsigned long long* __restrict__ bad,
+                                 uint32_t* __restrict__ key, uint32_t* __restrict__ val) {
+    uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= cap) return;
+    uint32_t k = last;
+    if (i < *nitems_dev) {
+        int lo = 0, hi = npairs;  // pair_items[lo] <= i < pair_items[hi]
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (pair_items[mid] <= i) lo = mid;
+            else hi = mid;
+        }
+        uint32_t c;
+        if (*bad) {
+            c = cost_key(items[i].cost);
+        } else {
+            const float b = fminf(fmaxf(2.f * pred[i], 0.f), 63.f);
+            c = 63u - (uint32_t)b;
+        }
+        k = ((uint32_t)lo << 6) | c;
+    }
+    key[i] = k;
+    val[i] = i;
+}
+
 __global__ void k_item_permute(const Item* __restrict__ in, const uint32_t* __restrict__ perm,
                                const uint32_t* __restrict__ nitems_dev, uint32_t cap, Item* __restrict__ out) {
     uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;

@@ -93,3 +93,49 @@ def test_batch_rejects_open_plan_without_bounds():
     with pytest.raises(fcfc.FcfcError) as ei:
         fcfc.Batch(plan, [(x, None)])
     assert ei.value.name == "FCFC_ESTATE"
+
+
+def test_batch_learned_order_keeps_counts():
+    """A batch whose plan runs the learned order (a trained model attached)
+    gives the same histograms as the heuristic order, bit for bit; so does a
+    model whose predictions are not finite (the heuristic key takes over), and
+    retraining the model after the batch was made changes nothing."""
+    import torch
+    from paper_2301_12557_amd import fcfc
+    L = 300.0
+    xs, _ = _mocks(12, L, 21, lo=2000, hi=8000)
+    e1 = synth.linear_edges(0, 60, 12)
+    e2 = synth.mu_edges(10)
+    dx = [to_dev(x) for x in xs]
+    plan = fcfc.Plan("smu", e1, e2, box=L, n_hint=5000, record_timing=1)
+    c = plan.build_cells(dx[0])
+    plan.count(c)
+    feat, logt = plan.timings()
+    c.close()
+    md = fcfc.Model(seed=4)
+    md.train(feat, logt, epochs=10, batch=128, lr=2e-3, seed=1)
+    nb = plan.n1 * plan.n2
+    ref = torch.empty(len(xs) * nb, dtype=torch.int64, device="cuda")
+    bh = fcfc.Batch(fcfc.Plan("smu", e1, e2, box=L, n_hint=5000), [(x, None) for x in dx])
+    bh.run(ref, use_graph=True)
+    bh.check()
+    for name, model in (("trained", md), ("nan", None)):
+        if model is None:
+            model = fcfc.Model(seed=5)
+            p, n = md.get()
+            p[-1] = np.nan
+            model.set(p, n)
+        pl = fcfc.Plan("smu", e1, e2, box=L, n_hint=5000, order="learned")
+        pl.set_model(model)
+        b = fcfc.Batch(pl, [(x, None) for x in dx])
+        out = torch.empty_like(ref)
+        for use_graph in (False, True, True):
+            out.fill_(-1)
+            b.run(out, use_graph=use_graph)
+            b.check()
+            assert torch.equal(out, ref), f"{name} graph={use_graph}"
+            if name == "trained" and use_graph:
+                md.train(feat, logt, epochs=1, batch=128, lr=2e-3, seed=2)  # the batch holds its own copy
+        b.close()
+        pl.close()
+    bh.close()
