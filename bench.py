@@ -44,6 +44,8 @@ def parse():
     ap.add_argument("--no-learned", action="store_true", help="skip training and the held-out C5 comparison")
     ap.add_argument("--no-peaks", action="store_true", help="skip the roofline microbenchmarks")
     ap.add_argument("--no-pairs", action="store_true", help="skip the multi-tracer pair-list comparison")
+    ap.add_argument("--no-binning", action="store_true", help="skip the histogram-update microbenchmark")
+    ap.add_argument("--binning-values", type=float, default=6.4e9, help="squared separations per binning call")
     ap.add_argument("--shards", type=int, default=0,
                     help="also count each of G work-list shards (one GPU's share of a G-GPU run) and report "
                          "their kernel times")
@@ -397,6 +399,72 @@ def pairs_section(fcfc, synth, torch, repeats=3):
     }
 
 
+BIN_LAYOUTS = (("linear", 20), ("linear", 200), ("log", 20), ("log", 200))
+
+
+def binning_section(fcfc, synth, torch, nvals, repeats=5, cpu_values=10_000_000):
+    """The histogram update routine alone (App. C input: s^2 = x^(2/3) 200^2,
+    nvals values resident in HBM; 20 and 200 bins, linear on [0, 200) and
+    logarithmic on [0.1, 200)): kernel time over HIP events on the launch
+    stream, against the HBM roofline of reading 8 B per value once; then the
+    look-up table size scan on the 200 logarithmic bins; the oracle on a
+    bounded sample for scale."""
+    from oracle import histogram as H
+    n = int(nvals)
+    v = synth.s2_samples_torch(n, 200.0, synth.config_seed(6))
+    torch.cuda.synchronize()
+    rows = []
+    for layout, nb in BIN_LAYOUTS:
+        e = synth.linear_edges(0, 200, nb) if layout == "linear" else synth.log_edges(0.1, 200, nb)
+        plan = fcfc.Plan("s", e, box=800.0)
+        plan.bin_squared(v)
+        ms = []
+        for _ in range(repeats):
+            plan.bin_squared(v)
+            ms.append(plan.stats()["kernel_ms"])
+        st = plan.stats()
+        k = float(np.mean(ms))
+        gbs = 8.0 * n / (k * 1e-3) / 1e9
+        rows.append({"bins": nb, "layout": layout, "kernel_ms": k, "kernel_ms_sd": float(np.std(ms)),
+                     "values_per_s": n / (k * 1e-3), "ps_per_value": k * 1e9 / n,
+                     "hbm_gbps": gbs, "hbm_frac": gbs / 8000.0, "rechecks": int(st["rechecks"]),
+                     "in_range": int(st["in_range"]), "lut_entries": int(st["lut_entries"])})
+        plan.close()
+    scan = []
+    e = synth.log_edges(0.1, 200, 200)
+    for lg in (8, 9, 10, 11, 12, 13, 14):
+        plan = fcfc.Plan("s", e, box=800.0, lut_log2=lg)
+        plan.bin_squared(v)
+        ms = []
+        for _ in range(3):
+            plan.bin_squared(v)
+            ms.append(plan.stats()["kernel_ms"])
+        st = plan.stats()
+        scan.append({"lut_log2": lg, "lut_entries": int(st["lut_entries"]), "kernel_ms": float(np.mean(ms)),
+                     "recheck_rate": st["rechecks"] / n})
+        plan.close()
+    # the oracle on a bounded sample of the same values
+    sample = v[:cpu_values].cpu().numpy()
+    del v
+    torch.cuda.empty_cache()
+    cpu = []
+    for layout, nb in BIN_LAYOUTS:
+        e = synth.linear_edges(0, 200, nb) if layout == "linear" else synth.log_edges(0.1, 200, nb)
+        t0 = time.perf_counter()
+        H.bin_squared(sample, e)
+        cpu.append({"bins": nb, "layout": layout, "values_per_s": len(sample) / (time.perf_counter() - t0)})
+    return {
+        "workload": f"{n} squared separations s^2 = x^(2/3) 200^2 (x uniform, App. C), FP64, resident in HBM",
+        "kernel": "k_bin_squared",
+        "roofline": {"bound": "hbm", "per_unit": "8 B per value (read once)", "peak": 8000.0, "unit": "GB/s"},
+        "layouts": rows,
+        "lut_scan_log200": scan,
+        "cpu_oracle": {"kind": "oracle", "sample": f"first {len(sample)} values", "rows": cpu,
+                       "note": "numpy, one comparison pass per edge"},
+        "paper_context": "about 2 ns per update on one Haswell core (scalar), not this machine",
+    }
+
+
 def c3_main(args, fcfc, torch):
     """C3 (open box, mid-point line of sight): DD and DR (and RR) per step."""
     weighted = not args.unweighted
@@ -634,6 +702,11 @@ def main():
         res["pairs"] = pairs_section(fcfc, synth, torch)
         log(f"multi-tracer pairs: separate {res['pairs']['separate_ms']:.1f} ms, "
             f"one batch {res['pairs']['batch_ms']:.1f} ms, equal {res['pairs']['counts_equal']}")
+    if not args.no_binning:
+        from paper_2301_12557_amd import synth
+        res["binning"] = binning_section(fcfc, synth, torch, args.binning_values)
+        log("binning: " + " ".join(f"{r['layout']}{r['bins']} {r['kernel_ms']:.2f} ms ({r['hbm_frac']:.2f})"
+                                   for r in res["binning"]["layouts"]))
     if not args.no_cpu_baseline:
         log("timing the CPU oracle")
         res["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)

@@ -413,6 +413,26 @@ fcfc_status fcfc_angular_plan(const double *theta_deg, int32_t n, const fcfc_tun
                               double *chord_out, fcfc_plan_t *out);
 
 /*
+ * fcfc_bin_squared -- the histogram update routine on its own (Sect. 3.2):
+ * bins n squared separations d_s2[0..n) (device FP64, 8-byte aligned, read
+ * only) into d_counts[0..n1) (device int64, overwritten) with the plan's
+ * first-axis bins: value v counts in bin i when E_i <= v < E_{i+1}, where
+ * E_i is the FP64 square of edge i.  NaN, negative values and values at or
+ * above the top squared edge count nowhere; -0.0 counts as 0.  The look-up
+ * table (2^lut_log2 entries, 2^14 by default) is built from the edges alone
+ * on the first call and kept by the plan; its FP32 bands cover the rounding
+ * of a value to FP32, and any value inside a band is compared in FP64, so
+ * the counts are exact.  Any plan works, periodic or open, with or without
+ * bounds.  Enqueued on `stream`; fcfc_plan_stats afterwards gives the values
+ * (candidates), FP64 rechecks, values in range and the kernel time.
+ * Errors: FCFC_EINVAL (null plan or counts, n < 0 or above 2^61, unaligned
+ * values), FCFC_EEDGES (edges too close for FP32 bands), FCFC_ERANGE (the
+ * bins and table do not fit the LDS), FCFC_EHIP.
+ */
+fcfc_status fcfc_bin_squared(fcfc_plan_t plan, const double *d_s2, int64_t n, int64_t *d_counts,
+                             void *stream);
+
+/*
  * From pair counts to correlation functions (Sect. 1, App. D).  All arrays
  * are device FP64; counts enter as FP64 (exact below 2^53).
  *

@@ -108,6 +108,7 @@ struct Plan {
     double e_axis = 0;          // bound on the FP32 error of one displacement component
     Lut1D lut1, lut2;           // s (or s_perp) and pi tables
     Lut1D lut1b, lut2b;         // the same with twice the entries (has_big)
+    Lut1D lutbin;               // first-axis table for binning given FP64 values (built on first use)
     bool has_big = false;       // counts may use the larger tables where LDS allows
     float r2prune32 = 0;        // FP32 candidate threshold (>= every relevant value)
     float d2small = 0;          // pairs closer than this are always rechecked (mu)
@@ -160,7 +161,11 @@ fcfc_status fcfc_set_bounds_internal(Plan* p, const double lo[3], const double h
 fcfc_status plan_finalize_grid(Plan* p);
 fcfc_status plan_finalize_numerics(Plan* p);
 int choose_k(const Plan* p, int64_t n_hint);
-int stencil_rows(const Plan* p, bool half, std::vector<int4>& rows);  // (dy, dz, kx, float bits of the x reach)
+int stencil_rows(const Plan* p, bool half, std::vector<int4>& rows);
+// Table over the first-axis squared edges for binning values given in FP64:
+// its bands cover only the rounding of a value to FP32, so it depends on the
+// edges alone (no grid); built on first use and kept by the plan.
+fcfc_status plan_bin_table(Plan* p, const Lut1D** out);  // (dy, dz, kx, float bits of the x reach)
 
 // build (build.hip)
 fcfc_status build_cells(Plan* p, const fcfc_catalog* cat, hipStream_t st, Cells** out);

@@ -222,6 +222,22 @@ static fcfc_status build_lut(Lut1D& t, const std::vector<double>& edges, const E
     return FCFC_OK;
 }
 
+fcfc_status plan_bin_table(Plan* p, const Lut1D** out) {
+    if (p->lutbin.n == 0) {
+        // a value rounded to FP32 moves by at most half an ulp; the bands
+        // build_lut adds around every edge (2 u of the edge) cover that
+        const ErrModel rounding_only;
+        const int lg = p->tune.lut_log2 > 0 ? std::min(14, std::max(8, p->tune.lut_log2)) : 14;
+        fcfc_status s = build_lut(p->lutbin, p->e1, rounding_only, lg);
+        if (s != FCFC_OK) {
+            p->lutbin = Lut1D();
+            return s;
+        }
+    }
+    *out = &p->lutbin;
+    return FCFC_OK;
+}
+
 fcfc_status plan_finalize_numerics(Plan* p) {
     const Grid& g = p->grid;
     const double u = U32;

@@ -107,6 +107,7 @@ SIGNATURES = [
     ("fcfc_radec_to_unit", _I32, [_P, _P, _I64, _P, _P]),
     ("fcfc_angular_plan", _I32, [ctypes.POINTER(_D), _I32, ctypes.POINTER(Tuning), ctypes.POINTER(_D),
                                  ctypes.POINTER(_P)]),
+    ("fcfc_bin_squared", _I32, [_P, _P, _I64, _P, _P]),
     ("fcfc_status_str", ctypes.c_char_p, [_I32]),
     ("fcfc_last_error", ctypes.c_char_p, []),
     ("fcfc_version", _I32, []),
@@ -240,6 +241,19 @@ class Plan:
         check(load().fcfc_count_pairs(self.h, c1.h, c2.h if c2 is not None else None, out.data_ptr(),
                                       wout.data_ptr() if weighted else None, _stream_ptr(stream)))
         return out.view(self.shape), (wout.view(self.shape) if weighted else None)
+
+    def bin_squared(self, s2, out=None, stream=None):
+        """Counts (int64, n1 bins of the first axis) of the squared separations s2
+        (1-D CUDA float64 tensor): s2 in [edges[i]^2, edges[i+1]^2) counts in bin i."""
+        import torch
+        if not (isinstance(s2, torch.Tensor) and s2.is_cuda and s2.dtype == torch.float64 and s2.dim() == 1
+                and s2.is_contiguous()):
+            raise ValueError("s2 must be a contiguous 1-D CUDA float64 tensor")
+        if out is None:
+            out = torch.empty(self.n1, dtype=torch.int64, device=s2.device)
+        _out_tensor(out, self.n1, torch.int64, "out")
+        check(load().fcfc_bin_squared(self.h, s2.data_ptr(), int(s2.shape[0]), out.data_ptr(), _stream_ptr(stream)))
+        return out
 
     def stats(self):
         s = Stats()
@@ -623,6 +637,20 @@ def angular_count(u1, u2=None, *, theta_deg, w1=None, w2=None, stream=None, **tu
     finally:
         plan.close()
     return counts, wcounts, chord
+
+
+def bin_squared(s2, edges, *, stream=None, **tuning):
+    """Histogram of squared separations s2 (1-D CUDA float64 tensor) in the
+    separation bins `edges`: value v counts in bin i when edges[i]^2 <= v <
+    edges[i+1]^2.  Returns (int64 counts, plan stats)."""
+    e = np.asarray(edges, dtype=np.float64)
+    plan = Plan("s", e, box=0.0, **tuning)
+    try:
+        out = plan.bin_squared(s2, stream=stream)
+        st = plan.stats()
+    finally:
+        plan.close()
+    return out, st
 
 
 def count_pairs(x1, x2=None, *, kind="s", edges1, edges2=None, los="z", box=0.0, w1=None, w2=None,

@@ -113,6 +113,23 @@ def s2_samples(n, rmax, seed):
     return rng.random(int(n)) ** (2.0 / 3.0) * float(rmax) ** 2
 
 
+def s2_samples_torch(n, rmax, seed, device="cuda"):
+    """s2_samples drawn with torch's Philox generator on `device` (float64), for
+    the benchmark sizes (6.4e9 values); generated in place, so the only memory
+    is the 8 n bytes of the result.  A different stream of numbers from
+    s2_samples for the same seed."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    v = torch.empty(int(n), dtype=torch.float64, device=device)
+    step = 1 << 28
+    for lo in range(0, int(n), step):
+        part = v[lo:lo + step]
+        part.uniform_(0.0, 1.0, generator=g)
+        part.pow_(2.0 / 3.0).mul_(float(rmax) ** 2)
+    return v
+
+
 def linear_edges(lo, hi, n):
     return np.linspace(float(lo), float(hi), int(n) + 1)
 
