@@ -46,6 +46,7 @@ def parse():
     ap.add_argument("--no-pairs", action="store_true", help="skip the multi-tracer pair-list comparison")
     ap.add_argument("--no-binning", action="store_true", help="skip the histogram-update microbenchmark")
     ap.add_argument("--binning-values", type=float, default=6.4e9, help="squared separations per binning call")
+    ap.add_argument("--no-triplets", action="store_true", help="skip the triangle-count measurement")
     ap.add_argument("--shards", type=int, default=0,
                     help="also count each of G work-list shards (one GPU's share of a G-GPU run) and report "
                          "their kernel times")
@@ -465,6 +466,55 @@ def binning_section(fcfc, synth, torch, nvals, repeats=5, cpu_values=10_000_000)
     }
 
 
+PEAK_FP64_TFLOPS = 78.6
+FLOP_PER_SIDE = 8  # 3 sub, 3 mul, 2 add of one FP64 squared separation
+
+
+def triplets_section(fcfc, synth, torch, n=2_000_000, L=1000.0, rmax=30.0, nbins=15, repeats=3):
+    """Triangle counts (three-point extension): n uniform points in a periodic
+    box, sides binned in nbins linear bins over [0, rmax).  Kernel time over
+    HIP events on the launch stream; roofline of the FP64 side evaluations
+    against the FP64 vector peak; the oracle (neighbour lists, all host cores)
+    on a periodic sub-box of the same density for scale."""
+    import oracle
+    x = torch.from_numpy(synth.uniform_box(n, L, synth.config_seed(7))).cuda()
+    e = synth.linear_edges(0, rmax, nbins)
+    plan = fcfc.Plan("s", e, box=L, n_hint=n)
+    cells = plan.build_cells(x)
+    plan.count_triplets(cells)
+    ms = []
+    for _ in range(repeats):
+        h = plan.count_triplets(cells)
+        ms.append(plan.stats()["kernel_ms"])
+    st = plan.stats()
+    tri = int(h.sum().item())
+    k = float(np.mean(ms))
+    sides = int(st["candidates"])
+    achieved = FLOP_PER_SIDE * sides / (k * 1e-3) / 1e12
+    cells.close()
+    plan.close()
+    # oracle on a periodic sub-box of the same density
+    Ls = 200.0
+    ns = int(round(n * (Ls / L) ** 3))
+    xs = synth.uniform_box(ns, Ls, synth.config_seed(7) + 1)
+    t0 = time.perf_counter()
+    ref = oracle.triplets(xs, edges=e, box=Ls)
+    cpu_s = time.perf_counter() - t0
+    return {
+        "workload": f"{n} uniform points, periodic box {L:g}, {nbins} linear side bins over [0, {rmax:g})",
+        "kernel": "k_triplets", "kernel_ms": k, "kernel_ms_sd": float(np.std(ms)),
+        "triangles": tri, "triangles_per_s": tri / (k * 1e-3),
+        "side_evaluations": sides, "side_evaluations_per_s": sides / (k * 1e-3),
+        "rechecks": int(st["rechecks"]),
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP64_TFLOPS,
+                     "per_unit": f"{FLOP_PER_SIDE} FP64 flops per side evaluation"},
+        "cpu_oracle": {"kind": "oracle", "sample": f"{ns} points in a periodic box {Ls:g} (same density)",
+                       "seconds": cpu_s, "triangles": int(ref.sum()), "triangles_per_s": int(ref.sum()) / cpu_s,
+                       "cores": int(os.environ.get("OMP_NUM_THREADS") or os.cpu_count() or 1)},
+    }
+
+
 def c3_main(args, fcfc, torch):
     """C3 (open box, mid-point line of sight): DD and DR (and RR) per step."""
     weighted = not args.unweighted
@@ -707,6 +757,11 @@ def main():
         res["binning"] = binning_section(fcfc, synth, torch, args.binning_values)
         log("binning: " + " ".join(f"{r['layout']}{r['bins']} {r['kernel_ms']:.2f} ms ({r['hbm_frac']:.2f})"
                                    for r in res["binning"]["layouts"]))
+    if not args.no_triplets:
+        from paper_2301_12557_amd import synth
+        res["triplets"] = triplets_section(fcfc, synth, torch)
+        log(f"triplets: {res['triplets']['kernel_ms']:.2f} ms, {res['triplets']['triangles']} triangles, "
+            f"{res['triplets']['roofline']['frac']:.3f} of FP64 peak")
     if not args.no_cpu_baseline:
         log("timing the CPU oracle")
         res["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)

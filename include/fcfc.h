@@ -433,6 +433,26 @@ fcfc_status fcfc_bin_squared(fcfc_plan_t plan, const double *d_s2, int64_t n, in
                              void *stream);
 
 /*
+ * fcfc_count_triplets -- exact triangle counts of one cell set, the
+ * three-point extension of the pair counts (Sect. 6 lists three-point
+ * statistics as future work).  Every set {i, j, k} of three distinct points
+ * is counted once when each of its three sides s = |x_b - x_a| (Sect. 2.5;
+ * per-axis minimum image in a periodic box) lies in [e_0, e_n) of the plan's
+ * s edges.  Its bin is (a, b, c), the three side bins sorted so that
+ * a <= b <= c, in d_counts: device int64 [n1][n1][n1] row-major, overwritten
+ * (entries with a > b or b > c are zero).  Sides are evaluated in FP64, in
+ * the operation order of the pair definition, and binned exactly.
+ *   plan   an s plan (FCFC_BIN_S) with at most 32 bins; periodic or open.
+ *   cells  built on that plan by fcfc_build_cells (weights are ignored).
+ * Enqueued on `stream`; fcfc_plan_stats afterwards gives the side evaluations
+ * (candidates), FP64 rechecks, triangles counted (in_range) and the kernel
+ * time.  Errors: FCFC_EINVAL (null arguments, not an s plan), FCFC_EGRID
+ * (cells of another plan), FCFC_ERANGE (more than 32 bins, or the tables do
+ * not fit the LDS), FCFC_EHIP.
+ */
+fcfc_status fcfc_count_triplets(fcfc_plan_t plan, fcfc_cells_t cells, int64_t *d_counts, void *stream);
+
+/*
  * From pair counts to correlation functions (Sect. 1, App. D).  All arrays
  * are device FP64; counts enter as FP64 (exact below 2^53).
  *

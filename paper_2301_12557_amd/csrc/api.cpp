@@ -66,7 +66,10 @@ extern "C" fcfc_status fcfc_count_pairs(fcfc_plan_t plan, fcfc_cells_t c1, fcfc_
         return FCFC_EGRID;
     }
     fcfc_status s = count_pairs(p, a, b, d_counts, d_wcounts, (hipStream_t)stream);
-    if (s == FCFC_OK) p->last_counts = d_counts;
+    if (s == FCFC_OK) {
+        p->last_counts = d_counts;
+        p->last_counts_n = 0;
+    }
     return s;
 }
 
@@ -80,7 +83,7 @@ extern "C" fcfc_status fcfc_plan_stats(fcfc_plan_t plan, fcfc_stats* out) {
     }
     unsigned long long h[8];
     FCFC_HIP(hipMemcpyAsync(h, p->stats_dev, 64, hipMemcpyDeviceToHost, p->last_stream));
-    std::vector<int64_t> cnt((size_t)p->nbins);
+    std::vector<int64_t> cnt((size_t)(p->last_counts_n > 0 ? p->last_counts_n : p->nbins));
     if (p->last_counts)
         FCFC_HIP(hipMemcpyAsync(cnt.data(), p->last_counts, cnt.size() * 8, hipMemcpyDeviceToHost, p->last_stream));
     FCFC_HIP(hipStreamSynchronize(p->last_stream));

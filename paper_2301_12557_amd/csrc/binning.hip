@@ -21,6 +21,7 @@
 
 #include <algorithm>
 
+#include "binlut.h"
 #include "internal.h"
 
 namespace fcfc {
@@ -50,64 +51,9 @@ struct BinArgs {
     unsigned long long* stats;  // [0] values, [1] FP64 rechecks
 };
 
-// Edges certainly at or below v, walking forward from the first edge k0 whose
-// band meets the table entry (edges before it lie wholly below the entry);
-// band[k] = (lo_k, hi_k).  Returns the bin, -1 (no bin) or -2 (v inside an
-// edge's band).
-__device__ inline int bin_hot(const float2* __restrict__ band, int nb, int k0, float v) {
-    int k = k0;
-    for (; k <= nb; k++) {
-        const float2 b = band[k];
-        if (v >= b.y) continue;  // at or above E_k for certain
-        if (v >= b.x) return -2;  // inside E_k's band
-        break;                    // below E_k for certain
-    }
-    return (k >= 1 && k <= nb) ? k - 1 : -1;
-}
-
-// FP64 definition: the number c of squared edges at or below x, by binary
-// search; bin c - 1 when 1 <= c <= nb.
-__device__ inline int bin_exact(const double* __restrict__ E, int nb, double x) {
-    int lo = 0, hi = nb + 1;
-    while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if (E[mid] <= x)
-            lo = mid + 1;
-        else
-            hi = mid;
-    }
-    return (lo >= 1 && lo <= nb) ? lo - 1 : -1;
-}
-
-struct BinSmem {
-    const int16_t* lut;
-    const float2* band;  // (lo_k, hi_k) for k = 0..nb, then (+inf, +inf)
-    const double* E;
+struct BinSmem : BinTable {
     uint32_t* hist;
-    float scale, vmax;
-    int nb;
 };
-
-// Table entry of x: the bin (>= 0), -1 (no bin) or a hot entry (<= -2).
-__device__ __attribute__((always_inline)) inline int bin_entry(const BinSmem& s, double x, float& v) {
-    v = (float)x;
-    // NaN and negative values (-0.0 compares equal to 0) and values at or
-    // above the top band end (at or above E_n) land in no bin
-    const bool ok = (x >= 0.0) && (v < s.vmax);
-    const int e = s.lut[ok ? (uint32_t)(v * s.scale) : 0u];
-    return ok ? e : -1;
-}
-
-// Rare path: walk the bands from k0; a value inside a band takes the FP64
-// definition.
-__device__ __attribute__((noinline)) int bin_resolve(const BinSmem& s, int k0, float v, double x, uint32_t& rechk) {
-    int b = bin_hot(s.band, s.nb, k0, v);
-    if (b == -2) {
-        rechk++;
-        b = bin_exact(s.E, s.nb, x);
-    }
-    return b;
-}
 
 // Bin 2U values: every table read is issued before the first is used.  Hot
 // entries (edge k0) are placed against (lo, hi) of band k0 and lo of band
@@ -131,11 +77,9 @@ __device__ __attribute__((always_inline)) inline void bin_values(const BinSmem& 
         for (int k = 0; k < 2 * U; k++) {
             const bool h = e[k] < -1;
             k0[k] = h ? -2 - e[k] : 0;
-            const float2 b0 = s.band[k0[k]];
-            const float lo1 = s.band[k0[k] + 1].x;
             // below band k0: k0 edges at or below v; between bands k0 and
             // k0+1: k0+1 edges (bin k0, the dump row when k0 = nb)
-            const int r = v[k] < b0.x ? k0[k] - 1 : ((v[k] >= b0.y && v[k] < lo1) ? k0[k] : -2);
+            const int r = bin_near(s, k0[k], v[k]);
             if (h) e[k] = r;
             slow |= h && r == -2;
         }
@@ -300,11 +244,13 @@ extern "C" fcfc_status fcfc_bin_squared(fcfc_plan_t plan, const double* d_s2, in
     const int nb = p->n1, nt = (int)T.tab.size();
 
     BinArgs a{};
+    std::vector<char>& h = p->host_stage;
+    const BinBlob L = bin_blob(T, h);
     a.nt = nt;
     a.nb = nb;
-    a.off_band = al16(nt * 2);
-    a.off_e = a.off_band + al16((nb + 2) * 8);
-    a.off_hist = a.off_e + al16((nb + 1) * 8);
+    a.off_band = L.off_band;
+    a.off_e = L.off_e;
+    a.off_hist = L.bytes;
     const int tab_bytes = a.off_hist;
     int dev = 0, maxlds = 65536;
     FCFC_HIP(hipGetDevice(&dev));
@@ -325,22 +271,10 @@ extern "C" fcfc_status fcfc_bin_squared(fcfc_plan_t plan, const double* d_s2, in
     a.scale = T.scale;
     a.vmax = T.vmax;
 
-    // tables blob in the LDS layout
-    p->host_stage.assign((size_t)tab_bytes, 0);
-    char* h = p->host_stage.data();
-    memcpy(h, T.tab.data(), (size_t)nt * 2);
-    float* band = (float*)(h + a.off_band);
-    for (int k = 0; k <= nb; k++) {
-        band[2 * k] = T.lo[k];
-        band[2 * k + 1] = T.hi[k];
-    }
-    band[2 * (nb + 1)] = INFINITY;  // sentinel: no edge above the top one
-    band[2 * (nb + 1) + 1] = INFINITY;
-    memcpy(h + a.off_e, T.E.data(), (size_t)(nb + 1) * 8);
     void* blob = nullptr;
     FCFC_TRY(dev_alloc(&blob, (size_t)tab_bytes, st));
     fcfc_status s = FCFC_OK;
-    if (hipMemcpyAsync(blob, h, (size_t)tab_bytes, hipMemcpyHostToDevice, st) != hipSuccess) s = FCFC_EHIP;
+    if (hipMemcpyAsync(blob, h.data(), (size_t)tab_bytes, hipMemcpyHostToDevice, st) != hipSuccess) s = FCFC_EHIP;
 
     if (s == FCFC_OK && !p->stats_dev) {
         if (hipMalloc(&p->stats_dev, 64) != hipSuccess || hipEventCreate(&p->ev0) != hipSuccess ||
@@ -389,6 +323,7 @@ extern "C" fcfc_status fcfc_bin_squared(fcfc_plan_t plan, const double* d_s2, in
     }
     p->last_stream = st;
     p->last_counts = d_counts;
+    p->last_counts_n = 0;
     p->have_stats = true;
     p->stats.items = 0;
     p->stats.lut_entries = nt;

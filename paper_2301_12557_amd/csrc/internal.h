@@ -122,6 +122,7 @@ struct Plan {
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     bool have_stats = false;
     int64_t* last_counts = nullptr;  // device histogram of the last count (for stats)
+    int64_t last_counts_n = 0;       // its entries when not nbins (triangle counts)
     void* timing_dev = nullptr;      // last recorded per-item times (u32) followed by the items
     uint32_t timing_n = 0;
     int last_pts = 0;

@@ -1,0 +1,433 @@
+// triplets.hip -- exact triangle counts by side lengths, the three-point
+// extension of the pair counts (Sect. 6 lists three-point statistics as
+// future work): every set of three distinct points is counted once when its
+// three sides s = |x_b - x_a| (Sect. 2.5; minimum image in a periodic box)
+// lie in [e_0, e_n), into the bin of its sorted side bins (a <= b <= c).
+//
+// Each wave takes one primary point i at a time (sorted order, from a global
+// cursor).  It gathers the points j > i whose side ij is in range from the
+// cells around i's cell into an LDS list (ballot compaction; the list is the
+// scan order of the cells), then bins every pair (p, q) of the list by its
+// third side.  A triangle is found exactly once, from its lowest sorted index.
+// Lists longer than the LDS region are taken in chunks: chunk A against itself
+// and against every later chunk B, each chunk rebuilt by rescanning the cells.
+//
+// All sides are FP64, in the same operation order as the pair definition, and
+// binned with the look-up table of binlut.h, so the counts are exact.  On
+// gfx950 FP64 vector arithmetic runs at the rate of unpacked FP32.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <cstdlib>
+#include <vector>
+
+#include "binlut.h"
+#include "internal.h"
+
+namespace fcfc {
+
+constexpr int TRI_CAP = 128;       // list entries per LDS region (two regions per wave)
+constexpr int TRI_MAX_WAVES = 16;
+constexpr int TRI_MAX_BINS = 32;   // sorted bin triples: C(34, 3) = 5984 u64 counters
+
+struct TriArgs {
+    const double* pos;        // sorted FP64 xyz
+    const uint32_t* cs;       // cell_start, ncell + 1
+    const uint32_t* xkey;     // sorted keys: cell << xbits | sub-cell x
+    int xbits;
+    const int4* stencil;      // cell offsets (dx, dy, dz, 0)
+    int nst;
+    int nx, ny, nz;
+    double L, halfL;          // L > 0: periodic
+    int64_t n;
+    const uint4* tab;         // binning tables blob (binlut.h layout)
+    int tab_words;
+    int off_band, off_e, off_hist, off_lists;
+    int nb;
+    float scale, vmax;
+    int nhist;                // sorted bin triples
+    unsigned long long* out;  // nhist counters (accumulated)
+    uint32_t* cursor;
+    unsigned long long* stats;  // [0] side evaluations, [1] FP64 rechecks
+};
+
+// Squared separation of (bx, by, bz) - (ax, ay, az): per-axis minimum image
+// in a periodic box, then (dx dx + dy dy) + dz dz, no fused operations.
+__device__ __attribute__((always_inline)) inline double side2(double ax, double ay, double az, double bx, double by,
+                                                              double bz, double L, double h) {
+    double dx = bx - ax, dy = by - ay, dz = bz - az;
+    if (L > 0.0) {
+        if (dx > h) dx -= L; else if (dx < -h) dx += L;
+        if (dy > h) dy -= L; else if (dy < -h) dy += L;
+        if (dz > h) dz -= L; else if (dz < -h) dz += L;
+    }
+    return (dx * dx + dy * dy) + dz * dz;  // built with -ffp-contract=off
+}
+
+// Counter of the sorted bin triple a <= b <= c: C(c+2, 3) + C(b+1, 2) + a.
+__device__ __attribute__((always_inline)) inline int tri_slot(int b1, int b2, int b3) {
+    const int lo = min(b1, min(b2, b3));
+    const int hi = max(b1, max(b2, b3));
+    const int mid = b1 + b2 + b3 - lo - hi;
+    return hi * (hi + 1) * (hi + 2) / 6 + mid * (mid + 1) / 2 + lo;
+}
+
+struct TriList {
+    double* x;
+    double* y;
+    double* z;
+    int* b;
+};
+
+__device__ inline void wave_sync_lds_tri() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+__device__ inline uint32_t lane_prefix_tri(uint64_t m) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+// Scan the cells around primary i (cell cx, cy, cz) and keep the neighbours
+// j > i with side ij in range whose position in the scan order lies in
+// [lo, lo + TRI_CAP), into R.  Returns the number found up to the point the
+// scan stopped (all of them when `whole`).
+__device__ uint32_t tri_gather(const TriArgs& a, const BinTable& T, int64_t i, double xi, double yi, double zi,
+                               int cx, int cy, int cz, uint32_t lo, bool whole, const TriList& R, int lane,
+                               unsigned long long& nside, uint32_t& rechk) {
+    uint32_t running = 0;
+    const uint32_t hi = lo + TRI_CAP;
+    for (int s = 0; s < a.nst; s++) {
+        const int4 o = a.stencil[s];
+        int x = cx + o.x, y = cy + o.y, z = cz + o.z;
+        if (a.L > 0.0) {
+            x = ((x % a.nx) + a.nx) % a.nx;
+            y = ((y % a.ny) + a.ny) % a.ny;
+            z = ((z % a.nz) + a.nz) % a.nz;
+        } else if (x < 0 || x >= a.nx || y < 0 || y >= a.ny || z < 0 || z >= a.nz) {
+            continue;
+        }
+        const uint32_t cell = ((uint32_t)z * (uint32_t)a.ny + (uint32_t)y) * (uint32_t)a.nx + (uint32_t)x;
+        const uint32_t b0 = a.cs[cell], b1 = a.cs[cell + 1];
+        for (uint32_t j0 = b0; j0 < b1; j0 += 64) {
+            const uint32_t j = j0 + (uint32_t)lane;
+            int bin = -1;
+            double xj = 0, yj = 0, zj = 0;
+            if (j < b1 && (int64_t)j > i) {
+                xj = a.pos[3 * (size_t)j];
+                yj = a.pos[3 * (size_t)j + 1];
+                zj = a.pos[3 * (size_t)j + 2];
+                bin = bin_value(T, side2(xi, yi, zi, xj, yj, zj, a.L, a.halfL), rechk);
+                nside++;
+            }
+            const bool ok = bin >= 0;
+            const uint64_t m = __ballot(ok);
+            if (ok) {
+                const uint32_t seq = running + lane_prefix_tri(m);
+                if (seq >= lo && seq < hi) {
+                    const uint32_t e = seq - lo;
+                    R.x[e] = xj;
+                    R.y[e] = yj;
+                    R.z[e] = zj;
+                    R.b[e] = bin;
+                }
+            }
+            running += (uint32_t)__popcll(m);
+        }
+        if (!whole && running >= hi) break;
+    }
+    wave_sync_lds_tri();
+    return running;
+}
+
+// Every pair p < q of one list.
+__device__ void tri_self(const TriArgs& a, const BinTable& T, const TriList& R, int m, unsigned long long* hist,
+                         int lane, unsigned long long& nside, uint32_t& rechk) {
+    const int npair = m * (m - 1) / 2;
+    for (int t = lane; t < npair; t += 64) {
+        // t = q (q - 1) / 2 + p with 0 <= p < q
+        int q = (int)((1.0f + sqrtf(1.0f + 8.0f * (float)t)) * 0.5f);
+        if (q * (q - 1) / 2 > t) q--;
+        if ((q + 1) * q / 2 <= t) q++;
+        const int p = t - q * (q - 1) / 2;
+        const int b = bin_value(T, side2(R.x[p], R.y[p], R.z[p], R.x[q], R.y[q], R.z[q], a.L, a.halfL), rechk);
+        nside++;
+        if (b >= 0) atomicAdd(&hist[tri_slot(R.b[p], R.b[q], b)], 1ull);
+    }
+}
+
+// Every pair of an earlier list P (m1 entries) and a later list Q (m2).
+__device__ void tri_cross(const TriArgs& a, const BinTable& T, const TriList& P, int m1, const TriList& Q, int m2,
+                          unsigned long long* hist, int lane, unsigned long long& nside, uint32_t& rechk) {
+    for (int p = 0; p < m1; p++) {
+        const double px = P.x[p], py = P.y[p], pz = P.z[p];
+        const int pb = P.b[p];
+        for (int q = lane; q < m2; q += 64) {
+            const int b = bin_value(T, side2(px, py, pz, Q.x[q], Q.y[q], Q.z[q], a.L, a.halfL), rechk);
+            nside++;
+            if (b >= 0) atomicAdd(&hist[tri_slot(pb, Q.b[q], b)], 1ull);
+        }
+    }
+}
+
+__global__ __launch_bounds__(TRI_MAX_WAVES * 64) void k_triplets(TriArgs a) {
+    extern __shared__ __align__(16) char smem[];
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    {
+        uint4* dst = (uint4*)smem;
+        for (int k = tid; k < a.tab_words; k += nthr) dst[k] = a.tab[k];
+        unsigned long long* h = (unsigned long long*)(smem + a.off_hist);
+        for (int k = tid; k < a.nhist; k += nthr) h[k] = 0ull;
+    }
+    __syncthreads();
+    BinTable T;
+    T.lut = (const int16_t*)smem;
+    T.band = (const float2*)(smem + a.off_band);
+    T.E = (const double*)(smem + a.off_e);
+    T.scale = a.scale;
+    T.vmax = a.vmax;
+    T.nb = a.nb;
+    unsigned long long* hist = (unsigned long long*)(smem + a.off_hist);
+    const int lane = tid & 63, wave = tid >> 6;
+    // two regions per wave, each x[CAP], y[CAP], z[CAP] (FP64) and b[CAP]
+    char* base = smem + a.off_lists + (size_t)wave * 2 * (TRI_CAP * 28);
+    TriList R1, R2;
+    R1.x = (double*)base;
+    R1.y = R1.x + TRI_CAP;
+    R1.z = R1.y + TRI_CAP;
+    R1.b = (int*)(R1.z + TRI_CAP);
+    R2.x = (double*)(base + TRI_CAP * 28);
+    R2.y = R2.x + TRI_CAP;
+    R2.z = R2.y + TRI_CAP;
+    R2.b = (int*)(R2.z + TRI_CAP);
+    unsigned long long nside = 0;
+    uint32_t rechk = 0;
+    for (;;) {
+        uint32_t ii = 0;
+        if (lane == 0) ii = atomicAdd(a.cursor, 1u);
+        ii = __shfl(ii, 0, 64);
+        if ((int64_t)ii >= a.n) break;
+        const int64_t i = ii;
+        const double xi = a.pos[3 * (size_t)i], yi = a.pos[3 * (size_t)i + 1], zi = a.pos[3 * (size_t)i + 2];
+        const uint32_t cell = a.xkey[i] >> a.xbits;
+        const int cx = (int)(cell % (uint32_t)a.nx);
+        const int cy = (int)((cell / (uint32_t)a.nx) % (uint32_t)a.ny);
+        const int cz = (int)(cell / ((uint32_t)a.nx * (uint32_t)a.ny));
+        const uint32_t m = tri_gather(a, T, i, xi, yi, zi, cx, cy, cz, 0, true, R1, lane, nside, rechk);
+        if (m < 2) continue;
+        const uint32_t nch = (m + TRI_CAP - 1) / TRI_CAP;
+        for (uint32_t A = 0; A < nch; A++) {
+            if (A > 0) {
+                wave_sync_lds_tri();
+                tri_gather(a, T, i, xi, yi, zi, cx, cy, cz, A * TRI_CAP, false, R1, lane, nside, rechk);
+            }
+            const int mA = (int)std::min<uint32_t>(TRI_CAP, m - A * TRI_CAP);
+            tri_self(a, T, R1, mA, hist, lane, nside, rechk);
+            for (uint32_t B = A + 1; B < nch; B++) {
+                wave_sync_lds_tri();
+                tri_gather(a, T, i, xi, yi, zi, cx, cy, cz, B * TRI_CAP, false, R2, lane, nside, rechk);
+                const int mB = (int)std::min<uint32_t>(TRI_CAP, m - B * TRI_CAP);
+                tri_cross(a, T, R1, mA, R2, mB, hist, lane, nside, rechk);
+            }
+        }
+        wave_sync_lds_tri();
+    }
+    __syncthreads();
+    for (int k = tid; k < a.nhist; k += nthr) {
+        const unsigned long long v = hist[k];
+        if (v) atomicAdd(&a.out[k], v);
+    }
+    // statistics: one atomic per wave
+    for (int o = 32; o >= 1; o >>= 1) {
+        nside += __shfl_xor(nside, o, 64);
+        rechk += __shfl_xor(rechk, o, 64);
+    }
+    if (lane == 0) {
+        atomicAdd(&a.stats[0], nside);
+        if (rechk) atomicAdd(&a.stats[1], (unsigned long long)rechk);
+    }
+}
+
+// compact sorted-triple counters -> the row-major [nb][nb][nb] histogram
+__global__ void k_tri_expand(const unsigned long long* __restrict__ c, int nb, int64_t* __restrict__ out) {
+    const int f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= nb * nb * nb) return;
+    const int a = f / (nb * nb), b = (f / nb) % nb, cc = f % nb;
+    out[f] = (a <= b && b <= cc) ? (int64_t)c[cc * (cc + 1) * (cc + 2) / 6 + b * (b + 1) / 2 + a] : 0;
+}
+
+// cell offsets whose nearest points can be within reff of each other; a
+// periodic axis with fewer than 2K + 1 cells takes each of its cells once
+static void tri_stencil(const Grid& g, double rprune, std::vector<int4>& st) {
+    const double s = g.side;
+    const double reff = rprune * (1.0 + 1e-7) + 1e-9 * s;
+    const int K = (int)ceil(reff / s) + 1;
+    const int n[3] = {g.nx, g.ny, g.nz};
+    std::vector<int> off[3];
+    std::vector<bool> prune[3];
+    for (int ax = 0; ax < 3; ax++) {
+        if (g.L > 0 && n[ax] < 2 * K + 1) {
+            for (int d = 0; d < n[ax]; d++) {
+                off[ax].push_back(d);
+                prune[ax].push_back(false);
+            }
+        } else {
+            for (int d = -K; d <= K; d++) {
+                off[ax].push_back(d);
+                prune[ax].push_back(true);
+            }
+        }
+    }
+    st.clear();
+    for (size_t iz = 0; iz < off[2].size(); iz++)
+        for (size_t iy = 0; iy < off[1].size(); iy++)
+            for (size_t ix = 0; ix < off[0].size(); ix++) {
+                double t2 = 0;
+                const int d[3] = {off[0][ix], off[1][iy], off[2][iz]};
+                const bool pr[3] = {prune[0][ix], prune[1][iy], prune[2][iz]};
+                for (int ax = 0; ax < 3; ax++) {
+                    if (!pr[ax]) continue;
+                    const double gap = std::max(std::abs(d[ax]) - 1, 0) * s;
+                    t2 += gap * gap;
+                }
+                if (t2 < reff * reff) st.push_back(make_int4(d[0], d[1], d[2], 0));
+            }
+}
+
+}  // namespace fcfc
+
+using namespace fcfc;
+
+extern "C" fcfc_status fcfc_count_triplets(fcfc_plan_t plan, fcfc_cells_t cells, int64_t* d_counts, void* stream) {
+    clear_error();
+    Plan* p = (Plan*)plan;
+    Cells* c = (Cells*)cells;
+    if (!p || !c || !d_counts) {
+        set_error("count_triplets: null plan, cells or output");
+        return FCFC_EINVAL;
+    }
+    if (p->kind != FCFC_BIN_S) {
+        set_error("count_triplets: needs an s plan");
+        return FCFC_EINVAL;
+    }
+    if (c->plan_id != p->id) {
+        set_error("count_triplets: the cell set was built on a different plan");
+        return FCFC_EGRID;
+    }
+    const int nb = p->n1;
+    if (nb > TRI_MAX_BINS) {
+        set_error("count_triplets: at most %d bins", TRI_MAX_BINS);
+        return FCFC_ERANGE;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    const Lut1D* Tp = nullptr;
+    FCFC_TRY(plan_bin_table(p, &Tp));
+    const Grid& g = c->grid;
+    std::vector<int4> sten;
+    tri_stencil(g, p->rprune, sten);
+
+    TriArgs a{};
+    std::vector<char> blob_h;
+    const BinBlob B = bin_blob(*Tp, blob_h);
+    a.nhist = (nb + 2) * (nb + 1) * nb / 6;
+    a.off_band = B.off_band;
+    a.off_e = B.off_e;
+    a.off_hist = B.bytes;
+    a.off_lists = a.off_hist + bin_al16(a.nhist * 8);
+    const int per_wave = 2 * TRI_CAP * 28;
+    int dev = 0, maxlds = 65536;
+    FCFC_HIP(hipGetDevice(&dev));
+    if (hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) maxlds = 65536;
+    int waves = TRI_MAX_WAVES;
+    while (waves > 1 && a.off_lists + waves * per_wave > maxlds) waves--;
+    if (a.off_lists + waves * per_wave > maxlds) {
+        set_error("count_triplets: the tables and histogram do not fit the LDS");
+        return FCFC_ERANGE;
+    }
+    const int lds = a.off_lists + waves * per_wave;
+
+    // device block: tables, stencil, counters, cursor
+    const size_t sz_tab = (size_t)B.bytes, sz_st = sten.size() * sizeof(int4), sz_out = (size_t)a.nhist * 8;
+    const size_t o_st = sz_tab, o_out = o_st + ((sz_st + 255) & ~(size_t)255),
+                 o_cur = o_out + ((sz_out + 255) & ~(size_t)255), total = o_cur + 256;
+    std::vector<char>& h = p->host_stage;
+    h.assign(o_out, 0);
+    memcpy(h.data(), blob_h.data(), sz_tab);
+    memcpy(h.data() + o_st, sten.data(), sz_st);
+    char* blk = nullptr;
+    FCFC_TRY(dev_alloc((void**)&blk, total, st));
+    fcfc_status s = FCFC_OK;
+    if (hipMemcpyAsync(blk, h.data(), o_out, hipMemcpyHostToDevice, st) != hipSuccess) s = FCFC_EHIP;
+    if (s == FCFC_OK && !p->stats_dev) {
+        if (hipMalloc(&p->stats_dev, 64) != hipSuccess || hipEventCreate(&p->ev0) != hipSuccess ||
+            hipEventCreate(&p->ev1) != hipSuccess)
+            s = FCFC_EHIP;
+    }
+    if (s == FCFC_OK) {
+        fill_u64((uint64_t*)(blk + o_out), 0ull, a.nhist, st);
+        fill_u32((uint32_t*)(blk + o_cur), 0u, 1, st);
+        fill_u64((uint64_t*)p->stats_dev, 0ull, 8, st);
+        a.pos = c->pos64;
+        a.cs = c->cell_start;
+        a.xkey = c->xkey;
+        a.xbits = c->xbits;
+        a.stencil = (const int4*)(blk + o_st);
+        a.nst = (int)sten.size();
+        a.nx = g.nx;
+        a.ny = g.ny;
+        a.nz = g.nz;
+        a.L = g.L > 0 ? g.L : 0.0;
+        a.halfL = a.L * 0.5;
+        a.n = c->n;
+        a.tab = (const uint4*)blk;
+        a.tab_words = B.bytes / 16;
+        a.nb = nb;
+        a.scale = B.scale;
+        a.vmax = B.vmax;
+        a.out = (unsigned long long*)(blk + o_out);
+        a.cursor = (uint32_t*)(blk + o_cur);
+        a.stats = (unsigned long long*)p->stats_dev;
+        static bool attr_set[64] = {};
+        if (dev < 64 && !attr_set[dev]) {
+            if (hipFuncSetAttribute((const void*)k_triplets, hipFuncAttributeMaxDynamicSharedMemorySize, maxlds) !=
+                hipSuccess)
+                s = FCFC_EHIP;
+            else
+                attr_set[dev] = true;
+        }
+        int occ = 0;
+        if (s == FCFC_OK &&
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)k_triplets, waves * 64, lds) != hipSuccess)
+            s = FCFC_EHIP;
+        if (s == FCFC_OK) {
+            int64_t nblk = (int64_t)device_cu_count() * std::max(1, occ);
+            const int64_t need = std::max<int64_t>(1, (c->n + waves - 1) / waves);
+            nblk = std::min(nblk, need);
+            if (hipEventRecord(p->ev0, st) != hipSuccess) s = FCFC_EHIP;
+            if (s == FCFC_OK) {
+                hipLaunchKernelGGL(k_triplets, dim3((unsigned)nblk), dim3(waves * 64), (size_t)lds, st, a);
+                if (hipGetLastError() != hipSuccess || hipEventRecord(p->ev1, st) != hipSuccess) s = FCFC_EHIP;
+            }
+            if (s == FCFC_OK) {
+                const int nf = nb * nb * nb;
+                hipLaunchKernelGGL(k_tri_expand, dim3((nf + 255) / 256), dim3(256), 0, st,
+                                   (const unsigned long long*)(blk + o_out), nb, d_counts);
+                if (hipGetLastError() != hipSuccess) s = FCFC_EHIP;
+            }
+        }
+    }
+    dev_free(blk, st);
+    if (s != FCFC_OK) {
+        set_error("count_triplets: HIP failure");
+        return s;
+    }
+    p->last_stream = st;
+    p->last_counts = d_counts;
+    p->last_counts_n = (int64_t)nb * nb * nb;
+    p->have_stats = true;
+    p->stats.items = c->n;
+    p->stats.lut_entries = (int32_t)Tp->tab.size();
+    p->stats.group_waves = waves;
+    return FCFC_OK;
+}

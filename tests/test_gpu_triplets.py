@@ -1,0 +1,88 @@
+"""Triangle counts on the GPU (fcfc_count_triplets) against the oracle, bit for
+bit: the cubic-lattice closed forms, uniform periodic and open boxes, clustered
+points whose neighbour lists exceed one LDS region (chunked lists), several
+grid sizes, and tiny catalogues."""
+import numpy as np
+import pytest
+
+import oracle
+from helpers import note, to_dev, assert_same
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _gpu_tri(x, edges, box, **tuning):
+    import torch
+    from paper_2301_12557_amd import fcfc
+    c, st = fcfc.count_triplets(to_dev(x), edges=edges, box=box, return_stats=True, **tuning)
+    torch.cuda.synchronize()
+    return c.cpu().numpy(), st
+
+
+def test_cubic_lattice():
+    g = np.arange(6, dtype=np.float64)
+    x = np.stack(np.meshgrid(g, g, g, indexing="ij"), -1).reshape(-1, 3)
+    N = len(x)
+    e = [0.5, 1.2, 1.5, 1.8, 2.1]
+    note("triplets: cubic lattice 6^3, periodic")
+    got, st = _gpu_tri(x, e, 6.0)
+    assert got[0, 0, 1] == 12 * N and got[1, 1, 1] == 8 * N and got[0, 1, 2] == 24 * N
+    assert got[0, 0, 3] == 3 * N and got[1, 1, 3] == 12 * N and got[2, 2, 3] == 12 * N
+    assert_same(got, oracle.triplets(x, edges=e, box=6.0, method="brute"), what="lattice")
+    assert st["in_range"] == got.sum()
+
+
+@pytest.mark.parametrize("box", [100.0, 0.0])
+def test_uniform_box(box):
+    rng = np.random.default_rng(11)
+    x = rng.uniform(0, 100, (3000, 3))
+    e = np.linspace(1.0, 10.0, 10)
+    note(f"triplets: uniform 3000 in 100^3, box {box}")
+    got, st = _gpu_tri(x, e, box)
+    ref = oracle.triplets(x, edges=e, box=box)
+    assert ref.sum() > 10000
+    assert_same(got, ref, what=f"uniform box {box}")
+
+
+@pytest.mark.parametrize("box", [100.0, 0.0])
+def test_clustered_long_lists(box):
+    """Tight Gaussian blobs: hundreds of neighbours per point, so the lists are
+    taken in chunks of 128 (chunk against itself and every later chunk)."""
+    rng = np.random.default_rng(12)
+    cen = rng.uniform(10, 90, (6, 3))
+    x = cen[rng.integers(0, 6, 3000)] + rng.normal(0, 1.2, (3000, 3))
+    x = np.concatenate([x, rng.uniform(0, 100, (1000, 3))])
+    x = np.clip(x, 0, np.nextafter(100.0, 0))
+    e = np.concatenate([[0.05], np.geomspace(0.2, 6.0, 12)])
+    note(f"triplets: clustered 4000, box {box}")
+    got, st = _gpu_tri(x, e, box)
+    ref = oracle.triplets(x, edges=e, box=box)
+    assert ref.sum() > 1e6
+    assert_same(got, ref, what=f"clustered box {box}")
+
+
+def test_grid_sizes_agree():
+    rng = np.random.default_rng(13)
+    x = rng.uniform(0, 50, (2000, 3))
+    e = np.linspace(0.0, 6.0, 7)
+    ref = oracle.triplets(x, edges=e, box=50.0)
+    for k in (1, 2, 3, 4):
+        note(f"triplets: cells_per_rmax {k}")
+        got, _ = _gpu_tri(x, e, 50.0, cells_per_rmax=k)
+        assert_same(got, ref, what=f"k={k}")
+
+
+def test_tiny_catalogues():
+    rng = np.random.default_rng(14)
+    e = [0.0, 1.0, 2.0, 3.0]
+    for n in (0, 1, 2, 3, 7):
+        x = rng.uniform(0, 2, (n, 3)) if n else np.zeros((0, 3))
+        got, _ = _gpu_tri(x, e, 10.0)
+        assert_same(got, oracle.triplets(x, edges=e, box=10.0, method="brute"), what=f"n={n}")
