@@ -86,3 +86,28 @@ def test_tiny_catalogues():
         x = rng.uniform(0, 2, (n, 3)) if n else np.zeros((0, 3))
         got, _ = _gpu_tri(x, e, 10.0)
         assert_same(got, oracle.triplets(x, edges=e, box=10.0, method="brute"), what=f"n={n}")
+
+
+def test_full_size_invariances():
+    """The bench workload (2e6 uniform points, periodic box 1000, 15 bins to 30),
+    in the launch the bench times: the counts do not change with the grid (1 or
+    2 cells per r_max: other stencils, scan orders and list chunks) or with the
+    order of the input points, and the total matches the stats."""
+    import torch
+    from paper_2301_12557_amd import fcfc, synth
+    n, L = 2_000_000, 1000.0
+    x = torch.from_numpy(synth.uniform_box(n, L, synth.config_seed(7))).cuda()
+    e = synth.linear_edges(0, 30.0, 15)
+    note("triplets: full size, default grid")
+    a, st = fcfc.count_triplets(x, edges=e, box=L, return_stats=True)
+    assert a.sum().item() == st["in_range"] > 7e9
+    note("triplets: full size, 2 cells per r_max")
+    b = fcfc.count_triplets(x, edges=e, box=L, cells_per_rmax=2)
+    assert torch.equal(a, b)
+    note("triplets: full size, permuted input")
+    perm = torch.randperm(n, generator=torch.Generator().manual_seed(5)).cuda()
+    c = fcfc.count_triplets(x[perm].contiguous(), edges=e, box=L)
+    assert torch.equal(a, c)
+    # sorted-bin structure: nothing below the diagonal
+    idx = torch.nonzero(a)
+    assert bool((idx[:, 0] <= idx[:, 1]).all() and (idx[:, 1] <= idx[:, 2]).all())
