@@ -58,9 +58,11 @@ __device__ __attribute__((always_inline)) inline double side2(double ax, double 
                                                               double bz, double L, double h) {
     double dx = bx - ax, dy = by - ay, dz = bz - az;
     if (L > 0.0) {
-        if (dx > h) dx -= L; else if (dx < -h) dx += L;
-        if (dy > h) dy -= L; else if (dy < -h) dy += L;
-        if (dz > h) dz -= L; else if (dz < -h) dz += L;
+        // the same two candidate results as "if (d > h) d -= L; else if
+        // (d < -h) d += L", chosen by selects instead of branches
+        dx = dx > h ? dx - L : (dx < -h ? dx + L : dx);
+        dy = dy > h ? dy - L : (dy < -h ? dy + L : dy);
+        dz = dz > h ? dz - L : (dz < -h ? dz + L : dz);
     }
     return (dx * dx + dy * dy) + dz * dz;  // built with -ffp-contract=off
 }
@@ -146,8 +148,9 @@ __device__ void tri_self(const TriArgs& a, const BinTable& T, const TriList& R, 
                          int lane, unsigned long long& nside, uint32_t& rechk) {
     const int npair = m * (m - 1) / 2;
     for (int t = lane; t < npair; t += 64) {
-        // t = q (q - 1) / 2 + p with 0 <= p < q
-        int q = (int)((1.0f + sqrtf(1.0f + 8.0f * (float)t)) * 0.5f);
+        // t = q (q - 1) / 2 + p with 0 <= p < q; the hardware square root
+        // is within an ulp, and the two corrections below make q exact
+        int q = (int)((1.0f + __builtin_amdgcn_sqrtf(1.0f + 8.0f * (float)t)) * 0.5f);
         if (q * (q - 1) / 2 > t) q--;
         if ((q + 1) * q / 2 <= t) q++;
         const int p = t - q * (q - 1) / 2;
