@@ -96,6 +96,22 @@ __device__ __attribute__((always_inline)) inline int bin_value(const BinTable& s
     return e;
 }
 
+// bin_value for a value known to be finite and non-negative (a squared
+// separation of finite points): the FP64 sign and NaN test is not needed.
+__device__ __attribute__((always_inline)) inline int bin_value_nonneg(const BinTable& s, double x, uint32_t& rechk) {
+    const float v = (float)x;
+    const bool ok = v < s.vmax;
+    int e = s.lut[ok ? (uint32_t)(v * s.scale) : 0u];
+    e = ok ? e : -1;
+    if (e < -1) {
+        const int k0 = -2 - e;
+        e = bin_near(s, k0, v);
+        if (e == -2) e = bin_resolve(s, k0, v, x, rechk);
+        if (e >= s.nb) e = -1;
+    }
+    return e;
+}
+
 static inline int bin_al16(int b) { return (b + 15) & ~15; }
 
 // Host: the tables blob in the LDS layout; offsets of the bands and edges and

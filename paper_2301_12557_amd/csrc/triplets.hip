@@ -40,6 +40,7 @@ struct TriArgs {
     int nst;
     int nx, ny, nz;
     double L, halfL;          // L > 0: periodic
+    double inner;             // > 0: a primary farther than this from every face needs no wrap for its pairs
     int64_t n;
     const uint4* tab;         // binning tables blob (binlut.h layout)
     int tab_words;
@@ -68,11 +69,15 @@ __device__ __attribute__((always_inline)) inline double side2(double ax, double 
 }
 
 // Counter of the sorted bin triple a <= b <= c: C(c+2, 3) + C(b+1, 2) + a.
+// All products are below 2^24 (at most 32 bins), so the full-rate 24-bit
+// multiply serves; the product of three consecutive integers is even, and
+// y / 3 = (y * 43691) >> 17 exactly for y < 2^16.
 __device__ __attribute__((always_inline)) inline int tri_slot(int b1, int b2, int b3) {
     const int lo = min(b1, min(b2, b3));
     const int hi = max(b1, max(b2, b3));
     const int mid = b1 + b2 + b3 - lo - hi;
-    return hi * (hi + 1) * (hi + 2) / 6 + mid * (mid + 1) / 2 + lo;
+    const uint32_t y = __umul24(__umul24((uint32_t)hi, (uint32_t)hi + 1u), (uint32_t)hi + 2u) >> 1;
+    return (int)((__umul24(y, 43691u) >> 17) + (__umul24((uint32_t)mid, (uint32_t)mid + 1u) >> 1)) + lo;
 }
 
 struct TriList {
@@ -96,8 +101,8 @@ __device__ inline uint32_t lane_prefix_tri(uint64_t m) {
 // [lo, lo + TRI_CAP), into R.  Returns the number found up to the point the
 // scan stopped (all of them when `whole`).
 __device__ uint32_t tri_gather(const TriArgs& a, const BinTable& T, int64_t i, double xi, double yi, double zi,
-                               int cx, int cy, int cz, uint32_t lo, bool whole, const TriList& R, int lane,
-                               unsigned long long& nside, uint32_t& rechk) {
+                               uint32_t icell, int cx, int cy, int cz, uint32_t lo, bool whole, const TriList& R,
+                               int lane, unsigned long long& nside, uint32_t& rechk) {
     uint32_t running = 0;
     const uint32_t hi = lo + TRI_CAP;
     for (int s = 0; s < a.nst; s++) {
@@ -111,6 +116,8 @@ __device__ uint32_t tri_gather(const TriArgs& a, const BinTable& T, int64_t i, d
             continue;
         }
         const uint32_t cell = ((uint32_t)z * (uint32_t)a.ny + (uint32_t)y) * (uint32_t)a.nx + (uint32_t)x;
+        // points are sorted by cell: a cell below the primary's holds only j < i
+        if (cell < icell) continue;
         const uint32_t b0 = a.cs[cell], b1 = a.cs[cell + 1];
         for (uint32_t j0 = b0; j0 < b1; j0 += 64) {
             const uint32_t j = j0 + (uint32_t)lane;
@@ -120,7 +127,7 @@ __device__ uint32_t tri_gather(const TriArgs& a, const BinTable& T, int64_t i, d
                 xj = a.pos[3 * (size_t)j];
                 yj = a.pos[3 * (size_t)j + 1];
                 zj = a.pos[3 * (size_t)j + 2];
-                bin = bin_value(T, side2(xi, yi, zi, xj, yj, zj, a.L, a.halfL), rechk);
+                bin = bin_value_nonneg(T, side2(xi, yi, zi, xj, yj, zj, a.L, a.halfL), rechk);
                 nside++;
             }
             const bool ok = bin >= 0;
@@ -143,33 +150,51 @@ __device__ uint32_t tri_gather(const TriArgs& a, const BinTable& T, int64_t i, d
     return running;
 }
 
-// Every pair p < q of one list.
-__device__ void tri_self(const TriArgs& a, const BinTable& T, const TriList& R, int m, unsigned long long* hist,
-                         int lane, unsigned long long& nside, uint32_t& rechk) {
+// (p, q) of pair t = q (q - 1) / 2 + p, 0 <= p < q; the hardware square root
+// is within an ulp, and the two corrections make q exact.
+__device__ __attribute__((always_inline)) inline void tri_decode(int t, int& p, int& q) {
+    q = (int)((1.0f + __builtin_amdgcn_sqrtf(1.0f + 8.0f * (float)t)) * 0.5f);
+    if ((int)(__umul24((uint32_t)q, (uint32_t)q - 1u) >> 1) > t) q--;
+    if ((int)(__umul24((uint32_t)q + 1u, (uint32_t)q) >> 1) <= t) q++;
+    p = t - (int)(__umul24((uint32_t)q, (uint32_t)q - 1u) >> 1);
+}
+
+// Every pair p < q of one list, two pairs per lane per step (t and t + 64),
+// both pairs' LDS reads issued before either side is formed.
+__device__ void tri_self(const TriArgs& a, const BinTable& T, const TriList& R, int m, double L,
+                         unsigned long long* hist, int lane, unsigned long long& nside, uint32_t& rechk) {
     const int npair = m * (m - 1) / 2;
-    for (int t = lane; t < npair; t += 64) {
-        // t = q (q - 1) / 2 + p with 0 <= p < q; the hardware square root
-        // is within an ulp, and the two corrections below make q exact
-        int q = (int)((1.0f + __builtin_amdgcn_sqrtf(1.0f + 8.0f * (float)t)) * 0.5f);
-        if (q * (q - 1) / 2 > t) q--;
-        if ((q + 1) * q / 2 <= t) q++;
-        const int p = t - q * (q - 1) / 2;
-        const int b = bin_value(T, side2(R.x[p], R.y[p], R.z[p], R.x[q], R.y[q], R.z[q], a.L, a.halfL), rechk);
-        nside++;
-        if (b >= 0) atomicAdd(&hist[tri_slot(R.b[p], R.b[q], b)], 1ull);
+    for (int t = lane; t < npair; t += 128) {
+        const bool two = t + 64 < npair;
+        int p0, q0, p1, q1;
+        tri_decode(t, p0, q0);
+        tri_decode(two ? t + 64 : t, p1, q1);
+        const double ax = R.x[p0], ay = R.y[p0], az = R.z[p0], bx = R.x[q0], by = R.y[q0], bz = R.z[q0];
+        const double cx = R.x[p1], cy = R.y[p1], cz = R.z[p1], dx = R.x[q1], dy = R.y[q1], dz = R.z[q1];
+        const int b0 = bin_value_nonneg(T, side2(ax, ay, az, bx, by, bz, L, a.halfL), rechk);
+        const int b1 = two ? bin_value_nonneg(T, side2(cx, cy, cz, dx, dy, dz, L, a.halfL), rechk) : -1;
+        nside += two ? 2 : 1;
+        if (b0 >= 0) atomicAdd(&hist[tri_slot(R.b[p0], R.b[q0], b0)], 1ull);
+        if (b1 >= 0) atomicAdd(&hist[tri_slot(R.b[p1], R.b[q1], b1)], 1ull);
     }
 }
 
-// Every pair of an earlier list P (m1 entries) and a later list Q (m2).
+// Every pair of an earlier list P (m1 entries) and a later list Q (m2), two
+// entries of Q per lane per step.
 __device__ void tri_cross(const TriArgs& a, const BinTable& T, const TriList& P, int m1, const TriList& Q, int m2,
-                          unsigned long long* hist, int lane, unsigned long long& nside, uint32_t& rechk) {
+                          double L, unsigned long long* hist, int lane, unsigned long long& nside, uint32_t& rechk) {
     for (int p = 0; p < m1; p++) {
         const double px = P.x[p], py = P.y[p], pz = P.z[p];
         const int pb = P.b[p];
-        for (int q = lane; q < m2; q += 64) {
-            const int b = bin_value(T, side2(px, py, pz, Q.x[q], Q.y[q], Q.z[q], a.L, a.halfL), rechk);
-            nside++;
-            if (b >= 0) atomicAdd(&hist[tri_slot(pb, Q.b[q], b)], 1ull);
+        for (int q = lane; q < m2; q += 128) {
+            const bool two = q + 64 < m2;
+            const int q1 = two ? q + 64 : q;
+            const double bx = Q.x[q], by = Q.y[q], bz = Q.z[q], dx = Q.x[q1], dy = Q.y[q1], dz = Q.z[q1];
+            const int b0 = bin_value_nonneg(T, side2(px, py, pz, bx, by, bz, L, a.halfL), rechk);
+            const int b1 = two ? bin_value_nonneg(T, side2(px, py, pz, dx, dy, dz, L, a.halfL), rechk) : -1;
+            nside += two ? 2 : 1;
+            if (b0 >= 0) atomicAdd(&hist[tri_slot(pb, Q.b[q], b0)], 1ull);
+            if (b1 >= 0) atomicAdd(&hist[tri_slot(pb, Q.b[q1], b1)], 1ull);
         }
     }
 }
@@ -217,21 +242,27 @@ __global__ __launch_bounds__(TRI_MAX_WAVES * 64) void k_triplets(TriArgs a) {
         const int cx = (int)(cell % (uint32_t)a.nx);
         const int cy = (int)((cell / (uint32_t)a.nx) % (uint32_t)a.ny);
         const int cz = (int)(cell / ((uint32_t)a.nx * (uint32_t)a.ny));
-        const uint32_t m = tri_gather(a, T, i, xi, yi, zi, cx, cy, cz, 0, true, R1, lane, nside, rechk);
+        const uint32_t m = tri_gather(a, T, i, xi, yi, zi, cell, cx, cy, cz, 0, true, R1, lane, nside, rechk);
         if (m < 2) continue;
+        // every neighbour of a primary this far inside the box is unwrapped,
+        // and two of them differ by less than L/2 per axis: the minimum image
+        // would change nothing, so the pairs skip it
+        const bool inside = a.inner > 0.0 && xi > a.inner && xi < a.L - a.inner && yi > a.inner &&
+                            yi < a.L - a.inner && zi > a.inner && zi < a.L - a.inner;
+        const double Lp = inside ? 0.0 : a.L;
         const uint32_t nch = (m + TRI_CAP - 1) / TRI_CAP;
         for (uint32_t A = 0; A < nch; A++) {
             if (A > 0) {
                 wave_sync_lds_tri();
-                tri_gather(a, T, i, xi, yi, zi, cx, cy, cz, A * TRI_CAP, false, R1, lane, nside, rechk);
+                tri_gather(a, T, i, xi, yi, zi, cell, cx, cy, cz, A * TRI_CAP, false, R1, lane, nside, rechk);
             }
             const int mA = (int)std::min<uint32_t>(TRI_CAP, m - A * TRI_CAP);
-            tri_self(a, T, R1, mA, hist, lane, nside, rechk);
+            tri_self(a, T, R1, mA, Lp, hist, lane, nside, rechk);
             for (uint32_t B = A + 1; B < nch; B++) {
                 wave_sync_lds_tri();
-                tri_gather(a, T, i, xi, yi, zi, cx, cy, cz, B * TRI_CAP, false, R2, lane, nside, rechk);
+                tri_gather(a, T, i, xi, yi, zi, cell, cx, cy, cz, B * TRI_CAP, false, R2, lane, nside, rechk);
                 const int mB = (int)std::min<uint32_t>(TRI_CAP, m - B * TRI_CAP);
-                tri_cross(a, T, R1, mA, R2, mB, hist, lane, nside, rechk);
+                tri_cross(a, T, R1, mA, R2, mB, Lp, hist, lane, nside, rechk);
             }
         }
         wave_sync_lds_tri();
@@ -382,6 +413,11 @@ extern "C" fcfc_status fcfc_count_triplets(fcfc_plan_t plan, fcfc_cells_t cells,
         a.nz = g.nz;
         a.L = g.L > 0 ? g.L : 0.0;
         a.halfL = a.L * 0.5;
+        // neighbours lie within r (slightly more, for rounding) of the
+        // primary; pairs of them differ by less than 2 r' per axis, which
+        // needs 2 r' <= L / 2
+        const double rr = p->rprune * (1.0 + 1e-6) + 1e-9 * a.L;
+        a.inner = (a.L > 0 && 4.0 * rr <= a.L) ? rr : 0.0;
         a.n = c->n;
         a.tab = (const uint4*)blk;
         a.tab_words = B.bytes / 16;
