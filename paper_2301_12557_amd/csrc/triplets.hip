@@ -337,22 +337,26 @@ extern "C" fcfc_status fcfc_count_triplets(fcfc_plan_t plan, fcfc_cells_t cells,
     clear_error();
     Plan* p = (Plan*)plan;
     Cells* c = (Cells*)cells;
-    if (!p || !c || !d_counts) {
-        set_error("count_triplets: null plan, cells or output");
+    if (!p) {
+        set_error("count_triplets: null plan");
         return FCFC_EINVAL;
     }
     if (p->kind != FCFC_BIN_S) {
         set_error("count_triplets: needs an s plan");
         return FCFC_EINVAL;
     }
-    if (c->plan_id != p->id) {
-        set_error("count_triplets: the cell set was built on a different plan");
-        return FCFC_EGRID;
-    }
     const int nb = p->n1;
     if (nb > TRI_MAX_BINS) {
         set_error("count_triplets: at most %d bins", TRI_MAX_BINS);
         return FCFC_ERANGE;
+    }
+    if (!c || !d_counts) {
+        set_error("count_triplets: null cells or output");
+        return FCFC_EINVAL;
+    }
+    if (c->plan_id != p->id) {
+        set_error("count_triplets: the cell set was built on a different plan");
+        return FCFC_EGRID;
     }
     hipStream_t st = (hipStream_t)stream;
     const Lut1D* Tp = nullptr;
