@@ -40,6 +40,8 @@ def _load():
         lib.oracle_triplets_brute.restype = ci
         lib.oracle_triplets_list.argtypes = [P, i64, cd, P, ci, P, ci]
         lib.oracle_triplets_list.restype = ci
+        lib.oracle_triplets_list_w.argtypes = [P, P, i64, cd, P, ci, P, P, ci]
+        lib.oracle_triplets_list_w.restype = ci
         lib.oracle_version.restype = ci
         _lib = lib
     return _lib
@@ -106,17 +108,28 @@ def count(x1, x2=None, *, kind="s", edges1, edges2=None, los="z", box=0.0,
     return counts.reshape(shape), (wcounts.reshape(shape) if weighted else None)
 
 
-def triplets(x, *, edges, box=0.0, method="list", threads=0):
+def triplets(x, *, edges, box=0.0, method="list", w=None, threads=0):
     """Triangle counts of the points x ((N,3) float64): every set of three
     distinct points once, when its three sides lie in [edges[0], edges[-1]),
     binned by the sorted side bins (a <= b <= c) into an int64 [n, n, n]
     histogram (zero where a > b or b > c).  method "brute" (triple loop) or
-    "list" (neighbour lists from each point's lowest-index triangles)."""
+    "list" (neighbour lists from each point's lowest-index triangles).
+    With weights w (list method): returns (counts, weighted counts), a
+    triangle weighing fl(fl(a*b)*c) for its weights sorted a <= b <= c, each
+    bin the exact sum rounded once."""
     lib = _load()
     x = _f64(x, 3)
     e = _f64(edges)
     nb = len(e) - 1
     counts = np.zeros(nb * nb * nb, dtype=np.int64)
+    if w is not None:
+        wa = _f64(w)
+        wc = np.zeros(nb * nb * nb, dtype=np.float64)
+        rc = lib.oracle_triplets_list_w(_ptr(x), _ptr(wa), len(x), float(box), _ptr(e), nb, _ptr(counts),
+                                        _ptr(wc), int(threads))
+        if rc != 0:
+            raise OracleError(f"oracle returned {rc}")
+        return counts.reshape(nb, nb, nb), wc.reshape(nb, nb, nb)
     fn = {"brute": lib.oracle_triplets_brute, "list": lib.oracle_triplets_list}[method]
     rc = fn(_ptr(x), len(x), float(box), _ptr(e), nb, _ptr(counts), int(threads))
     if rc != 0:

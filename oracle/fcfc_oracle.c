@@ -585,6 +585,12 @@ long oracle_classify_pair(const double *p1, const double *p2, int kind, int los,
  * version: for each i, the j > i with side ij in range; then every pair of
  * them whose third side is in range.  A triangle with all sides in range is
  * found exactly once, from its lowest index.
+ * Weighted (neighbour-list counter, w non-NULL): a triangle's weight is the
+ * product of its three point weights taken in ascending order of value,
+ * fl(fl(a*b)*c), so that it does not depend on the order of the points; a
+ * bin's weighted count is the exact real sum of those products rounded once
+ * to FP64, kept exactly in 128-bit fixed point as for pairs (every product
+ * is an integer multiple of 2^-S, S from the smallest possible product).
  * ------------------------------------------------------------------------- */
 static long orc_tri_index(int n, int b1, int b2, int b3)
 {
@@ -638,19 +644,51 @@ int oracle_triplets_brute(const double *x, int64_t n, double L, const double *e,
     return ORC_OK;
 }
 
+static double orc_tri_weight(double a, double b, double c)
+{
+    double t;
+    if (a > b) { t = a; a = b; b = t; }
+    if (b > c) { t = b; b = c; c = t; }
+    if (a > b) { t = a; a = b; b = t; }
+    return (a * b) * c;
+}
+
+int oracle_triplets_list_w(const double *x, const double *w, int64_t n, double L, const double *e, int nb,
+                           int64_t *counts, double *wcounts, int nthreads);
+
 int oracle_triplets_list(const double *x, int64_t n, double L, const double *e, int nb,
                          int64_t *counts, int nthreads)
+{
+    return oracle_triplets_list_w(x, NULL, n, L, e, nb, counts, NULL, nthreads);
+}
+
+int oracle_triplets_list_w(const double *x, const double *w, int64_t n, double L, const double *e, int nb,
+                           int64_t *counts, double *wcounts, int nthreads)
 {
     orc_spec sp;
     int rc = orc_spec_init(&sp, ORC_KIND_S, ORC_LOS_Z, L, e, nb, NULL, 0);
     if (rc) { orc_spec_free(&sp); return rc; }
     if (n < 0 || (n > 0 && !x) || orc_check_points(x, n, L)) { orc_spec_free(&sp); return ORC_EINVAL; }
     long nbins = (long)nb * nb * nb;
+    int weighted = (w != NULL && wcounts != NULL);
+    int S = 0;
+    if (weighted) {
+        double m = orc_min_abs_nonzero(w, n), M = orc_max_abs(w, n);
+        if (m < INFINITY) {
+            double pmin = (m * m) * m, pmax = (M * M) * M;
+            int ex;
+            frexp(pmin, &ex);
+            S = 53 - ex;
+            if (!(ldexp(pmax, S) < ldexp(1.0, 62))) { orc_spec_free(&sp); return ORC_EINVAL; }
+        }
+    }
     int nth = 1;
 #ifdef _OPENMP
     nth = nthreads > 0 ? nthreads : omp_get_max_threads();
 #endif
     int64_t *acc = (int64_t *)calloc((size_t)nth * (size_t)nbins, sizeof(int64_t));
+    __int128 *wacc = weighted ? (__int128 *)calloc((size_t)nth * (size_t)nbins, sizeof(__int128)) : NULL;
+    if (weighted && !wacc) { free(acc); orc_spec_free(&sp); return ORC_ENOMEM; }
     int64_t *nbr = (int64_t *)malloc((size_t)nth * (size_t)(n > 0 ? n : 1) * sizeof(int64_t));
     long *nbin = (long *)malloc((size_t)nth * (size_t)(n > 0 ? n : 1) * sizeof(long));
     if (!acc || !nbr || !nbin) { free(acc); free(nbr); free(nbin); orc_spec_free(&sp); return ORC_ENOMEM; }
@@ -661,6 +699,7 @@ int oracle_triplets_list(const double *x, int64_t n, double L, const double *e, 
         t = omp_get_thread_num();
 #endif
         int64_t *h = acc + (size_t)t * (size_t)nbins;
+        __int128 *hw = weighted ? wacc + (size_t)t * (size_t)nbins : NULL;
         int64_t *lj = nbr + (size_t)t * (size_t)n;
         long *lb = nbin + (size_t)t * (size_t)n;
         int64_t m = 0;
@@ -673,16 +712,28 @@ int oracle_triplets_list(const double *x, int64_t n, double L, const double *e, 
             for (int64_t q = p + 1; q < m; q++) {
                 const double *xq = x + 3 * lj[q];
                 long bpq = orc_classify(&sp, xp[0], xp[1], xp[2], xq[0], xq[1], xq[2]);
-                if (bpq >= 0) h[orc_tri_index(nb, (int)lb[p], (int)lb[q], (int)bpq)]++;
+                if (bpq < 0) continue;
+                long slot = orc_tri_index(nb, (int)lb[p], (int)lb[q], (int)bpq);
+                h[slot]++;
+                if (weighted) {
+                    double tw = orc_tri_weight(w[i], w[lj[p]], w[lj[q]]);
+                    hw[slot] += (__int128)ldexp(tw, S);
+                }
             }
         }
     }
     for (long b = 0; b < nbins; b++) {
         int64_t v = 0;
-        for (int t = 0; t < nth; t++) v += acc[(size_t)t * (size_t)nbins + b];
+        __int128 vw = 0;
+        for (int t = 0; t < nth; t++) {
+            v += acc[(size_t)t * (size_t)nbins + b];
+            if (weighted) vw += wacc[(size_t)t * (size_t)nbins + b];
+        }
         counts[b] = v;
+        if (weighted) wcounts[b] = orc_i128_to_double(vw, S);
     }
     free(acc);
+    free(wacc);
     free(nbr);
     free(nbin);
     orc_spec_free(&sp);

@@ -94,3 +94,43 @@ def test_invariances():
     shifted = np.mod(x + np.array([7.25, 13.5, 2.125]), L)
     assert np.array_equal(oracle.triplets(shifted, edges=e, box=L), ref)
     assert np.array_equal(oracle.triplets(2 * x, edges=2 * e, box=2 * L), ref)
+
+
+def test_weighted_closed_forms_and_exact_sums():
+    """Weighted triangles: unit weights give the counts, weights of 2 give 8x
+    the counts exactly; with mixed-sign random weights every bin equals the
+    exact rational sum (fractions) of fl(fl(a b) c) over its triangles, weights
+    sorted a <= b <= c, rounded once."""
+    from fractions import Fraction
+    rng = np.random.default_rng(21)
+    L = 10.0
+    x = rng.uniform(0, L, (150, 3))
+    e = [0.5, 1.0, 2.0, 3.0]
+    c0 = oracle.triplets(x, edges=e, box=L)
+    c1, w1 = oracle.triplets(x, edges=e, box=L, w=np.ones(len(x)))
+    assert np.array_equal(c1, c0) and np.array_equal(w1, c0.astype(np.float64))
+    _, w2 = oracle.triplets(x, edges=e, box=L, w=np.full(len(x), 2.0))
+    assert np.array_equal(w2, 8.0 * c0)
+    w = rng.uniform(0.5, 2.0, len(x)) * rng.choice([-1.0, 1.0], len(x))
+    c, wc = oracle.triplets(x, edges=e, box=L, w=w)
+    assert np.array_equal(c, c0)
+    # independent: enumerate the triples with numpy, sum the products exactly
+    d = x[None, :, :] - x[:, None, :]
+    d = d - L * np.round(d / L)
+    s = np.sqrt((d * d).sum(-1))
+    E = np.asarray(e)
+    b = np.searchsorted(E, s, side="right") - 1
+    b[(s < E[0]) | (s >= E[-1])] = -1
+    nb = len(e) - 1
+    ref = {}
+    for i, j, k in combinations(range(len(x)), 3):
+        t = (b[i, j], b[i, k], b[j, k])
+        if min(t) < 0:
+            continue
+        a1, a2, a3 = sorted((w[i], w[j], w[k]))
+        key = tuple(sorted(t))
+        ref[key] = ref.get(key, Fraction(0)) + Fraction((a1 * a2) * a3)
+    expect = np.zeros((nb, nb, nb))
+    for key, v in ref.items():
+        expect[key] = float(v)
+    assert np.array_equal(wc, expect)
