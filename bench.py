@@ -484,7 +484,7 @@ def triplets_section(fcfc, synth, torch, n=2_000_000, L=1000.0, rmax=30.0, nbins
     plan.count_triplets(cells)
     ms = []
     for _ in range(repeats):
-        h = plan.count_triplets(cells)
+        h, _ = plan.count_triplets(cells)
         ms.append(plan.stats()["kernel_ms"])
     st = plan.stats()
     tri = int(h.sum().item())

@@ -442,15 +442,22 @@ fcfc_status fcfc_bin_squared(fcfc_plan_t plan, const double *d_s2, int64_t n, in
  * a <= b <= c, in d_counts: device int64 [n1][n1][n1] row-major, overwritten
  * (entries with a > b or b > c are zero).  Sides are evaluated in FP64, in
  * the operation order of the pair definition, and binned exactly.
- *   plan   an s plan (FCFC_BIN_S) with at most 32 bins; periodic or open.
- *   cells  built on that plan by fcfc_build_cells (weights are ignored).
+ *   plan       an s plan (FCFC_BIN_S) with at most 32 bins; periodic or open.
+ *   cells      built on that plan by fcfc_build_cells.
+ *   d_wcounts  NULL, or device FP64 [n1][n1][n1] (overwritten) for weighted
+ *              counts: a triangle weighs fl(fl(a*b)*c) for its three point
+ *              weights sorted by value a <= b <= c; each bin is the exact sum
+ *              of those products rounded once.  Needs a cell set built with
+ *              weights, and (max |w| / min non-zero |w|)^3 below about 2^9.
  * Enqueued on `stream`; fcfc_plan_stats afterwards gives the side evaluations
  * (candidates), FP64 rechecks, triangles counted (in_range) and the kernel
- * time.  Errors: FCFC_EINVAL (null arguments, not an s plan), FCFC_EGRID
- * (cells of another plan), FCFC_ERANGE (more than 32 bins, or the tables do
- * not fit the LDS), FCFC_EHIP.
+ * time.  Errors: FCFC_EINVAL (null arguments, not an s plan, weighted counts
+ * of an unweighted cell set), FCFC_EGRID (cells of another plan),
+ * FCFC_ERANGE (more than 32 bins, the tables or weighted sums do not fit the
+ * LDS, or the weight range is too wide), FCFC_EHIP.
  */
-fcfc_status fcfc_count_triplets(fcfc_plan_t plan, fcfc_cells_t cells, int64_t *d_counts, void *stream);
+fcfc_status fcfc_count_triplets(fcfc_plan_t plan, fcfc_cells_t cells, int64_t *d_counts,
+                                double *d_wcounts, void *stream);
 
 /*
  * From pair counts to correlation functions (Sect. 1, App. D).  All arrays

@@ -15,6 +15,13 @@
 // All sides are FP64, in the same operation order as the pair definition, and
 // binned with the look-up table of binlut.h, so the counts are exact.  On
 // gfx950 FP64 vector arithmetic runs at the rate of unpacked FP32.
+//
+// Weighted counts: a triangle weighs fl(fl(a b) c) for its three point
+// weights sorted by value, a <= b <= c (independent of the point order); a
+// bin's weighted count is the exact sum of those products rounded once.  Each
+// product times 2^S is an integer below 2^62 in magnitude; the workgroup sums
+// it in three LDS limbs (bits 0-23, 24-47 and the signed rest), which cannot
+// overflow before 2^40 additions, and merges them into 128-bit accumulators.
 #include <math.h>
 #include <string.h>
 
@@ -42,6 +49,10 @@ struct TriArgs {
     double L, halfL;          // L > 0: periodic
     double inner;             // > 0: a primary farther than this from every face needs no wrap for its pairs
     int64_t n;
+    const double* w;          // sorted weights (weighted counts)
+    double wscale;            // 2^S
+    unsigned long long* out_w;  // 2 per counter: low, high 64 bits of a signed 128-bit sum
+    int off_wl;               // LDS: three u64 limbs per counter
     const uint4* tab;         // binning tables blob (binlut.h layout)
     int tab_words;
     int off_band, off_e, off_hist, off_lists;
@@ -84,8 +95,25 @@ struct TriList {
     double* x;
     double* y;
     double* z;
+    double* w;  // weighted counts only
     int* b;
 };
+
+// weight of a triangle: the three weights sorted by value, fl(fl(a b) c)
+__device__ __attribute__((always_inline)) inline double tri_weight(double a, double b, double c) {
+    const double lo = fmin(a, fmin(b, c)), hi = fmax(a, fmax(b, c));
+    const double mid = (a <= b) ? ((b <= c) ? b : fmax(a, c)) : ((a <= c) ? a : fmax(b, c));
+    return (lo * mid) * hi;
+}
+
+// add q = (weight) 2^S, an integer below 2^62 in magnitude, to counter k
+__device__ __attribute__((always_inline)) inline void tri_add_weight(unsigned long long* wl, int nhist, int k,
+                                                                    double q) {
+    const long long t = (long long)q;
+    atomicAdd(&wl[k], (unsigned long long)(t & 0xffffffll));
+    atomicAdd(&wl[nhist + k], (unsigned long long)((t >> 24) & 0xffffffll));
+    atomicAdd(&wl[2 * nhist + k], (unsigned long long)(t >> 48));
+}
 
 __device__ inline void wave_sync_lds_tri() {
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -100,6 +128,7 @@ __device__ inline uint32_t lane_prefix_tri(uint64_t m) {
 // j > i with side ij in range whose position in the scan order lies in
 // [lo, lo + TRI_CAP), into R.  Returns the number found up to the point the
 // scan stopped (all of them when `whole`).
+template <bool W>
 __device__ uint32_t tri_gather(const TriArgs& a, const BinTable& T, int64_t i, double xi, double yi, double zi,
                                uint32_t icell, int cx, int cy, int cz, uint32_t lo, bool whole, const TriList& R,
                                int lane, unsigned long long& nside, uint32_t& rechk) {
@@ -140,6 +169,7 @@ __device__ uint32_t tri_gather(const TriArgs& a, const BinTable& T, int64_t i, d
                     R.y[e] = yj;
                     R.z[e] = zj;
                     R.b[e] = bin;
+                    if (W) R.w[e] = a.w[j];
                 }
             }
             running += (uint32_t)__popcll(m);
@@ -161,8 +191,10 @@ __device__ __attribute__((always_inline)) inline void tri_decode(int t, int& p, 
 
 // Every pair p < q of one list, two pairs per lane per step (t and t + 64),
 // both pairs' LDS reads issued before either side is formed.
-__device__ void tri_self(const TriArgs& a, const BinTable& T, const TriList& R, int m, double L,
-                         unsigned long long* hist, int lane, unsigned long long& nside, uint32_t& rechk) {
+template <bool W>
+__device__ void tri_self(const TriArgs& a, const BinTable& T, const TriList& R, int m, double L, double wi,
+                         unsigned long long* hist, unsigned long long* wl, int lane, unsigned long long& nside,
+                         uint32_t& rechk) {
     const int npair = m * (m - 1) / 2;
     for (int t = lane; t < npair; t += 128) {
         const bool two = t + 64 < npair;
@@ -174,18 +206,29 @@ __device__ void tri_self(const TriArgs& a, const BinTable& T, const TriList& R, 
         const int b0 = bin_value_nonneg(T, side2(ax, ay, az, bx, by, bz, L, a.halfL), rechk);
         const int b1 = two ? bin_value_nonneg(T, side2(cx, cy, cz, dx, dy, dz, L, a.halfL), rechk) : -1;
         nside += two ? 2 : 1;
-        if (b0 >= 0) atomicAdd(&hist[tri_slot(R.b[p0], R.b[q0], b0)], 1ull);
-        if (b1 >= 0) atomicAdd(&hist[tri_slot(R.b[p1], R.b[q1], b1)], 1ull);
+        if (b0 >= 0) {
+            const int k = tri_slot(R.b[p0], R.b[q0], b0);
+            atomicAdd(&hist[k], 1ull);
+            if (W) tri_add_weight(wl, a.nhist, k, tri_weight(wi, R.w[p0], R.w[q0]) * a.wscale);
+        }
+        if (b1 >= 0) {
+            const int k = tri_slot(R.b[p1], R.b[q1], b1);
+            atomicAdd(&hist[k], 1ull);
+            if (W) tri_add_weight(wl, a.nhist, k, tri_weight(wi, R.w[p1], R.w[q1]) * a.wscale);
+        }
     }
 }
 
 // Every pair of an earlier list P (m1 entries) and a later list Q (m2), two
 // entries of Q per lane per step.
+template <bool W>
 __device__ void tri_cross(const TriArgs& a, const BinTable& T, const TriList& P, int m1, const TriList& Q, int m2,
-                          double L, unsigned long long* hist, int lane, unsigned long long& nside, uint32_t& rechk) {
+                          double L, double wi, unsigned long long* hist, unsigned long long* wl, int lane,
+                          unsigned long long& nside, uint32_t& rechk) {
     for (int p = 0; p < m1; p++) {
         const double px = P.x[p], py = P.y[p], pz = P.z[p];
         const int pb = P.b[p];
+        const double pw = W ? P.w[p] : 0.0;
         for (int q = lane; q < m2; q += 128) {
             const bool two = q + 64 < m2;
             const int q1 = two ? q + 64 : q;
@@ -193,12 +236,27 @@ __device__ void tri_cross(const TriArgs& a, const BinTable& T, const TriList& P,
             const int b0 = bin_value_nonneg(T, side2(px, py, pz, bx, by, bz, L, a.halfL), rechk);
             const int b1 = two ? bin_value_nonneg(T, side2(px, py, pz, dx, dy, dz, L, a.halfL), rechk) : -1;
             nside += two ? 2 : 1;
-            if (b0 >= 0) atomicAdd(&hist[tri_slot(pb, Q.b[q], b0)], 1ull);
-            if (b1 >= 0) atomicAdd(&hist[tri_slot(pb, Q.b[q1], b1)], 1ull);
+            if (b0 >= 0) {
+                const int k = tri_slot(pb, Q.b[q], b0);
+                atomicAdd(&hist[k], 1ull);
+                if (W) tri_add_weight(wl, a.nhist, k, tri_weight(wi, pw, Q.w[q]) * a.wscale);
+            }
+            if (b1 >= 0) {
+                const int k = tri_slot(pb, Q.b[q1], b1);
+                atomicAdd(&hist[k], 1ull);
+                if (W) tri_add_weight(wl, a.nhist, k, tri_weight(wi, pw, Q.w[q1]) * a.wscale);
+            }
         }
     }
 }
 
+// LDS bytes of one list region
+template <bool W>
+constexpr int tri_region_bytes() {
+    return TRI_CAP * (W ? 36 : 28);
+}
+
+template <bool W>
 __global__ __launch_bounds__(TRI_MAX_WAVES * 64) void k_triplets(TriArgs a) {
     extern __shared__ __align__(16) char smem[];
     const int tid = threadIdx.x, nthr = blockDim.x;
@@ -207,6 +265,10 @@ __global__ __launch_bounds__(TRI_MAX_WAVES * 64) void k_triplets(TriArgs a) {
         for (int k = tid; k < a.tab_words; k += nthr) dst[k] = a.tab[k];
         unsigned long long* h = (unsigned long long*)(smem + a.off_hist);
         for (int k = tid; k < a.nhist; k += nthr) h[k] = 0ull;
+        if (W) {
+            unsigned long long* z = (unsigned long long*)(smem + a.off_wl);
+            for (int k = tid; k < 3 * a.nhist; k += nthr) z[k] = 0ull;
+        }
     }
     __syncthreads();
     BinTable T;
@@ -217,18 +279,23 @@ __global__ __launch_bounds__(TRI_MAX_WAVES * 64) void k_triplets(TriArgs a) {
     T.vmax = a.vmax;
     T.nb = a.nb;
     unsigned long long* hist = (unsigned long long*)(smem + a.off_hist);
+    unsigned long long* wl = W ? (unsigned long long*)(smem + a.off_wl) : nullptr;
     const int lane = tid & 63, wave = tid >> 6;
-    // two regions per wave, each x[CAP], y[CAP], z[CAP] (FP64) and b[CAP]
-    char* base = smem + a.off_lists + (size_t)wave * 2 * (TRI_CAP * 28);
+    // two regions per wave, each x[CAP], y[CAP], z[CAP] (FP64), w[CAP] when
+    // weighted, and b[CAP]
+    constexpr int RB = tri_region_bytes<W>();
+    char* base = smem + a.off_lists + (size_t)wave * 2 * RB;
     TriList R1, R2;
     R1.x = (double*)base;
     R1.y = R1.x + TRI_CAP;
     R1.z = R1.y + TRI_CAP;
-    R1.b = (int*)(R1.z + TRI_CAP);
-    R2.x = (double*)(base + TRI_CAP * 28);
+    R1.w = R1.z + TRI_CAP;
+    R1.b = (int*)(W ? R1.w + TRI_CAP : R1.z + TRI_CAP);
+    R2.x = (double*)(base + RB);
     R2.y = R2.x + TRI_CAP;
     R2.z = R2.y + TRI_CAP;
-    R2.b = (int*)(R2.z + TRI_CAP);
+    R2.w = R2.z + TRI_CAP;
+    R2.b = (int*)(W ? R2.w + TRI_CAP : R2.z + TRI_CAP);
     unsigned long long nside = 0;
     uint32_t rechk = 0;
     for (;;) {
@@ -238,11 +305,12 @@ __global__ __launch_bounds__(TRI_MAX_WAVES * 64) void k_triplets(TriArgs a) {
         if ((int64_t)ii >= a.n) break;
         const int64_t i = ii;
         const double xi = a.pos[3 * (size_t)i], yi = a.pos[3 * (size_t)i + 1], zi = a.pos[3 * (size_t)i + 2];
+        const double wi = W ? a.w[i] : 0.0;
         const uint32_t cell = a.xkey[i] >> a.xbits;
         const int cx = (int)(cell % (uint32_t)a.nx);
         const int cy = (int)((cell / (uint32_t)a.nx) % (uint32_t)a.ny);
         const int cz = (int)(cell / ((uint32_t)a.nx * (uint32_t)a.ny));
-        const uint32_t m = tri_gather(a, T, i, xi, yi, zi, cell, cx, cy, cz, 0, true, R1, lane, nside, rechk);
+        const uint32_t m = tri_gather<W>(a, T, i, xi, yi, zi, cell, cx, cy, cz, 0, true, R1, lane, nside, rechk);
         if (m < 2) continue;
         // every neighbour of a primary this far inside the box is unwrapped,
         // and two of them differ by less than L/2 per axis: the minimum image
@@ -254,15 +322,15 @@ __global__ __launch_bounds__(TRI_MAX_WAVES * 64) void k_triplets(TriArgs a) {
         for (uint32_t A = 0; A < nch; A++) {
             if (A > 0) {
                 wave_sync_lds_tri();
-                tri_gather(a, T, i, xi, yi, zi, cell, cx, cy, cz, A * TRI_CAP, false, R1, lane, nside, rechk);
+                tri_gather<W>(a, T, i, xi, yi, zi, cell, cx, cy, cz, A * TRI_CAP, false, R1, lane, nside, rechk);
             }
             const int mA = (int)std::min<uint32_t>(TRI_CAP, m - A * TRI_CAP);
-            tri_self(a, T, R1, mA, Lp, hist, lane, nside, rechk);
+            tri_self<W>(a, T, R1, mA, Lp, wi, hist, wl, lane, nside, rechk);
             for (uint32_t B = A + 1; B < nch; B++) {
                 wave_sync_lds_tri();
-                tri_gather(a, T, i, xi, yi, zi, cell, cx, cy, cz, B * TRI_CAP, false, R2, lane, nside, rechk);
+                tri_gather<W>(a, T, i, xi, yi, zi, cell, cx, cy, cz, B * TRI_CAP, false, R2, lane, nside, rechk);
                 const int mB = (int)std::min<uint32_t>(TRI_CAP, m - B * TRI_CAP);
-                tri_cross(a, T, R1, mA, R2, mB, Lp, hist, lane, nside, rechk);
+                tri_cross<W>(a, T, R1, mA, R2, mB, Lp, wi, hist, wl, lane, nside, rechk);
             }
         }
         wave_sync_lds_tri();
@@ -271,6 +339,18 @@ __global__ __launch_bounds__(TRI_MAX_WAVES * 64) void k_triplets(TriArgs a) {
     for (int k = tid; k < a.nhist; k += nthr) {
         const unsigned long long v = hist[k];
         if (v) atomicAdd(&a.out[k], v);
+        if (W) {
+            // limbs -> one signed 128-bit value, added with the carry
+            const unsigned long long l0 = wl[k], l1 = wl[a.nhist + k], l2 = wl[2 * a.nhist + k];
+            if (l0 | l1 | l2) {
+                const __int128 s128 = ((__int128)(long long)l2 << 48) + ((__int128)l1 << 24) + (__int128)l0;
+                const unsigned long long vlo = (unsigned long long)s128;
+                unsigned long long vhi = (unsigned long long)(s128 >> 64);
+                const unsigned long long o = atomicAdd(&a.out_w[2 * k], vlo);
+                if (o + vlo < o) vhi += 1ull;
+                if (vhi) atomicAdd(&a.out_w[2 * k + 1], vhi);
+            }
+        }
     }
     // statistics: one atomic per wave
     for (int o = 32; o >= 1; o >>= 1) {
@@ -289,6 +369,40 @@ __global__ void k_tri_expand(const unsigned long long* __restrict__ c, int nb, i
     if (f >= nb * nb * nb) return;
     const int a = f / (nb * nb), b = (f / nb) % nb, cc = f % nb;
     out[f] = (a <= b && b <= cc) ? (int64_t)c[cc * (cc + 1) * (cc + 2) / 6 + b * (b + 1) / 2 + a] : 0;
+}
+
+// signed 128-bit fixed point (lo, hi) times 2^-S, rounded once to nearest even
+__device__ inline double tri_fixed_to_double(unsigned long long lo, unsigned long long hi, int S) {
+    const __int128 v = (__int128)(((unsigned __int128)hi << 64) | (unsigned __int128)lo);
+    const bool neg = v < 0;
+    const unsigned __int128 m = neg ? (unsigned __int128)(-(v + 1)) + 1u : (unsigned __int128)v;
+    if (m == 0) return 0.0;
+    const unsigned long long mh = (unsigned long long)(m >> 64), ml = (unsigned long long)m;
+    const int nbits = mh ? 128 - __clzll(mh) : 64 - __clzll(ml);
+    double r;
+    if (nbits <= 53) {
+        r = ldexp((double)ml, -S);
+    } else {
+        const int sh = nbits - 53;
+        unsigned __int128 top = m >> sh;
+        const unsigned __int128 rem = m - (top << sh);
+        const unsigned __int128 half = (unsigned __int128)1 << (sh - 1);
+        if (rem > half || (rem == half && (top & 1u))) top += 1u;
+        r = ldexp((double)(unsigned long long)top, sh - S);
+    }
+    return neg ? -r : r;
+}
+
+__global__ void k_tri_expand_w(const unsigned long long* __restrict__ acc, int nb, int S, double* __restrict__ out) {
+    const int f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= nb * nb * nb) return;
+    const int a = f / (nb * nb), b = (f / nb) % nb, cc = f % nb;
+    if (a <= b && b <= cc) {
+        const int k = cc * (cc + 1) * (cc + 2) / 6 + b * (b + 1) / 2 + a;
+        out[f] = tri_fixed_to_double(acc[2 * k], acc[2 * k + 1], S);
+    } else {
+        out[f] = 0.0;
+    }
 }
 
 // cell offsets whose nearest points can be within reff of each other; a
@@ -333,7 +447,8 @@ static void tri_stencil(const Grid& g, double rprune, std::vector<int4>& st) {
 
 using namespace fcfc;
 
-extern "C" fcfc_status fcfc_count_triplets(fcfc_plan_t plan, fcfc_cells_t cells, int64_t* d_counts, void* stream) {
+extern "C" fcfc_status fcfc_count_triplets(fcfc_plan_t plan, fcfc_cells_t cells, int64_t* d_counts,
+                                           double* d_wcounts, void* stream) {
     clear_error();
     Plan* p = (Plan*)plan;
     Cells* c = (Cells*)cells;
@@ -358,6 +473,25 @@ extern "C" fcfc_status fcfc_count_triplets(fcfc_plan_t plan, fcfc_cells_t cells,
         set_error("count_triplets: the cell set was built on a different plan");
         return FCFC_EGRID;
     }
+    const bool weighted = d_wcounts != nullptr;
+    if (weighted && !c->weighted) {
+        set_error("count_triplets: weighted counts need a cell set built with weights");
+        return FCFC_EINVAL;
+    }
+    // every product fl(fl(a b) c) is a multiple of 2^-S; its magnitude lies
+    // between those of the smallest and the largest non-zero weights cubed
+    int S = 0;
+    if (weighted && c->wmin > 0) {
+        const double pmin = (c->wmin * c->wmin) * c->wmin, pmax = (c->wmax * c->wmax) * c->wmax;
+        int ex;
+        frexp(pmin, &ex);
+        S = 53 - ex;
+        if (!(ldexp(pmax, S) < ldexp(1.0, 62))) {
+            set_error("count_triplets: weight dynamic range too wide for exact sums (max/min weight %.3g)",
+                      c->wmax / c->wmin);
+            return FCFC_ERANGE;
+        }
+    }
     hipStream_t st = (hipStream_t)stream;
     const Lut1D* Tp = nullptr;
     FCFC_TRY(plan_bin_table(p, &Tp));
@@ -372,23 +506,28 @@ extern "C" fcfc_status fcfc_count_triplets(fcfc_plan_t plan, fcfc_cells_t cells,
     a.off_band = B.off_band;
     a.off_e = B.off_e;
     a.off_hist = B.bytes;
-    a.off_lists = a.off_hist + bin_al16(a.nhist * 8);
-    const int per_wave = 2 * TRI_CAP * 28;
+    a.off_wl = a.off_hist + bin_al16(a.nhist * 8);
+    a.off_lists = a.off_wl + (weighted ? bin_al16(a.nhist * 24) : 0);
+    const int per_wave = 2 * (weighted ? tri_region_bytes<true>() : tri_region_bytes<false>());
     int dev = 0, maxlds = 65536;
     FCFC_HIP(hipGetDevice(&dev));
     if (hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) maxlds = 65536;
     int waves = TRI_MAX_WAVES;
     while (waves > 1 && a.off_lists + waves * per_wave > maxlds) waves--;
     if (a.off_lists + waves * per_wave > maxlds) {
-        set_error("count_triplets: the tables and histogram do not fit the LDS");
+        set_error("count_triplets: the tables and histogram of %d bins do not fit the LDS%s", nb,
+                  weighted ? " with weighted sums" : "");
         return FCFC_ERANGE;
     }
     const int lds = a.off_lists + waves * per_wave;
+    const void* kern = weighted ? (const void*)k_triplets<true> : (const void*)k_triplets<false>;
 
-    // device block: tables, stencil, counters, cursor
-    const size_t sz_tab = (size_t)B.bytes, sz_st = sten.size() * sizeof(int4), sz_out = (size_t)a.nhist * 8;
-    const size_t o_st = sz_tab, o_out = o_st + ((sz_st + 255) & ~(size_t)255),
-                 o_cur = o_out + ((sz_out + 255) & ~(size_t)255), total = o_cur + 256;
+    // device block: tables, stencil, counters, weighted sums, cursor
+    const size_t sz_tab = (size_t)B.bytes, sz_st = sten.size() * sizeof(int4), sz_out = (size_t)a.nhist * 8,
+                 sz_w = weighted ? (size_t)a.nhist * 16 : 0;
+    auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    const size_t o_st = sz_tab, o_out = o_st + up(sz_st), o_w = o_out + up(sz_out), o_cur = o_w + up(sz_w),
+                 total = o_cur + 256;
     std::vector<char>& h = p->host_stage;
     h.assign(o_out, 0);
     memcpy(h.data(), blob_h.data(), sz_tab);
@@ -404,9 +543,13 @@ extern "C" fcfc_status fcfc_count_triplets(fcfc_plan_t plan, fcfc_cells_t cells,
     }
     if (s == FCFC_OK) {
         fill_u64((uint64_t*)(blk + o_out), 0ull, a.nhist, st);
+        if (weighted) fill_u64((uint64_t*)(blk + o_w), 0ull, 2 * (int64_t)a.nhist, st);
         fill_u32((uint32_t*)(blk + o_cur), 0u, 1, st);
         fill_u64((uint64_t*)p->stats_dev, 0ull, 8, st);
         a.pos = c->pos64;
+        a.w = weighted ? c->w : nullptr;
+        a.wscale = ldexp(1.0, S);
+        a.out_w = weighted ? (unsigned long long*)(blk + o_w) : nullptr;
         a.cs = c->cell_start;
         a.xkey = c->xkey;
         a.xbits = c->xbits;
@@ -431,17 +574,15 @@ extern "C" fcfc_status fcfc_count_triplets(fcfc_plan_t plan, fcfc_cells_t cells,
         a.out = (unsigned long long*)(blk + o_out);
         a.cursor = (uint32_t*)(blk + o_cur);
         a.stats = (unsigned long long*)p->stats_dev;
-        static bool attr_set[64] = {};
-        if (dev < 64 && !attr_set[dev]) {
-            if (hipFuncSetAttribute((const void*)k_triplets, hipFuncAttributeMaxDynamicSharedMemorySize, maxlds) !=
-                hipSuccess)
+        static bool attr_set[2][64] = {};
+        if (dev < 64 && !attr_set[weighted][dev]) {
+            if (hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, maxlds) != hipSuccess)
                 s = FCFC_EHIP;
             else
-                attr_set[dev] = true;
+                attr_set[weighted][dev] = true;
         }
         int occ = 0;
-        if (s == FCFC_OK &&
-            hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)k_triplets, waves * 64, lds) != hipSuccess)
+        if (s == FCFC_OK && hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, waves * 64, lds) != hipSuccess)
             s = FCFC_EHIP;
         if (s == FCFC_OK) {
             int64_t nblk = (int64_t)device_cu_count() * std::max(1, occ);
@@ -449,13 +590,19 @@ extern "C" fcfc_status fcfc_count_triplets(fcfc_plan_t plan, fcfc_cells_t cells,
             nblk = std::min(nblk, need);
             if (hipEventRecord(p->ev0, st) != hipSuccess) s = FCFC_EHIP;
             if (s == FCFC_OK) {
-                hipLaunchKernelGGL(k_triplets, dim3((unsigned)nblk), dim3(waves * 64), (size_t)lds, st, a);
+                if (weighted)
+                    hipLaunchKernelGGL(k_triplets<true>, dim3((unsigned)nblk), dim3(waves * 64), (size_t)lds, st, a);
+                else
+                    hipLaunchKernelGGL(k_triplets<false>, dim3((unsigned)nblk), dim3(waves * 64), (size_t)lds, st, a);
                 if (hipGetLastError() != hipSuccess || hipEventRecord(p->ev1, st) != hipSuccess) s = FCFC_EHIP;
             }
             if (s == FCFC_OK) {
                 const int nf = nb * nb * nb;
                 hipLaunchKernelGGL(k_tri_expand, dim3((nf + 255) / 256), dim3(256), 0, st,
                                    (const unsigned long long*)(blk + o_out), nb, d_counts);
+                if (weighted)
+                    hipLaunchKernelGGL(k_tri_expand_w, dim3((nf + 255) / 256), dim3(256), 0, st,
+                                       (const unsigned long long*)(blk + o_w), nb, S, d_wcounts);
                 if (hipGetLastError() != hipSuccess) s = FCFC_EHIP;
             }
         }

@@ -108,7 +108,7 @@ SIGNATURES = [
     ("fcfc_angular_plan", _I32, [ctypes.POINTER(_D), _I32, ctypes.POINTER(Tuning), ctypes.POINTER(_D),
                                  ctypes.POINTER(_P)]),
     ("fcfc_bin_squared", _I32, [_P, _P, _I64, _P, _P]),
-    ("fcfc_count_triplets", _I32, [_P, _P, _P, _P]),
+    ("fcfc_count_triplets", _I32, [_P, _P, _P, _P, _P]),
     ("fcfc_status_str", ctypes.c_char_p, [_I32]),
     ("fcfc_last_error", ctypes.c_char_p, []),
     ("fcfc_version", _I32, []),
@@ -256,15 +256,21 @@ class Plan:
         check(load().fcfc_bin_squared(self.h, s2.data_ptr(), int(s2.shape[0]), out.data_ptr(), _stream_ptr(stream)))
         return out
 
-    def count_triplets(self, cells, out=None, stream=None):
-        """Triangle counts (int64 [n1, n1, n1], sorted side bins a <= b <= c) of a cell set."""
+    def count_triplets(self, cells, weighted=False, out=None, wout=None, stream=None):
+        """Triangle counts (int64 [n1, n1, n1], sorted side bins a <= b <= c) of a
+        cell set, and the weighted counts (float64, or None)."""
         import torch
         nb = self.n1
         if out is None:
             out = torch.empty(nb ** 3, dtype=torch.int64, device=cells.device)
         _out_tensor(out, nb ** 3, torch.int64, "out")
-        check(load().fcfc_count_triplets(self.h, cells.h, out.data_ptr(), _stream_ptr(stream)))
-        return out.view(nb, nb, nb)
+        if weighted and wout is None:
+            wout = torch.empty(nb ** 3, dtype=torch.float64, device=cells.device)
+        if weighted:
+            _out_tensor(wout, nb ** 3, torch.float64, "wout")
+        check(load().fcfc_count_triplets(self.h, cells.h, out.data_ptr(), wout.data_ptr() if weighted else None,
+                                         _stream_ptr(stream)))
+        return out.view(nb, nb, nb), (wout.view(nb, nb, nb) if weighted else None)
 
     def stats(self):
         s = Stats()
@@ -664,23 +670,25 @@ def bin_squared(s2, edges, *, stream=None, **tuning):
     return out, st
 
 
-def count_triplets(x, *, edges, box=0.0, stream=None, return_stats=False, **tuning):
+def count_triplets(x, *, edges, box=0.0, w=None, stream=None, return_stats=False, **tuning):
     """Triangle counts of a device catalogue (CUDA float64 N x 3): every set of
     three distinct points once when its sides lie in [edges[0], edges[-1]),
-    binned by the sorted side bins into an int64 [n, n, n] tensor."""
+    binned by the sorted side bins into an int64 [n, n, n] tensor.  With
+    weights w: returns (counts, weighted counts)."""
     if "n_hint" not in tuning:
         tuning["n_hint"] = int(x.shape[0])
     plan = Plan("s", edges, box=box, **tuning)
     try:
         if box == 0.0:
             plan.fit_bounds([(x, None)], stream)
-        c = plan.build_cells(x, None, stream)
-        counts = plan.count_triplets(c, stream=stream)
+        c = plan.build_cells(x, w, stream)
+        counts, wcounts = plan.count_triplets(c, weighted=w is not None, stream=stream)
         st = plan.stats() if return_stats else None
         c.close()
     finally:
         plan.close()
-    return (counts, st) if return_stats else counts
+    res = counts if w is None else (counts, wcounts)
+    return (res, st) if return_stats else res
 
 
 def count_pairs(x1, x2=None, *, kind="s", edges1, edges2=None, los="z", box=0.0, w1=None, w2=None,

@@ -273,19 +273,19 @@ def test_bin_and_triplet_arguments_rejected_on_the_host():
     assert lib.fcfc_bin_squared(p, fake, (1 << 61) + 1, fake, None) == -1
     assert lib.fcfc_bin_squared(p, ctypes.c_void_p((1 << 20) + 4), 10, fake, None) == -1
     assert b"aligned" in lib.fcfc_last_error()
-    assert lib.fcfc_count_triplets(None, None, fake, None) == -1
-    assert lib.fcfc_count_triplets(p, None, fake, None) == -1
-    assert lib.fcfc_count_triplets(p, fake, None, None) == -1
+    assert lib.fcfc_count_triplets(None, None, fake, None, None) == -1
+    assert lib.fcfc_count_triplets(p, None, fake, None, None) == -1
+    assert lib.fcfc_count_triplets(p, fake, None, None, None) == -1
     lib.fcfc_plan_free(p)
     m = np.linspace(0.0, 1.0, 5)
     assert lib.fcfc_plan_create(1, 0, e.ctypes.data_as(ctypes.c_void_p), 3, m.ctypes.data_as(ctypes.c_void_p), 4,
                                 10.0, None, ctypes.byref(p)) == 0
-    assert lib.fcfc_count_triplets(p, fake, fake, None) == -1
+    assert lib.fcfc_count_triplets(p, fake, fake, None, None) == -1
     assert b"s plan" in lib.fcfc_last_error()
     lib.fcfc_plan_free(p)
     e40 = np.linspace(0.0, 2.0, 41)
     assert lib.fcfc_plan_create(0, 0, e40.ctypes.data_as(ctypes.c_void_p), 40, None, 0, 10.0, None,
                                 ctypes.byref(p)) == 0
-    assert lib.fcfc_count_triplets(p, fake, fake, None) == -5
+    assert lib.fcfc_count_triplets(p, fake, fake, None, None) == -5
     assert b"32" in lib.fcfc_last_error()
     lib.fcfc_plan_free(p)

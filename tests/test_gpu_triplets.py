@@ -111,3 +111,45 @@ def test_full_size_invariances():
     # sorted-bin structure: nothing below the diagonal
     idx = torch.nonzero(a)
     assert bool((idx[:, 0] <= idx[:, 1]).all() and (idx[:, 1] <= idx[:, 2]).all())
+
+
+def _gpu_tri_w(x, w, edges, box, **tuning):
+    import torch
+    from paper_2301_12557_amd import fcfc
+    (c, wc), st = fcfc.count_triplets(to_dev(x), edges=edges, box=box, w=to_dev(w), return_stats=True, **tuning)
+    torch.cuda.synchronize()
+    return c.cpu().numpy(), wc.cpu().numpy(), st
+
+
+@pytest.mark.parametrize("box", [100.0, 0.0])
+def test_weighted_match_oracle(box):
+    """Weighted triangles (weights sorted by value, fl(fl(a b) c), exact sums
+    rounded once): uniform points with mixed-sign weights, and clustered points
+    whose lists are chunked; counts bit for bit, weighted sums within 1e-12."""
+    rng = np.random.default_rng(31)
+    x = rng.uniform(0, 100, (3000, 3))
+    w = rng.uniform(0.5, 2.0, len(x)) * rng.choice([-1.0, 1.0], len(x))
+    e = np.linspace(1.0, 10.0, 10)
+    note(f"triplets weighted: uniform 3000, box {box}")
+    c, wc, _ = _gpu_tri_w(x, w, e, box)
+    rc, rw = oracle.triplets(x, edges=e, box=box, w=w)
+    assert_same(c, rc, wc, rw, what=f"weighted uniform box {box}")
+    cen = rng.uniform(10, 90, (6, 3))
+    x = cen[rng.integers(0, 6, 3000)] + rng.normal(0, 1.2, (3000, 3))
+    x = np.clip(np.concatenate([x, rng.uniform(0, 100, (1000, 3))]), 0, np.nextafter(100.0, 0))
+    w = rng.uniform(0.6, 1.8, len(x))
+    e = np.concatenate([[0.05], np.geomspace(0.2, 6.0, 12)])
+    note(f"triplets weighted: clustered 4000, box {box}")
+    c, wc, _ = _gpu_tri_w(x, w, e, box)
+    rc, rw = oracle.triplets(x, edges=e, box=box, w=w)
+    assert_same(c, rc, wc, rw, what=f"weighted clustered box {box}")
+
+
+def test_weighted_closed_forms():
+    rng = np.random.default_rng(32)
+    x = rng.uniform(0, 50, (2000, 3))
+    e = np.linspace(0.0, 6.0, 7)
+    c1, w1, _ = _gpu_tri_w(x, np.ones(len(x)), e, 50.0)
+    assert np.array_equal(w1, c1.astype(np.float64))
+    c2, w2, _ = _gpu_tri_w(x, np.full(len(x), 2.0), e, 50.0)
+    assert np.array_equal(c2, c1) and np.array_equal(w2, 8.0 * c1)
