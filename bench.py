@@ -492,6 +492,16 @@ def triplets_section(fcfc, synth, torch, n=2_000_000, L=1000.0, rmax=30.0, nbins
     sides = int(st["candidates"])
     achieved = FLOP_PER_SIDE * sides / (k * 1e-3) / 1e12
     cells.close()
+    # weighted: weights U[0.5, 1.5]
+    wt = torch.from_numpy(synth.uniform_weights(n, 0.5, 1.5, synth.config_seed(7) + 2)).cuda()
+    cw = plan.build_cells(x, wt)
+    plan.count_triplets(cw, weighted=True)
+    msw = []
+    for _ in range(repeats):
+        hw, ww = plan.count_triplets(cw, weighted=True)
+        msw.append(plan.stats()["kernel_ms"])
+    same = bool(torch.equal(hw, h))
+    cw.close()
     plan.close()
     # oracle on a periodic sub-box of the same density
     Ls = 200.0
@@ -509,6 +519,8 @@ def triplets_section(fcfc, synth, torch, n=2_000_000, L=1000.0, rmax=30.0, nbins
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP64_TFLOPS,
                      "per_unit": f"{FLOP_PER_SIDE} FP64 flops per side evaluation"},
+        "weighted": {"weights": "U[0.5, 1.5]", "kernel_ms": float(np.mean(msw)), "kernel_ms_sd": float(np.std(msw)),
+                     "counts_equal_unweighted": same},
         "cpu_oracle": {"kind": "oracle", "sample": f"{ns} points in a periodic box {Ls:g} (same density)",
                        "seconds": cpu_s, "triangles": int(ref.sum()), "triangles_per_s": int(ref.sum()) / cpu_s,
                        "cores": int(os.environ.get("OMP_NUM_THREADS") or os.cpu_count() or 1)},
