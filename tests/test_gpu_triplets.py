@@ -153,3 +153,47 @@ def test_weighted_closed_forms():
     assert np.array_equal(w1, c1.astype(np.float64))
     c2, w2, _ = _gpu_tri_w(x, np.full(len(x), 2.0), e, 50.0)
     assert np.array_equal(c2, c1) and np.array_equal(w2, 8.0 * c1)
+
+
+def test_cross_catalogue_terms_from_weighted_counts():
+    """Data weight 1 and randoms weight t on the merged catalogue give
+    DDD + t DDR + t^2 DRR + t^3 RRR per bin, exactly for small integers t; with
+    t = 2 and t = -1 and DDD, RRR counted alone, DDR and DRR follow exactly.
+    Checked against an enumeration of typed triples."""
+    from itertools import combinations
+    rng = np.random.default_rng(33)
+    L = 10.0
+    d = rng.uniform(0, L, (150, 3))
+    r = rng.uniform(0, L, (150, 3))
+    e = [0.5, 1.5, 2.5, 3.5]
+    x = np.concatenate([d, r])
+    ddd, _, _ = _gpu_tri_w(d, np.ones(len(d)), e, L)
+    rrr, _, _ = _gpu_tri_w(r, np.ones(len(r)), e, L)
+    _, w2, _ = _gpu_tri_w(x, np.r_[np.ones(len(d)), np.full(len(r), 2.0)], e, L)
+    _, wm, _ = _gpu_tri_w(x, np.r_[np.ones(len(d)), np.full(len(r), -1.0)], e, L)
+    A = w2 - ddd - 8.0 * rrr
+    B = wm - ddd + rrr
+    ddr = (A - 4.0 * B) / 6.0
+    drr = (A + 2.0 * B) / 6.0
+    # typed enumeration
+    dv = x[None, :, :] - x[:, None, :]
+    dv = dv - L * np.round(dv / L)
+    s = np.sqrt((dv * dv).sum(-1))
+    E = np.asarray(e)
+    b = np.searchsorted(E, s, side="right") - 1
+    b[(s < E[0]) | (s >= E[-1])] = -1
+    nb = len(e) - 1
+    nd = len(d)
+    tr = np.array(list(combinations(range(len(x)), 3)))
+    sides = np.stack([b[tr[:, 0], tr[:, 1]], b[tr[:, 0], tr[:, 2]], b[tr[:, 1], tr[:, 2]]], axis=1)
+    nr = (tr >= nd).sum(1)
+    ok = (sides >= 0).all(1)
+    sides = np.sort(sides, axis=1)
+    ref = {}
+    for kind in (1, 2):
+        sel = ok & (nr == kind)
+        h = np.zeros(nb ** 3)
+        np.add.at(h, (sides[sel, 0] * nb + sides[sel, 1]) * nb + sides[sel, 2], 1)
+        ref[kind] = h.reshape(nb, nb, nb)
+    assert ref[1].sum() > 1000 and ref[2].sum() > 1000
+    assert np.array_equal(ddr, ref[1]) and np.array_equal(drr, ref[2])
