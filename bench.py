@@ -403,14 +403,13 @@ def pairs_section(fcfc, synth, torch, repeats=3):
 BIN_LAYOUTS = (("linear", 20), ("linear", 200), ("log", 20), ("log", 200))
 
 
-def binning_section(fcfc, synth, torch, nvals, repeats=5, cpu_values=10_000_000):
+def binning_section(fcfc, synth, torch, nvals, repeats=5, cpu_values=10_000_000, cpu=True):
     """The histogram update routine alone (App. C input: s^2 = x^(2/3) 200^2,
     nvals values resident in HBM; 20 and 200 bins, linear on [0, 200) and
     logarithmic on [0.1, 200)): kernel time over HIP events on the launch
     stream, against the HBM roofline of reading 8 B per value once; then the
     look-up table size scan on the 200 logarithmic bins; the oracle on a
     bounded sample for scale."""
-    from oracle import histogram as H
     n = int(nvals)
     v = synth.s2_samples_torch(n, 200.0, synth.config_seed(6))
     torch.cuda.synchronize()
@@ -444,24 +443,27 @@ def binning_section(fcfc, synth, torch, nvals, repeats=5, cpu_values=10_000_000)
         scan.append({"lut_log2": lg, "lut_entries": int(st["lut_entries"]), "kernel_ms": float(np.mean(ms)),
                      "recheck_rate": st["rechecks"] / n})
         plan.close()
-    # the oracle on a bounded sample of the same values
-    sample = v[:cpu_values].cpu().numpy()
+    # CPU baseline: the oracle on a bounded sample of the same values
+    sample = v[:cpu_values].cpu().numpy() if cpu else None
     del v
     torch.cuda.empty_cache()
-    cpu = []
-    for layout, nb in BIN_LAYOUTS:
+    cpu_rows = []
+    if cpu:
+        from oracle import histogram as H
+    for layout, nb in (BIN_LAYOUTS if cpu else ()):
         e = synth.linear_edges(0, 200, nb) if layout == "linear" else synth.log_edges(0.1, 200, nb)
         t0 = time.perf_counter()
         H.bin_squared(sample, e)
-        cpu.append({"bins": nb, "layout": layout, "values_per_s": len(sample) / (time.perf_counter() - t0)})
+        cpu_rows.append({"bins": nb, "layout": layout, "values_per_s": len(sample) / (time.perf_counter() - t0)})
     return {
         "workload": f"{n} squared separations s^2 = x^(2/3) 200^2 (x uniform, App. C), FP64, resident in HBM",
         "kernel": "k_bin_squared",
         "roofline": {"bound": "hbm", "per_unit": "8 B per value (read once)", "peak": 8000.0, "unit": "GB/s"},
         "layouts": rows,
         "lut_scan_log200": scan,
-        "cpu_oracle": {"kind": "oracle", "sample": f"first {len(sample)} values", "rows": cpu,
-                       "note": "numpy, one comparison pass per edge"},
+        "cpu_baseline": ({"kind": "oracle", "sample": f"first {cpu_values} values", "rows": cpu_rows,
+                          "unit": "values/s", "cores": 1, "note": "numpy, one comparison pass per edge"}
+                         if cpu else None),
         "paper_context": "about 2 ns per update on one Haswell core (scalar), not this machine",
     }
 
@@ -470,13 +472,12 @@ PEAK_FP64_TFLOPS = 78.6
 FLOP_PER_SIDE = 8  # 3 sub, 3 mul, 2 add of one FP64 squared separation
 
 
-def triplets_section(fcfc, synth, torch, n=2_000_000, L=1000.0, rmax=30.0, nbins=15, repeats=3):
+def triplets_section(fcfc, synth, torch, n=2_000_000, L=1000.0, rmax=30.0, nbins=15, repeats=3, cpu=True):
     """Triangle counts (three-point extension): n uniform points in a periodic
     box, sides binned in nbins linear bins over [0, rmax).  Kernel time over
     HIP events on the launch stream; roofline of the FP64 side evaluations
     against the FP64 vector peak; the oracle (neighbour lists, all host cores)
     on a periodic sub-box of the same density for scale."""
-    import oracle
     x = torch.from_numpy(synth.uniform_box(n, L, synth.config_seed(7))).cuda()
     e = synth.linear_edges(0, rmax, nbins)
     plan = fcfc.Plan("s", e, box=L, n_hint=n)
@@ -503,13 +504,19 @@ def triplets_section(fcfc, synth, torch, n=2_000_000, L=1000.0, rmax=30.0, nbins
     same = bool(torch.equal(hw, h))
     cw.close()
     plan.close()
-    # oracle on a periodic sub-box of the same density
+    # CPU baseline: the oracle on a periodic sub-box of the same density
     Ls = 200.0
     ns = int(round(n * (Ls / L) ** 3))
-    xs = synth.uniform_box(ns, Ls, synth.config_seed(7) + 1)
-    t0 = time.perf_counter()
-    ref = oracle.triplets(xs, edges=e, box=Ls)
-    cpu_s = time.perf_counter() - t0
+    base = None
+    if cpu:
+        import oracle
+        xs = synth.uniform_box(ns, Ls, synth.config_seed(7) + 1)
+        t0 = time.perf_counter()
+        ref = oracle.triplets(xs, edges=e, box=Ls)
+        cpu_s = time.perf_counter() - t0
+        base = {"kind": "oracle", "sample": f"{ns} points in a periodic box {Ls:g} (same density)",
+                "seconds": cpu_s, "triangles": int(ref.sum()), "value": int(ref.sum()) / cpu_s,
+                "unit": "triangles/s", "cores": int(os.environ.get("OMP_NUM_THREADS") or os.cpu_count() or 1)}
     return {
         "workload": f"{n} uniform points, periodic box {L:g}, {nbins} linear side bins over [0, {rmax:g})",
         "kernel": "k_triplets", "kernel_ms": k, "kernel_ms_sd": float(np.std(ms)),
@@ -521,9 +528,7 @@ def triplets_section(fcfc, synth, torch, n=2_000_000, L=1000.0, rmax=30.0, nbins
                      "per_unit": f"{FLOP_PER_SIDE} FP64 flops per side evaluation"},
         "weighted": {"weights": "U[0.5, 1.5]", "kernel_ms": float(np.mean(msw)), "kernel_ms_sd": float(np.std(msw)),
                      "counts_equal_unweighted": same},
-        "cpu_oracle": {"kind": "oracle", "sample": f"{ns} points in a periodic box {Ls:g} (same density)",
-                       "seconds": cpu_s, "triangles": int(ref.sum()), "triangles_per_s": int(ref.sum()) / cpu_s,
-                       "cores": int(os.environ.get("OMP_NUM_THREADS") or os.cpu_count() or 1)},
+        "cpu_baseline": base,
     }
 
 
@@ -766,12 +771,12 @@ def main():
             f"one batch {res['pairs']['batch_ms']:.1f} ms, equal {res['pairs']['counts_equal']}")
     if not args.no_binning:
         from paper_2301_12557_amd import synth
-        res["binning"] = binning_section(fcfc, synth, torch, args.binning_values)
+        res["binning"] = binning_section(fcfc, synth, torch, args.binning_values, cpu=not args.no_cpu_baseline)
         log("binning: " + " ".join(f"{r['layout']}{r['bins']} {r['kernel_ms']:.2f} ms ({r['hbm_frac']:.2f})"
                                    for r in res["binning"]["layouts"]))
     if not args.no_triplets:
         from paper_2301_12557_amd import synth
-        res["triplets"] = triplets_section(fcfc, synth, torch)
+        res["triplets"] = triplets_section(fcfc, synth, torch, cpu=not args.no_cpu_baseline)
         log(f"triplets: {res['triplets']['kernel_ms']:.2f} ms, {res['triplets']['triangles']} triangles, "
             f"{res['triplets']['roofline']['frac']:.3f} of FP64 peak")
     if not args.no_cpu_baseline:
