@@ -72,13 +72,13 @@ def workload(name, weighted):
     return w, desc
 
 
-def measured_traffic(kernel_variant):
-    """HBM bytes per launch of the counting kernel from the committed rocprofv3
-    FETCH_SIZE / WRITE_SIZE summary (profiles/k_count_c2_*_traffic.md), if it was
-    taken on the current kernel source and the same kernel variant; else None."""
+def measured_traffic(kernel_variant, sources=("count.hip",), key="count_hip_sha256_16"):
+    """HBM bytes per launch of a kernel from a committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE summary (profiles/*_traffic.md), if it was taken on the current
+    kernel sources and the same kernel variant; else None."""
     import hashlib
     try:
-        src = open(os.path.join(ROOT, "paper_2301_12557_amd", "csrc", "count.hip"), "rb").read()
+        src = b"".join(open(os.path.join(ROOT, "paper_2301_12557_amd", "csrc", f), "rb").read() for f in sources)
         digest = hashlib.sha256(src).hexdigest()[:16]
         pdir = os.path.join(ROOT, "profiles")
         for fn in sorted(os.listdir(pdir)):
@@ -87,7 +87,7 @@ def measured_traffic(kernel_variant):
             for line in open(os.path.join(pdir, fn)):
                 if line.startswith("traffic-record:"):
                     rec = json.loads(line.split(":", 1)[1])
-                    if rec.get("variant") == kernel_variant and rec.get("count_hip_sha256_16") == digest:
+                    if rec.get("variant") == kernel_variant and rec.get(key) == digest:
                         return float(rec["hbm_bytes_per_launch"])
     except Exception:
         return None
@@ -458,7 +458,9 @@ def binning_section(fcfc, synth, torch, nvals, repeats=5, cpu_values=10_000_000,
     return {
         "workload": f"{n} squared separations s^2 = x^(2/3) 200^2 (x uniform, App. C), FP64, resident in HBM",
         "kernel": "k_bin_squared",
-        "roofline": {"bound": "hbm", "per_unit": "8 B per value (read once)", "peak": 8000.0, "unit": "GB/s"},
+        "roofline": {"bound": "hbm", "per_unit": "8 B per value (read once)", "peak": 8000.0, "unit": "GB/s",
+                     "traffic": (measured_traffic("binning/6.4e9", ("binning.hip", "binlut.h"), "src_sha256_16")
+                                 if n == 6_400_000_000 else None)},
         "layouts": rows,
         "lut_scan_log200": scan,
         "cpu_baseline": ({"kind": "oracle", "sample": f"first {cpu_values} values", "rows": cpu_rows,
