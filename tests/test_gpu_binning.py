@@ -163,3 +163,18 @@ def test_full_size_properties(name):
     plan.close()
     del v
     torch.cuda.empty_cache()
+
+
+def test_any_plan_bins_its_first_axis():
+    """An (s, mu) or (s_perp, pi) plan bins given values by its first-axis edges,
+    exactly as the s plan of the same edges and the oracle do."""
+    from paper_2301_12557_amd import fcfc
+    edges = LAYOUTS["lin20"]
+    v = _values(400_000, edges, 17)
+    dv = to_dev(v)
+    ref = H.bin_squared(v, edges)
+    for kind, e2, box in (("s", None, 4 * R), ("smu", synth.mu_edges(10), 4 * R), ("spi", synth.linear_edges(0, 50, 5), 0.0)):
+        plan = fcfc.Plan(kind, edges, e2, box=box)
+        note(f"bin_squared with a {kind} plan")
+        assert_same(_gpu_bins(fcfc, plan, dv), ref, what=f"{kind} plan")
+        plan.close()
