@@ -55,7 +55,7 @@ struct TriArgs {
     int off_wl;               // LDS: three u64 limbs per counter
     const uint4* tab;         // binning tables blob (binlut.h layout)
     int tab_words;
-    int off_band, off_e, off_hist, off_lists;
+    int off_band, off_e, off_hist, off_t3, off_lists;
     int nb;
     float scale, vmax;
     int nhist;                // sorted bin triples
@@ -79,16 +79,14 @@ __device__ __attribute__((always_inline)) inline double side2(double ax, double 
     return (dx * dx + dy * dy) + dz * dz;  // built with -ffp-contract=off
 }
 
-// Counter of the sorted bin triple a <= b <= c: C(c+2, 3) + C(b+1, 2) + a.
-// All products are below 2^24 (at most 32 bins), so the full-rate 24-bit
-// multiply serves; the product of three consecutive integers is even, and
-// y / 3 = (y * 43691) >> 17 exactly for y < 2^16.
-__device__ __attribute__((always_inline)) inline int tri_slot(int b1, int b2, int b3) {
+// Counter of the sorted bin triple a <= b <= c: C(c+2, 3) + C(b+1, 2) + a,
+// with C(c+2, 3) from a table in LDS (t3[c]) and the full-rate 24-bit
+// multiply for C(b+1, 2).
+__device__ __attribute__((always_inline)) inline int tri_slot(const int* t3, int b1, int b2, int b3) {
     const int lo = min(b1, min(b2, b3));
     const int hi = max(b1, max(b2, b3));
     const int mid = b1 + b2 + b3 - lo - hi;
-    const uint32_t y = __umul24(__umul24((uint32_t)hi, (uint32_t)hi + 1u), (uint32_t)hi + 2u) >> 1;
-    return (int)((__umul24(y, 43691u) >> 17) + (__umul24((uint32_t)mid, (uint32_t)mid + 1u) >> 1)) + lo;
+    return t3[hi] + (int)(__umul24((uint32_t)mid, (uint32_t)mid + 1u) >> 1) + lo;
 }
 
 struct TriList {
@@ -193,7 +191,7 @@ __device__ __attribute__((always_inline)) inline void tri_decode(int t, int& p, 
 // both pairs' LDS reads issued before either side is formed.
 template <bool W>
 __device__ void tri_self(const TriArgs& a, const BinTable& T, const TriList& R, int m, double L, double wi,
-                         unsigned long long* hist, unsigned long long* wl, int lane, unsigned long long& nside,
+                         const int* t3, unsigned long long* hist, unsigned long long* wl, int lane, unsigned long long& nside,
                          uint32_t& rechk) {
     const int npair = m * (m - 1) / 2;
     for (int t = lane; t < npair; t += 128) {
@@ -207,12 +205,12 @@ __device__ void tri_self(const TriArgs& a, const BinTable& T, const TriList& R, 
         const int b1 = two ? bin_value_nonneg(T, side2(cx, cy, cz, dx, dy, dz, L, a.halfL), rechk) : -1;
         nside += two ? 2 : 1;
         if (b0 >= 0) {
-            const int k = tri_slot(R.b[p0], R.b[q0], b0);
+            const int k = tri_slot(t3, R.b[p0], R.b[q0], b0);
             atomicAdd(&hist[k], 1ull);
             if (W) tri_add_weight(wl, a.nhist, k, tri_weight(wi, R.w[p0], R.w[q0]) * a.wscale);
         }
         if (b1 >= 0) {
-            const int k = tri_slot(R.b[p1], R.b[q1], b1);
+            const int k = tri_slot(t3, R.b[p1], R.b[q1], b1);
             atomicAdd(&hist[k], 1ull);
             if (W) tri_add_weight(wl, a.nhist, k, tri_weight(wi, R.w[p1], R.w[q1]) * a.wscale);
         }
@@ -223,7 +221,7 @@ __device__ void tri_self(const TriArgs& a, const BinTable& T, const TriList& R, 
 // entries of Q per lane per step.
 template <bool W>
 __device__ void tri_cross(const TriArgs& a, const BinTable& T, const TriList& P, int m1, const TriList& Q, int m2,
-                          double L, double wi, unsigned long long* hist, unsigned long long* wl, int lane,
+                          double L, double wi, const int* t3, unsigned long long* hist, unsigned long long* wl, int lane,
                           unsigned long long& nside, uint32_t& rechk) {
     for (int p = 0; p < m1; p++) {
         const double px = P.x[p], py = P.y[p], pz = P.z[p];
@@ -237,12 +235,12 @@ __device__ void tri_cross(const TriArgs& a, const BinTable& T, const TriList& P,
             const int b1 = two ? bin_value_nonneg(T, side2(px, py, pz, dx, dy, dz, L, a.halfL), rechk) : -1;
             nside += two ? 2 : 1;
             if (b0 >= 0) {
-                const int k = tri_slot(pb, Q.b[q], b0);
+                const int k = tri_slot(t3, pb, Q.b[q], b0);
                 atomicAdd(&hist[k], 1ull);
                 if (W) tri_add_weight(wl, a.nhist, k, tri_weight(wi, pw, Q.w[q]) * a.wscale);
             }
             if (b1 >= 0) {
-                const int k = tri_slot(pb, Q.b[q1], b1);
+                const int k = tri_slot(t3, pb, Q.b[q1], b1);
                 atomicAdd(&hist[k], 1ull);
                 if (W) tri_add_weight(wl, a.nhist, k, tri_weight(wi, pw, Q.w[q1]) * a.wscale);
             }
@@ -265,6 +263,8 @@ __global__ __launch_bounds__(TRI_MAX_WAVES * 64) void k_triplets(TriArgs a) {
         for (int k = tid; k < a.tab_words; k += nthr) dst[k] = a.tab[k];
         unsigned long long* h = (unsigned long long*)(smem + a.off_hist);
         for (int k = tid; k < a.nhist; k += nthr) h[k] = 0ull;
+        int* t3w = (int*)(smem + a.off_t3);
+        for (int k = tid; k <= TRI_MAX_BINS; k += nthr) t3w[k] = k * (k + 1) * (k + 2) / 6;
         if (W) {
             unsigned long long* z = (unsigned long long*)(smem + a.off_wl);
             for (int k = tid; k < 3 * a.nhist; k += nthr) z[k] = 0ull;
@@ -279,6 +279,7 @@ __global__ __launch_bounds__(TRI_MAX_WAVES * 64) void k_triplets(TriArgs a) {
     T.vmax = a.vmax;
     T.nb = a.nb;
     unsigned long long* hist = (unsigned long long*)(smem + a.off_hist);
+    const int* t3 = (const int*)(smem + a.off_t3);
     unsigned long long* wl = W ? (unsigned long long*)(smem + a.off_wl) : nullptr;
     const int lane = tid & 63, wave = tid >> 6;
     // two regions per wave, each x[CAP], y[CAP], z[CAP] (FP64), w[CAP] when
@@ -325,12 +326,12 @@ __global__ __launch_bounds__(TRI_MAX_WAVES * 64) void k_triplets(TriArgs a) {
                 tri_gather<W>(a, T, i, xi, yi, zi, cell, cx, cy, cz, A * TRI_CAP, false, R1, lane, nside, rechk);
             }
             const int mA = (int)std::min<uint32_t>(TRI_CAP, m - A * TRI_CAP);
-            tri_self<W>(a, T, R1, mA, Lp, wi, hist, wl, lane, nside, rechk);
+            tri_self<W>(a, T, R1, mA, Lp, wi, t3, hist, wl, lane, nside, rechk);
             for (uint32_t B = A + 1; B < nch; B++) {
                 wave_sync_lds_tri();
                 tri_gather<W>(a, T, i, xi, yi, zi, cell, cx, cy, cz, B * TRI_CAP, false, R2, lane, nside, rechk);
                 const int mB = (int)std::min<uint32_t>(TRI_CAP, m - B * TRI_CAP);
-                tri_cross<W>(a, T, R1, mA, R2, mB, Lp, wi, hist, wl, lane, nside, rechk);
+                tri_cross<W>(a, T, R1, mA, R2, mB, Lp, wi, t3, hist, wl, lane, nside, rechk);
             }
         }
         wave_sync_lds_tri();
@@ -506,7 +507,8 @@ extern "C" fcfc_status fcfc_count_triplets(fcfc_plan_t plan, fcfc_cells_t cells,
     a.off_band = B.off_band;
     a.off_e = B.off_e;
     a.off_hist = B.bytes;
-    a.off_wl = a.off_hist + bin_al16(a.nhist * 8);
+    a.off_t3 = a.off_hist + bin_al16(a.nhist * 8);
+    a.off_wl = a.off_t3 + bin_al16((TRI_MAX_BINS + 1) * 4);
     a.off_lists = a.off_wl + (weighted ? bin_al16(a.nhist * 24) : 0);
     const int per_wave = 2 * (weighted ? tri_region_bytes<true>() : tri_region_bytes<false>());
     int dev = 0, maxlds = 65536;
