@@ -178,3 +178,26 @@ def test_any_plan_bins_its_first_axis():
         note(f"bin_squared with a {kind} plan")
         assert_same(_gpu_bins(fcfc, plan, dv), ref, what=f"{kind} plan")
         plan.close()
+
+
+@pytest.mark.parametrize("layout,nb", [("log", 1000), ("linear", 2000)])
+def test_many_bins_few_copies(layout, nb):
+    """1000 or 2000 bins leave room for only 16 or 8 LDS histogram copies per
+    workgroup (lanes share copies, and each bin's copies are summed by one
+    thread): still exact.  Far more bins than the LDS holds are refused."""
+    from paper_2301_12557_amd import fcfc
+    edges = synth.log_edges(0.1, R, nb) if layout == "log" else synth.linear_edges(0, R, nb)
+    v = _values(2_000_001, edges, 50 + nb)
+    plan = fcfc.Plan("s", edges, box=4 * R)
+    note(f"bin_squared {layout}{nb}")
+    assert_same(_gpu_bins(fcfc, plan, to_dev(v)), H.bin_squared(v, edges), what=f"{layout}{nb}")
+    plan.close()
+
+
+def test_too_many_bins_refused():
+    from paper_2301_12557_amd import fcfc
+    edges = synth.linear_edges(0, R, 12000)
+    plan = fcfc.Plan("s", edges, box=4 * R)
+    with pytest.raises(fcfc.FcfcError):
+        plan.bin_squared(to_dev(np.ones(16)))
+    plan.close()
