@@ -197,3 +197,24 @@ def test_cross_catalogue_terms_from_weighted_counts():
         ref[kind] = h.reshape(nb, nb, nb)
     assert ref[1].sum() > 1000 and ref[2].sum() > 1000
     assert np.array_equal(ddr, ref[1]) and np.array_equal(drr, ref[2])
+
+
+def test_most_bins():
+    """32 bins (the most; 5984 counters leave fewer waves per workgroup), and
+    20 bins weighted, exact; 32 bins weighted do not fit the LDS and are
+    refused."""
+    from paper_2301_12557_amd import fcfc
+    rng = np.random.default_rng(34)
+    x = rng.uniform(0, 40, (3000, 3))
+    e32 = np.linspace(0.2, 6.6, 33)
+    note("triplets: 32 bins")
+    got, st = _gpu_tri(x, e32, 40.0)
+    assert_same(got, oracle.triplets(x, edges=e32, box=40.0), what="32 bins")
+    w = rng.uniform(0.5, 2.0, len(x))
+    e20 = np.linspace(0.2, 6.2, 21)
+    note("triplets: 20 bins weighted")
+    c, wc, _ = _gpu_tri_w(x, w, e20, 40.0)
+    rc, rw = oracle.triplets(x, edges=e20, box=40.0, w=w)
+    assert_same(c, rc, wc, rw, what="20 bins weighted")
+    with pytest.raises(fcfc.FcfcError):
+        _gpu_tri_w(x, w, e32, 40.0)
