@@ -13,9 +13,10 @@
 // value to FP32, so every decision taken in FP32 is the FP64 decision.
 //
 // The input is streamed once with 16-byte loads by a grid of one
-// 1024-thread workgroup per CU; each workgroup counts into LDS histogram
-// copies laid out so that the 64 lanes of a wave never share an address, and
-// merges them into the int64 counts with one global atomic per bin at the end.
+// 1024-thread workgroup per CU.  Each workgroup counts into as many LDS
+// histogram copies as fit (up to one per thread), laid out [bin][copy]: with
+// 64 or more copies the 64 lanes of a wave never share an address.  At the
+// end it merges them into the int64 counts with one global atomic per bin.
 #include <math.h>
 #include <string.h>
 
