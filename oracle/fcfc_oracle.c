@@ -395,8 +395,14 @@ int oracle_count_brute(const double *x1, const double *w1, int64_t n1,
  * Cell side >= cell_size; a point's neighbour cells are all cells within
  * ceil(r_prune / side) + 1 cells per axis (wrapped and de-duplicated for a
  * periodic box), where r_prune = s_max, or sqrt(sigma_max^2 + pi_max^2).  This
- * holds every partner in range with a whole cell of margin; every candidate is
- * classified by the same per-pair function as the brute force.
+ * holds every partner in range with a whole cell of margin.  A neighbour cell
+ * is skipped when the point's distance to it exceeds r_prune (the pruning of
+ * node pairs whose minimum separation is beyond the largest edge, Sect. 3.1):
+ * per axis the gap between the point's coordinate and the cell's slab, the
+ * smallest over every wrap offset that reaches the cell; the test keeps a
+ * relative margin of 1e-9 for the rounding of the slab bounds and of the
+ * pair's own separation.  Every remaining candidate is classified by the same
+ * per-pair function as the brute force.
  * ------------------------------------------------------------------------- */
 typedef struct {
     int n[3];
@@ -497,6 +503,14 @@ int oracle_count_grid(const double *x1, const double *w1, int64_t n1,
     if (orc_grid_build(&g2, x2, n2)) { orc_grid_free(&g2); orc_spec_free(&sp); return ORC_ENOMEM; }
     int reach[3];
     for (int a = 0; a < 3; a++) reach[a] = (int)ceil(rmax / g.side[a]) + 1;
+    /* cells farther than this from a point hold no partner in range */
+    double cmag = (L > 0.0) ? L : 0.0;
+    for (int a = 0; a < 3; a++) {
+        double m = fabs(g.lo[a]) + g.side[a] * (double)g.n[a];
+        if (m > cmag) cmag = m;
+    }
+    double lim = rmax * (1.0 + 1e-9) + 1e-9 * cmag;
+    double lim2 = lim * lim;
 
     int nth = 1;
 #ifdef _OPENMP
@@ -513,34 +527,54 @@ int oracle_count_grid(const double *x1, const double *w1, int64_t n1,
 #ifdef _OPENMP
         t = omp_get_thread_num();
 #endif
-        /* per-axis neighbour index lists (wrapped and de-duplicated) */
+        /* per-axis neighbour index lists (wrapped and de-duplicated), with the
+         * smallest gap between the point and each listed cell's slab */
         int *lst[3];
+        double *gap[3];
         int cnt[3];
-        for (int a = 0; a < 3; a++) lst[a] = (int *)malloc(sizeof(int) * (size_t)(2 * reach[a] + 1));
+        for (int a = 0; a < 3; a++) {
+            lst[a] = (int *)malloc(sizeof(int) * (size_t)(2 * reach[a] + 1));
+            gap[a] = (double *)malloc(sizeof(double) * (size_t)(2 * reach[a] + 1));
+        }
 #pragma omp for schedule(dynamic, 64)
         for (int64_t i = 0; i < n1; i++) {
             double xi = x1[3 * i], yi = x1[3 * i + 1], zi = x1[3 * i + 2];
             double wi = ws.weighted ? w1[i] : 0.0;
             long ci = orc_cell_of(&g2, xi, yi, zi);
             long c3[3] = {ci % g.n[0], (ci / g.n[0]) % g.n[1], ci / ((long)g.n[0] * g.n[1])};
+            double pv[3] = {xi, yi, zi};
             for (int a = 0; a < 3; a++) {
                 cnt[a] = 0;
                 for (int d = -reach[a]; d <= reach[a]; d++) {
                     long c = c3[a] + d;
+                    /* the slab of this offset, unwrapped */
+                    double slo = g.lo[a] + (double)c * g.side[a];
+                    double shi = slo + g.side[a];
+                    double gp = 0.0;
+                    if (pv[a] < slo) gp = slo - pv[a];
+                    else if (pv[a] > shi) gp = pv[a] - shi;
                     if (L > 0.0) {
                         c %= g.n[a];
                         if (c < 0) c += g.n[a];
                     } else if (c < 0 || c >= g.n[a]) {
                         continue;
                     }
-                    int seen = 0;
-                    for (int q = 0; q < cnt[a]; q++) if (lst[a][q] == (int)c) seen = 1;
-                    if (!seen) lst[a][cnt[a]++] = (int)c;
+                    int seen = -1;
+                    for (int q = 0; q < cnt[a]; q++) if (lst[a][q] == (int)c) seen = q;
+                    if (seen < 0) {
+                        lst[a][cnt[a]] = (int)c;
+                        gap[a][cnt[a]] = gp;
+                        cnt[a]++;
+                    } else if (gp < gap[a][seen]) {
+                        gap[a][seen] = gp;
+                    }
                 }
             }
             for (int qz = 0; qz < cnt[2]; qz++)
                 for (int qy = 0; qy < cnt[1]; qy++)
                     for (int qx = 0; qx < cnt[0]; qx++) {
+                        double gsq = (gap[0][qx] * gap[0][qx] + gap[1][qy] * gap[1][qy]) + gap[2][qz] * gap[2][qz];
+                        if (gsq > lim2) continue;
                         long c = ((long)lst[2][qz] * g.n[1] + lst[1][qy]) * g.n[0] + lst[0][qx];
                         for (int64_t p = g2.start[c]; p < g2.start[c + 1]; p++) {
                             int64_t j = g2.order[p];
@@ -550,7 +584,7 @@ int oracle_count_grid(const double *x1, const double *w1, int64_t n1,
                         }
                     }
         }
-        for (int a = 0; a < 3; a++) free(lst[a]);
+        for (int a = 0; a < 3; a++) { free(lst[a]); free(gap[a]); }
     }
     orc_finish(acc, nth, nbins, &ws, counts, wcounts);
     orc_acc_free(acc, nth);

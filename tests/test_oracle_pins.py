@@ -324,3 +324,154 @@ def test_no_fused_multiply_add():
     p2 = np.array([dx, dy, 0.0])
     b = oracle.classify_pair(p1, p2, kind="s", edges1=[0.0, edge, 2 * edge + 1.0])
     assert b == 1          # unfused d2 == edge^2 -> upper bin
+
+
+# ---------------------------------------------------------------------------
+# The cell-list counter against the brute-force double loop.  The cell list is
+# the checker behind every full-size GPU test, so its every path is pinned to
+# the plain definition (all pairs, Sect. 3.1) on catalogues shaped like the
+# workloads: clustered periodic boxes with many cells, log bins reaching small
+# separations, and open survey shells (bounding box, ceil cell counts,
+# clamping at the upper bound, wrap-free reach), weighted, for every kind of
+# bins and both lines of sight.
+# ---------------------------------------------------------------------------
+def _grid_vs_brute(x1, x2=None, cells=(None,), **kw):
+    ob, obw = oracle.count(x1, x2, method="brute", **kw)
+    for cell in cells:
+        og, ogw = oracle.count(x1, x2, method="grid", cell=cell, **kw)
+        assert np.array_equal(og, ob), (cell, int(og.sum()), int(ob.sum()))
+        if obw is not None:
+            assert np.array_equal(ogw, obw), cell
+    return ob
+
+
+@pytest.mark.parametrize("weighted", [False, True])
+def test_grid_equals_brute_c2_shape(weighted):
+    """C2 shape: lognormal box L = 2000, (s, mu) 40 x 100 to s = 200, line of
+    sight z; 12,000 points, cells of r/2 (default), r/3 and r/5."""
+    n = 12000
+    x = synth.lognormal_box(n, 2000.0, synth.config_seed(2), ngrid=64)
+    w = synth.uniform_weights(n, 0.5, 1.5, 3) if weighted else None
+    ob = _grid_vs_brute(x, kind="smu", edges1=synth.linear_edges(0, 200, 40), edges2=synth.mu_edges(100),
+                        box=2000.0, w1=w, cells=(None, 200 / 3, 40.0))
+    assert ob.sum() > 10000
+
+
+def test_grid_equals_brute_c5_shape():
+    """C5 shape: lognormal box L = 3000, 50 log s bins over [0.1, 50): a grid of
+    120 cells per axis at the default cell, and the 256-per-axis clamp at a
+    cell far below L / 256."""
+    n = 20000
+    x = synth.lognormal_box(n, 3000.0, synth.config_seed(5), ngrid=64)
+    ob = _grid_vs_brute(x, kind="s", edges1=synth.log_edges(0.1, 50.0, 50), box=3000.0, cells=(None, 7.0, 1.0))
+    assert ob.sum() > 1000
+
+
+@pytest.mark.parametrize("kind,los", [("spi", "mid"), ("smu", "mid"), ("s", "z"), ("spi", "z"), ("smu", "z")])
+def test_grid_equals_brute_c3_shell(kind, los):
+    """C3 shape: open survey shell r in [1000, 2000] over a 60 x 30 degree patch,
+    data 20,000 and randoms 40,000, weights in [0.5, 2): DD, DR and RR; the
+    prune radius of (s_perp, pi) 40 x 40 over [0, 200) is 282.8."""
+    d = synth.survey_shell(20000, 31)
+    r = synth.survey_shell(40000, 32)
+    wd = synth.uniform_weights(len(d), 0.5, 2.0, 33)
+    wr = synth.uniform_weights(len(r), 0.5, 2.0, 34)
+    e = synth.linear_edges(0, 200, 40)
+    e2 = {"spi": e, "smu": synth.mu_edges(20), "s": None}[kind]
+    kw = dict(kind=kind, los=los, edges1=e, edges2=e2, box=0.0)
+    cells = (None, 90.0) if kind == "spi" and los == "mid" else (None,)
+    dd = _grid_vs_brute(d, w1=wd, cells=cells, **kw)
+    dr = _grid_vs_brute(d, r, w1=wd, w2=wr, cells=cells, **kw)
+    # DR has 4 times the pairs of DD (20k x 40k against 20k^2 / 2)
+    assert dd.sum() > 1000 and 3 * dd.sum() < dr.sum() < 5 * dd.sum()
+    if kind == "spi" and los == "mid":
+        rr = _grid_vs_brute(r, w1=wr, **kw)
+        assert 0.8 * dr.sum() < rr.sum() < 1.25 * dr.sum()  # 40k^2 / 2 pairs, as many as DR
+
+
+def test_grid_equals_brute_open_box_edges():
+    """Open boxes whose extent is not a multiple of the cell (ceil), points
+    exactly on the upper bound (clamped into the last cell), a flat catalogue
+    (zero extent on one axis) and an elongated one (many cells on one axis,
+    one on the others)."""
+    rng = np.random.default_rng(40)
+    e = np.array([0.0, 0.7, 1.5, 2.2, 3.9, 5.0])
+    a = rng.random((1500, 3)) * np.array([13.3, 7.1, 9.9])
+    a[:20] = np.array([13.3, 7.1, 9.9])  # on the upper bound of every axis
+    a[20:40, 0] = 13.3
+    _grid_vs_brute(a, kind="s", edges1=e, box=0.0, cells=(None, 1.3, 0.4))
+    _grid_vs_brute(a, kind="smu", edges1=e, edges2=synth.mu_edges(7), box=0.0, cells=(None, 1.3))
+    flat = rng.random((1200, 3)) * np.array([20.0, 20.0, 0.0]) + np.array([0.0, 0.0, 5.0])
+    _grid_vs_brute(flat, kind="spi", edges1=e, edges2=e, box=0.0, cells=(None, 0.9))
+    rod = rng.random((1500, 3)) * np.array([400.0, 2.0, 2.0])
+    b = rng.random((900, 3)) * np.array([400.0, 2.0, 2.0]) + np.array([0.0, 1.0, -1.0])
+    _grid_vs_brute(rod, b, kind="s", edges1=e, box=0.0, cells=(None, 2.0))
+
+
+@pytest.mark.parametrize("kind", ["s", "smu", "spi"])
+def test_grid_equals_brute_small_periodic_boxes(kind):
+    """Periodic boxes of only a few cells per axis, so that wrap offsets reach
+    the same cell from both sides (the de-duplicated neighbour lists), with the
+    prune radius at L/2 and clustered points."""
+    rng = np.random.default_rng(41)
+    for L, cell in ((10.0, 2.0), (10.0, 4.0), (7.0, 3.4), (12.0, 12.0)):
+        x = np.concatenate([rng.random((500, 3)) * L, (0.5 * L + rng.normal(0, 0.4, (300, 3))) % L])
+        x = np.minimum(x, np.nextafter(L, 0))
+        e = np.linspace(0.0, 0.5 * L if kind != "spi" else 0.35 * L, 6)
+        e2 = synth.mu_edges(5) if kind == "smu" else (np.linspace(0.0, 0.35 * L, 4) if kind == "spi" else None)
+        _grid_vs_brute(x, kind=kind, edges1=e, edges2=e2, box=L, cells=(None, cell))
+
+
+def _pairs_at_cell_faces(rmax, side, nside, deltas, rng, periodic_L=0.0, lo=0.0):
+    """Pairs (a_i, b_i) at distance rmax (1 - delta) with b_i just past a cell
+    face in every axis that the direction crosses, so the cell list's gap to
+    b_i's cell is within a hair of the pair's distance: a prune limit tighter
+    than rmax by more than delta drops the pair."""
+    dirs = [np.array(v, float) for v in ((1, 0, 0), (0, -1, 0), (0, 0, 1), (1, 1, 0), (0, -1, 1), (1, 1, 1),
+                                         (-1, 1, -1), (1, -1, 1))]
+    A, B = [], []
+    for dv in dirs:
+        u = dv / np.linalg.norm(dv)
+        for dl in deltas:
+            d = rmax * (1.0 - dl)
+            k = rng.integers(2, nside - 2, 3)
+            # b sits 1e-9 of a cell past the face that the direction enters from
+            b = lo + (k + np.where(u >= 0, 1e-9, 1.0 - 1e-9)) * side
+            a = b - d * u
+            if periodic_L > 0:
+                a = np.minimum(np.mod(a, periodic_L), np.nextafter(periodic_L, 0))
+            A.append(a)
+            B.append(b)
+    return np.array(A), np.array(B)
+
+
+@pytest.mark.parametrize("case", ["periodic", "open", "open-spi-mid"])
+def test_grid_keeps_pairs_just_inside_the_prune_radius(case):
+    """Constructed pairs at relative distances 1e-12 .. 1e-3 inside the prune
+    radius, each with its far point just past a cell face: the cell list keeps
+    every one (grid == brute, and the top bin holds them all)."""
+    rng = np.random.default_rng(44)
+    deltas = [1e-12, 1e-9, 1e-6, 1e-4, 1e-3]
+    if case == "periodic":
+        L, cell, rmax = 100.0, 10.0, 25.0
+        a, b = _pairs_at_cell_faces(rmax, 10.0, 10, deltas, rng, periodic_L=L)
+        kw = dict(kind="s", edges1=np.array([0.0, 20.0, rmax]), box=L)
+    elif case == "open":
+        cell, rmax = 10.0, 25.0
+        a, b = _pairs_at_cell_faces(rmax, 10.0, 12, deltas, rng, lo=0.0)
+        anchors = np.array([[-40.0, -40.0, -40.0], [160.0, 160.0, 160.0]])  # box [-40, 160]^3: side 10
+        a = np.concatenate([a, anchors])
+        kw = dict(kind="smu", edges1=np.array([0.0, 20.0, rmax]), edges2=synth.mu_edges(4), box=0.0)
+    else:
+        cell = 10.0
+        rmax = float(np.hypot(20.0, 15.0))
+        a, b = _pairs_at_cell_faces(rmax, 10.0, 12, deltas, rng, lo=0.0)
+        shift = np.array([1000.0, 0.0, 0.0])  # away from the observer at the origin
+        a, b = a + shift, b + shift
+        anchors = np.array([[960.0, -40.0, -40.0], [1160.0, 160.0, 160.0]])
+        a = np.concatenate([a, anchors])
+        kw = dict(kind="spi", los="mid", edges1=np.array([0.0, 10.0, 20.0]), edges2=np.array([0.0, 15.0]), box=0.0)
+    npairs = len(b)
+    ob = _grid_vs_brute(a, b, cells=(cell,), **kw)
+    if case != "open-spi-mid":
+        assert ob.reshape(len(kw["edges1"]) - 1, -1)[-1].sum() >= npairs
