@@ -87,7 +87,7 @@ typedef struct {
     int32_t cells_per_rmax;  /* k: cell side = r_prune / k, 1..8 */
     int32_t tile_points;     /* A points per wavefront tile: 64 or 128 */
     int32_t seg_cells;       /* consecutive A cells a tile may span, 1..32 (0: 32) */
-    int32_t b_chunk;         /* max B points per work item, >= 256 */
+    int32_t b_chunk;         /* max B points per work item, 256..2^19 (0: 16384) */
     int32_t hist_copies;     /* LDS histogram copies per workgroup: 1, 2 or 4 */
     int32_t order;           /* FCFC_ORDER_* */
     int32_t record_timing;   /* 1: record per-item GPU time (training data) */
@@ -97,7 +97,11 @@ typedef struct {
     int32_t shard_count;     /* 0 or 1: the whole work list; G > 1: count one of G shards */
     int32_t shard_index;     /* the shard counted, 0..G-1: ordered items i with i % G == index */
     int32_t batch_chunk;     /* batches: work items per wavefront a workgroup takes at once, 1..1024 (0: 32) */
-    int32_t reserved[3];
+    int32_t flush_log2;      /* a wavefront empties the workgroup's LDS histograms into the outputs
+                                once it has claimed 2^flush_log2 candidate pairs since it last did,
+                                1..26 (0: 26); the bound that keeps the 32-bit LDS counters from
+                                overflowing, lowered only to exercise that merge */
+    int32_t reserved[2];
 } fcfc_tuning;
 
 /* Statistics of the last count on a plan (host copy; see fcfc_plan_stats). */
@@ -116,6 +120,7 @@ typedef struct {
     int32_t wg_per_cu;       /* resident counting workgroups per CU */
     int32_t order_used;      /* FCFC_ORDER_* the work list actually ran in */
     int32_t group_waves;     /* wavefronts per counting workgroup */
+    int64_t flushes;         /* LDS histogram merges made before the end of the launch (flush_log2) */
 } fcfc_stats;
 
 /*
@@ -188,6 +193,25 @@ fcfc_status fcfc_count_pairs(fcfc_plan_t plan, fcfc_cells_t c1, fcfc_cells_t c2,
 fcfc_status fcfc_plan_stats(fcfc_plan_t plan, fcfc_stats *out);
 
 /*
+ * fcfc_weight_scale -- the fixed-point scale of the exact weighted sums, on
+ * the host (no GPU work).  The weighted counts add up the FP64 products of
+ * weights exactly (the product w_i*w_j for a pair; fl(fl(a*b)*c) for a
+ * triangle), as integers in units of 2^-S: every non-zero product is then an
+ * integer below 2^62 after scaling by 2^S.  wmin1/wmin2 are the smallest
+ * non-zero |w| of the two catalogues (0 if a catalogue has none), wmax1/wmax2
+ * the largest |w|; nfactors is 2 (pairs) or 3 (triangles, which use wmin1
+ * and wmax1 only).  *S receives the scale exponent.  fcfc_count_pairs,
+ * fcfc_batch_create and fcfc_count_triplets apply exactly this rule to the
+ * weights of their cell sets.
+ * Errors: FCFC_EINVAL (null S, nfactors not 2 or 3, negative or non-finite
+ * arguments); FCFC_ERANGE when the smallest product underflows (is zero or
+ * subnormal), when 2^S would overflow, or when the largest product over the
+ * smallest does not fit 2^62 / 2^53 (about 5e2 for pairs).
+ */
+fcfc_status fcfc_weight_scale(double wmin1, double wmax1, double wmin2, double wmax2, int32_t nfactors,
+                              int32_t *S);
+
+/*
  * fcfc_batch_create / fcfc_batch_run -- auto counts of many catalogues on one
  * plan in one pipeline: one cell build keyed by (catalogue, cell), one work
  * list, one persistent counting launch that writes ncat histograms
@@ -236,6 +260,14 @@ fcfc_status fcfc_batch_run(fcfc_batch_t batch, int64_t *d_counts, double *d_wcou
  * catalogue contents changed since fcfc_batch_create; counts are then invalid).
  */
 fcfc_status fcfc_batch_check(fcfc_batch_t batch, void* stream, uint32_t *n_items, float *ms);
+/*
+ * fcfc_batch_stats -- wait for `stream` and report the counting launch of the
+ * last fcfc_batch_run: out[0] candidate pairs evaluated in FP32, out[1] pairs
+ * re-evaluated in FP64, out[2] LDS histogram merges made before the end of
+ * the launch (see fcfc_tuning.flush_log2).  Errors: FCFC_EINVAL (null
+ * arguments), FCFC_EHIP.
+ */
+fcfc_status fcfc_batch_stats(fcfc_batch_t batch, void *stream, int64_t out[3]);
 void fcfc_batch_free(fcfc_batch_t batch);
 
 void fcfc_cells_free(fcfc_cells_t cells);

@@ -91,12 +91,33 @@ extern "C" fcfc_status fcfc_plan_stats(fcfc_plan_t plan, fcfc_stats* out) {
     if (hipEventElapsedTime(&ms, p->ev0, p->ev1) != hipSuccess) ms = -1;
     p->stats.candidates = (int64_t)h[0];
     p->stats.rechecks = (int64_t)h[1];
+    p->stats.flushes = (int64_t)h[6];
     int64_t tot = 0;
     for (int64_t v : cnt) tot += v;
     p->stats.in_range = tot;
     p->stats.kernel_ms = ms;
     if (p->stats.order_used == FCFC_ORDER_LEARNED && h[5] != 0) p->stats.order_used = FCFC_ORDER_HEURISTIC;
     *out = p->stats;
+    return FCFC_OK;
+}
+
+extern "C" fcfc_status fcfc_weight_scale(double wmin1, double wmax1, double wmin2, double wmax2, int32_t nfactors,
+                                         int32_t* S) {
+    clear_error();
+    if (!S || (nfactors != 2 && nfactors != 3)) {
+        set_error("weight_scale: null S or nfactors not 2 or 3");
+        return FCFC_EINVAL;
+    }
+    const double v[4] = {wmin1, wmax1, wmin2, wmax2};
+    for (double x : v) {
+        if (!(x >= 0.0) || !isfinite(x)) {
+            set_error("weight_scale: arguments must be finite and >= 0");
+            return FCFC_EINVAL;
+        }
+    }
+    int s = 0;
+    FCFC_TRY(weight_scale_rule(wmin1, wmax1, wmin2, wmax2, nfactors, &s));
+    *S = s;
     return FCFC_OK;
 }
 

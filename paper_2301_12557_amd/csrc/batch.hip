@@ -70,4 +70,13 @@ extern "C" fcfc_status fcfc_batch_check(fcfc_batch_t batch, void* stream, uint32
     return batch_check_impl((BatchImpl*)batch, (hipStream_t)stream, n_items, ms);
 }
 
+extern "C" fcfc_status fcfc_batch_stats(fcfc_batch_t batch, void* stream, int64_t out[3]) {
+    clear_error();
+    if (!batch || !out) {
+        set_error("batch_stats: null batch or output");
+        return FCFC_EINVAL;
+    }
+    return batch_stats_impl((BatchImpl*)batch, (hipStream_t)stream, out);
+}
+
 extern "C" void fcfc_batch_free(fcfc_batch_t batch) { batch_free_impl((BatchImpl*)batch); }

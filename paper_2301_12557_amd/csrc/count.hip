@@ -66,7 +66,9 @@ template <int KIND, int LOS>
 struct QStride {
     static constexpr int value = (LOS == FCFC_LOS_MIDPOINT && KIND != FCFC_BIN_S) ? 4 : 3;
 };
-constexpr uint64_t FLUSH_PAIRS = 1ull << 26;  // per wave
+// A wavefront empties the LDS histograms into the outputs after claiming
+// 2^26 candidate pairs since it last did (fcfc_tuning.flush_log2 lowers it).
+constexpr int FLUSH_LOG2_MAX = 26;
 
 struct CountArgs {
     const float4* posA;
@@ -88,7 +90,7 @@ struct CountArgs {
     const double* E2;
     unsigned long long* out_counts;
     unsigned long long* out_w;  // 2 per bin: low, high 64 bits of a signed 128-bit sum
-    unsigned long long* stats;  // [0] candidates [1] rechecks [2] in range
+    unsigned long long* stats;  // [0] candidates [1] rechecks [5] bad prediction [6] early merges
     uint32_t* times;            // per item duration (wall clock ticks) or null
     int nlut1, nlut2;
     float scale1, scale2, vmax1, vmax2;
@@ -101,6 +103,7 @@ struct CountArgs {
     int mu_top_closed;
     double wscale;
     int copies;
+    unsigned long long flush_pairs;     // a wave merges after claiming this many pairs
     uint32_t shard_count, shard_index;  // this launch takes items shard_index, + shard_count, ...
     // batched mode: chunks of items per output histogram (one per catalogue pair)
     const uint32_t* nchunks_dev;
@@ -552,11 +555,15 @@ __global__ __launch_bounds__(CT_MAX) void k_count(const CountArgs* argp) {
     };
 
     unsigned long long wave_pairs = 0;  // pairs claimed since this wave last emptied the histogram
+    unsigned long long nflush = 0;      // merges made by this wave before the end
+    const unsigned long long flush_pairs = a.flush_pairs;
     uint32_t out_off = 0;               // first bin of the current catalogue in the outputs
     // u32 overflow guard of the LDS histogram: every wave empties it (atomic
-    // exchange) after claiming 2^26 pairs, so it never holds 16 * (2^26 + item)
-    // < 2^31 increments
+    // exchange) after claiming flush_pairs <= 2^26 pairs, so it never holds
+    // more than 16 (2^26 + 128 x 2^19) = 2^31 increments (items hold at most
+    // 128 x b_chunk pairs, b_chunk <= 2^19)
     auto exchange_out = [&]() __attribute__((always_inline)) {
+        nflush++;
         for (int b = lane; b < k.nbins * k.copies; b += 64) {
             uint32_t v = atomicExch(&s.hist[b], 0u);
             if (v) atomicAdd(&a.out_counts[out_off + b % k.nbins], (unsigned long long)v);
@@ -643,7 +650,7 @@ __global__ __launch_bounds__(CT_MAX) void k_count(const CountArgs* argp) {
         const uint64_t pairs = (uint64_t)acnt * (uint64_t)(b_end - b_begin);
         ncand += pairs;
         wave_pairs += pairs;
-        if (wave_pairs >= FLUSH_PAIRS) {
+        if (wave_pairs >= flush_pairs) {
             wave_pairs = 0;
             exchange_out();
         }
@@ -822,6 +829,7 @@ __global__ __launch_bounds__(CT_MAX) void k_count(const CountArgs* argp) {
     if (lane == 0 && a.stats) {
         atomicAdd(&a.stats[0], ncand);
         atomicAdd(&a.stats[1], c.nrechk);
+        if (nflush) atomicAdd(&a.stats[6], nflush);
     }
 }
 
@@ -911,19 +919,7 @@ struct LaunchSetup {
 
 // Common fixed-point scale 2^S making every weight product an integer.
 static fcfc_status weight_scale(double wmin1, double wmax1, double wmin2, double wmax2, int* S) {
-    *S = 0;
-    if (wmin1 > 0 && wmin2 > 0) {
-        double pmin = wmin1 * wmin2;
-        int e;
-        frexp(pmin, &e);
-        *S = 53 - e;
-        double pmax = wmax1 * wmax2;
-        if (!(ldexp(pmax, *S) < ldexp(1.0, 62))) {
-            set_error("weight dynamic range too wide for exact accumulation (max/min pair weight %.3g)", pmax / pmin);
-            return FCFC_ERANGE;
-        }
-    }
-    return FCFC_OK;
+    return weight_scale_rule(wmin1, wmax1, wmin2, wmax2, 2, S);
 }
 
 // Most cells a tile may span, unless tuned: 32, so that tiles are cut by
@@ -1090,6 +1086,8 @@ static fcfc_status setup_launch(Plan* p, bool is_auto, bool weighted, bool batch
     a.mu_top_closed = 1;
     a.wscale = ldexp(1.0, S);
     a.ncat = 1;
+    a.flush_pairs = 1ull << (p->tune.flush_log2 >= 1 && p->tune.flush_log2 <= FLUSH_LOG2_MAX ? p->tune.flush_log2
+                                                                                              : FLUSH_LOG2_MAX);
     a.shard_count = (p->tune.shard_count >= 1) ? (uint32_t)p->tune.shard_count : 1u;
     a.shard_index = (p->tune.shard_count >= 1) ? (uint32_t)p->tune.shard_index : 0u;
     FCFC_HIP(hipFuncSetAttribute((const void*)L.kern, hipFuncAttributeMaxDynamicSharedMemorySize, a.lds_bytes));
@@ -1260,6 +1258,7 @@ fcfc_status count_pairs(Plan* p, Cells* c1, Cells* c2, int64_t* d_counts, double
         set_error("count_pairs: cannot allocate %zu bytes of scratch", s1);
         return FCFC_ENOMEM;
     }
+    auto release = [&](char* ptr) { dev_free(ptr, st); };
     char* q = scr;
     char* tab = q;
     q += s_tab;
@@ -1328,8 +1327,8 @@ fcfc_status count_pairs(Plan* p, Cells* c1, Cells* c2, int64_t* d_counts, double
             FCFC_HIP(hipMemcpyAsync(tk, dsum, 16, hipMemcpyDeviceToHost, st));
         }
         FCFC_HIP(hipStreamSynchronize(st));
-        dev_free(scr2, st);
-        dev_free(scr, st);
+        release(scr2);
+        release(scr);
         int khz = 0;
         if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, 0) != hipSuccess || khz <= 0) khz = 100000;
         pr->items = nitems;
@@ -1337,12 +1336,14 @@ fcfc_status count_pairs(Plan* p, Cells* c1, Cells* c2, int64_t* d_counts, double
         pr->pred_ms = std::max(tk[0] / ((double)nblk * L.waves), tk[1]) / (double)khz;
         return FCFC_OK;
     }
+    // launch statistics: the plan's buffer and events, made by its first count
     if (!p->stats_dev) {
         FCFC_HIP(hipMalloc(&p->stats_dev, 64));
         FCFC_HIP(hipEventCreate(&p->ev0));
         FCFC_HIP(hipEventCreate(&p->ev1));
     }
-    fill_u64((uint64_t*)p->stats_dev, 0ull, 8, st);
+    const bool keep_stats = p->stats_dev != nullptr;
+    if (keep_stats) fill_u64((uint64_t*)p->stats_dev, 0ull, 8, st);
     if (sorted && nitems > 1) {
         uint32_t* k0 = (uint32_t*)(scr2 + 2 * s_items);
         uint32_t* v0 = (uint32_t*)(scr2 + 2 * s_items + s_sort);
@@ -1353,7 +1354,8 @@ fcfc_status count_pairs(Plan* p, Cells* c1, Cells* c2, int64_t* d_counts, double
             // learned order: longest predicted first; any non-finite prediction
             // sends the whole list back to the heuristic key (flag in stats[5])
             model_item_costs(model, items, nitems, kcells, pred + nitems, pred, st);
-            unsigned long long* bad = (unsigned long long*)p->stats_dev + 5;
+            // (ctr[8..9] were zeroed with the other counters)
+            unsigned long long* bad = keep_stats ? (unsigned long long*)p->stats_dev + 5 : (unsigned long long*)&ctr[8];
             hipLaunchKernelGGL(k_pred_check, dim3(std::min<uint32_t>((nitems + 255) / 256, 1024)), dim3(256), 0, st,
                                pred, nitems, bad);
             hipLaunchKernelGGL(k_pred_keys, dim3((nitems + 255) / 256), dim3(256), 0, st, items, pred, bad, nitems, k0,
@@ -1385,19 +1387,19 @@ fcfc_status count_pairs(Plan* p, Cells* c1, Cells* c2, int64_t* d_counts, double
     a.cursor = &ctr[2];
     a.out_counts = (unsigned long long*)d_counts;
     a.out_w = weighted ? wacc : nullptr;
-    a.stats = (unsigned long long*)p->stats_dev;
+    a.stats = keep_stats ? (unsigned long long*)p->stats_dev : nullptr;
     a.times = times;
 
     int occ = 1;
     const int nblk = grid_blocks(L, nitems, &occ);
-    FCFC_HIP(hipEventRecord(p->ev0, st));
+    if (keep_stats) FCFC_HIP(hipEventRecord(p->ev0, st));
     p->host_args.resize(sizeof(CountArgs));
     memcpy(p->host_args.data(), &a, sizeof(CountArgs));
     FCFC_HIP(hipMemcpyAsync(args_dev, p->host_args.data(), sizeof(CountArgs), hipMemcpyHostToDevice, st));
     hipLaunchKernelGGL(L.kern, dim3((unsigned)nblk), dim3(L.waves * 64), (size_t)a.lds_bytes, st,
                        (const CountArgs*)args_dev);
     FCFC_HIP(hipGetLastError());
-    FCFC_HIP(hipEventRecord(p->ev1, st));
+    if (keep_stats) FCFC_HIP(hipEventRecord(p->ev1, st));
     if (weighted)
         hipLaunchKernelGGL(k_finalize_w, dim3((p->nbins + 255) / 256), dim3(256), 0, st, wacc, p->nbins, S, d_wcounts);
     if (times) {
@@ -1413,10 +1415,10 @@ fcfc_status count_pairs(Plan* p, Cells* c1, Cells* c2, int64_t* d_counts, double
             p->timing_n = nitems;
         }
     }
-    dev_free(scr2, st);
-    dev_free(scr, st);
+    release(scr2);
+    release(scr);
     p->last_stream = st;
-    p->have_stats = true;
+    p->have_stats = keep_stats;
     p->stats.items = nitems;
     p->stats.cells = g.ncell();
     p->stats.grid[0] = g.nx;
@@ -1488,6 +1490,7 @@ struct BatchImpl {
     Tile* tiles = nullptr;
     Item* items = nullptr;
     uint32_t* ctr = nullptr;  // [0] ntiles [1] nitems [2] cursor [3] nchunks [4] chunk cursor [5] overflow
+    unsigned long long* kstats = nullptr;  // counting launch: [0] candidates [1] rechecks [6] early merges
     // pair_items: npairs + 1 item offsets; pair_order: pairs by decreasing estimated cost
     uint32_t *pair_items = nullptr, *pair_order = nullptr, *chunk_prefix = nullptr;
     unsigned long long* counts = nullptr;
@@ -1585,6 +1588,7 @@ static void batch_enqueue_back(BatchImpl* b, hipStream_t st) {
                        b->L.a.chunk_items, b->chunk_prefix, &b->ctr[3]);
     fill_u64((uint64_t*)b->counts, 0ull, (int64_t)b->npairs * p->nbins, st);
     if (b->weighted) fill_u64((uint64_t*)b->wacc, 0ull, 2 * (int64_t)b->npairs * p->nbins, st);
+    fill_u64((uint64_t*)b->kstats, 0ull, 8, st);
     hipLaunchKernelGGL(b->L.kern, dim3((unsigned)b->nblk), dim3(b->L.waves * 64), (size_t)b->L.a.lds_bytes, st,
                        (const CountArgs*)b->args_dev);
     if (b->weighted)
@@ -1702,6 +1706,7 @@ fcfc_status batch_create_impl(Plan* p, const fcfc_catalog* cats, int ncat, const
     BA(b->scan_scr, std::max(scan_scratch_bytes(b->nseg), scan_scratch_bytes(b->npair_tr)));
     BA(b->tiles, sizeof(Tile) * (size_t)b->wl.tiles_cap);
     BA(b->ctr, 256);
+    BA(b->kstats, 64);
     BA(b->pairs, 8 * (size_t)npairs);
     BA(b->ptile_off, 4 * (size_t)(npairs + 1));
     BA(b->ptile_first, 4 * (size_t)npairs);
@@ -1799,7 +1804,7 @@ fcfc_status batch_create_impl(Plan* p, const fcfc_catalog* cats, int ncat, const
     a.cursor = &b->ctr[2];
     a.out_counts = b->counts;
     a.out_w = b->weighted ? b->wacc : nullptr;
-    a.stats = nullptr;
+    a.stats = b->kstats;
     a.times = nullptr;
     a.wscale = ldexp(1.0, b->S);
     a.nchunks_dev = &b->ctr[3];
@@ -1864,6 +1869,16 @@ fcfc_status batch_check_impl(BatchImpl* b, hipStream_t st, uint32_t* nitems, flo
         set_error("batch: the work list outgrew the capacity sized at creation (catalogue contents changed)");
         return FCFC_ERANGE;
     }
+    return FCFC_OK;
+}
+
+fcfc_status batch_stats_impl(BatchImpl* b, hipStream_t st, int64_t out[3]) {
+    unsigned long long h[8];
+    FCFC_HIP(hipMemcpyAsync(h, b->kstats, 64, hipMemcpyDeviceToHost, st));
+    FCFC_HIP(hipStreamSynchronize(st));
+    out[0] = (int64_t)h[0];
+    out[1] = (int64_t)h[1];
+    out[2] = (int64_t)h[6];
     return FCFC_OK;
 }
 

@@ -168,6 +168,13 @@ int stencil_rows(const Plan* p, bool half, std::vector<int4>& rows);
 // edges alone (no grid); built on first use and kept by the plan.
 fcfc_status plan_bin_table(Plan* p, const Lut1D** out);  // (dy, dz, kx, float bits of the x reach)
 
+// Fixed-point scale 2^S of the exact weighted sums (plan.cpp): every non-zero
+// product of nfactors (2: pairs, 3: triangles) weights is an integer below
+// 2^62 once multiplied by 2^S.  wmin*: smallest non-zero |w| (0: none),
+// wmax*: largest |w|.  FCFC_ERANGE when the smallest product underflows, 2^S
+// overflows or the range is too wide.
+fcfc_status weight_scale_rule(double wmin1, double wmax1, double wmin2, double wmax2, int nfactors, int* S);
+
 // build (build.hip)
 fcfc_status build_cells(Plan* p, const fcfc_catalog* cat, hipStream_t st, Cells** out);
 fcfc_status fit_bounds(Plan* p, const fcfc_catalog* cats, int ncat, hipStream_t st);
@@ -231,6 +238,7 @@ fcfc_status batch_create_impl(Plan* p, const fcfc_catalog* cats, int ncat, const
                               hipStream_t st, BatchImpl** out);
 fcfc_status batch_run_impl(BatchImpl* b, int64_t* d_counts, double* d_wcounts, bool use_graph, hipStream_t st);
 fcfc_status batch_check_impl(BatchImpl* b, hipStream_t st, uint32_t* nitems, float* ms);
+fcfc_status batch_stats_impl(BatchImpl* b, hipStream_t st, int64_t out[3]);
 void batch_free_impl(BatchImpl* b);
 
 int device_cu_count();

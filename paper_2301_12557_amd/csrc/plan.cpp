@@ -1,6 +1,7 @@
 // plan.cpp -- host-side planning: validation of bins, squared edges, the
 // grid, the pruned row stencil, FP32 error bands and the squared-separation
 // look-up tables.
+#include <float.h>
 #include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
@@ -411,6 +412,21 @@ extern "C" fcfc_status fcfc_plan_create(int32_t kind, int32_t los, const double*
     if (kind != FCFC_BIN_S) p->e2.assign(edges2, edges2 + n2 + 1);
     p->L = box_L;
     if (tune) p->tune = *tune;
+    // Work items hold at most 128 A points x b_chunk B points, and a wavefront
+    // empties the LDS histograms after claiming 2^flush_log2 <= 2^26 pairs, so
+    // the up to 16 wavefronts of a workgroup add at most
+    // 16 (2^26 + 2^7 2^19) = 2^31 increments to a 32-bit LDS counter between
+    // two merges.
+    if (p->tune.b_chunk != 0 && (p->tune.b_chunk < 256 || p->tune.b_chunk > (1 << 19))) {
+        delete p;
+        set_error("plan_create: b_chunk must be 0 or lie in [256, 2^19]");
+        return FCFC_EINVAL;
+    }
+    if (p->tune.flush_log2 < 0 || p->tune.flush_log2 > 26) {
+        delete p;
+        set_error("plan_create: flush_log2 must lie in [0, 26]");
+        return FCFC_EINVAL;
+    }
     if (p->tune.shard_count < 0 || (p->tune.shard_count > 1 &&
                                     (p->tune.shard_index < 0 || p->tune.shard_index >= p->tune.shard_count))) {
         delete p;
@@ -450,6 +466,47 @@ extern "C" fcfc_status fcfc_plan_create(int32_t kind, int32_t los, const double*
         p->grid_set = true;
     }
     *out = (fcfc_plan_t)p;
+    return FCFC_OK;
+}
+
+fcfc_status fcfc::weight_scale_rule(double wmin1, double wmax1, double wmin2, double wmax2, int nfactors, int* S) {
+    *S = 0;
+    if (nfactors == 3) {
+        wmin2 = wmin1;
+        wmax2 = wmax1;
+    }
+    if (!(wmin1 > 0 && wmin2 > 0)) return FCFC_OK;  // every product is zero
+    // products of FP64 weights are rounded, and rounding is monotone, so the
+    // smallest and largest non-zero magnitudes are these (pairs: a b;
+    // triangles: fl(fl(a b) c))
+    const double pmin = nfactors == 3 ? (wmin1 * wmin1) * wmin1 : wmin1 * wmin2;
+    const double pmax = nfactors == 3 ? (wmax1 * wmax1) * wmax1 : wmax1 * wmax2;
+    if (!(pmax <= DBL_MAX)) {
+        set_error("weights: the largest weight product overflows FP64 (max |w| %.3g)", wmax1);
+        return FCFC_ERANGE;
+    }
+    if (!(pmin >= DBL_MIN)) {
+        // a zero or subnormal product has lost bits: no common scale makes
+        // every product an integer without rounding it
+        set_error("weights: the smallest weight product underflows FP64 (min non-zero |w| %.3g and %.3g)", wmin1,
+                  wmin2);
+        return FCFC_ERANGE;
+    }
+    // pmin = f 2^e with f in [0.5, 1): every product >= pmin is a multiple of
+    // ulp(pmin) = 2^(e - 53), so it becomes an integer once scaled by 2^(53 - e)
+    int e = 0;
+    frexp(pmin, &e);
+    const int s = 53 - e;
+    if (s > 1023) {
+        set_error("weights: products near %.3g need a scale 2^%d beyond FP64", pmin, s);
+        return FCFC_ERANGE;
+    }
+    if (!(ldexp(pmax, s) < ldexp(1.0, 62))) {
+        set_error("weights: dynamic range too wide for exact accumulation (max/min weight product %.3g)",
+                  pmax / pmin);
+        return FCFC_ERANGE;
+    }
+    *S = s;
     return FCFC_OK;
 }
 

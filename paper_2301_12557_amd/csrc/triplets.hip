@@ -482,17 +482,7 @@ extern "C" fcfc_status fcfc_count_triplets(fcfc_plan_t plan, fcfc_cells_t cells,
     // every product fl(fl(a b) c) is a multiple of 2^-S; its magnitude lies
     // between those of the smallest and the largest non-zero weights cubed
     int S = 0;
-    if (weighted && c->wmin > 0) {
-        const double pmin = (c->wmin * c->wmin) * c->wmin, pmax = (c->wmax * c->wmax) * c->wmax;
-        int ex;
-        frexp(pmin, &ex);
-        S = 53 - ex;
-        if (!(ldexp(pmax, S) < ldexp(1.0, 62))) {
-            set_error("count_triplets: weight dynamic range too wide for exact sums (max/min weight %.3g)",
-                      c->wmax / c->wmin);
-            return FCFC_ERANGE;
-        }
-    }
+    if (weighted) FCFC_TRY(weight_scale_rule(c->wmin, c->wmax, c->wmin, c->wmax, 3, &S));
     hipStream_t st = (hipStream_t)stream;
     const Lut1D* Tp = nullptr;
     FCFC_TRY(plan_bin_table(p, &Tp));

@@ -39,7 +39,8 @@ class Tuning(ctypes.Structure):
                 ("record_timing", ctypes.c_int32), ("n_hint", ctypes.c_int32),
                 ("lut_log2", ctypes.c_int32), ("group_waves", ctypes.c_int32),
                 ("shard_count", ctypes.c_int32), ("shard_index", ctypes.c_int32),
-                ("batch_chunk", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+                ("batch_chunk", ctypes.c_int32), ("flush_log2", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2)]
 
 
 class Stats(ctypes.Structure):
@@ -48,7 +49,8 @@ class Stats(ctypes.Structure):
                 ("cells_per_rmax", ctypes.c_int32), ("cell_side", ctypes.c_double),
                 ("kernel_ms", ctypes.c_double), ("band_d2_rel", ctypes.c_double),
                 ("lut_entries", ctypes.c_int32), ("wg_per_cu", ctypes.c_int32),
-                ("order_used", ctypes.c_int32), ("group_waves", ctypes.c_int32)]
+                ("order_used", ctypes.c_int32), ("group_waves", ctypes.c_int32),
+                ("flushes", ctypes.c_int64)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_}
@@ -69,10 +71,12 @@ SIGNATURES = [
     ("fcfc_build_cells", _I32, [_P, ctypes.POINTER(Catalog), _P, ctypes.POINTER(_P)]),
     ("fcfc_count_pairs", _I32, [_P, _P, _P, _P, _P, _P]),
     ("fcfc_plan_stats", _I32, [_P, ctypes.POINTER(Stats)]),
+    ("fcfc_weight_scale", _I32, [_D, _D, _D, _D, _I32, ctypes.POINTER(_I32)]),
     ("fcfc_batch_create", _I32, [_P, ctypes.POINTER(Catalog), _I32, _P, ctypes.POINTER(_P)]),
     ("fcfc_batch_create_pairs", _I32, [_P, ctypes.POINTER(Catalog), _I32, _P, _I32, _P, ctypes.POINTER(_P)]),
     ("fcfc_batch_run", _I32, [_P, _P, _P, _I32, _P]),
     ("fcfc_batch_check", _I32, [_P, _P, ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_float)]),
+    ("fcfc_batch_stats", _I32, [_P, _P, ctypes.POINTER(_I64)]),
     ("fcfc_batch_free", None, [_P]),
     ("fcfc_cells_free", None, [_P]),
     ("fcfc_plan_free", None, [_P]),
@@ -165,6 +169,18 @@ def _out_tensor(t, n, dtype, name):
             and t.numel() == n):
         raise ValueError(f"{name} must be a contiguous CUDA {dtype} tensor with {n} elements")
     return t
+
+
+def weight_scale(wmin1, wmax1, wmin2=None, wmax2=None, nfactors=2):
+    """Fixed-point scale exponent S of the exact weighted sums for weights whose
+    smallest non-zero and largest magnitudes are given (fcfc_weight_scale);
+    raises FcfcError (FCFC_ERANGE) for weights the exact sums cannot hold."""
+    if wmin2 is None:
+        wmin2, wmax2 = wmin1, wmax1
+    S = ctypes.c_int32()
+    check(load().fcfc_weight_scale(float(wmin1), float(wmax1), float(wmin2), float(wmax2), int(nfactors),
+                                   ctypes.byref(S)))
+    return S.value
 
 
 def make_tuning(**kw):
@@ -385,6 +401,13 @@ class Batch:
         check(load().fcfc_batch_check(self.h, _stream_ptr(stream), ctypes.byref(n), ctypes.byref(ms)))
         return n.value, ms.value
 
+    def stats(self, stream=None):
+        """Wait, then return the counting launch of the last run: candidates, rechecks and
+        early LDS merges (flushes)."""
+        v = (ctypes.c_int64 * 3)()
+        check(load().fcfc_batch_stats(self.h, _stream_ptr(stream), v))
+        return {"candidates": v[0], "rechecks": v[1], "flushes": v[2]}
+
     def close(self):
         if getattr(self, "h", None):
             load().fcfc_batch_free(self.h)
@@ -581,7 +604,8 @@ def wp(xi_spi, pi_edges, stream=None):
 
 
 TUNING_KEYS = ("cells_per_rmax", "tile_points", "seg_cells", "b_chunk", "hist_copies", "order",
-               "record_timing", "n_hint", "lut_log2", "group_waves", "shard_count", "shard_index", "batch_chunk")
+               "record_timing", "n_hint", "lut_log2", "group_waves", "shard_count", "shard_index", "batch_chunk",
+               "flush_log2")
 
 
 def autotune(x1, x2=None, *, model=None, kind="s", edges1, edges2=None, los="z", box=0.0, w1=None, w2=None,

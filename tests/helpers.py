@@ -54,9 +54,7 @@ def assert_same(g, o, gw=None, ow=None, what=""):
 
 
 def check_case(name, x1, x2=None, *, method="brute", cell=None, **kw):
-    tuning = {k: kw.pop(k) for k in list(kw) if k in ("cells_per_rmax", "tile_points", "seg_cells", "b_chunk",
-                                                     "hist_copies", "order", "lut_log2", "record_timing", "group_waves",
-                                                     "shard_count", "shard_index", "batch_chunk")}
+    tuning = {k: kw.pop(k) for k in list(kw) if k in fcfc.TUNING_KEYS}
     note(f"{name}: n1={len(x1)} n2={None if x2 is None else len(x2)} kind={kw.get('kind')} "
          f"los={kw.get('los', 'z')} box={kw.get('box', 0.0)} w={kw.get('w1') is not None} tuning={tuning}")
     g, gw, st = gpu_count(x1, x2, **kw, **tuning)

@@ -289,3 +289,81 @@ def test_bin_and_triplet_arguments_rejected_on_the_host():
     assert lib.fcfc_count_triplets(p, fake, fake, None, None) == -5
     assert b"32" in lib.fcfc_last_error()
     lib.fcfc_plan_free(p)
+
+
+def test_plan_rejects_bad_chunk_and_flush():
+    """b_chunk bounds the pairs of one work item and flush_log2 the pairs a
+    wavefront claims between two merges of the 32-bit LDS counters; values that
+    could overflow them are refused."""
+    for chunk, rc in ((0, 0), (256, 0), (1 << 19, 0), (255, -1), ((1 << 19) + 1, -1), (-5, -1)):
+        t = fcfc.Tuning()
+        t.b_chunk = chunk
+        assert _create(tune=t) == rc, chunk
+    for fl, rc in ((0, 0), (1, 0), (26, 0), (27, -1), (-1, -1)):
+        t = fcfc.Tuning()
+        t.flush_log2 = fl
+        assert _create(tune=t) == rc, fl
+
+
+def _oracle_refuses(w1, w2):
+    """The oracle's answer for a weighted cross count of two points with these weights."""
+    import oracle
+    x = np.array([[1.0, 1.0, 1.0]])
+    y = np.array([[1.5, 1.0, 1.0]])
+    try:
+        oracle.count(x, y, kind="s", edges1=[0.0, 1.0], w1=np.array([w1]), w2=np.array([w2]))
+    except oracle.OracleError:
+        return True
+    return False
+
+
+@pytest.mark.parametrize("wmin,wmax,ok", [
+    (1e-200, 1.0, False),      # the smallest product 1e-400 underflows to zero
+    (1e-160, 1e-160, False),   # the smallest product 1e-320 is subnormal
+    (1e-150, 1e-150, False),   # 1e-300 is normal but needs a scale 2^1049 beyond FP64
+    (0.5, 2.0, True),
+    (0.5, 1.5, True),
+    (1e-100, 1e-100, True),
+    (1.0, 1e3, False),         # max/min product 1e6: beyond 2^62 / 2^53
+])
+def test_weight_scale_refuses_underflowing_products(wmin, wmax, ok):
+    """The exact weighted sums need every pair product w_i*w_j to be an FP64
+    multiple of one power of two that fits: products that underflow (zero or
+    subnormal), a scale 2^S beyond FP64, or a range too wide are FCFC_ERANGE,
+    and the oracle refuses the same weights."""
+    if ok:
+        S = fcfc.weight_scale(wmin, wmax)
+        p = wmin * wmin
+        assert 2.0 ** 52 <= p * 2.0 ** S < 2.0 ** 53
+        assert wmax * wmax * 2.0 ** S < 2.0 ** 62
+    else:
+        with pytest.raises(fcfc.FcfcError) as ei:
+            fcfc.weight_scale(wmin, wmax)
+        assert ei.value.name == "FCFC_ERANGE"
+    if wmax / wmin < 100:
+        assert _oracle_refuses(wmin, wmin) == (not ok)
+
+
+def test_weight_scale_cross_and_triangles():
+    """Cross counts combine the ranges of both catalogues; triangles take the
+    cube of one catalogue's range (fl(fl(a b) c))."""
+    assert fcfc.weight_scale(1e300, 2e300, 1e-300, 2e-300) >= 0
+    with pytest.raises(fcfc.FcfcError):
+        fcfc.weight_scale(1e-200, 1.0, 1e-200, 1.0)
+    assert _oracle_refuses(1e-200, 1e-200)
+    S = fcfc.weight_scale(0.5, 2.0, nfactors=3)
+    assert 2.0 ** 52 <= 0.125 * 2.0 ** S < 2.0 ** 53
+    with pytest.raises(fcfc.FcfcError) as ei:
+        fcfc.weight_scale(1e-110, 1e-110, nfactors=3)  # 1e-330: subnormal
+    assert ei.value.name == "FCFC_ERANGE"
+    with pytest.raises(fcfc.FcfcError) as ei:
+        fcfc.weight_scale(1e200, 1e200)  # the largest product overflows
+    assert ei.value.name == "FCFC_ERANGE"
+    # all-zero weights: every product is zero, nothing to scale
+    assert fcfc.weight_scale(0.0, 0.0, 0.5, 1.0) == 0
+    lib = fcfc.load()
+    S = ctypes.c_int32()
+    assert lib.fcfc_weight_scale(1.0, 1.0, 1.0, 1.0, 4, ctypes.byref(S)) == -1
+    assert lib.fcfc_weight_scale(-1.0, 1.0, 1.0, 1.0, 2, ctypes.byref(S)) == -1
+    assert lib.fcfc_weight_scale(float("nan"), 1.0, 1.0, 1.0, 2, ctypes.byref(S)) == -1
+    assert lib.fcfc_weight_scale(1.0, 1.0, 1.0, 1.0, 2, None) == -1

@@ -10,7 +10,7 @@ import numpy as np
 import pytest
 
 from paper_2301_12557_amd import synth
-from helpers import check_case, gpu_count, note, oracle_count, assert_same
+from helpers import check_case, gpu_count, note, oracle_count, assert_same, to_dev
 
 pytestmark = pytest.mark.gpu
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -297,10 +297,18 @@ def test_c3_full_size_sampled():
     assert full.sum() == st["in_range"]
     h = len(d) // 2
     note("C3 DD halves")
-    aa, _, _ = gpu_count(d[:h], **kw)
-    bb, _, _ = gpu_count(d[h:], **kw)
-    ab, _, _ = gpu_count(d[:h], d[h:], **kw)
+    aa, aw, _ = gpu_count(d[:h], w1=wd[:h], **kw)
+    bb, bw, _ = gpu_count(d[h:], w1=wd[h:], **kw)
+    ab, abw, _ = gpu_count(d[:h], d[h:], w1=wd[:h], w2=wd[h:], **kw)
     assert np.array_equal(aa + bb + ab, full)
+    # each weighted bin is its exact sum rounded once: the three parts add up to
+    # the whole within a few roundings
+    assert np.all(np.abs((aw + bw + abw) - fw) <= 4e-16 * np.abs(fw))
+    # merging the LDS histograms every 2^16 claimed pairs changes nothing
+    note("C3 DD full, early merges")
+    fm, fwm, stm = gpu_count(d, w1=wd, flush_log2=16, **kw)
+    assert stm["flushes"] > 0
+    assert np.array_equal(fm, full) and np.array_equal(fwm, fw)
     rng = np.random.default_rng(7)
     idx = rng.choice(len(d), 1000, replace=False)
     note("C3 DD sample x full data")
@@ -481,3 +489,106 @@ def test_c4_full_size_batch_sampled():
         assert_same(g, o, what=f"C4 mock {pick[i]} sample x full")
     b.close()
     plan.close()
+
+
+@pytest.mark.parametrize("wlo,whi", [(1e-200, 1.0), (1e-160, 1e-160)])
+def test_weight_products_underflow_refused(wlo, whi):
+    """Weights whose smallest pair product underflows FP64 (zero, or subnormal)
+    cannot be summed exactly: the pair count, the batched pipeline and the
+    triangle count refuse them with FCFC_ERANGE, as the oracle refuses them,
+    and the outputs are left untouched."""
+    import oracle
+    import torch
+    from paper_2301_12557_amd import fcfc
+    rng = np.random.default_rng(12)
+    x = rng.random((300, 3)) * 50.0
+    w = np.where(rng.random(300) < 0.5, wlo, whi)
+    w[0], w[1] = wlo, whi
+    e = synth.linear_edges(0, 10, 5)
+    with pytest.raises(oracle.OracleError):
+        oracle_count(x, kind="s", edges1=e, box=50.0, w1=w)
+    with pytest.raises(fcfc.FcfcError) as ei:
+        gpu_count(x, kind="s", edges1=e, box=50.0, w1=w)
+    assert ei.value.name == "FCFC_ERANGE"
+    plan = fcfc.Plan("s", e, box=50.0)
+    dx, dw = to_dev(x), to_dev(w)
+    with pytest.raises(fcfc.FcfcError) as ei:
+        fcfc.Batch(plan, [(dx, dw), (dx, dw)])
+    assert ei.value.name == "FCFC_ERANGE"
+    cells = plan.build_cells(dx, dw)
+    out = torch.full((5,), -7, dtype=torch.int64, device="cuda")
+    wout = torch.full((5,), -7.0, dtype=torch.float64, device="cuda")
+    with pytest.raises(fcfc.FcfcError) as ei:
+        plan.count(cells, weighted=True, out=out, wout=wout)
+    assert ei.value.name == "FCFC_ERANGE"
+    assert int(out.sum()) == -35 and float(wout.sum()) == -35.0
+    with pytest.raises(fcfc.FcfcError) as ei:
+        fcfc.count_triplets(dx, edges=e, box=50.0, w=dw)
+    assert ei.value.name == "FCFC_ERANGE"
+    cells.close()
+    plan.close()
+
+
+# ---------------------------------------------------------------------------
+# Full-size histograms against the oracle's cell list, bin for bin: the
+# benchmark's own counts (definitions of Sect. 2.5, each unordered pair once
+# as in Sect. 3.1).  The cell list is pinned to the brute-force loop on the
+# same shapes by the CPU tests.
+# ---------------------------------------------------------------------------
+def test_c2_full_size_weighted_vs_oracle():
+    """C2, the headline count, in full: all 1,000,000 clustered points, weighted
+    (s, mu) 40 x 100, line of sight z, periodic L = 2000.  Counts and exact
+    weighted sums equal the oracle's in every bin."""
+    w = synth.workload(2, weighted=True)
+    kw = dict(kind="smu", edges1=w["edges1"], edges2=w["edges2"], box=w["box"], w1=w["w1"])
+    note("C2 full weighted, GPU")
+    g, gw, st = gpu_count(w["x1"], **kw)
+    note(f"C2 full weighted, oracle ({st['in_range']} pairs)")
+    o, ow = oracle_count(w["x1"], method="grid", **kw)
+    assert_same(g, o, gw, ow, what="C2 full weighted")
+    assert np.array_equal(gw, ow)
+
+
+def test_c5_full_size_vs_oracle():
+    """C5 in full, as the benchmark draws it on the GPU: 10,000,000 clustered
+    points, periodic L = 3000, 50 log s bins over [0.1, 50) (hybrid table)."""
+    import torch
+    x = synth.lognormal_box_torch(10_000_000, 3000.0, synth.config_seed(5), device="cuda")
+    e1 = synth.log_edges(0.1, 50.0, 50)
+    note("C5 full, GPU")
+    from paper_2301_12557_amd import fcfc
+    c, _, st = fcfc.count_pairs(x, kind="s", edges1=e1, box=3000.0, return_stats=True)
+    torch.cuda.synchronize()
+    g = c.cpu().numpy()
+    xh = x.cpu().numpy()
+    del x
+    note(f"C5 full, oracle ({st['in_range']} pairs)")
+    o, _ = oracle_count(xh, kind="s", edges1=e1, box=3000.0, method="grid")
+    assert_same(g, o, what="C5 full")
+
+
+def test_c4_smallest_mocks_batched_vs_oracle():
+    """C4 through the batched pipeline replayed from a HIP graph, as the
+    benchmark runs it: the 20 smallest of the 200 mocks (L = 1000, (s, mu)
+    40 x 100), each histogram equal to the oracle's in every bin."""
+    import torch
+    from paper_2301_12557_amd import fcfc
+    sizes = synth.mock_sizes(200)
+    pick = [int(m) for m in np.argsort(sizes, kind="stable")[:20]]
+    e1 = synth.linear_edges(0, 200, 40)
+    e2 = synth.mu_edges(100)
+    xs = [synth.lognormal_box_torch(int(sizes[m]), 1000.0, synth.MOCK_SEED_BASE + m, device="cuda") for m in pick]
+    note(f"C4 batch of the 20 smallest mocks, {int(sizes[pick].sum())} points")
+    plan = fcfc.Plan("smu", e1, e2, box=1000.0, n_hint=int(np.median(sizes)))
+    b = fcfc.Batch(plan, [(x, None) for x in xs])
+    nb = 40 * 100
+    out = torch.empty(len(xs) * nb, dtype=torch.int64, device="cuda")
+    for _ in range(2):
+        b.run(out, use_graph=True)
+        b.check()
+    got = out.cpu().numpy().reshape(len(xs), 40, 100)
+    b.close()
+    plan.close()
+    for i, x in enumerate(xs):
+        o, _ = oracle_count(x.cpu().numpy(), kind="smu", edges1=e1, edges2=e2, box=1000.0, method="grid")
+        assert_same(got[i], o, what=f"C4 mock {pick[i]}")
