@@ -188,6 +188,32 @@ fcfc_status fcfc_build_cells(fcfc_plan_t plan, const fcfc_catalog *cat, void *st
 fcfc_status fcfc_count_pairs(fcfc_plan_t plan, fcfc_cells_t c1, fcfc_cells_t c2,
                              int64_t *d_counts, double *d_wcounts, void *stream);
 
+/*
+ * fcfc_count_pairs_noalloc -- fcfc_count_pairs for callers that cannot
+ * allocate device memory (code under stream capture, tight serving loops,
+ * harnesses that forbid hipMalloc): the same counts, bit for bit, with every
+ * scratch buffer of the count (work list, counters, sort space, kernel
+ * arguments, exact weighted accumulators) carved out of one library-owned
+ * device array of fcfc_noalloc_scratch_bytes() bytes (64 MiB) per device,
+ * which each device keeps until the process ends.  The caller still passes
+ * the cell sets and the outputs; no hipMalloc, hipFree or allocating routine
+ * is called.  Every call on a device shares that device's array and leaves
+ * it holding its own contents (what must start at zero is cleared on the
+ * stream first), so calls that overlap in time on one device race: serialise
+ * them (one stream, or events).  Synchronises `stream` once to size the work
+ * list, as fcfc_count_pairs does.  Per-item timings (record_timing) are not
+ * recorded.  fcfc_plan_stats reports this count only on a plan that has
+ * already run an allocating count (which made its statistics buffer);
+ * otherwise it returns FCFC_ESTATE.
+ * Errors: as fcfc_count_pairs, plus FCFC_ERANGE when the count's scratch
+ * (about 100 bytes per work item plus the tables, tiles and row counts)
+ * exceeds the array; the outputs are then untouched.
+ */
+fcfc_status fcfc_count_pairs_noalloc(fcfc_plan_t plan, fcfc_cells_t c1, fcfc_cells_t c2,
+                                     int64_t *d_counts, double *d_wcounts, void *stream);
+/* Bytes of the per-device scratch array of fcfc_count_pairs_noalloc. */
+int64_t fcfc_noalloc_scratch_bytes(void);
+
 /* Statistics of the last fcfc_count_pairs on this plan (synchronises the
  * stream that count ran on).  Errors: FCFC_EINVAL, FCFC_ESTATE. */
 fcfc_status fcfc_plan_stats(fcfc_plan_t plan, fcfc_stats *out);

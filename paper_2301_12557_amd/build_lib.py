@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUTDIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(OUTDIR, "libfcfc.so")
 SOURCES = ["plan.cpp", "api.cpp", "mem.cpp", "build.hip", "worklist.hip", "count.hip", "batch.hip", "mlp.hip", "tune.cpp",
-           "diag.hip", "estimators.hip", "angular.hip", "binning.hip", "triplets.hip"]
+           "diag.hip", "estimators.hip", "angular.hip", "binning.hip", "triplets.hip", "noalloc.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

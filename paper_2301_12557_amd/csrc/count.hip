@@ -1214,7 +1214,7 @@ __global__ void k_pred_keys(const Item* __restrict__ items, const float* __restr
 // single count
 // ---------------------------------------------------------------------------
 fcfc_status count_pairs(Plan* p, Cells* c1, Cells* c2, int64_t* d_counts, double* d_wcounts, hipStream_t st,
-                        PredictReq* pr) {
+                        PredictReq* pr, const Workspace* ws) {
     const bool is_auto = (c2 == nullptr);
     Cells* cb = is_auto ? c1 : c2;
     const bool weighted = d_wcounts != nullptr;
@@ -1254,11 +1254,21 @@ fcfc_status count_pairs(Plan* p, Cells* c1, Cells* c2, int64_t* d_counts, double
     size_t s_acc = weighted ? al256((size_t)p->nbins * 16) : 0;
     size_t s1 = s_tab + 2 * s_tc + s_tiles + 2 * s_ic + s_scan + s_ctr + s_args + s_acc;
     char* scr = nullptr;
-    if (dev_alloc((void**)&scr, s1, st) != FCFC_OK) {
+    if (ws) {
+        // the caller's workspace: nothing is allocated
+        if (s1 > ws->bytes) {
+            set_error("count_pairs: %zu bytes of scratch needed before the work list, the workspace holds %zu", s1,
+                      ws->bytes);
+            return FCFC_ERANGE;
+        }
+        scr = ws->base;
+    } else if (dev_alloc((void**)&scr, s1, st) != FCFC_OK) {
         set_error("count_pairs: cannot allocate %zu bytes of scratch", s1);
         return FCFC_ENOMEM;
     }
-    auto release = [&](char* ptr) { dev_free(ptr, st); };
+    auto release = [&](char* ptr) {
+        if (!ws) dev_free(ptr, st);
+    };
     char* q = scr;
     char* tab = q;
     q += s_tab;
@@ -1298,11 +1308,19 @@ fcfc_status count_pairs(Plan* p, Cells* c1, Cells* c2, int64_t* d_counts, double
     size_t s_items = al256((size_t)std::max<uint32_t>(nitems, 1) * sizeof(Item));
     size_t s_sort = sorted ? al256((size_t)std::max<uint32_t>(nitems, 1) * 4) : 0;
     size_t s_rs = sorted ? al256(radix_scratch_bytes(nitems)) : 0;
-    size_t s_times = (p->tune.record_timing && !pr) ? al256((size_t)std::max<uint32_t>(nitems, 1) * 4) : 0;
+    size_t s_times = (p->tune.record_timing && !pr && !ws) ? al256((size_t)std::max<uint32_t>(nitems, 1) * 4) : 0;
     size_t s_pred = model ? al256((size_t)std::max<uint32_t>(nitems, 1) * 20) : 0;
     size_t s2 = 2 * s_items + 4 * s_sort + s_rs + s_times + s_pred;
     char* scr2 = nullptr;
-    if (dev_alloc((void**)&scr2, s2, st) != FCFC_OK) {
+    if (ws) {
+        // s1 is a sum of 256-byte multiples, so the second part stays aligned
+        if (s1 + s2 > ws->bytes) {
+            set_error("count_pairs: %u work items need %zu bytes of scratch, the workspace holds %zu", nitems, s1 + s2,
+                      ws->bytes);
+            return FCFC_ERANGE;
+        }
+        scr2 = ws->base + s1;
+    } else if (dev_alloc((void**)&scr2, s2, st) != FCFC_OK) {
         dev_free(scr, st);
         set_error("count_pairs: cannot allocate %zu bytes for %u work items", s2, nitems);
         return FCFC_ENOMEM;
@@ -1336,8 +1354,9 @@ fcfc_status count_pairs(Plan* p, Cells* c1, Cells* c2, int64_t* d_counts, double
         pr->pred_ms = std::max(tk[0] / ((double)nblk * L.waves), tk[1]) / (double)khz;
         return FCFC_OK;
     }
-    // launch statistics: the plan's buffer and events, made by its first count
-    if (!p->stats_dev) {
+    // launch statistics: the plan's buffer and events, made by the first
+    // allocating count (a count into a workspace keeps none without them)
+    if (!p->stats_dev && !ws) {
         FCFC_HIP(hipMalloc(&p->stats_dev, 64));
         FCFC_HIP(hipEventCreate(&p->ev0));
         FCFC_HIP(hipEventCreate(&p->ev1));

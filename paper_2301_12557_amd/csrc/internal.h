@@ -229,8 +229,17 @@ struct PredictReq {
     double pred_ms = 0;
     int64_t items = 0;
 };
+// Caller-provided device scratch for a count that must not allocate: every
+// scratch buffer of the count is carved out of [base, base + bytes)
+// (256-byte aligned); FCFC_ERANGE when it does not fit.  Per-item timings
+// are then not recorded, and launch statistics are kept only in a plan whose
+// statistics buffer an earlier allocating count has already made.
+struct Workspace {
+    char* base = nullptr;
+    size_t bytes = 0;
+};
 fcfc_status count_pairs(Plan* p, Cells* c1, Cells* c2, int64_t* d_counts, double* d_wcounts,
-                        hipStream_t st, PredictReq* pr = nullptr);
+                        hipStream_t st, PredictReq* pr = nullptr, const Workspace* ws = nullptr);
 
 struct BatchImpl;
 // pairs: 2 * npairs catalogue indices (A, B), A == B for an auto count

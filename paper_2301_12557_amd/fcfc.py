@@ -70,6 +70,8 @@ SIGNATURES = [
     ("fcfc_plan_set_bounds", _I32, [_P, _P, _P]),
     ("fcfc_build_cells", _I32, [_P, ctypes.POINTER(Catalog), _P, ctypes.POINTER(_P)]),
     ("fcfc_count_pairs", _I32, [_P, _P, _P, _P, _P, _P]),
+    ("fcfc_count_pairs_noalloc", _I32, [_P, _P, _P, _P, _P, _P]),
+    ("fcfc_noalloc_scratch_bytes", _I64, []),
     ("fcfc_plan_stats", _I32, [_P, ctypes.POINTER(Stats)]),
     ("fcfc_weight_scale", _I32, [_D, _D, _D, _D, _I32, ctypes.POINTER(_I32)]),
     ("fcfc_batch_create", _I32, [_P, ctypes.POINTER(Catalog), _I32, _P, ctypes.POINTER(_P)]),
