@@ -101,9 +101,11 @@ struct CountArgs {
     float r2prune, d2small;
     float mu_n, tolA, tolB, tolC;
     int mu_top_closed;
-    double wscale;
+    double wscale;  // 2^(S - 32): pair weight -> the high limb of the exact sum's fixed point
     int copies;
     unsigned long long flush_pairs;     // a wave merges after claiming this many pairs
+    uint32_t grab_single;               // single claims below this list position
+    unsigned long long grab_gap;        // then claims of up to 8 positions at least this many ticks apart
     uint32_t shard_count, shard_index;  // this launch takes items shard_index, + shard_count, ...
     // batched mode: chunks of items per output histogram (one per catalogue pair)
     const uint32_t* nchunks_dev;
@@ -129,9 +131,9 @@ struct Smem {
     const float* band1;
     const float* band2;
     uint32_t* hist;
-    unsigned long long* wlo;
-    unsigned long long* whi;
+    unsigned long long* wl;  // exact weighted limbs, [bin][2]: low 32 bits, high part (signed)
     float* qf;        // this wave's compaction queue (entries of QStride floats)
+    const float* qf_lane;  // qf + lane * QStride: this lane's entry when binning from entry 0
     uint32_t* rb;     // this wave's recheck entries (a, b, item)
     float4* astage;   // this wave's A points in absolute FP32 (mid-point line of sight)
     unsigned long long* misc;
@@ -261,17 +263,23 @@ __device__ inline int lut_hot_bin(const float* __restrict__ band, int n, int e, 
 // Kernel constants kept in registers.
 struct KConst {
     float scale1, scale2, vmax1, vmax2, r2prune, d2small, mu_n, mu_nm1, tolA, tolB, tolC, side32;
+    float tolC_v;  // tolC held in a vector register (an fma takes one scalar operand)
     int n1, n2, nbins, nx, copies;
     double wscale;
 };
 
-// q: the pair weight times 2^S, an integer below 2^62 in magnitude
-__device__ inline void add_weight(const Smem& s, int flat, double q) {
-    long long t = (long long)q;
-    unsigned long long lo = (unsigned long long)(uint32_t)(t & 0xffffffffll);
-    unsigned long long hi = (unsigned long long)(t >> 32);
-    atomicAdd(&s.wlo[flat], lo);
-    atomicAdd(&s.whi[flat], hi);
+// t: the pair weight times 2^(S - 32), where the weight times 2^S is an
+// integer q below 2^62 in magnitude.  The limbs of q are hi = floor(t), the
+// floor of q / 2^32, and lo = (t - hi) 2^32 in [0, 2^32), so q = hi 2^32 + lo;
+// every step is exact in FP64 (t has at most 30 integer bits and its
+// fraction holds the 32 low bits of q).
+__device__ inline void add_weight(const Smem& s, int flat, double t) {
+    const double hi = floor(t);
+    const uint32_t lo = (uint32_t)((t - hi) * 4294967296.0);
+    const int hi32 = (int)hi;
+    unsigned long long* wb = s.wl + 2 * flat;
+    atomicAdd(wb, (unsigned long long)lo);
+    atomicAdd(wb + 1, (unsigned long long)(long long)hi32);
 }
 
 // Re-evaluate `cnt` queued pairs (entries base .. base+cnt-1) in FP64.
@@ -304,6 +312,16 @@ __device__ inline void wave_sync_lds() {
     __builtin_amdgcn_wave_barrier();
 }
 
+// Third word of a raw buffer resource on gfx9-family devices (32-bit data format).
+constexpr int BUFFER_RSRC_WORD3 = 0x00020000;
+
+// 16 bytes at byte offset voff + soff of a buffer (zeros past its end).
+__device__ inline float4 load_b(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+    typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+    const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, (int)soff, 0);
+    return make_float4(__uint_as_float(v.x), __uint_as_float(v.y), __uint_as_float(v.z), __uint_as_float(v.w));
+}
+
 __device__ inline uint32_t lane_prefix(uint64_t m) {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
@@ -316,13 +334,14 @@ struct WaveCtx {
 };
 
 // Bin `cnt` queued in-range pairs (entries base .. base+cnt-1), one per lane.
-// Entry: (v1, v2, ids) with ids = (b - b_begin) << 7 | a_slot, and
+// Entry: (v1, v2, ids) with ids = (b - b_begin) << 10 | a_slot << 3, and
 //   s:              v1 = d2
 //   (s,mu), z:      v1 = d2, v2 = dz
 //   (sp,pi), z:     v1 = sp2, v2 = pi2
 //   mid-point:      (dx, dy, dz, ids) (line of sight from the staged A point)
-// Weighted pairs take the A weight from the wave's staged weights and the B
-// weight from memory.
+// ids holds the byte offsets of the pair's weights from the item's first A
+// and B weights: a_slot * 8 = ids & 0x3f8 and (b - b_begin) * 8 = (ids >> 7)
+// with the low three bits cleared.
 // The common path is branch-free; hot table entries and rechecks take
 // wave-uniform branches that are rarely entered.
 template <int KIND, int LOS, bool W>
@@ -336,7 +355,11 @@ __device__ __attribute__((always_inline)) inline void bin_queue(ArgsRef a, const
     float4 e = make_float4(0.f, 0.f, 0.f, 0.f);
     uint32_t ids = 0;
     if (valid) {
-        const float* qe = s.qf + (size_t)(base + lane) * QS;
+        // the scalar byte offset of the first entry, kept opaque so that it is
+        // added once instead of being re-associated with negative constants
+        int boff = base * QS * 4;
+        __asm__ volatile("" : "+s"(boff));
+        const float* qe = (const float*)((const char*)s.qf_lane + boff);
         if (MIDQ) {
             e = *(const float4*)qe;
             ids = __float_as_uint(e.w);
@@ -349,11 +372,15 @@ __device__ __attribute__((always_inline)) inline void bin_queue(ArgsRef a, const
     // the weights of the pair, fetched early (product formed only for pairs in range)
     double wa = 0.0, wb = 0.0;
     if (W && valid) {
-        wb = a.wB[c.b_begin + (ids >> 7)];
-        wa = a.wA[c.a_begin + (ids & 127u)];
+        wb = *(const double*)((const char*)(a.wB + c.b_begin) + ((ids >> 7) & ~7u));
+        wa = *(const double*)((const char*)(a.wA + c.a_begin) + (ids & 0x3f8u));
     }
-    bool amb = false;
-    bool okb;  // a bin was found (flat is meaningful)
+    // Wave masks, each built from ballots of single compares (a ballot of a
+    // compare is that compare's lane mask, so no per-lane boolean is formed):
+    //   rm: pairs within an FP32 band of an edge (FP64 recheck),
+    //   um: pairs binned here (in range, not rechecked).
+    const uint64_t vmask = cnt >= 64 ? ~0ull : ((1ull << cnt) - 1ull);
+    uint64_t rm, um;
     int flat;
     if (KIND == FCFC_BIN_S) {
         const float d2 = e.x;
@@ -362,8 +389,8 @@ __device__ __attribute__((always_inline)) inline void bin_queue(ArgsRef a, const
         if (__builtin_amdgcn_ballot_w64(hot)) {
             if (hot) sb = lut_hot_bin(s.band1, k.n1, sb, d2);
         }
-        amb = sb == -2;
-        okb = sb >= 0;
+        rm = __builtin_amdgcn_ballot_w64(sb == -2) & vmask;
+        um = __builtin_amdgcn_ballot_w64(sb >= 0) & vmask;
         flat = sb;
     } else if (KIND == FCFC_BIN_S_MU) {
         float d2, proj_n;  // proj_n: |projection on the line of sight| * n_mu / |l|
@@ -373,7 +400,7 @@ __device__ __attribute__((always_inline)) inline void bin_queue(ArgsRef a, const
         } else {
             const float dxx = e.x, dyy = e.y, dzz = e.z;
             d2 = __builtin_fmaf(dzz, dzz, __builtin_fmaf(dyy, dyy, dxx * dxx));
-            const float4 q = s.astage[ids & 127u];
+            const float4 q = *(const float4*)((const char*)s.astage + ((ids & 0x3f8u) << 1));
             const float lx = q.x + dxx, ly = q.y + dyy, lz = q.z + dzz;
             const float dot = __builtin_fmaf(dzz, lz, __builtin_fmaf(dyy, ly, dxx * lx));
             const float ll = __builtin_fmaf(lz, lz, __builtin_fmaf(ly, ly, lx * lx));
@@ -387,12 +414,14 @@ __device__ __attribute__((always_inline)) inline void bin_queue(ArgsRef a, const
         const float rs = __builtin_amdgcn_rsqf(d2);
         const float mun = proj_n * rs;
         const int mb = min((int)mun, k.n2 - 1);
-        const float cr = rintf(mun);
-        const float dist = fabsf(mun - cr);
-        const float tol = __builtin_fmaf(__builtin_fmaf(k.tolB, rs, k.tolA), rs, k.tolC);
-        const bool near_edge = (dist < tol) & (cr >= 1.0f) & (cr <= k.mu_nm1);
-        amb = (sb == -2) | near_edge | (d2 < k.d2small);
-        okb = sb >= 0;
+        // distance to the nearest interior mu edge (edges 0 and n need no
+        // recheck: mu >= 0 always, and mu = 1 belongs to the last bin)
+        const float cr = __builtin_amdgcn_fmed3f(rintf(mun), 1.0f, k.mu_nm1);
+        const float tol = __builtin_fmaf(k.tolA, rs, k.tolC_v);
+        rm = (__builtin_amdgcn_ballot_w64(sb == -2) | __builtin_amdgcn_ballot_w64(fabsf(mun - cr) < tol) |
+              __builtin_amdgcn_ballot_w64(d2 < k.d2small)) &
+             vmask;
+        um = __builtin_amdgcn_ballot_w64(sb >= 0) & vmask & ~rm;
         flat = (int)__umul24((uint32_t)sb, (uint32_t)k.n2) + mb;
     } else {
         float sp2, pi2;
@@ -402,7 +431,7 @@ __device__ __attribute__((always_inline)) inline void bin_queue(ArgsRef a, const
         } else {
             const float dxx = e.x, dyy = e.y, dzz = e.z;
             const float d2 = __builtin_fmaf(dzz, dzz, __builtin_fmaf(dyy, dyy, dxx * dxx));
-            const float4 q = s.astage[ids & 127u];
+            const float4 q = *(const float4*)((const char*)s.astage + ((ids & 0x3f8u) << 1));
             const float lx = q.x + dxx, ly = q.y + dyy, lz = q.z + dzz;
             const float dot = __builtin_fmaf(dzz, lz, __builtin_fmaf(dyy, ly, dxx * lx));
             const float ll = __builtin_fmaf(lz, lz, __builtin_fmaf(ly, ly, lx * lx));
@@ -410,7 +439,9 @@ __device__ __attribute__((always_inline)) inline void bin_queue(ArgsRef a, const
             sp2 = fmaxf(d2 - pi2, 0.0f);
         }
         // beyond a table's top band end the pair is certainly out of range
-        const bool inr = (sp2 < k.vmax1) & (pi2 < k.vmax2);
+        const uint64_t inm =
+            __builtin_amdgcn_ballot_w64(sp2 < k.vmax1) & __builtin_amdgcn_ballot_w64(pi2 < k.vmax2) & vmask;
+        const bool inr = __builtin_amdgcn_inverse_ballot_w64(inm);
         const float sp2c = inr ? sp2 : 0.0f;
         const float pi2c = inr ? pi2 : 0.0f;
         int b1 = lut_entry(s.lut1, k.scale1, sp2c);
@@ -420,26 +451,25 @@ __device__ __attribute__((always_inline)) inline void bin_queue(ArgsRef a, const
             if (hot1) b1 = lut_hot_bin(s.band1, k.n1, b1, sp2c);
             if (hot2) b2 = lut_hot_bin(s.band2, k.n2, b2, pi2c);
         }
-        amb = ((b1 == -2) | (b2 == -2)) & inr;
-        okb = inr & (b1 >= 0) & (b2 >= 0);
+        rm = (__builtin_amdgcn_ballot_w64(b1 == -2) | __builtin_amdgcn_ballot_w64(b2 == -2)) & inm;
+        um = __builtin_amdgcn_ballot_w64(b1 >= 0) & __builtin_amdgcn_ballot_w64(b2 >= 0) & inm & ~rm;
         flat = (int)__umul24((uint32_t)b1, (uint32_t)k.n2) + b2;
     }
-    amb = amb & valid;
-    const uint64_t m = __builtin_amdgcn_ballot_w64(amb);
-    if (valid & okb & !amb) {
+    if (__builtin_amdgcn_inverse_ballot_w64(um)) {
         atomicAdd(&hist_l[flat], 1u);
         if (W) {
-            // fl(wa * wb) * 2^S is exact: the scale only moves the exponent, and
-            // the host chose S so that the largest scaled product stays below 2^62
+            // fl(wa * wb) * 2^(S - 32) is exact: the scale only moves the exponent, and
+            // the host chose S so that every scaled product lies in [2^20, 2^30)
             add_weight(s, flat, (wa * wb) * k.wscale);
         }
     }
+    const uint64_t m = rm;
     if (m) {
         const int pos = c.rcount + (int)lane_prefix(m);
-        if ((m >> lane) & 1ull) {
+        if (__builtin_amdgcn_inverse_ballot_w64(m)) {
             uint32_t* r = s.rb + (size_t)pos * 3;
-            r[0] = c.a_begin + (ids & 127u);
-            r[1] = c.b_begin + (ids >> 7);
+            r[0] = c.a_begin + ((ids >> 3) & 127u);
+            r[1] = c.b_begin + (ids >> 10);
             r[2] = c.it;
         }
         c.rcount += (int)__popcll(m);
@@ -467,10 +497,10 @@ __global__ __launch_bounds__(CT_MAX) void k_count(const CountArgs* argp) {
     s.band1 = (const float*)(smem + a.off_band1);
     s.band2 = (const float*)(smem + a.off_band2);
     s.hist = (uint32_t*)(smem + a.off_hist);
-    s.wlo = (unsigned long long*)(smem + a.off_whist);
-    s.whi = s.wlo + a.nbins;
+    s.wl = (unsigned long long*)(smem + a.off_whist);
     constexpr int QS = QStride<KIND, LOS>::value;
     s.qf = (float*)(smem + a.off_q) + (size_t)wave * (QCAP + 1) * QS;
+    s.qf_lane = s.qf + lane * QS;
     s.rb = (uint32_t*)(smem + a.off_rb) + (size_t)wave * RB_CAP * 3;
     s.astage = (float4*)(smem + a.off_astage) + (size_t)wave * ASTAGE;
     s.misc = (unsigned long long*)(smem + a.off_misc);
@@ -493,7 +523,7 @@ __global__ __launch_bounds__(CT_MAX) void k_count(const CountArgs* argp) {
         }
         for (int i = tid; i < a.nbins * a.copies; i += nthr) s.hist[i] = 0u;
         if (W)
-            for (int i = tid; i < 2 * a.nbins; i += nthr) s.wlo[i] = 0ull;
+            for (int i = tid; i < 2 * a.nbins; i += nthr) s.wl[i] = 0ull;
         if (tid < 4) s.misc[tid] = 0ull;
     }
     __syncthreads();
@@ -507,9 +537,12 @@ __global__ __launch_bounds__(CT_MAX) void k_count(const CountArgs* argp) {
     k.d2small = a.d2small;
     k.mu_n = a.mu_n;
     k.mu_nm1 = a.mu_n - 1.0f;
-    k.tolA = a.tolA;
+    // one mu bin has no interior edge: nothing is near one
+    k.tolA = a.n2 > 1 ? a.tolA : 0.0f;
     k.tolB = a.tolB;
-    k.tolC = a.tolC;
+    k.tolC = a.n2 > 1 ? a.tolC : 0.0f;
+    k.tolC_v = k.tolC;
+    __asm__ volatile("" : "+v"(k.tolC_v));
     k.side32 = a.side32;
     k.n1 = a.n1;
     k.n2 = a.n2;
@@ -570,8 +603,8 @@ __global__ __launch_bounds__(CT_MAX) void k_count(const CountArgs* argp) {
         }
         if (W) {
             for (int b = lane; b < k.nbins; b += 64) {
-                unsigned long long lo = atomicExch(&s.wlo[b], 0ull);
-                unsigned long long hi = atomicExch(&s.whi[b], 0ull);
+                unsigned long long lo = atomicExch(&s.wl[2 * b], 0ull);
+                unsigned long long hi = atomicExch(&s.wl[2 * b + 1], 0ull);
                 __int128 v = ((__int128)(long long)hi << 32) + (__int128)lo;
                 unsigned long long vlo = (unsigned long long)v;
                 unsigned long long vhi = (unsigned long long)(v >> 64);
@@ -591,9 +624,9 @@ __global__ __launch_bounds__(CT_MAX) void k_count(const CountArgs* argp) {
             }
             if (cnt) atomicAdd(&a.out_counts[out_off + b], (unsigned long long)cnt);
             if (W) {
-                unsigned long long lo = s.wlo[b], hi = s.whi[b];
-                s.wlo[b] = 0ull;
-                s.whi[b] = 0ull;
+                unsigned long long lo = s.wl[2 * b], hi = s.wl[2 * b + 1];
+                s.wl[2 * b] = 0ull;
+                s.wl[2 * b + 1] = 0ull;
                 if (lo | hi) {
                     __int128 v = ((__int128)(long long)hi << 32) + (__int128)lo;
                     unsigned long long vlo = (unsigned long long)v;
@@ -647,6 +680,7 @@ __global__ __launch_bounds__(CT_MAX) void k_count(const CountArgs* argp) {
         c.a_begin = a_begin;
         c.b_begin = b_begin;
         c.it = it;
+
         const uint64_t pairs = (uint64_t)acnt * (uint64_t)(b_end - b_begin);
         ncand += pairs;
         wave_pairs += pairs;
@@ -663,7 +697,7 @@ __global__ __launch_bounds__(CT_MAX) void k_count(const CountArgs* argp) {
         for (int p = 0; p < P; p++) {
             const uint32_t i = (uint32_t)(lane + 64 * p);
             aidx[p] = a_begin + i;
-            ids_lane[p] = i;
+            ids_lane[p] = i << 3;
             const float4 v = cur.av[p];
             ax[p] = v.x;
             ay[p] = v.y - Dy;
@@ -679,57 +713,88 @@ __global__ __launch_bounds__(CT_MAX) void k_count(const CountArgs* argp) {
         int xw = xb0 - sxi * a.nx;
         int t = 0;
         uint32_t j = b_begin;
-        while (j < b_end && xw < a.nx) {
-            uint32_t cell_end = (t + 1 < 64) ? __builtin_amdgcn_readlane(cur.csv, t + 1)
-                                             : ldc_u32(a.csB, item.b_rowcell + (uint32_t)xw + 1u);
-            cell_end = cell_end < b_end ? cell_end : b_end;
-            if (cell_end > j) {
-                float axx[P];
+        // The current B cell: points up to cell_end, A x positions relative to it.
+        uint32_t cell_end = 0;
+        float axx[P];
+        // Advance to the next cell of the row piece that holds points at or after
+        // j (cells are consecutive in the sorted points); false when none is left.
+        auto next_cell = [&]() __attribute__((always_inline)) -> bool {
+            while (xw < a.nx) {
+                uint32_t ce = (t + 1 < 64) ? __builtin_amdgcn_readlane(cur.csv, t + 1)
+                                           : ldc_u32(a.csB, item.b_rowcell + (uint32_t)xw + 1u);
+                ce = ce < b_end ? ce : b_end;
+                const int xc = xu;
+                xw++;
+                xu++;
+                t++;
+                if (ce > j) {
+                    cell_end = ce;
 #pragma unroll
-                for (int p = 0; p < P; p++) axx[p] = ax[p] - (float)(xu - acx[p]) * k.side32;
-                auto cell_loop = [&](auto mask_tag) __attribute__((always_inline)) {
-                    constexpr bool MASK = decltype(mask_tag)::value;
-                    // running scalar pointer to the next B point and its queue id bits
-                    const float FCFC_CONST* bp = (const float FCFC_CONST*)a.posB + 4 * (size_t)j;
-                    uint32_t jbits = (j - b_begin) << 7;
-                    float3 nb = make_float3(bp[0], bp[1], bp[2]);
-                    for (; j < cell_end; j++, jbits += 128u) {
-                        const float3 b = nb;
-                        // prefetch the next B point (arrays carry padding past the last point)
-                        bp += 4;
-                        nb = make_float3(bp[0], bp[1], bp[2]);
+                    for (int p = 0; p < P; p++) axx[p] = ax[p] - (float)(xc - acx[p]) * k.side32;
+                    return true;
+                }
+            }
+            return false;
+        };
+        bool have = j < b_end && next_cell();
+        // B points arrive 64 at a time, one per lane, by buffer loads issued a
+        // whole batch ahead, and each step takes its point from the batch with
+        // v_readlane.  (Fetching one point per step left every step waiting on
+        // a load issued only a step or two before.)  Even batches live in bx,
+        // odd ones in by, and each register set is reloaded in place once it is
+        // used up, so no batch is copied.  The buffer covers the item's B range;
+        // offsets past it read zeros.
+        const __amdgpu_buffer_rsrc_t rB = __builtin_amdgcn_make_buffer_rsrc(
+            (void*)(a.posB + b_begin), (short)0, (int)((b_end - b_begin) * 16u), BUFFER_RSRC_WORD3);
+        const uint32_t lane16 = (uint32_t)lane * 16u;
+        float4 bx = load_b(rB, lane16, 0u);
+        float4 by = load_b(rB, lane16, 1024u);
+        uint32_t bstart = b_begin;  // first point of the batch being counted
+        // Count the points of the batch in `buf` (from j to the batch's end).
+        auto run_batch = [&](const float4& buf, auto mask_tag) __attribute__((always_inline)) {
+            constexpr bool MASK = decltype(mask_tag)::value;
+            const uint32_t bend = min(bstart + 64u, b_end);
+            while (have && j < bend) {
+                const uint32_t stop = min(cell_end, bend);
+                uint32_t jbits = (j - b_begin) << 10;
+                for (; j < stop; j++, jbits += 1024u) {
+                    const int tl = (int)(j - bstart);  // the lane holding point j
+                    const float3 b = make_float3(__int_as_float(__builtin_amdgcn_readlane(__float_as_int(buf.x), tl)),
+                                                 __int_as_float(__builtin_amdgcn_readlane(__float_as_int(buf.y), tl)),
+                                                 __int_as_float(__builtin_amdgcn_readlane(__float_as_int(buf.z), tl)));
 #pragma unroll
-                        for (int p = 0; p < P; p++) {
-                            const float dx = b.x - axx[p];
-                            const float dy = b.y - ay[p];
-                            const float dz = b.z - az[p];
-                            bool in;
-                            float v1, v2, v3 = 0.f;
-                            if (KIND == FCFC_BIN_SPERP_PI && LOS == FCFC_LOS_Z) {
-                                v1 = __builtin_fmaf(dy, dy, dx * dx);
-                                v2 = dz * dz;
-                                in = (v1 < k.vmax1) & (v2 < k.vmax2);
+                    for (int p = 0; p < P; p++) {
+                        const float dx = b.x - axx[p];
+                        const float dy = b.y - ay[p];
+                        const float dz = b.z - az[p];
+                        bool in;
+                        float v1, v2, v3 = 0.f;
+                        if (KIND == FCFC_BIN_SPERP_PI && LOS == FCFC_LOS_Z) {
+                            v1 = __builtin_fmaf(dy, dy, dx * dx);
+                            v2 = dz * dz;
+                            in = (v1 < k.vmax1) & (v2 < k.vmax2);
+                        } else {
+                            const float d2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
+                            in = d2 < k.r2prune;
+                            if (LOS == FCFC_LOS_MIDPOINT && KIND != FCFC_BIN_S) {
+                                v1 = dx;
+                                v2 = dy;
+                                v3 = dz;
                             } else {
-                                const float d2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
-                                in = d2 < k.r2prune;
-                                if (LOS == FCFC_LOS_MIDPOINT && KIND != FCFC_BIN_S) {
-                                    v1 = dx;
-                                    v2 = dy;
-                                    v3 = dz;
-                                } else {
-                                    v1 = d2;
-                                    v2 = dz;
-                                }
+                                v1 = d2;
+                                v2 = dz;
                             }
-                            if (MASK) in = in & (j > aidx[p]);
-                            const uint64_t m = __builtin_amdgcn_ballot_w64(in);
-                            // queue position of every lane (qn + lanes below in the mask);
-                            // lanes out of range write the dump entry QCAP
-                            const uint32_t pre = __builtin_amdgcn_mbcnt_hi(
-                                (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, (uint32_t)qn));
-                            const uint32_t slot = in ? pre : (uint32_t)QCAP;
+                        }
+                        if (MASK) in = in & (j > aidx[p]);
+                        const uint64_t m = __builtin_amdgcn_ballot_w64(in);
+                        // lanes in range append at qn + (lanes below in the mask);
+                        // the others store nothing
+                        float* qb = s.qf + qn * QS;
+                        if (in) {
+                            const uint32_t pre = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                                           __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
                             const float idf = __uint_as_float(jbits | ids_lane[p]);
-                            float* qe = s.qf + (size_t)slot * QS;
+                            float* qe = qb + pre * QS;
                             if (QS == 4) {
                                 *(float4*)qe = make_float4(v1, v2, v3, idf);
                             } else {
@@ -737,26 +802,35 @@ __global__ __launch_bounds__(CT_MAX) void k_count(const CountArgs* argp) {
                                 qe[1] = v2;
                                 qe[2] = idf;
                             }
-                            qn += (int)__popcll(m);
                         }
-                        while (qn >= 64) {
-                            wave_sync_lds();
-                            bin_queue<KIND, LOS, W>(a, k, s, hist_l, qn - 64, 64, lane, c);
-                            wave_sync_lds();
-                            qn -= 64;
-                        }
+                        qn += (int)__popcll(m);
                     }
-                };
-                if (samerow)
-                    cell_loop(std::integral_constant<bool, true>());
-                else
-                    cell_loop(std::integral_constant<bool, false>());
-                j = cell_end;
+                    while (qn >= 64) {
+                        wave_sync_lds();
+                        bin_queue<KIND, LOS, W>(a, k, s, hist_l, qn - 64, 64, lane, c);
+                        wave_sync_lds();
+                        qn -= 64;
+                    }
+                }
+                if (j == cell_end) have = next_cell();
             }
-            xw++;
-            xu++;
-            t++;
-        }
+        };
+        auto run_item = [&](auto mask_tag) __attribute__((always_inline)) {
+            for (;;) {
+                run_batch(bx, mask_tag);
+                if (!have || j >= b_end) break;
+                bstart += 64u;
+                bx = load_b(rB, lane16, (bstart + 64u - b_begin) * 16u);
+                run_batch(by, mask_tag);
+                if (!have || j >= b_end) break;
+                bstart += 64u;
+                by = load_b(rB, lane16, (bstart + 64u - b_begin) * 16u);
+            }
+        };
+        if (samerow)
+            run_item(std::integral_constant<bool, true>());
+        else
+            run_item(std::integral_constant<bool, false>());
         if (qn > 0) {
             wave_sync_lds();
             bin_queue<KIND, LOS, W>(a, k, s, hist_l, 0, qn, lane, c);
@@ -772,10 +846,36 @@ __global__ __launch_bounds__(CT_MAX) void k_count(const CountArgs* argp) {
     if (!BATCH) {
         const uint32_t nitems = __builtin_amdgcn_readfirstlane(*a.nitems_dev);
         const uint32_t sc = a.shard_count, si = a.shard_index;
+        // Every wave of the device claims work on one cursor; at one claim per
+        // item those atomics serialise (about 12 ns each on MI355X) into the
+        // bound of a launch of short items.  Past the first grab_single positions
+        // (the largest items of the longest-first list, claimed one at a time so
+        // that they spread over the waves) a wave claims as many positions (up
+        // to 8) as keep its claims grab_gap wall-clock ticks apart, judged by
+        // the time its last claim took to count.
+        const uint32_t gsingle = a.grab_single;
+        const uint64_t ggap = a.grab_gap;
+        uint32_t chunk_pos = 0, chunk_left = 0, claimed = 0;
+        uint64_t t_claim = 0;
         process_items([&]() -> uint32_t {
-            uint32_t v = 0;
-            if (lane == 0) v = atomicAdd(a.cursor, 1u);
-            v = __builtin_amdgcn_readfirstlane(v);
+            if (chunk_left == 0) {
+                uint32_t want = 1u;
+                if (chunk_pos >= gsingle) {
+                    const uint64_t now = wall_clock64();
+                    if (claimed > 0) {
+                        const uint64_t per = (now - t_claim) / claimed;
+                        want = per == 0 ? 8u : (uint32_t)min<uint64_t>(8u, max<uint64_t>(1u, (ggap + per - 1) / per));
+                    }
+                    t_claim = now;
+                }
+                uint32_t v = 0;
+                if (lane == 0) v = atomicAdd(a.cursor, want);
+                chunk_pos = __builtin_amdgcn_readfirstlane(v);
+                chunk_left = want;
+                claimed = want;
+            }
+            const uint32_t v = chunk_pos++;
+            chunk_left--;
             // one shard of the ordered list: items si, si + sc, si + 2 sc, ...
             const uint64_t idx = (uint64_t)v * sc + si;
             return idx < nitems ? (uint32_t)idx : ~0u;
@@ -1084,7 +1184,7 @@ static fcfc_status setup_launch(Plan* p, bool is_auto, bool weighted, bool batch
     a.tolB = p->mu_tolB;
     a.tolC = p->mu_tolC;
     a.mu_top_closed = 1;
-    a.wscale = ldexp(1.0, S);
+    a.wscale = ldexp(1.0, S - 32);
     a.ncat = 1;
     a.flush_pairs = 1ull << (p->tune.flush_log2 >= 1 && p->tune.flush_log2 <= FLUSH_LOG2_MAX ? p->tune.flush_log2
                                                                                               : FLUSH_LOG2_MAX);
@@ -1131,6 +1231,23 @@ static WLArgs make_wl(const Plan* p, const LaunchSetup& L, bool is_auto, int nca
     w.tiles_cap = (uint32_t)std::min<int64_t>(nrow * ((g.nx + L.seg - 1) / L.seg + 1) + npoints_a / L.T + 1,
                                               0xffffffffLL);
     return w;
+}
+
+// Claims on the work cursor: the first four rounds of positions (one per
+// wave each) one at a time; after that each wave spaces its claims so that
+// all waves together make at most one claim per 24 ns, about half of what
+// one cursor sustains (measured on MI355X: C5 5.4 -> 4.4 ms once claims were
+// grouped; grouping the largest items as well slowed counts of few items,
+// and grouping large items slowed C3 DR).
+static void set_grab(CountArgs& a, uint32_t nitems, int64_t waves) {
+    (void)nitems;
+    const int64_t w = std::max<int64_t>(1, waves);
+    a.grab_single = (uint32_t)std::min<int64_t>(4 * w, 0xffffffffLL);
+    int dev = 0, khz = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || khz <= 0)
+        khz = 100000;
+    a.grab_gap = (unsigned long long)((double)w * 24e-9 * (double)khz * 1e3);
 }
 
 static int grid_blocks(const LaunchSetup& L, uint32_t nitems, int* occ_out = nullptr) {
@@ -1411,6 +1528,7 @@ fcfc_status count_pairs(Plan* p, Cells* c1, Cells* c2, int64_t* d_counts, double
 
     int occ = 1;
     const int nblk = grid_blocks(L, nitems, &occ);
+    set_grab(a, nitems, (int64_t)nblk * L.waves);
     if (keep_stats) FCFC_HIP(hipEventRecord(p->ev0, st));
     p->host_args.resize(sizeof(CountArgs));
     memcpy(p->host_args.data(), &a, sizeof(CountArgs));
@@ -1825,7 +1943,7 @@ fcfc_status batch_create_impl(Plan* p, const fcfc_catalog* cats, int ncat, const
     a.out_w = b->weighted ? b->wacc : nullptr;
     a.stats = b->kstats;
     a.times = nullptr;
-    a.wscale = ldexp(1.0, b->S);
+    a.wscale = ldexp(1.0, b->S - 32);
     a.nchunks_dev = &b->ctr[3];
     a.chunk_cursor = &b->ctr[4];
     a.chunk_prefix = b->chunk_prefix;

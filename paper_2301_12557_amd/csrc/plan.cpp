@@ -316,6 +316,11 @@ fcfc_status plan_finalize_numerics(Plan* p) {
         }
         // below this separation the mu band is wide: always recheck
         p->d2small = (float)std::max(1e-30, (64.0 * e) * (64.0 * e));
+        // The kernel evaluates the band as A' rs + C with one fma: for every pair
+        // it does not recheck, d2 >= d2small, so B rs^2 <= (B / sqrt(d2small)) rs.
+        const double Aeff = ((double)p->mu_tolA + (double)p->mu_tolB / sqrt((double)p->d2small)) * (1.0 + 1e-6);
+        p->mu_tolA = f32_up(Aeff);
+        p->mu_tolB = 0.f;
     } else {
         p->d2small = 0.f;
     }
