@@ -47,6 +47,7 @@ def parse():
     ap.add_argument("--no-binning", action="store_true", help="skip the histogram-update microbenchmark")
     ap.add_argument("--binning-values", type=float, default=6.4e9, help="squared separations per binning call")
     ap.add_argument("--no-triplets", action="store_true", help="skip the triangle-count measurement")
+    ap.add_argument("--no-c3", action="store_true", help="skip the full-size C3 survey counts (DD, DR, RR)")
     ap.add_argument("--shards", type=int, default=0,
                     help="also count each of G work-list shards (one GPU's share of a G-GPU run) and report "
                          "their kernel times")
@@ -598,6 +599,84 @@ def c3_main(args, fcfc, torch):
     print(json.dumps(res), flush=True)
 
 
+def c3_section(fcfc, synth, torch, rr_shards=8):
+    """C3 at full size in the default run: the survey shell's DD, DR and RR
+    (2,000,000 data, 40,000,000 randoms, weighted (s_perp, pi) 40 x 40, mid-point
+    line of sight, open box), each counted once after one DD warm-up.  RR is
+    counted as rr_shards launches over disjoint shards of its work list (items
+    i % G == g), whose histograms sum exactly to the whole count; a progress
+    line follows each shard."""
+    w = synth.workload(3, weighted=True)
+    dev = torch.device("cuda:0")
+    d = torch.from_numpy(w["x1"]).to(dev)
+    r = torch.from_numpy(w["x2"]).to(dev)
+    wd = torch.from_numpy(w["w1"]).to(dev)
+    wr = torch.from_numpy(w["w2"]).to(dev)
+    kw = dict(los="mid", box=0.0, n_hint=len(w["x2"]))
+    plan = fcfc.Plan("spi", w["edges1"], w["edges2"], **kw)
+    plan.fit_bounds([(d, None), (r, None)])
+    builds = {}
+    cells = {}
+    for name, x, wt in (("data", d, wd), ("randoms", r, wr)):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        cells[name] = plan.build_cells(x, wt)
+        e1.record()
+        torch.cuda.synchronize()
+        builds[name] = e0.elapsed_time(e1)
+    plan.count(cells["data"], weighted=True)  # warm-up
+    out = {}
+
+    def entry(st, kernel_ms, note=None):
+        achieved = FLOP_PER_DISTANCE * st["candidates"] / (kernel_ms * 1e-3) / 1e12
+        e = {"in_range_pairs": int(st["in_range"]), "distance_evaluations": int(st["candidates"]),
+             "kernel_ms": kernel_ms, "kernel_pairs_per_s": st["in_range"] / (kernel_ms * 1e-3),
+             "candidates_per_pair": st["candidates"] / max(st["in_range"], 1),
+             "rechecks": int(st["rechecks"]), "recheck_rate": st["rechecks"] / max(st["candidates"], 1),
+             "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                          "frac": achieved / PEAK_FP32_TFLOPS}}
+        if note:
+            e["note"] = note
+        return e
+
+    plan.count(cells["data"], weighted=True)
+    out["DD"] = entry(plan.stats(), plan.stats()["kernel_ms"])
+    log(f"C3 DD: {out['DD']['kernel_ms']:.1f} ms")
+    plan.count(cells["data"], cells["randoms"], weighted=True)
+    st = plan.stats()
+    out["DR"] = entry(st, st["kernel_ms"])
+    log(f"C3 DR: {out['DR']['kernel_ms']:.0f} ms; RR in {rr_shards} shards next "
+        f"(about {10 * out['DR']['kernel_ms'] / 1e3:.0f} s)")
+    plan.close()
+    tot = {"in_range": 0, "candidates": 0, "rechecks": 0}
+    kms = 0.0
+    hist = None
+    for g in range(rr_shards):
+        ps = fcfc.Plan("spi", w["edges1"], w["edges2"], shard_count=rr_shards, shard_index=g, **kw)
+        ps.fit_bounds([(d, None), (r, None)])
+        cr = ps.build_cells(r, wr)
+        c, wc = ps.count(cr, weighted=True)
+        sg = ps.stats()
+        hist = c.clone() if hist is None else hist + c
+        for k in tot:
+            tot[k] += int(sg[k])
+        kms += sg["kernel_ms"]
+        cr.close()
+        ps.close()
+        log(f"C3 RR shard {g + 1}/{rr_shards}: {sg['kernel_ms']:.0f} ms")
+    tot["in_range"] = int(hist.sum())
+    out["RR"] = entry(tot, kms, note=f"{rr_shards} launches over disjoint shards of the work list; "
+                                     "kernel_ms is their sum, the histograms sum to the whole RR count")
+    for c in cells.values():
+        c.close()
+    del d, r, wd, wr
+    torch.cuda.empty_cache()
+    return {"workload": "C3 open survey shell r in [1000,2000], RA 60 deg x Dec 30 deg, data 2,000,000 + "
+                        "randoms 40,000,000, weighted (s_perp,pi) 40x40 over [0,200), mid-point LOS",
+            "build_ms": builds, "counts": out}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -781,6 +860,11 @@ def main():
         res["triplets"] = triplets_section(fcfc, synth, torch, cpu=not args.no_cpu_baseline)
         log(f"triplets: {res['triplets']['kernel_ms']:.2f} ms, {res['triplets']['triangles']} triangles, "
             f"{res['triplets']['roofline']['frac']:.3f} of FP64 peak")
+    if not args.no_c3:
+        from paper_2301_12557_amd import synth
+        res["c3"] = c3_section(fcfc, synth, torch)
+        log("C3: " + " ".join(f"{k} {v['kernel_ms']:.0f} ms ({v['roofline']['frac']:.3f})"
+                              for k, v in res["c3"]["counts"].items()))
     if not args.no_cpu_baseline:
         log("timing the CPU oracle")
         res["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)

@@ -483,8 +483,16 @@ __device__ __attribute__((always_inline)) inline void bin_queue(ArgsRef a, const
     }
 }
 
+// Unweighted counts along a fixed axis run two 12-wave workgroups per CU, six
+// waves per SIMD, which leaves each lane 80 VGPRs (512 per SIMD, allocated 8 at
+// a time): one register more drops a wave from every SIMD (on MI355X the
+// batched 200-mock pipeline ran 156 ms per 50 mocks at 79 VGPRs, 199 ms at 81).
+// Weighted and mid-point counts are held to 16 waves per CU by their LDS
+// tables and queues, so they keep the registers (capping the mid-point ones
+// at 80 only added spills).
 template <int KIND, int LOS, bool AUTO, bool W, int P, bool BATCH>
-__global__ __launch_bounds__(CT_MAX) void k_count(const CountArgs* argp) {
+__global__ __launch_bounds__(CT_MAX) __attribute__((amdgpu_waves_per_eu((W || LOS) ? 4 : 6))) void k_count(
+    const CountArgs* argp) {
     ArgsRef a = *(const CountArgs FCFC_CONST*)argp;
     extern __shared__ __align__(16) unsigned char smem[];
     const int tid = threadIdx.x;
