@@ -340,6 +340,56 @@ def c5_section(fcfc, synth, model):
     return res
 
 
+def clustered_section(fcfc, synth, model):
+    """Held-out catalogues far more clustered than the training boxes (Gaussian
+    blobs): the analytic cell size vs the model's pure choice vs the measured
+    search without and with the model proposing cell sizes; build + count time
+    (best of 3) of each tuning, measured afresh after the search."""
+    import torch
+    L = 500.0
+    e1 = synth.linear_edges(0, 40, 20)
+    e2 = synth.mu_edges(10)
+    out = {}
+    for name, (nblob, rad, frac, seed) in (("blobs30", (30, 15.0, 0.8, 8)), ("blobs10", (10, 5.0, 0.9, 9))):
+        x = torch.from_numpy(synth.blobs_box(300_000, L, nblob, rad, frac, seed)).to("cuda")
+
+        def measure(mdl=None, **tune):
+            tune.setdefault("n_hint", len(x))
+            plan = fcfc.Plan("smu", e1, e2, box=L, **tune)
+            if mdl is not None:
+                plan.set_model(mdl)
+            best = np.inf
+            for _ in range(3):
+                def go():
+                    c = plan.build_cells(x)
+                    plan.count(c)
+                    return c
+                ms, c = _sync_time(go)
+                c.close()
+                best = min(best, ms)
+            k = plan.stats()["cells_per_rmax"]
+            plan.close()
+            return {"ms": best, "cells_per_rmax": k}
+
+        kl, _ = fcfc.choose_cells(x, model=model, kind="smu", edges1=e1, edges2=e2, box=L)
+        t0 = fcfc.autotune(x, kind="smu", edges1=e1, edges2=e2, box=L)
+        t1 = fcfc.autotune(x, model=model, kind="smu", edges1=e1, edges2=e2, box=L)
+        k0 = {k: v for k, v in t0[0].items() if k != "record_timing"}
+        k1 = {k: v for k, v in t1[0].items() if k != "record_timing"}
+        r = {"analytic": measure(), "learned_k": measure(cells_per_rmax=kl),
+             "search_without_model": dict(measure(**k0), trials=t0[3]),
+             "search_with_model": dict(measure(mdl=model, **k1), trials=t1[3])}
+        a = r["analytic"]["ms"]
+        r["gain_learned_k"] = a / r["learned_k"]["ms"]
+        r["gain_search_without_model"] = a / r["search_without_model"]["ms"]
+        r["gain_search_with_model"] = a / r["search_with_model"]["ms"]
+        out[name] = r
+        del x
+    return {"workload": "300,000 points in [0,500)^3 periodic, 80 % in 30 Gaussian blobs of width 15 (blobs30) "
+                        "or 90 % in 10 of width 5 (blobs10), rest uniform; (s,mu) 20x10 over [0,40)",
+            **out}
+
+
 # The multi-tracer pair list of the paper's quick guide (App. D): LRG data
 # and randoms (L, R), ELG data and randoms (E, S).
 TRACERS = (("L", 100_000), ("R", 500_000), ("E", 150_000), ("S", 750_000))
@@ -845,6 +895,11 @@ def main():
         if not args.no_learned:
             res["learned"]["c5_heldout"] = c5_section(fcfc, synth, model)
             log("C5 held-out comparison done")
+            res["learned"]["clustered_heldout"] = clustered_section(fcfc, synth, model)
+            log("clustered held-out: " + " ".join(
+                f"{k} analytic {v['analytic']['ms']:.2f} ms, search {v['search_without_model']['ms']:.2f}, "
+                f"with model {v['search_with_model']['ms']:.2f}"
+                for k, v in res["learned"]["clustered_heldout"].items() if k != "workload"))
     if not args.no_pairs:
         from paper_2301_12557_amd import synth
         res["pairs"] = pairs_section(fcfc, synth, torch)

@@ -387,8 +387,8 @@ fcfc_status fcfc_choose_cells(fcfc_model_t model, int32_t kind, int32_t los, con
  * fcfc_autotune -- pick the tuning knobs of a count by timing it.  Not part
  * of the paper, which studies the cell size by hand (Sect. 2.1, App. B).
  * Runs build + count (best of two, GPU events) on the given catalogues for:
- * the analytic tuning; the cell sizes the model predicts fastest (its two
- * best k), or without a model the analytic k +- 1; then, from the fastest,
+ * the analytic tuning; the analytic k +- 1 and, with a model, the two cell
+ * sizes it predicts fastest (a proposal only adds trials); then, from the fastest,
  * 2 and 4 histogram copies, the other tile width, look-up tables of 2^12
  * and 2^14 entries, workgroups of 16, 14 and 12 wavefronts and, with a
  * model, the learned work order, keeping each

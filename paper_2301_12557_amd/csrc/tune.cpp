@@ -1,9 +1,9 @@
 // tune.cpp -- the autotuner: picks the tuning knobs of a count (cells per
 // prune radius, histogram copies, tile width, look-up table length,
 // workgroup size, work order) by timing
-// real builds and counts on a sample catalogue.  The learned cost model, when
-// given, proposes the cell sizes to try; the analytic choice is always tried;
-// measured GPU time decides.  Knobs never change a count.
+// real builds and counts on a sample catalogue.  The analytic cell size and
+// its neighbours are always tried; the learned cost model, when given, adds
+// the two cell sizes it predicts fastest; measured GPU time decides.  Knobs never change a count.
 #include <math.h>
 #include <stdio.h>
 #include <string.h>
@@ -165,8 +165,11 @@ extern "C" fcfc_status fcfc_autotune(fcfc_model_t model, int32_t kind, int32_t l
     // the analytic (heuristic) tuning: every knob left to the library
     int32_t kh = 0;
     FCFC_TRY(fcfc_choose_cells(nullptr, kind, los, edges1, n1, edges2, n2, box_L, &t0, c1, c2, stream, &kh, nullptr));
-    // cell sizes to try: the analytic one, and the model's two best (or the analytic one +- 1)
+    // cell sizes to try: the analytic one, its neighbours, and the model's two
+    // best (a proposal adds candidates, never takes the neighbours away)
     std::vector<int> ks{kh};
+    if (kh > 1) ks.push_back(kh - 1);
+    if (kh < 6) ks.push_back(kh + 1);
     if (model) {
         double pred[6];
         int32_t kl = 0;
@@ -176,9 +179,6 @@ extern "C" fcfc_status fcfc_autotune(fcfc_model_t model, int32_t kind, int32_t l
             if (isfinite(pred[k - 1])) order.push_back(k);
         std::sort(order.begin(), order.end(), [&](int a, int b) { return pred[a - 1] < pred[b - 1]; });
         for (size_t i = 0; i < order.size() && i < 2; i++) ks.push_back(order[i]);
-    } else {
-        if (kh > 1) ks.push_back(kh - 1);
-        if (kh < 6) ks.push_back(kh + 1);
     }
     std::sort(ks.begin() + 1, ks.end());
     ks.erase(std::unique(ks.begin() + 1, ks.end()), ks.end());

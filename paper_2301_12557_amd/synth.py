@@ -40,6 +40,18 @@ def uniform_box(n, L, seed):
     return _guard_box(x, float(L))
 
 
+def blobs_box(n, L, nblob, rad, frac, seed):
+    """A catalogue far more clustered than a lognormal field: a fraction `frac`
+    of the n points in nblob Gaussian blobs of width `rad` (centres at least
+    3 rad from the faces), the rest uniform, in [0, L)^3."""
+    rng = np.random.default_rng(seed)
+    nb = int(n * frac)
+    cen = rng.uniform(rad * 3, L - rad * 3, (nblob, 3))
+    x = cen[rng.integers(0, nblob, nb)] + rng.normal(0, rad, (nb, 3))
+    x = np.concatenate([x, rng.uniform(0, L, (n - nb, 3))])
+    return np.clip(x, 0, np.nextafter(L, 0))
+
+
 def gaussian_field(ngrid, L, slope, sigma, rng):
     """Gaussian random field on ngrid^3 cells with P(k) ~ k^slope (k=0 removed), unit->sigma variance."""
     g = rng.standard_normal((ngrid, ngrid, ngrid))

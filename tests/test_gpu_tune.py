@@ -70,13 +70,7 @@ def test_autotune_weighted_and_open_box():
 
 
 def _blobs(n, nblob, rad, frac, seed):
-    """Clustered catalogue: a fraction of the points in Gaussian blobs, the rest uniform."""
-    rng = np.random.default_rng(seed)
-    nb = int(n * frac)
-    cen = rng.uniform(rad * 3, L - rad * 3, (nblob, 3))
-    x = cen[rng.integers(0, nblob, nb)] + rng.normal(0, rad, (nb, 3))
-    x = np.concatenate([x, rng.uniform(0, L, (n - nb, 3))])
-    return np.clip(x, 0, np.nextafter(L, 0))
+    return synth.blobs_box(n, L, nblob, rad, frac, seed)
 
 
 def _time_count(fcfc, dx, reps=3, model=None, **tune):
@@ -98,12 +92,8 @@ def _time_count(fcfc, dx, reps=3, model=None, **tune):
     return best * 1e3
 
 
-def test_learned_tuning_gain_over_analytic():
-    """Train the cost model on timings of lognormal boxes, then tune a held-out
-    clustered catalogue with it: the tuned count is measured again, afresh,
-    against the analytic tuning, and must not be slower (5 % timing noise)."""
-    import torch
-    from paper_2301_12557_amd import fcfc
+def _train_model(fcfc, torch):
+    """Cost model trained on per-item timings of two lognormal boxes at k = 1..4."""
     feats, ts = [], []
     for i, n in enumerate((50000, 200000)):
         x = synth.lognormal_box_torch(n, L, 100 + i, device="cuda", ngrid=128)
@@ -118,10 +108,32 @@ def test_learned_tuning_gain_over_analytic():
             plan.close()
     md = fcfc.Model(seed=1)
     loss = md.train(torch.cat(feats), torch.cat(ts), epochs=10, batch=512, lr=2e-3, seed=1)
-    dx = to_dev(_blobs(300000, 30, 15.0, 0.8, 8))
-    t, best, heur, n = fcfc.autotune(dx, model=md, kind="smu", edges1=E1, edges2=E2, box=L)
-    tuned = _time_count(fcfc, dx, model=md, **_plan_kw(t))
-    analytic = _time_count(fcfc, dx)
-    note(f"model loss {loss:.3f}; tuned {t}: {tuned:.2f} ms, analytic {analytic:.2f} ms, "
-         f"gain x{analytic / tuned:.2f} ({n} trials)")
-    assert tuned <= 1.05 * analytic
+    return md, loss
+
+
+@pytest.mark.parametrize("blobs", [(30, 15.0, 0.8, 8), (10, 5.0, 0.9, 9)], ids=["blobs30", "blobs10"])
+def test_tuning_gain_on_clustered_catalogue(blobs):
+    """Held-out catalogues far more clustered than the analytic cell-size rule
+    assumes (80-90 % of 300,000 points in a few Gaussian blobs): the tuning
+    found with the learned model proposing cell sizes, measured again afresh,
+    must beat the analytic tuning by at least 1.25x (on MI355X: 2.1x and
+    1.8x).  The model only adds cell sizes to the model-free search, so its
+    result must not be slower than that search's by more than timing noise
+    and the other knobs' descent from another start (10 %); the gain the
+    model adds on its own is printed."""
+    import torch
+    from paper_2301_12557_amd import fcfc
+    md, loss = _train_model(fcfc, torch)
+    nblob, rad, frac, seed = blobs
+    dx = to_dev(_blobs(300000, nblob, rad, frac, seed))
+    t0, _, _, n0 = fcfc.autotune(dx, kind="smu", edges1=E1, edges2=E2, box=L)
+    t1, _, _, n1 = fcfc.autotune(dx, model=md, kind="smu", edges1=E1, edges2=E2, box=L)
+    analytic = min(_time_count(fcfc, dx) for _ in range(2))
+    free = min(_time_count(fcfc, dx, **_plan_kw(t0)) for _ in range(2))
+    tuned = min(_time_count(fcfc, dx, model=md, **_plan_kw(t1)) for _ in range(2))
+    note(f"model loss {loss:.3f}; analytic {analytic:.2f} ms; model-free search ({n0} trials, "
+         f"k={t0['cells_per_rmax']}) {free:.2f} ms; with the model ({n1} trials, k={t1['cells_per_rmax']}) "
+         f"{tuned:.2f} ms: gain x{analytic / tuned:.2f} over analytic, x{free / tuned:.2f} from the model")
+    assert n1 >= n0
+    assert analytic >= 1.25 * tuned
+    assert tuned <= 1.10 * free
