@@ -426,6 +426,56 @@ fcfc_status fcfc_diag_transcendental(double *rsq_max_rel, double *rcp_max_rel, d
                                      void *stream);
 
 /*
+ * fcfc_plan_numerics -- the FP32 constants the counting kernel takes from a
+ * plan: the grid its cell-local coordinates are relative to, the candidate
+ * threshold, and the bands around bin edges inside which a pair is binned
+ * again in FP64 (the single-precision evaluation of the separations of
+ * Sect. 2.5 made exact, with the squared-edge bins of Sect. 3.2.1).  Host
+ * only: needs no GPU, so that tests can replay the kernel's FP32 decisions.
+ *   nx, ny, nz, cells_per_rmax, lo, side  the grid (lo = 0 in a periodic box)
+ *   e_axis     bound on the FP32 error of one displacement component
+ *   side32     FP32 cell side the kernel forms displacements with
+ *   r2prune32  a pair is a candidate when its FP32 d2 is below this (every
+ *              kind except (s_perp, pi) along z, which tests vmax of both tables)
+ *   d2small    (s, mu): pairs with FP32 d2 below this are always rechecked
+ *   mu_tolA, mu_tolC  (s, mu): a pair whose FP32 mu*n2 lies closer than
+ *              mu_tolA * rsq(d2) + mu_tolC to an interior mu edge is rechecked
+ *   trans_rel  relative error assumed for the hardware rsq and rcp
+ *   has_big    the tables with twice the entries exist (fcfc_plan_table 2, 3)
+ * Errors: FCFC_EINVAL (null), FCFC_ESTATE (open box before its bounds are set).
+ */
+typedef struct fcfc_numerics {
+    int32_t nx, ny, nz, cells_per_rmax;
+    double lo[3];
+    double side;
+    double e_axis;
+    float side32, r2prune32, d2small, mu_tolA, mu_tolC, trans_rel;
+    int32_t has_big;
+    int32_t reserved;
+} fcfc_numerics;
+fcfc_status fcfc_plan_numerics(fcfc_plan_t plan, fcfc_numerics *out);
+
+/*
+ * fcfc_plan_table -- copy one of a plan's squared-separation look-up tables
+ * (Sect. 3.2.3) with its bands.  which: 0 the first axis (s or s_perp), 1 the
+ * second ((s_perp, pi): pi), 2 and 3 the same with twice the entries (when
+ * has_big).  Host only.  Every output may be NULL.
+ *   E          n+1 squared edges e_k * e_k in FP64 (n = bins of the axis)
+ *   lo, hi     n+1 FP32 band ends: an FP32 value v < lo[k] stands for a
+ *              squared separation below E[k], v >= hi[k] for one at or above
+ *              it (lo = hi = 0 where E = 0)
+ *   tab, cap   up to cap entries; entry j covers the FP32 values v with
+ *              floor(v * scale) = j and holds their bin (>= 0), -1 (out of
+ *              range), or -2 - k when the band of edge k is the first that
+ *              meets the entry (the kernel then compares v with the bands)
+ *   n_entries  the table length; scale a power of two; vmax = hi[n]
+ * Errors: FCFC_EINVAL (null plan, unknown or absent table), FCFC_ESTATE
+ * (open box before its bounds are set).
+ */
+fcfc_status fcfc_plan_table(fcfc_plan_t plan, int32_t which, double *E, float *lo, float *hi,
+                            int16_t *tab, int64_t cap, int64_t *n_entries, float *scale, float *vmax);
+
+/*
  * fcfc_diag_peaks -- roofline microbenchmarks on the current device, timed with
  * HIP events: FP32 FMA rate (one FMA per lane per instruction, no packed
  * math; TFLOP/s, 2 flops per FMA), conflict-free LDS ds_add_u32 and

@@ -36,6 +36,8 @@ def _load():
         lib.oracle_count_grid.restype = ci
         lib.oracle_classify_pair.argtypes = [P, P, ci, ci, cd, P, ci, P, ci]
         lib.oracle_classify_pair.restype = ctypes.c_long
+        lib.oracle_classify_pairs.argtypes = [P, P, i64, ci, ci, cd, P, ci, P, ci, P]
+        lib.oracle_classify_pairs.restype = ci
         lib.oracle_triplets_brute.argtypes = [P, i64, cd, P, ci, P, ci]
         lib.oracle_triplets_brute.restype = ci
         lib.oracle_triplets_list.argtypes = [P, i64, cd, P, ci, P, ci]
@@ -149,3 +151,20 @@ def classify_pair(p1, p2, *, kind="s", edges1, edges2=None, los="z", box=0.0):
     if r == -2:
         raise OracleError("bad specification")
     return int(r)
+
+
+def classify_pairs(p1, p2, *, kind="s", edges1, edges2=None, los="z", box=0.0):
+    """Flat bin index (int64, -1 out of range) of each pair (p1[i], p2[i]), (n, 3) arrays."""
+    lib = _load()
+    a = _f64(p1, 3)
+    b = _f64(p2, 3)
+    if a.shape != b.shape:
+        raise ValueError("p1 and p2 must have the same shape")
+    e1 = _f64(edges1)
+    e2 = np.array([0.0, 1.0]) if kind == "s" else _f64(edges2)
+    out = np.empty(len(a), dtype=np.int64)
+    r = lib.oracle_classify_pairs(_ptr(a), _ptr(b), len(a), KIND[kind], LOS[los], float(box), _ptr(e1),
+                                  len(e1) - 1, _ptr(e2), len(e2) - 1, _ptr(out))
+    if r == -2:
+        raise OracleError("bad specification")
+    return out

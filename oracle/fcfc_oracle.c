@@ -605,6 +605,20 @@ long oracle_classify_pair(const double *p1, const double *p2, int kind, int los,
     return b;
 }
 
+/* The same classification for n pairs (p1[3i..], p2[3i..]) into out[i]; returns
+ * ORC_OK, or -2 on a bad specification. */
+int oracle_classify_pairs(const double *p1, const double *p2, int64_t n, int kind, int los, double L,
+                          const double *e1, int nb1, const double *e2, int nb2, long *out)
+{
+    orc_spec sp;
+    if (orc_spec_init(&sp, kind, los, L, e1, nb1, e2, nb2)) { orc_spec_free(&sp); return -2; }
+    for (int64_t i = 0; i < n; i++)
+        out[i] = orc_classify(&sp, p1[3 * i], p1[3 * i + 1], p1[3 * i + 2],
+                              p2[3 * i], p2[3 * i + 1], p2[3 * i + 2]);
+    orc_spec_free(&sp);
+    return ORC_OK;
+}
+
 /* ---------------------------------------------------------------------------
  * Triangle counts (the three-point extension; Sect. 6 lists three-point
  * statistics as future work, so the definition is the plain one built from

@@ -559,6 +559,65 @@ extern "C" fcfc_status fcfc_plan_set_bounds(fcfc_plan_t plan, const double lo[3]
     return fcfc_set_bounds_internal(p, lo, hi);
 }
 
+extern "C" fcfc_status fcfc_plan_numerics(fcfc_plan_t plan, fcfc_numerics* out) {
+    clear_error();
+    const Plan* p = (const Plan*)plan;
+    if (!p || !out) return FCFC_EINVAL;
+    if (!p->numerics_ready) {
+        set_error("plan_numerics: the grid is not fixed yet (set or fit the bounds first)");
+        return FCFC_ESTATE;
+    }
+    fcfc_numerics n{};
+    n.nx = p->grid.nx;
+    n.ny = p->grid.ny;
+    n.nz = p->grid.nz;
+    n.cells_per_rmax = p->grid.k;
+    for (int a = 0; a < 3; a++) n.lo[a] = p->L > 0 ? 0.0 : p->grid.lo[a];
+    n.side = p->grid.side;
+    n.e_axis = p->e_axis;
+    n.side32 = (float)p->grid.side;
+    n.r2prune32 = p->r2prune32;
+    n.d2small = p->d2small;
+    n.mu_tolA = p->mu_tolA;
+    n.mu_tolC = p->mu_tolC;
+    n.trans_rel = (float)trans_rel_bound();
+    n.has_big = p->has_big ? 1 : 0;
+    *out = n;
+    return FCFC_OK;
+}
+
+extern "C" fcfc_status fcfc_plan_table(fcfc_plan_t plan, int32_t which, double* E, float* lo, float* hi,
+                                       int16_t* tab, int64_t cap, int64_t* n_entries, float* scale, float* vmax) {
+    clear_error();
+    const Plan* p = (const Plan*)plan;
+    if (!p) return FCFC_EINVAL;
+    if (!p->numerics_ready) {
+        set_error("plan_table: the grid is not fixed yet (set or fit the bounds first)");
+        return FCFC_ESTATE;
+    }
+    const Lut1D* t = nullptr;
+    switch (which) {
+        case 0: t = &p->lut1; break;
+        case 1: t = &p->lut2; break;
+        case 2: t = p->has_big ? &p->lut1b : nullptr; break;
+        case 3: t = p->has_big ? &p->lut2b : nullptr; break;
+        default: break;
+    }
+    if (!t || t->n == 0) {
+        set_error("plan_table: no table %d in this plan", which);
+        return FCFC_EINVAL;
+    }
+    if (E) memcpy(E, t->E.data(), sizeof(double) * (size_t)(t->n + 1));
+    if (lo) memcpy(lo, t->lo.data(), sizeof(float) * (size_t)(t->n + 1));
+    if (hi) memcpy(hi, t->hi.data(), sizeof(float) * (size_t)(t->n + 1));
+    const int64_t nt = (int64_t)t->tab.size();
+    if (tab && cap > 0) memcpy(tab, t->tab.data(), sizeof(int16_t) * (size_t)std::min(cap, nt));
+    if (n_entries) *n_entries = nt;
+    if (scale) *scale = t->scale;
+    if (vmax) *vmax = t->vmax;
+    return FCFC_OK;
+}
+
 extern "C" void fcfc_plan_free(fcfc_plan_t plan) {
     Plan* p = (Plan*)plan;
     if (!p) return;

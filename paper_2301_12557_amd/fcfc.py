@@ -59,6 +59,14 @@ class Stats(ctypes.Structure):
         return d
 
 
+class Numerics(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("cells_per_rmax", ctypes.c_int32), ("lo", ctypes.c_double * 3), ("side", ctypes.c_double),
+                ("e_axis", ctypes.c_double), ("side32", ctypes.c_float), ("r2prune32", ctypes.c_float),
+                ("d2small", ctypes.c_float), ("mu_tolA", ctypes.c_float), ("mu_tolC", ctypes.c_float),
+                ("trans_rel", ctypes.c_float), ("has_big", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
 # (name, restype, argtypes) of every exported entry point of include/fcfc.h
 _P = ctypes.c_void_p
 _I32 = ctypes.c_int32
@@ -73,6 +81,9 @@ SIGNATURES = [
     ("fcfc_count_pairs_noalloc", _I32, [_P, _P, _P, _P, _P, _P]),
     ("fcfc_noalloc_scratch_bytes", _I64, []),
     ("fcfc_plan_stats", _I32, [_P, ctypes.POINTER(Stats)]),
+    ("fcfc_plan_numerics", _I32, [_P, ctypes.POINTER(Numerics)]),
+    ("fcfc_plan_table", _I32, [_P, _I32, _P, _P, _P, _P, _I64, ctypes.POINTER(_I64), ctypes.POINTER(ctypes.c_float),
+                               ctypes.POINTER(ctypes.c_float)]),
     ("fcfc_weight_scale", _I32, [_D, _D, _D, _D, _I32, ctypes.POINTER(_I32)]),
     ("fcfc_batch_create", _I32, [_P, ctypes.POINTER(Catalog), _I32, _P, ctypes.POINTER(_P)]),
     ("fcfc_batch_create_pairs", _I32, [_P, ctypes.POINTER(Catalog), _I32, _P, _I32, _P, ctypes.POINTER(_P)]),
@@ -294,6 +305,32 @@ class Plan:
         s = Stats()
         check(load().fcfc_plan_stats(self.h, ctypes.byref(s)))
         return s.as_dict()
+
+    def numerics(self):
+        """The FP32 constants a count of this plan uses (fcfc_plan_numerics), as a dict."""
+        n = Numerics()
+        check(load().fcfc_plan_numerics(self.h, ctypes.byref(n)))
+        d = {k: getattr(n, k) for k, _ in Numerics._fields_ if k != "reserved"}
+        d["lo"] = list(n.lo)
+        return d
+
+    def table(self, which):
+        """Look-up table `which` (0: s or s_perp, 1: pi, 2 and 3: the same with twice
+        the entries) as a dict of numpy arrays E (FP64), lo, hi (FP32), tab (int16)
+        and the FP32 scale and vmax (fcfc_plan_table)."""
+        lib = load()
+        nt = _I64()
+        check(lib.fcfc_plan_table(self.h, int(which), None, None, None, None, 0, ctypes.byref(nt), None, None))
+        nb = self.n2 if which in (1, 3) else self.n1
+        E = np.empty(nb + 1, dtype=np.float64)
+        lo = np.empty(nb + 1, dtype=np.float32)
+        hi = np.empty(nb + 1, dtype=np.float32)
+        tab = np.empty(nt.value, dtype=np.int16)
+        sc = ctypes.c_float()
+        vm = ctypes.c_float()
+        check(lib.fcfc_plan_table(self.h, int(which), E.ctypes.data, lo.ctypes.data, hi.ctypes.data, tab.ctypes.data,
+                                  nt.value, ctypes.byref(nt), ctypes.byref(sc), ctypes.byref(vm)))
+        return {"E": E, "lo": lo, "hi": hi, "tab": tab, "scale": np.float32(sc.value), "vmax": np.float32(vm.value)}
 
     def set_model(self, model):
         """Attach a Model for order="learned" (None detaches); the plan keeps a reference."""
