@@ -267,28 +267,44 @@ fcfc_status plan_finalize_numerics(Plan* p) {
     } else {
         ErrModel m1 = d2m, m2 = d2m;
         if (p->los == FCFC_LOS_MIDPOINT) {
-            // Kernel: l = fl(2a) + d per axis from FP32 absolute coordinates (error
-            // el per axis), dot = d.l and ll = |l|^2 by fma chains, pi^2 =
-            // dot^2 rcp(ll).  With |d| <= r and |l| >= lmin (twice the distance from
-            // the observer to the box):
-            //   |dot32 - dot| / |l| <= dpi = sqrt3 e + sqrt3 el |d| / lmin + 3 u |d|
-            //   (taken with twice the middle term),
-            //   rcp(ll32) = (1 / ll)(1 + eps), |eps| <= rel = 2 sqrt3 el / lmin + 6 u + TRANS_REL,
-            // so |pi^2_32 - pi^2| <= (2 dpi |pi| + dpi^2)(1 + rel) + rel pi^2: a term in
-            // sqrt(E), a constant and a term in E at an edge E = pi^2.  Everything is
-            // doubled for margin.
-            double R = p->coord_max;
-            double el = 2.0 * (2.0 * u * R + e + u * (2.0 * R + r)) * 2.0;
-            double lmin = 2.0 * p->obs_dist;
-            double dpi = sqrt(3.0) * e + 2.0 * sqrt(3.0) * el * r / lmin + 3.0 * u * r;
-            double rel = 2.0 * sqrt(3.0) * el / lmin + 6.0 * u + TRANS_REL;
-            m2.A += 2.0 * 2.0 * dpi * (1.0 + rel);
-            m2.B += 2.0 * dpi * dpi * (1.0 + rel);
-            m2.C += 2.0 * rel;
-            // s_perp^2 = d2 - pi^2 carries the pi^2 error of any pi in range (up to
-            // just above the top pi edge) and the rounding of the difference
+            // Kernel: l = fl(2 fl(x_a) + d) per axis, dot = d.l and ll = |l|^2 by
+            // fma chains, pi^2 = fl(fl(dot^2) rcp(ll)).  Per axis l is off by at
+            // most el (the rounding of the absolute FP32 coordinate, doubled, the
+            // displacement's error e and the rounding of the sum).  With
+            // pi = d.l / |l|, d_perp the transverse part of d and |l| >= lmin (twice
+            // the distance from the observer to the box), dot32 / |l32| is off by at
+            // most
+            //   dpi = sqrt3 e + |d_perp| sqrt3 el / (lmin - sqrt3 el) + 3 u r
+            // (the displacement error along l; the turn of l, felt only through
+            // d_perp; the fma chain).  Squaring, the rounded reciprocal (relative
+            // error TRANS_REL), |l32|^2's chain and the product add a relative rel.
+            // A pair whose pi decides its bin has s_perp below the top s_perp edge
+            // (else the s_perp test drops or rechecks it), and one whose s_perp
+            // decides has pi below the top pi edge, so
+            //   |pi2_32 - pi^2|     <= (2 dpi pi + dpi^2)(1 + rel) + rel pi^2,
+            //   |sp2_32 - s_perp^2| <= the d2 error at d2 <= s_perp^2 + P2, plus the
+            //                          pi^2 error at P2, plus the rounding of the
+            //                          difference (u s_perp^2).
+            // Each of these terms is taken 1.5 times for margin.
+            const double M = 1.5;
+            const double R = p->coord_max;
+            const double el = (2.0 * u * R + e + u * (2.0 * R + r)) * (1.0 + 1e-6);
+            const double lmin = 2.0 * p->obs_dist;
+            const double lguard = lmin - sqrt(3.0) * el;
+            if (!(lguard > 0.5 * lmin)) {
+                set_error("mid-point line of sight: the box lies too close to the observer for FP32");
+                return FCFC_ERANGE;
+            }
+            const double sp_max = p->e1.back() * (1.0 + 1e-6);
+            const double dpi = (sqrt(3.0) * e + sp_max * sqrt(3.0) * el / lguard + 3.0 * u * r) * (1.0 + 1e-6);
+            const double rel = 5.0 * u + TRANS_REL + 1e-12;
+            m2.A += M * 2.0 * dpi * (1.0 + rel);
+            m2.B += M * dpi * dpi * (1.0 + rel);
+            m2.C += M * rel;
             const double P2 = p->e2.back() * p->e2.back() * (1.0 + 1e-3) + 1.0;
-            m1.B += 2.0 * ((2.0 * dpi * sqrt(P2) + dpi * dpi) * (1.0 + rel) + rel * P2) + u * r * r * 2.0;
+            m1.B += M * (d2m.A * sqrt(P2) + d2m.C * P2) +
+                    M * ((2.0 * dpi * sqrt(P2) + dpi * dpi) * (1.0 + rel) + rel * P2);
+            m1.C += M * u;
         }
         FCFC_TRY(build_lut(p->lut1, p->e1, m1, std::max(8, lg - 1)));
         FCFC_TRY(build_lut(p->lut2, p->e2, m2, std::max(8, lg - 1)));
