@@ -388,11 +388,13 @@ fcfc_status fcfc_choose_cells(fcfc_model_t model, int32_t kind, int32_t los, con
  * of the paper, which studies the cell size by hand (Sect. 2.1, App. B).
  * Runs build + count (best of two, GPU events) on the given catalogues for:
  * the analytic tuning; the analytic k +- 1 and, with a model, the two cell
- * sizes it predicts fastest (a proposal only adds trials); then, from the fastest,
- * 2 and 4 histogram copies, the other tile width, look-up tables of 2^12
- * and 2^14 entries, workgroups of 16, 14 and 12 wavefronts and, with a
- * model, the learned work order, keeping each
- * change that is faster.  Settings that are not possible for these bins are
+ * sizes it predicts fastest; then, from the fastest, 2 and 4 histogram
+ * copies, the other tile width, look-up tables of 2^12 and 2^14 entries,
+ * workgroups of 16, 14 and 12 wavefronts and, with a model, the learned work
+ * order, keeping each change that is faster.  When the fastest cell size is
+ * one only the model proposed, the same knobs are also searched from the
+ * fastest of the analytic k and its neighbours, and the faster result kept:
+ * a model only adds candidates to the search without it.  Settings that are not possible for these bins are
  * skipped.  With the learned order in *best, counts need the model attached
  * (fcfc_plan_set_model) to use it.
  *   base       NULL or knobs kept fixed (n_hint and the order are kept).

@@ -84,8 +84,8 @@ struct CountArgs {
     uint32_t* cursor;
     const int16_t* lut1;
     const int16_t* lut2;
-    const float* band1;  // lo[0..n1], hi[0..n1]
-    const float* band2;
+    const float2* band1;  // (lo_k, hi_k) for k = 0..n1, then (+inf, +inf)
+    const float2* band2;
     const double* E1;    // FP64 squared edges
     const double* E2;
     unsigned long long* out_counts;
@@ -128,8 +128,8 @@ typedef const CountArgs FCFC_CONST& ArgsRef;
 struct Smem {
     const int16_t* lut1;
     const int16_t* lut2;
-    const float* band1;
-    const float* band2;
+    const float2* band1;
+    const float2* band2;
     uint32_t* hist;
     unsigned long long* wl;  // exact weighted limbs, [bin][2]: low 32 bits, high part (signed)
     float* qf;        // this wave's compaction queue (entries of QStride floats)
@@ -242,22 +242,27 @@ __device__ inline int lut_entry(const int16_t* __restrict__ lut, float scale, fl
     return (int)lut[(uint32_t)(v * scale)];
 }
 // A clean entry (>= -1) is the bin itself, -1 meaning out of range.  A hot
-// entry (<= -2) holds -2 - k, k the first edge whose band meets the entry:
-// count the edges certainly <= v by a forward traversal over the few banded
-// edges.  Returns the bin, -1 (out of range) or -2 (v inside a band: the pair
-// needs the FP64 recheck).
-__device__ inline int lut_hot_bin(const float* __restrict__ band, int n, int e, float v) {
+// entry (<= -2) holds -2 - k, k the first edge whose band meets the entry (the
+// edges below k lie wholly below the entry).  Most hot entries meet one band:
+// v is then placed by band k and the start of band k + 1, read together; when
+// v reaches band k + 1 (several edges in one entry) the walk goes on over the
+// next bands.  band[k] = (lo_k, hi_k), band[n + 1] = (+inf, +inf).  Returns the
+// bin, -1 (out of range) or -2 (v inside a band: the pair needs the FP64
+// recheck).
+__device__ inline int lut_hot_bin(const float2* __restrict__ band, int n, int e, float v) {
     int k = -2 - e;
-    int c = k;
-    for (; k <= n; k++) {
-        if (v >= band[n + 1 + k]) {
-            c = k + 1;
-        } else {
-            if (v >= band[k]) return -2;
-            break;
-        }
+    const float2 b0 = band[k];
+    const float lo1 = band[k + 1].x;
+    if (v < b0.x) return k - 1;
+    if (v < b0.y) return -2;
+    if (v < lo1) return k < n ? k : -1;
+    for (k = k + 1; k <= n; k++) {
+        const float2 b = band[k];
+        if (v >= b.y) continue;
+        if (v >= b.x) return -2;
+        break;
     }
-    return (c >= 1 && c <= n) ? c - 1 : -1;
+    return (k >= 1 && k <= n) ? k - 1 : -1;
 }
 
 // Kernel constants kept in registers.
@@ -502,8 +507,8 @@ __global__ __launch_bounds__(CT_MAX) __attribute__((amdgpu_waves_per_eu((W || LO
     Smem s;
     s.lut1 = (const int16_t*)(smem + a.off_lut1);
     s.lut2 = (const int16_t*)(smem + a.off_lut2);
-    s.band1 = (const float*)(smem + a.off_band1);
-    s.band2 = (const float*)(smem + a.off_band2);
+    s.band1 = (const float2*)(smem + a.off_band1);
+    s.band2 = (const float2*)(smem + a.off_band2);
     s.hist = (uint32_t*)(smem + a.off_hist);
     s.wl = (unsigned long long*)(smem + a.off_whist);
     constexpr int QS = QStride<KIND, LOS>::value;
@@ -523,11 +528,11 @@ __global__ __launch_bounds__(CT_MAX) __attribute__((amdgpu_waves_per_eu((W || LO
             src = (const uint32_t*)a.lut2;
             for (int i = tid; i < (a.nlut2 + 1) / 2; i += nthr) d[i] = src[i];
         }
-        float* b1 = (float*)(smem + a.off_band1);
-        for (int i = tid; i < 2 * (a.n1 + 1); i += nthr) b1[i] = a.band1[i];
+        float2* b1 = (float2*)(smem + a.off_band1);
+        for (int i = tid; i < a.n1 + 2; i += nthr) b1[i] = a.band1[i];
         if (KIND == FCFC_BIN_SPERP_PI) {
-            float* b2 = (float*)(smem + a.off_band2);
-            for (int i = tid; i < 2 * (a.n2 + 1); i += nthr) b2[i] = a.band2[i];
+            float2* b2 = (float2*)(smem + a.off_band2);
+            for (int i = tid; i < a.n2 + 2; i += nthr) b2[i] = a.band2[i];
         }
         for (int i = tid; i < a.nbins * a.copies; i += nthr) s.hist[i] = 0u;
         if (W)
@@ -1056,8 +1061,8 @@ static fcfc_status setup_launch(Plan* p, bool is_auto, bool weighted, bool batch
     FCFC_HIP(hipFuncSetAttribute((const void*)L.kern, hipFuncAttributeMaxDynamicSharedMemorySize, maxlds));
     // LDS shared by the workgroup's waves for tables of n1t and n2t entries
     auto shared_for = [&](int n1t, int n2t) {
-        return al16(n1t * 2 + 4) + al16(n2t * 2 + 4) + al16(2 * (p->n1 + 1) * 4) +
-               al16(two ? 2 * (p->n2 + 1) * 4 : 0) + al16(p->nbins * 4 * L.copies) +
+        return al16(n1t * 2 + 4) + al16(n2t * 2 + 4) + al16((p->n1 + 2) * 8) +
+               al16(two ? (p->n2 + 2) * 8 : 0) + al16(p->nbins * 4 * L.copies) +
                (weighted ? al16(p->nbins * 16) : 0);
     };
     // Workgroup size for a given shared part, and the waves resident per CU.
@@ -1127,9 +1132,9 @@ static fcfc_status setup_launch(Plan* p, bool is_auto, bool weighted, bool batch
     a.off_lut2 = off;
     off += al16(a.nlut2 * 2 + 4);
     a.off_band1 = off;
-    off += al16(2 * (p->n1 + 1) * 4);
+    off += al16((p->n1 + 2) * 8);
     a.off_band2 = off;
-    off += al16(two ? 2 * (p->n2 + 1) * 4 : 0);
+    off += al16(two ? (p->n2 + 2) * 8 : 0);
     a.off_hist = off;
     off += al16(p->nbins * 4 * L.copies);
     a.off_whist = off;
@@ -1146,8 +1151,8 @@ static fcfc_status setup_launch(Plan* p, bool is_auto, bool weighted, bool batch
     // tables blob
     L.tb_l1 = (size_t)al16(a.nlut1 * 2 + 4);
     L.tb_l2 = (size_t)al16(a.nlut2 * 2 + 4);
-    L.tb_b1 = (size_t)al16(2 * (p->n1 + 1) * 4);
-    L.tb_b2 = (size_t)al16(2 * (p->n2 + 1) * 4);
+    L.tb_b1 = (size_t)al16((p->n1 + 2) * 8);
+    L.tb_b2 = (size_t)al16((p->n2 + 2) * 8);
     L.tb_e1 = (size_t)al16((p->n1 + 1) * 8);
     L.tb_e2 = (size_t)al16((p->n2 + 1) * 8);
     L.tb_rows = (size_t)al16(std::max(1, L.nrows) * 16);
@@ -1159,13 +1164,19 @@ static fcfc_status setup_launch(Plan* p, bool is_auto, bool weighted, bool batch
         o += L.tb_l1;
         if (two) memcpy(&L.htab[o], T2->tab.data(), T2->tab.size() * 2);
         o += L.tb_l2;
-        memcpy(&L.htab[o], T1->lo.data(), (p->n1 + 1) * 4);
-        memcpy(&L.htab[o + (p->n1 + 1) * 4], T1->hi.data(), (p->n1 + 1) * 4);
+        // bands as (lo, hi) pairs, then a sentinel pair above the top edge
+        auto put_bands = [&](size_t at, const Lut1D* T, int n) {
+            float* b = (float*)&L.htab[at];
+            for (int k = 0; k <= n; k++) {
+                b[2 * k] = T->lo[k];
+                b[2 * k + 1] = T->hi[k];
+            }
+            b[2 * (n + 1)] = INFINITY;
+            b[2 * (n + 1) + 1] = INFINITY;
+        };
+        put_bands(o, T1, p->n1);
         o += L.tb_b1;
-        if (two) {
-            memcpy(&L.htab[o], T2->lo.data(), (p->n2 + 1) * 4);
-            memcpy(&L.htab[o + (p->n2 + 1) * 4], T2->hi.data(), (p->n2 + 1) * 4);
-        }
+        if (two) put_bands(o, T2, p->n2);
         o += L.tb_b2;
         memcpy(&L.htab[o], T1->E.data(), (p->n1 + 1) * 8);
         o += L.tb_e1;
@@ -1209,9 +1220,9 @@ static int4* bind_tables(const LaunchSetup& L, char* tab, CountArgs& a) {
     o += L.tb_l1;
     a.lut2 = (const int16_t*)o;
     o += L.tb_l2;
-    a.band1 = (const float*)o;
+    a.band1 = (const float2*)o;
     o += L.tb_b1;
-    a.band2 = (const float*)o;
+    a.band2 = (const float2*)o;
     o += L.tb_b2;
     a.E1 = (const double*)o;
     o += L.tb_e1;

@@ -195,69 +195,91 @@ extern "C" fcfc_status fcfc_autotune(fcfc_model_t model, int32_t kind, int32_t l
     int ntried = 0;
     fcfc_tuning bt = t0;
     double bms = INFINITY;
-    auto consider = [&](const fcfc_tuning& t) {
-        if (s != FCFC_OK) return;
+    // time t; keep it as the best when faster; returns its time (infinite
+    // when the setting is not possible or an error stopped the search)
+    auto consider = [&](const fcfc_tuning& t) -> double {
+        if (s != FCFC_OK) return INFINITY;
         double ms = INFINITY;
         fcfc_status r = time_config(c, t, 2, &ms);
         ntried++;
-        if (r == FCFC_ERANGE) return;  // not possible (grid, LDS): skip
+        if (r == FCFC_ERANGE) return INFINITY;  // not possible (grid, LDS): skip
         if (r != FCFC_OK) {
             s = r;
-            return;
+            return INFINITY;
         }
         if (ms < bms) {
             bms = ms;
             bt = t;
         }
+        return ms;
     };
-    // 1. the analytic tuning, then the other cell sizes
-    {
+    // 1. the analytic tuning, then the other cell sizes; the fastest of the
+    // analytic size and its neighbours is also kept (the model-free start)
+    fcfc_tuning bt_free = t0;
+    double bms_free = INFINITY;
+    for (size_t i = 0; i < ks.size(); i++) {
+        if (i > 0 && ks[i] == kh) continue;
         fcfc_tuning t = t0;
-        t.cells_per_rmax = kh;
-        consider(t);
-        if (heuristic_ms) *heuristic_ms = bms;
-        for (size_t i = 1; i < ks.size(); i++)
-            if (ks[i] != kh) {
-                t.cells_per_rmax = ks[i];
-                consider(t);
-            }
-    }
-    // 2. histogram copies, 3. tile width, 4. look-up table length (coordinate descent)
-    const int copies[2] = {2, 4};
-    for (int cp : copies) {
-        fcfc_tuning t = bt;
-        if ((bt.hist_copies == 0 ? 1 : bt.hist_copies) == cp) continue;
-        t.hist_copies = cp;
-        consider(t);
-    }
-    {
-        fcfc_tuning t = bt;
-        t.tile_points = (bt.tile_points == 64) ? 128 : 64;
-        consider(t);
-    }
-    const int luts[2] = {12, 14};
-    for (int lg : luts) {
-        fcfc_tuning t = bt;
-        if ((bt.lut_log2 == 0 ? 13 : bt.lut_log2) == lg) continue;
-        t.lut_log2 = lg;
-        consider(t);
-    }
-    // 5. workgroup size (wavefronts per workgroup)
-    const int gws[3] = {16, 14, 12};
-    {
-        const fcfc_tuning t1 = bt;
-        for (int gw : gws) {
-            if (t1.group_waves == gw) continue;
-            fcfc_tuning t = t1;
-            t.group_waves = gw;
-            consider(t);
+        t.cells_per_rmax = ks[i];
+        const double ms = consider(t);
+        if (i == 0 && heuristic_ms) *heuristic_ms = ms;
+        if (abs(ks[i] - kh) <= 1 && ms < bms_free) {
+            bms_free = ms;
+            bt_free = t;
         }
     }
-    // 6. the learned work order
-    if (model && bt.order != FCFC_ORDER_LEARNED) {
-        fcfc_tuning t = bt;
-        t.order = FCFC_ORDER_LEARNED;
-        consider(t);
+    // 2.-6. coordinate descent from a start: histogram copies, tile width,
+    // look-up table length, workgroup size and, with a model, the learned order
+    auto descend = [&](const fcfc_tuning& start, double start_ms) {
+        bt = start;
+        bms = start_ms;
+        const int copies[2] = {2, 4};
+        for (int cp : copies) {
+            fcfc_tuning t = bt;
+            if ((bt.hist_copies == 0 ? 1 : bt.hist_copies) == cp) continue;
+            t.hist_copies = cp;
+            consider(t);
+        }
+        {
+            fcfc_tuning t = bt;
+            t.tile_points = (bt.tile_points == 64) ? 128 : 64;
+            consider(t);
+        }
+        const int luts[2] = {12, 14};
+        for (int lg : luts) {
+            fcfc_tuning t = bt;
+            if ((bt.lut_log2 == 0 ? 13 : bt.lut_log2) == lg) continue;
+            t.lut_log2 = lg;
+            consider(t);
+        }
+        const int gws[3] = {16, 14, 12};
+        {
+            const fcfc_tuning t1 = bt;
+            for (int gw : gws) {
+                if (t1.group_waves == gw) continue;
+                fcfc_tuning t = t1;
+                t.group_waves = gw;
+                consider(t);
+            }
+        }
+        if (model && bt.order != FCFC_ORDER_LEARNED) {
+            fcfc_tuning t = bt;
+            t.order = FCFC_ORDER_LEARNED;
+            consider(t);
+        }
+    };
+    descend(bt, bms);
+    // A cell size the model proposed may win the first step by timing noise
+    // alone; the other knobs are then searched from the model-free start too,
+    // so that a model only ever adds candidates to the model-free search.
+    if (model && isfinite(bms_free) && bt_free.cells_per_rmax != bt.cells_per_rmax) {
+        const fcfc_tuning best_a = bt;
+        const double ms_a = bms;
+        descend(bt_free, bms_free);
+        if (!(bms < ms_a)) {
+            bt = best_a;
+            bms = ms_a;
+        }
     }
     if (c.ev0) (void)hipEventDestroy(c.ev0);
     if (c.ev1) (void)hipEventDestroy(c.ev1);
