@@ -585,6 +585,25 @@ fcfc_status fcfc_count_triplets(fcfc_plan_t plan, fcfc_cells_t cells, int64_t *d
 fcfc_status fcfc_xi(int32_t nterms, const double *const *d_terms, const double *coef,
                     const double *norm, int32_t den, int64_t nbins, double *d_xi, void *stream);
 /*
+ * fcfc_pair_norm -- the number of pairs behind a count, the normalisation of
+ * the estimators (Sect. 1, App. D): n1 (n1 - 1) / 2 for an auto count of n1
+ * points (n2 < 0), n1 n2 for a cross count; formed exactly in 128-bit
+ * integers and rounded once to FP64.  Host only.  Weighted counts are
+ * normalised by sums of weight products instead (pass them to fcfc_xi).
+ * Errors: FCFC_EINVAL (null output, n1 < 0).
+ */
+fcfc_status fcfc_pair_norm(int64_t n1, int64_t n2, double *out);
+/*
+ * fcfc_landy_szalay -- the Landy-Szalay estimator of unweighted counts:
+ * xi = (DD/nDD - 2 DR/nDR + RR/nRR) / (RR/nRR) per bin, with the pair
+ * normalisations of fcfc_pair_norm (auto DD of n_d points, cross DR, auto RR
+ * of n_r points).  d_dd, d_dr, d_rr: device FP64 [nbins] (counts, exact below
+ * 2^53); d_xi: device FP64 [nbins], overwritten; NaN where RR is zero.
+ * Errors: FCFC_EINVAL (null arrays, n_d or n_r below 2), FCFC_EHIP.
+ */
+fcfc_status fcfc_landy_szalay(const double *d_dd, const double *d_dr, const double *d_rr, int64_t n_d,
+                              int64_t n_r, int64_t nbins, double *d_xi, void *stream);
+/*
  * fcfc_analytic_rr -- the pair counts of a uniform periodic box for the plan's
  * bins: npairs * V_bin / L^3 (npairs = N (N - 1) / 2 for an auto count, or
  * ((sum w)^2 - sum w^2) / 2 weighted).  V_bin is the separation-space volume

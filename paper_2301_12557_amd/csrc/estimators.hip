@@ -142,6 +142,34 @@ extern "C" fcfc_status fcfc_xi(int32_t nterms, const double* const* d_terms, con
     return FCFC_OK;
 }
 
+extern "C" fcfc_status fcfc_pair_norm(int64_t n1, int64_t n2, double* out) {
+    clear_error();
+    if (!out || n1 < 0) {
+        set_error("pair_norm: null output or negative size");
+        return FCFC_EINVAL;
+    }
+    const __int128 a = n1;
+    const __int128 pairs = n2 < 0 ? a * (a - 1) / 2 : a * (__int128)n2;
+    *out = (double)pairs;
+    return FCFC_OK;
+}
+
+extern "C" fcfc_status fcfc_landy_szalay(const double* d_dd, const double* d_dr, const double* d_rr, int64_t n_d,
+                                         int64_t n_r, int64_t nbins, double* d_xi, void* stream) {
+    clear_error();
+    if (!d_dd || !d_dr || !d_rr || n_d < 2 || n_r < 2) {
+        set_error("landy_szalay: need DD, DR and RR and at least 2 data and 2 random points");
+        return FCFC_EINVAL;
+    }
+    double norm[3];
+    FCFC_TRY(fcfc_pair_norm(n_d, -1, &norm[0]));
+    FCFC_TRY(fcfc_pair_norm(n_d, n_r, &norm[1]));
+    FCFC_TRY(fcfc_pair_norm(n_r, -1, &norm[2]));
+    const double* terms[3] = {d_dd, d_dr, d_rr};
+    const double coef[3] = {1.0, -2.0, 1.0};
+    return fcfc_xi(3, terms, coef, norm, 2, nbins, d_xi, stream);
+}
+
 extern "C" fcfc_status fcfc_analytic_rr(fcfc_plan_t plan, double npairs, double* d_rr, void* stream) {
     clear_error();
     Plan* p = (Plan*)plan;

@@ -119,6 +119,8 @@ SIGNATURES = [
     ("fcfc_diag_peaks", _I32, [ctypes.POINTER(_D), ctypes.POINTER(_D), ctypes.POINTER(_D), ctypes.POINTER(_D), _P]),
     ("fcfc_xi", _I32, [_I32, ctypes.POINTER(_P), ctypes.POINTER(_D), ctypes.POINTER(_D), _I32, _I64, _P, _P]),
     ("fcfc_analytic_rr", _I32, [_P, _D, _P, _P]),
+    ("fcfc_pair_norm", _I32, [_I64, _I64, ctypes.POINTER(_D)]),
+    ("fcfc_landy_szalay", _I32, [_P, _P, _P, _I64, _I64, _I64, _P, _P]),
     ("fcfc_multipoles", _I32, [_P, _I32, ctypes.POINTER(_D), _I32, ctypes.POINTER(_I32), _I32, _P, _P]),
     ("fcfc_wp", _I32, [_P, _I32, ctypes.POINTER(_D), _I32, _P, _P]),
     ("fcfc_radec_to_unit", _I32, [_P, _P, _I64, _P, _P]),
@@ -598,10 +600,25 @@ def xi(terms, coef, norm, den, stream=None):
     return out
 
 
+def pair_norm(n1, n2=None):
+    """Pairs behind a count: n1 (n1 - 1) / 2 (auto, n2 None) or n1 n2 (fcfc_pair_norm)."""
+    out = _D()
+    check(load().fcfc_pair_norm(int(n1), -1 if n2 is None else int(n2), ctypes.byref(out)))
+    return out.value
+
+
 def landy_szalay(dd, dr, rr, n_d, n_r, stream=None):
-    """LS estimator for auto counts DD, RR and the cross DR of n_d data and n_r random points."""
-    return xi([dd.double(), dr.double(), rr.double()], [1.0, -2.0, 1.0],
-              [n_d * (n_d - 1) / 2.0, float(n_d) * n_r, n_r * (n_r - 1) / 2.0], 2, stream)
+    """LS estimator (fcfc_landy_szalay) of auto counts DD, RR and the cross DR of
+    n_d data and n_r random points; the result has DD's shape."""
+    import torch
+    t = [_f64_dev(x.double().contiguous(), name) for x, name in ((dd, "dd"), (dr, "dr"), (rr, "rr"))]
+    n = t[0].numel()
+    if any(x.numel() != n for x in t):
+        raise ValueError("DD, DR and RR need the same number of bins")
+    out = torch.empty(n, dtype=torch.float64, device=t[0].device)
+    check(load().fcfc_landy_szalay(t[0].data_ptr(), t[1].data_ptr(), t[2].data_ptr(), int(n_d), int(n_r), n,
+                                   out.data_ptr(), _stream_ptr(stream)))
+    return out.view(dd.shape)
 
 
 def analytic_rr(plan, npairs, stream=None):

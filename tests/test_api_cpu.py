@@ -367,3 +367,17 @@ def test_weight_scale_cross_and_triangles():
     assert lib.fcfc_weight_scale(-1.0, 1.0, 1.0, 1.0, 2, ctypes.byref(S)) == -1
     assert lib.fcfc_weight_scale(float("nan"), 1.0, 1.0, 1.0, 2, ctypes.byref(S)) == -1
     assert lib.fcfc_weight_scale(1.0, 1.0, 1.0, 1.0, 2, None) == -1
+
+
+def test_pair_norm_exact():
+    """Pairs behind a count, formed exactly and rounded once (host only)."""
+    assert fcfc.pair_norm(4) == 6.0 and fcfc.pair_norm(3, 5) == 15.0 and fcfc.pair_norm(1) == 0.0
+    for n in (2_000_000, 40_000_000, 3_000_000_007, 2 ** 31 + 11):
+        assert fcfc.pair_norm(n) == float(n * (n - 1) // 2)
+        assert fcfc.pair_norm(n, n + 3) == float(n * (n + 3))
+    lib = fcfc.load()
+    out = ctypes.c_double()
+    assert lib.fcfc_pair_norm(-1, -1, ctypes.byref(out)) == -1
+    assert lib.fcfc_pair_norm(5, -1, None) == -1
+    # too few points: refused before anything touches a device
+    assert lib.fcfc_landy_szalay(None, None, None, 10, 10, 4, None, None) == -1

@@ -43,6 +43,22 @@ def test_linear_estimators():
         _close(g, E.xi_linear(terms, coef, norm[:len(terms)], den))
 
 
+def test_landy_szalay_normalises_in_the_library():
+    """fcfc_landy_szalay: the pair normalisations of auto DD, cross DR and auto
+    RR formed by the library equal N_D (N_D - 1) / 2, N_D N_R and N_R (N_R - 1) / 2
+    in the oracle's linear estimator; a zero RR bin gives NaN."""
+    from paper_2301_12557_amd import fcfc
+    rng = np.random.default_rng(3)
+    dd, dr, rr = (rng.integers(0, 10**7, (40, 40)).astype(np.float64) for _ in range(3))
+    rr[3, ::7] = 0.0
+    n_d, n_r = 2_000_000, 40_000_000
+    g = fcfc.landy_szalay(to_dev(dd), to_dev(dr), to_dev(rr), n_d, n_r).cpu().numpy()
+    assert g.shape == (40, 40)
+    norm = [n_d * (n_d - 1) / 2, float(n_d) * n_r, n_r * (n_r - 1) / 2]
+    _close(g.reshape(-1), E.xi_linear([dd.reshape(-1), dr.reshape(-1), rr.reshape(-1)], [1, -2, 1], norm, 2))
+    assert np.isnan(g[3, ::7]).all()
+
+
 @pytest.mark.parametrize("kind", ["s", "smu", "spi"])
 def test_analytic_rr(kind):
     from paper_2301_12557_amd import fcfc
