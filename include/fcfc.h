@@ -101,7 +101,12 @@ typedef struct {
                                 once it has claimed 2^flush_log2 candidate pairs since it last did,
                                 1..26 (0: 26); the bound that keeps the 32-bit LDS counters from
                                 overflowing, lowered only to exercise that merge */
-    int32_t reserved[2];
+    int32_t tree_leaf;       /* 0: the regular grid of Sect. 2.1.  32..128: a balanced k-d tree
+                                (Sect. 2.2) with leaves of at most this many points, counted
+                                through a dual-tree work list (Sect. 3.1); open boxes only
+                                (FCFC_EINVAL for a periodic plan).  Batches, triangle counts,
+                                predictions and the learned order take grid plans only */
+    int32_t reserved;
 } fcfc_tuning;
 
 /* Statistics of the last count on a plan (host copy; see fcfc_plan_stats). */

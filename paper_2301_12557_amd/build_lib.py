@@ -14,7 +14,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUTDIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(OUTDIR, "libfcfc.so")
-SOURCES = ["plan.cpp", "api.cpp", "mem.cpp", "build.hip", "worklist.hip", "count.hip", "batch.hip", "mlp.hip", "tune.cpp",
+SOURCES = ["plan.cpp", "api.cpp", "mem.cpp", "build.hip", "worklist.hip", "tree.hip", "count.hip", "batch.hip", "mlp.hip", "tune.cpp",
            "diag.hip", "estimators.hip", "angular.hip", "binning.hip", "triplets.hip", "noalloc.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",

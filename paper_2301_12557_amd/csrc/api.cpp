@@ -140,6 +140,6 @@ extern "C" fcfc_status fcfc_cells_info(fcfc_cells_t cells, int64_t* n_points, in
     Cells* c = (Cells*)cells;
     if (!c) return FCFC_EINVAL;
     if (n_points) *n_points = c->n;
-    if (n_cells) *n_cells = c->grid.ncell();
+    if (n_cells) *n_cells = c->tree ? (int64_t)tree_leaves(c) : c->grid.ncell();
     return FCFC_OK;
 }

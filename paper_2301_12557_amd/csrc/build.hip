@@ -357,7 +357,6 @@ struct GridArgs {
     double L;
 };
 
-enum : uint32_t { VF_NONFINITE = 1u, VF_BOX = 2u, VF_WNONFINITE = 4u };
 
 // Weight statistics of a workgroup: smallest non-zero and largest |w| as
 // ordered bits.  Each wave reduces its lanes with shuffles and one lane
@@ -501,7 +500,20 @@ static GridArgs make_grid_args(const Plan* p) {
     return g;
 }
 
+fcfc_status validate_points(Plan* p, const fcfc_catalog* cat, uint32_t* idx, uint32_t* keys, uint32_t* flags,
+                            uint64_t* wst, hipStream_t st) {
+    GridArgs g = make_grid_args(p);
+    fill_u32(flags, 0u, 1, st);
+    fill_u64(wst, 0ull, STAT_SLOTS * STAT_STRIDE, st);
+    if (cat->n > 0)
+        hipLaunchKernelGGL(k_keys, dim3((unsigned)((cat->n + 255) / 256)), dim3(256), 0, st, cat->xyz, cat->w, cat->n,
+                           g, key_xbits(p->grid.ncell()), keys, idx, flags, wst);
+    FCFC_HIP(hipGetLastError());
+    return FCFC_OK;
+}
+
 fcfc_status build_cells(Plan* p, const fcfc_catalog* cat, hipStream_t st, Cells** out) {
+    if (p->tune.tree_leaf > 0) return build_tree(p, cat, st, out);
     int64_t n = cat->n;
     const Grid& gr = p->grid;
     int64_t ncell = gr.ncell();

@@ -38,6 +38,10 @@ __device__ inline float4 ldc_f4(const float4* p, uint32_t i) {
 }
 __device__ inline double ldc_f64(const double* p, uint32_t i) { return ((const double FCFC_CONST*)p)[i]; }
 __device__ inline uint32_t ldc_u32(const uint32_t* p, uint32_t i) { return ((const uint32_t FCFC_CONST*)p)[i]; }
+__device__ inline int4 ldc_i4(const int4* p, uint32_t i) {
+    const int FCFC_CONST* q = (const int FCFC_CONST*)p + 4 * (size_t)i;
+    return make_int4(q[0], q[1], q[2], q[3]);
+}
 __device__ inline Item ldc_item(const Item* p, uint32_t i) {
     const uint32_t FCFC_CONST* q = (const uint32_t FCFC_CONST*)p + 8 * (size_t)i;
     Item it;
@@ -52,6 +56,7 @@ __device__ inline Item ldc_item(const Item* p, uint32_t i) {
     return it;
 }
 
+enum { COUNT_SINGLE = 0, COUNT_BATCH = 1, COUNT_TREE = 2 };
 constexpr int CT_MAX = 1024;        // threads per workgroup (16 waves: 4 per SIMD, one workgroup per CU)
 constexpr int QCAP = 192;           // compaction queue entries per wave (63 + 64 P), plus one dump entry
 // recheck entries per wave: RB_FLUSH - 1 waiting plus the up to 64 of one
@@ -97,6 +102,12 @@ struct CountArgs {
     int n1, n2, nbins;
     int nx;
     float side32;
+    // tree counts: lattice origins of the A and B leaves (units of tree_q),
+    // points per leaf, B leaves and B points
+    const int4* leaf_orgA;
+    const int4* leaf_orgB;
+    float tree_q;
+    uint32_t tree_leaf, tree_nleafB, nB;
     double L, halfL;
     float r2prune, d2small;
     float mu_n, tolA, tolB, tolC;
@@ -495,9 +506,13 @@ __device__ __attribute__((always_inline)) inline void bin_queue(ArgsRef a, const
 // Weighted and mid-point counts are held to 16 waves per CU by their LDS
 // tables and queues, so they keep the registers (capping the mid-point ones
 // at 80 only added spills).
-template <int KIND, int LOS, bool AUTO, bool W, int P, bool BATCH>
-__global__ __launch_bounds__(CT_MAX) __attribute__((amdgpu_waves_per_eu((W || LOS) ? 4 : 6))) void k_count(
-    const CountArgs* argp) {
+// MODE: COUNT_SINGLE (one grid count), COUNT_BATCH (a stacked build's pair
+// list) or COUNT_TREE (a count over k-d tree leaves).
+template <int KIND, int LOS, bool AUTO, bool W, int P, int MODE>
+__global__ __launch_bounds__(CT_MAX) __attribute__((amdgpu_waves_per_eu((W || LOS || MODE == COUNT_TREE) ? 4 : 6)))
+void k_count(const CountArgs* argp) {
+    constexpr bool BATCH = MODE == COUNT_BATCH;
+    constexpr bool TREE = MODE == COUNT_TREE;
     ArgsRef a = *(const CountArgs FCFC_CONST*)argp;
     extern __shared__ __align__(16) unsigned char smem[];
     const int tid = threadIdx.x;
@@ -578,6 +593,10 @@ __global__ __launch_bounds__(CT_MAX) __attribute__((amdgpu_waves_per_eu((W || LO
         float4 av[P];
         float4 aabs[P];
         uint32_t csv;  // lane t: start of B cell xw0 + t of the item's row
+        // tree: the A leaf origin, and in lane t the FP32 offset of B leaf
+        // b_rowcell + t from it
+        int4 ja;
+        float tox, toy, toz;
     };
     auto load_in = [&](uint32_t itx, ItemIn& in) __attribute__((always_inline)) {
         in.item = ldc_item(a.items, itx);
@@ -593,11 +612,19 @@ __global__ __launch_bounds__(CT_MAX) __attribute__((amdgpu_waves_per_eu((W || LO
                 if (i < acnt) in.aabs[p] = a.absA[a_begin + i];
             }
         }
-        const int xb0 = (int)(int16_t)(in.item.acnt_xb0 >> 16);
-        const int sxi = (int)((in.item.meta >> 16) & 3u) - 1;
-        const int xw0 = xb0 - sxi * a.nx;
-        const int cx = min(xw0 + lane, a.nx);
-        in.csv = a.csB[in.item.b_rowcell + (uint32_t)cx];
+        if (TREE) {
+            in.ja = ldc_i4(a.leaf_orgA, in.item.tile);
+            const int4 jb = a.leaf_orgB[min(in.item.b_rowcell + (uint32_t)lane, a.tree_nleafB - 1u)];
+            in.tox = (float)(jb.x - in.ja.x) * a.tree_q;
+            in.toy = (float)(jb.y - in.ja.y) * a.tree_q;
+            in.toz = (float)(jb.z - in.ja.z) * a.tree_q;
+        } else {
+            const int xb0 = (int)(int16_t)(in.item.acnt_xb0 >> 16);
+            const int sxi = (int)((in.item.meta >> 16) & 3u) - 1;
+            const int xw0 = xb0 - sxi * a.nx;
+            const int cx = min(xw0 + lane, a.nx);
+            in.csv = a.csB[in.item.b_rowcell + (uint32_t)cx];
+        }
     };
 
     unsigned long long wave_pairs = 0;  // pairs claimed since this wave last emptied the histogram
@@ -704,6 +731,8 @@ __global__ __launch_bounds__(CT_MAX) __attribute__((amdgpu_waves_per_eu((W || LO
         const float Dy = (float)idy * k.side32;
         const float Dz = (float)idz * k.side32;
         float ax[P], ay[P], az[P];
+        // tree: the A points relative to their leaf origin (offset per B leaf)
+        float ayr[P], azr[P];
         int acx[P];
         uint32_t aidx[P], ids_lane[P];
 #pragma unroll
@@ -715,6 +744,8 @@ __global__ __launch_bounds__(CT_MAX) __attribute__((amdgpu_waves_per_eu((W || LO
             ax[p] = v.x;
             ay[p] = v.y - Dy;
             az[p] = v.z - Dz;
+            ayr[p] = v.y;
+            azr[p] = v.z;
             acx[p] = __float_as_int(v.w);
             if (LOS == FCFC_LOS_MIDPOINT && KIND != FCFC_BIN_S) {
                 const float4 q = cur.aabs[p];
@@ -732,6 +763,41 @@ __global__ __launch_bounds__(CT_MAX) __attribute__((amdgpu_waves_per_eu((W || LO
         // Advance to the next cell of the row piece that holds points at or after
         // j (cells are consecutive in the sorted points); false when none is left.
         auto next_cell = [&]() __attribute__((always_inline)) -> bool {
+            if (j >= b_end) return false;  // the item's B points are done
+            if (TREE) {
+                // the next B leaf that holds points at or after j: its end, and
+                // the A points moved into its frame (leaf origins lie on a
+                // lattice of power-of-two spacing, so the offset is exact)
+                uint32_t leaf = item.b_rowcell + (uint32_t)t;
+                while (leaf < a.tree_nleafB) {
+                    uint32_t ce = min((leaf + 1u) * a.tree_leaf, a.nB);
+                    ce = ce < b_end ? ce : b_end;
+                    float ox, oy, oz;
+                    if (t < 64) {  // prefetched with the item
+                        ox = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(cur.tox), t));
+                        oy = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(cur.toy), t));
+                        oz = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(cur.toz), t));
+                    } else {
+                        const int4 jb = ldc_i4(a.leaf_orgB, leaf);
+                        ox = (float)(jb.x - cur.ja.x) * a.tree_q;
+                        oy = (float)(jb.y - cur.ja.y) * a.tree_q;
+                        oz = (float)(jb.z - cur.ja.z) * a.tree_q;
+                    }
+                    leaf++;
+                    t++;
+                    if (ce > j) {
+                        cell_end = ce;
+#pragma unroll
+                        for (int p = 0; p < P; p++) {
+                            axx[p] = ax[p] - ox;
+                            ay[p] = ayr[p] - oy;
+                            az[p] = azr[p] - oz;
+                        }
+                        return true;
+                    }
+                }
+                return false;
+            }
             while (xw < a.nx) {
                 uint32_t ce = (t + 1 < 64) ? __builtin_amdgcn_readlane(cur.csv, t + 1)
                                            : ldc_u32(a.csB, item.b_rowcell + (uint32_t)xw + 1u);
@@ -979,15 +1045,30 @@ __global__ void k_finalize_w(const unsigned long long* __restrict__ acc, int nbi
 // ---------------------------------------------------------------------------
 typedef void (*CountKernel)(const CountArgs*);
 
-template <int KIND, int LOS, bool AUTO, bool W, bool B>
+template <int KIND, int LOS, bool AUTO, bool W, int MODE>
 static CountKernel pick_p(int P) {
-    if (P == 1) return k_count<KIND, LOS, AUTO, W, 1, B>;
-    return k_count<KIND, LOS, AUTO, W, 2, B>;
+    if (P == 1) return k_count<KIND, LOS, AUTO, W, 1, MODE>;
+    return k_count<KIND, LOS, AUTO, W, 2, MODE>;
 }
 template <int KIND, int LOS>
 static CountKernel pick_aw(bool is_auto, bool w, int P) {
-    if (is_auto) return w ? pick_p<KIND, LOS, true, true, false>(P) : pick_p<KIND, LOS, true, false, false>(P);
-    return w ? pick_p<KIND, LOS, false, true, false>(P) : pick_p<KIND, LOS, false, false, false>(P);
+    if (is_auto)
+        return w ? pick_p<KIND, LOS, true, true, COUNT_SINGLE>(P) : pick_p<KIND, LOS, true, false, COUNT_SINGLE>(P);
+    return w ? pick_p<KIND, LOS, false, true, COUNT_SINGLE>(P) : pick_p<KIND, LOS, false, false, COUNT_SINGLE>(P);
+}
+// tree counts: tiles of 128 points (a leaf holds at most 128)
+template <int KIND, int LOS>
+static CountKernel pick_tw(bool is_auto, bool w) {
+    if (is_auto) return w ? k_count<KIND, LOS, true, true, 2, COUNT_TREE> : k_count<KIND, LOS, true, false, 2, COUNT_TREE>;
+    return w ? k_count<KIND, LOS, false, true, 2, COUNT_TREE> : k_count<KIND, LOS, false, false, 2, COUNT_TREE>;
+}
+static CountKernel pick_tree_kernel(int kind, int los, bool is_auto, bool w) {
+    if (kind == FCFC_BIN_S) return pick_tw<FCFC_BIN_S, FCFC_LOS_Z>(is_auto, w);
+    if (kind == FCFC_BIN_S_MU)
+        return los == FCFC_LOS_Z ? pick_tw<FCFC_BIN_S_MU, FCFC_LOS_Z>(is_auto, w)
+                                 : pick_tw<FCFC_BIN_S_MU, FCFC_LOS_MIDPOINT>(is_auto, w);
+    return los == FCFC_LOS_Z ? pick_tw<FCFC_BIN_SPERP_PI, FCFC_LOS_Z>(is_auto, w)
+                             : pick_tw<FCFC_BIN_SPERP_PI, FCFC_LOS_MIDPOINT>(is_auto, w);
 }
 static CountKernel pick_kernel(int kind, int los, bool is_auto, bool w, int P) {
     if (kind == FCFC_BIN_S) return pick_aw<FCFC_BIN_S, FCFC_LOS_Z>(is_auto, w, P);
@@ -1002,7 +1083,7 @@ static CountKernel pick_kernel(int kind, int los, bool is_auto, bool w, int P) {
 // same-row flag
 template <int KIND, int LOS>
 static CountKernel pick_bw(bool w, int P) {
-    return w ? pick_p<KIND, LOS, true, true, true>(P) : pick_p<KIND, LOS, true, false, true>(P);
+    return w ? pick_p<KIND, LOS, true, true, COUNT_BATCH>(P) : pick_p<KIND, LOS, true, false, COUNT_BATCH>(P);
 }
 static CountKernel pick_batch_kernel(int kind, int los, bool w, int P) {
     if (kind == FCFC_BIN_S) return pick_bw<FCFC_BIN_S, FCFC_LOS_Z>(w, P);
@@ -1043,10 +1124,13 @@ static int tile_seg(const Plan* p) { return p->tune.seg_cells > 0 ? std::min(32,
 
 static fcfc_status setup_launch(Plan* p, bool is_auto, bool weighted, bool batch, int S, LaunchSetup& L) {
     const Grid& g = p->grid;
-    L.T = p->tune.tile_points == 64 ? 64 : 128;
+    const bool tree = p->tune.tree_leaf > 0 && !batch;
+    L.T = (tree || p->tune.tile_points != 64) ? 128 : 64;
     L.P = L.T / 64;
     L.seg = tile_seg(p);
-    L.bchunk = p->tune.b_chunk >= 256 ? p->tune.b_chunk : 16384;
+    // B points per item: tree ranges (whole subtrees) are cut finer than the
+    // grid's row pieces, which are short by themselves
+    L.bchunk = p->tune.b_chunk >= 256 ? p->tune.b_chunk : (tree ? 2048 : 16384);
     L.copies = (p->tune.hist_copies == 2 || p->tune.hist_copies == 4) ? p->tune.hist_copies : 1;
     L.nrows = stencil_rows(p, is_auto, L.rows);
     const bool two = (p->kind == FCFC_BIN_SPERP_PI);
@@ -1056,8 +1140,9 @@ static fcfc_status setup_launch(Plan* p, bool is_auto, bool weighted, bool batch
     int dev = 0, maxlds = 65536;
     FCFC_HIP(hipGetDevice(&dev));
     if (hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) maxlds = 65536;
-    L.kern = batch ? pick_batch_kernel(p->kind, p->los, weighted, L.P)
-                   : pick_kernel(p->kind, p->los, is_auto, weighted, L.P);
+    L.kern = tree    ? pick_tree_kernel(p->kind, p->los, is_auto, weighted)
+             : batch ? pick_batch_kernel(p->kind, p->los, weighted, L.P)
+                     : pick_kernel(p->kind, p->los, is_auto, weighted, L.P);
     FCFC_HIP(hipFuncSetAttribute((const void*)L.kern, hipFuncAttributeMaxDynamicSharedMemorySize, maxlds));
     // LDS shared by the workgroup's waves for tables of n1t and n2t entries
     auto shared_for = [&](int n1t, int n2t) {
@@ -1355,6 +1440,24 @@ fcfc_status count_pairs(Plan* p, Cells* c1, Cells* c2, int64_t* d_counts, double
     Cells* cb = is_auto ? c1 : c2;
     const bool weighted = d_wcounts != nullptr;
     const Grid& g = p->grid;
+    const bool tree = c1->tree;
+    if (tree != cb->tree || tree != (p->tune.tree_leaf > 0)) {
+        set_error("count_pairs: cell sets and plan disagree on grid or tree");
+        return FCFC_EGRID;
+    }
+    if (tree) {
+        if (pr) {
+            set_error("count_pairs: predictions take grid plans only");
+            return FCFC_EINVAL;
+        }
+        // FP32 bands for leaf-local coordinates: rebuilt when these trees hold
+        // points farther from their leaf origins than the bands assume
+        const double ext = std::max(c1->tree_ext, cb->tree_ext);
+        if (ext > p->tree_side) {
+            p->tree_side = ext * (1.0 + 1e-9);
+            FCFC_TRY(plan_finalize_numerics(p));
+        }
+    }
     int S = 0;
     if (weighted) {
         if (!c1->weighted || !cb->weighted) {
@@ -1367,17 +1470,19 @@ fcfc_status count_pairs(Plan* p, Cells* c1, Cells* c2, int64_t* d_counts, double
     FCFC_TRY(setup_launch(p, is_auto, weighted, false, S, L));
     CountArgs& a = L.a;
     const bool sorted = !pr && p->tune.order != FCFC_ORDER_BUILT;
-    const Model* model = pr ? pr->model : (p->tune.order == FCFC_ORDER_LEARNED ? p->model : nullptr);
+    const Model* model =
+        pr ? pr->model : ((p->tune.order == FCFC_ORDER_LEARNED && !tree) ? p->model : nullptr);
     WLArgs w = make_wl(p, L, is_auto, 1, c1->n);
     w.keyB = cb->xkey;
     w.xbits = cb->xbits;
-    const int64_t nseg = (int64_t)g.ny * g.nz;  // A rows (tile counts per row)
-    const int64_t tiles_cap = w.tiles_cap;
+    // grid: A rows and tiles x stencil rows; tree: A leaves
+    const int64_t nseg = tree ? 1 : (int64_t)g.ny * g.nz;
+    const int64_t tiles_cap = tree ? 1 : w.tiles_cap;
     if (tiles_cap >= 0xffffffffLL / std::max(1, L.nrows)) {
         set_error("count_pairs: work list too large");
         return FCFC_ERANGE;
     }
-    const int64_t npair_tr = tiles_cap * w.nrows;
+    const int64_t npair_tr = tree ? ((int64_t)tree_leaves(c1) << tree_wl_split(c1, cb)) : tiles_cap * w.nrows;
 
     // scratch 1: tables, tiles, tile counts/offsets, item counts/offsets, counters, arguments
     size_t s_tab = al256(L.tb_total);
@@ -1430,12 +1535,17 @@ fcfc_status count_pairs(Plan* p, Cells* c1, Cells* c2, int64_t* d_counts, double
     FCFC_HIP(hipMemcpyAsync(tab, p->host_stage.data(), L.tb_total, hipMemcpyHostToDevice, st));
     int4* srows = bind_tables(L, tab, a);
     fill_u32(ctr, 0u, 64, st);
-    hipLaunchKernelGGL(k_tile_count, dim3((unsigned)((nseg + 255) / 256)), dim3(256), 0, st, c1->cell_start, w, tcount);
-    scan_exclusive_u32(tcount, toff, nseg, &ctr[0], scan_scr, st);
-    hipLaunchKernelGGL(k_tile_write, dim3((unsigned)((nseg + 255) / 256)), dim3(256), 0, st, c1->cell_start, c1->xkey,
-                       w, toff, tiles);
-    hipLaunchKernelGGL(k_item_count, dim3((unsigned)((npair_tr + 255) / 256)), dim3(256), 0, st, tiles, &ctr[0], srows,
-                       cb->cell_start, w, icount);
+    if (tree) {
+        tree_items_enqueue(c1, cb, is_auto, p->rprune, p->coord_max, L.bchunk, nullptr, icount, nullptr, 0, st);
+    } else {
+        hipLaunchKernelGGL(k_tile_count, dim3((unsigned)((nseg + 255) / 256)), dim3(256), 0, st, c1->cell_start, w,
+                           tcount);
+        scan_exclusive_u32(tcount, toff, nseg, &ctr[0], scan_scr, st);
+        hipLaunchKernelGGL(k_tile_write, dim3((unsigned)((nseg + 255) / 256)), dim3(256), 0, st, c1->cell_start,
+                           c1->xkey, w, toff, tiles);
+        hipLaunchKernelGGL(k_item_count, dim3((unsigned)((npair_tr + 255) / 256)), dim3(256), 0, st, tiles, &ctr[0],
+                           srows, cb->cell_start, w, icount);
+    }
     scan_exclusive_u32(icount, ioff, npair_tr, &ctr[1], scan_scr, st);
     uint32_t hctr[2] = {0, 0};
     FCFC_HIP(hipMemcpyAsync(hctr, ctr, 8, hipMemcpyDeviceToHost, st));
@@ -1463,8 +1573,11 @@ fcfc_status count_pairs(Plan* p, Cells* c1, Cells* c2, int64_t* d_counts, double
     }
     Item* items = (Item*)scr2;
     Item* items2 = (Item*)(scr2 + s_items);
-    hipLaunchKernelGGL(k_item_write, dim3((unsigned)((npair_tr + 255) / 256)), dim3(256), 0, st, tiles, &ctr[0], srows,
-                       cb->cell_start, w, ioff, items, nitems);
+    if (tree)
+        tree_items_enqueue(c1, cb, is_auto, p->rprune, p->coord_max, L.bchunk, ioff, nullptr, items, nitems, st);
+    else
+        hipLaunchKernelGGL(k_item_write, dim3((unsigned)((npair_tr + 255) / 256)), dim3(256), 0, st, tiles, &ctr[0],
+                           srows, cb->cell_start, w, ioff, items, nitems);
     Item* run_items = items;
     float* pred = model ? (float*)(scr2 + 2 * s_items + 4 * s_sort + s_rs + s_times) : nullptr;
     const float kcells = (float)(p->rprune / g.side);
@@ -1537,6 +1650,14 @@ fcfc_status count_pairs(Plan* p, Cells* c1, Cells* c2, int64_t* d_counts, double
     a.p64B = cb->pos64;
     a.wB = cb->w;
     a.csB = cb->cell_start;
+    if (tree) {
+        a.leaf_orgA = c1->leaf_org;
+        a.leaf_orgB = cb->leaf_org;
+        a.tree_q = (float)c1->tree_q;
+        a.tree_leaf = (uint32_t)cb->xbits;
+        a.tree_nleafB = tree_leaves(cb);
+        a.nB = (uint32_t)cb->n;
+    }
     a.items = run_items;
     a.nitems_dev = &ctr[1];
     a.cursor = &ctr[2];
@@ -1576,7 +1697,7 @@ fcfc_status count_pairs(Plan* p, Cells* c1, Cells* c2, int64_t* d_counts, double
     p->last_stream = st;
     p->have_stats = keep_stats;
     p->stats.items = nitems;
-    p->stats.cells = g.ncell();
+    p->stats.cells = tree ? (int64_t)tree_leaves(c1) : g.ncell();
     p->stats.grid[0] = g.nx;
     p->stats.grid[1] = g.ny;
     p->stats.grid[2] = g.nz;
@@ -1754,6 +1875,10 @@ static void batch_enqueue_back(BatchImpl* b, hipStream_t st) {
 
 fcfc_status batch_create_impl(Plan* p, const fcfc_catalog* cats, int ncat, const int32_t* pairs, int npairs,
                               hipStream_t st, BatchImpl** out) {
+    if (p->tune.tree_leaf > 0) {
+        set_error("batch_create: batches take grid plans (tree_leaf = 0)");
+        return FCFC_EINVAL;
+    }
     if (p->L <= 0 && !p->grid_set) {
         set_error("batch_create: an open-box plan needs fcfc_plan_fit_bounds or fcfc_plan_set_bounds first");
         return FCFC_ESTATE;

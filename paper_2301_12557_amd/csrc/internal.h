@@ -130,6 +130,9 @@ struct Plan {
     std::vector<char> host_args;
     // learned cost model for FCFC_ORDER_LEARNED (not owned)
     struct Model* model = nullptr;
+    // tree plans: the leaf extent the FP32 bands were built for (raised, and
+    // the bands rebuilt, when a count meets larger leaves)
+    double tree_side = 0;
 };
 
 struct Cells {
@@ -149,6 +152,17 @@ struct Cells {
     uint32_t* xkey = nullptr;
     int xbits = 0;
     void* block = nullptr;      // single allocation holding everything
+    // k-d tree of a tree plan: points in tree order, 2^tree_levels leaves
+    // (cell_start then holds the leaf offsets), each leaf's points relative
+    // to a lattice origin leaf_org * tree_q (tree_q a power of two, so that
+    // the FP32 offset between two leaves is exact), and the FP64 bounding
+    // box of every node in heap order (node h has children 2h+1, 2h+2)
+    bool tree = false;
+    int tree_levels = 0;
+    int4* leaf_org = nullptr;
+    double* node_box = nullptr;  // 6 per node: lo x, y, z, hi x, y, z
+    double tree_q = 0;
+    double tree_ext = 0;         // largest coordinate of a point relative to its leaf origin
 };
 
 // Sub-cell x bits of the sort key for a grid of ncells cells (catalogues x
@@ -177,6 +191,22 @@ fcfc_status weight_scale_rule(double wmin1, double wmax1, double wmin2, double w
 
 // build (build.hip)
 fcfc_status build_cells(Plan* p, const fcfc_catalog* cat, hipStream_t st, Cells** out);
+// k-d tree build and dual-tree work list (tree.hip)
+fcfc_status build_tree(Plan* p, const fcfc_catalog* cat, hipStream_t st, Cells** out);
+// Work items of a tree count: every A leaf against the B ranges its
+// traversal of the B tree keeps; item counts per A leaf into icount (count
+// pass, items == nullptr) or the items at ioff (write pass).
+void tree_items_enqueue(const Cells* ca, const Cells* cb, bool is_auto, double rprune, double coord_max, int bchunk,
+                        const uint32_t* ioff, uint32_t* icount, Item* items, uint32_t items_cap, hipStream_t st);
+uint32_t tree_leaves(const Cells* c);
+// B tree level split among the work-list threads: tree_leaves(ca) << split slots
+int tree_wl_split(const Cells* ca, const Cells* cb);
+// validation flags of a build
+enum : uint32_t { VF_NONFINITE = 1u, VF_BOX = 2u, VF_WNONFINITE = 4u };
+// validation of a catalogue against the plan (finite, inside the box) and its
+// weight range, with idx[i] = i (build.hip)
+fcfc_status validate_points(Plan* p, const fcfc_catalog* cat, uint32_t* idx, uint32_t* keys, uint32_t* flags,
+                            uint64_t* wst, hipStream_t st);
 fcfc_status fit_bounds(Plan* p, const fcfc_catalog* cats, int ncat, hipStream_t st);
 void fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t st);
 void fill_u64(uint64_t* p, uint64_t v, int64_t n, hipStream_t st);

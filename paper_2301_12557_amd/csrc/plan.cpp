@@ -243,7 +243,9 @@ fcfc_status plan_finalize_numerics(Plan* p) {
     const Grid& g = p->grid;
     const double u = U32;
     double r = p->rprune;
-    double side = g.side * (1.0 + 1e-6);
+    // cell-local coordinates (grid) or leaf-local ones (tree, once a count
+    // has met the trees: the largest coordinate relative to a leaf origin)
+    double side = ((p->tune.tree_leaf > 0 && p->tree_side > 0) ? p->tree_side : g.side) * (1.0 + 1e-6);
     double coord = std::max(p->coord_max, p->L);
     double e = 2.0 * u * (9.0 * side + 4.0 * r * 1.01) + 8e-16 * (coord + r) * 4.0;
     p->e_axis = e;
@@ -398,6 +400,10 @@ extern "C" fcfc_status fcfc_plan_create(int32_t kind, int32_t los, const double*
     }
     if (!(box_L >= 0) || !isfinite(box_L)) {
         set_error("plan_create: box_L must be finite and >= 0");
+        return FCFC_EINVAL;
+    }
+    if (tune && tune->tree_leaf != 0 && (tune->tree_leaf < 32 || tune->tree_leaf > 128 || box_L > 0)) {
+        set_error("plan_create: tree_leaf must be 0 or 32..128, and trees need an open box");
         return FCFC_EINVAL;
     }
     if (kind == FCFC_BIN_S) los = FCFC_LOS_Z;

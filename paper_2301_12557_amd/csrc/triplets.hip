@@ -470,6 +470,10 @@ extern "C" fcfc_status fcfc_count_triplets(fcfc_plan_t plan, fcfc_cells_t cells,
         set_error("count_triplets: null cells or output");
         return FCFC_EINVAL;
     }
+    if (c->tree) {
+        set_error("count_triplets: takes the cells of a grid plan");
+        return FCFC_EINVAL;
+    }
     if (c->plan_id != p->id) {
         set_error("count_triplets: the cell set was built on a different plan");
         return FCFC_EGRID;

@@ -40,7 +40,7 @@ class Tuning(ctypes.Structure):
                 ("lut_log2", ctypes.c_int32), ("group_waves", ctypes.c_int32),
                 ("shard_count", ctypes.c_int32), ("shard_index", ctypes.c_int32),
                 ("batch_chunk", ctypes.c_int32), ("flush_log2", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 2)]
+                ("tree_leaf", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -661,7 +661,7 @@ def wp(xi_spi, pi_edges, stream=None):
 
 TUNING_KEYS = ("cells_per_rmax", "tile_points", "seg_cells", "b_chunk", "hist_copies", "order",
                "record_timing", "n_hint", "lut_log2", "group_waves", "shard_count", "shard_index", "batch_chunk",
-               "flush_log2")
+               "flush_log2", "tree_leaf")
 
 
 def autotune(x1, x2=None, *, model=None, kind="s", edges1, edges2=None, los="z", box=0.0, w1=None, w2=None,

@@ -381,3 +381,15 @@ def test_pair_norm_exact():
     assert lib.fcfc_pair_norm(5, -1, None) == -1
     # too few points: refused before anything touches a device
     assert lib.fcfc_landy_szalay(None, None, None, 10, 10, 4, None, None) == -1
+
+
+def test_tree_plan_validation():
+    """Tree plans: leaves of 32..128 points, open boxes only (host checks)."""
+    t = fcfc.Tuning()
+    for leaf, box, rc in ((128, 0.0, 0), (32, 0.0, 0), (31, 0.0, -1), (129, 0.0, -1), (64, 1000.0, -1)):
+        t.tree_leaf = leaf
+        assert _create(kind=2, los=1, e1=[0, 1, 2], e2=[0, 1, 3], L=box, tune=t) == rc, (leaf, box)
+    p = fcfc.Plan("spi", [0.0, 10.0, 20.0], [0.0, 10.0, 20.0], los="mid", box=0.0, tree_leaf=64)
+    p.set_bounds([500.0, 0.0, -100.0], [900.0, 400.0, 100.0])
+    assert p.numerics()["nx"] > 0
+    p.close()
