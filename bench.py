@@ -690,15 +690,45 @@ def c3_section(fcfc, synth, torch, rr_shards=8):
             e["note"] = note
         return e
 
-    plan.count(cells["data"], weighted=True)
+    grid_hist = {}
+    walls = {}
+    walls["DD"], (c, wc) = _sync_time(lambda: plan.count(cells["data"], weighted=True))
+    grid_hist["DD"] = (c.clone(), wc.clone())
     out["DD"] = entry(plan.stats(), plan.stats()["kernel_ms"])
     log(f"C3 DD: {out['DD']['kernel_ms']:.1f} ms")
-    plan.count(cells["data"], cells["randoms"], weighted=True)
+    walls["DR"], (c, wc) = _sync_time(lambda: plan.count(cells["data"], cells["randoms"], weighted=True))
+    grid_hist["DR"] = (c.clone(), wc.clone())
     st = plan.stats()
     out["DR"] = entry(st, st["kernel_ms"])
     log(f"C3 DR: {out['DR']['kernel_ms']:.0f} ms; RR in {rr_shards} shards next "
         f"(about {10 * out['DR']['kernel_ms'] / 1e3:.0f} s)")
     plan.close()
+    for cl in cells.values():
+        cl.close()
+    # the same DD and DR through the k-d tree (leaves of 128 points)
+    tree = {"leaf_points": 128}
+    tplan = fcfc.Plan("spi", w["edges1"], w["edges2"], tree_leaf=128, **kw)
+    tplan.fit_bounds([(d, None), (r, None)])
+    tcells = {}
+    tb = {}
+    for name, x, wt in (("data", d, wd), ("randoms", r, wr)):
+        tb[name], tcells[name] = _sync_time(lambda: tplan.build_cells(x, wt))
+    tree["build_ms"] = tb
+    tree["grid_build_ms"] = builds
+    for name, args in (("DD", (tcells["data"],)), ("DR", (tcells["data"], tcells["randoms"]))):
+        wall, (c, wc) = _sync_time(lambda: tplan.count(*args, weighted=True))
+        st = tplan.stats()
+        g_c, g_wc = grid_hist[name]
+        tree[name] = dict(entry(st, st["kernel_ms"]), wall_ms=wall, items=int(st["items"]),
+                          grid_wall_ms=walls[name], grid_kernel_ms=out[name]["kernel_ms"],
+                          grid_distance_evaluations=out[name]["distance_evaluations"],
+                          equal_to_grid=bool(torch.equal(c, g_c) and torch.equal(wc, g_wc)))
+        log(f"C3 {name} tree: kernel {st['kernel_ms']:.1f} ms (grid {out[name]['kernel_ms']:.1f}), "
+            f"wall {wall:.1f} ms (grid {walls[name]:.1f}), equal {tree[name]['equal_to_grid']}")
+    for cl in tcells.values():
+        cl.close()
+    tplan.close()
+    del grid_hist
     tot = {"in_range": 0, "candidates": 0, "rechecks": 0}
     kms = 0.0
     hist = None
@@ -718,13 +748,11 @@ def c3_section(fcfc, synth, torch, rr_shards=8):
     tot["in_range"] = int(hist.sum())
     out["RR"] = entry(tot, kms, note=f"{rr_shards} launches over disjoint shards of the work list; "
                                      "kernel_ms is their sum, the histograms sum to the whole RR count")
-    for c in cells.values():
-        c.close()
     del d, r, wd, wr
     torch.cuda.empty_cache()
     return {"workload": "C3 open survey shell r in [1000,2000], RA 60 deg x Dec 30 deg, data 2,000,000 + "
                         "randoms 40,000,000, weighted (s_perp,pi) 40x40 over [0,200), mid-point LOS",
-            "build_ms": builds, "counts": out}
+            "build_ms": builds, "counts": out, "tree": tree}
 
 
 def main():
