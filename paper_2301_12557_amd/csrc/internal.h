@@ -109,6 +109,8 @@ struct Plan {
     Lut1D lut1, lut2;           // s (or s_perp) and pi tables
     Lut1D lut1b, lut2b;         // the same with twice the entries (has_big)
     Lut1D lutbin;               // first-axis table for binning given FP64 values (built on first use)
+    Lut1D luttri;               // table for FP32 triangle sides (bands for luttri_e per axis)
+    double luttri_e = 0;
     bool has_big = false;       // counts may use the larger tables where LDS allows
     float r2prune32 = 0;        // FP32 candidate threshold (>= every relevant value)
     float d2small = 0;          // pairs closer than this are always rechecked (mu)
@@ -180,7 +182,11 @@ int stencil_rows(const Plan* p, bool half, std::vector<int4>& rows);
 // Table over the first-axis squared edges for binning values given in FP64:
 // its bands cover only the rounding of a value to FP32, so it depends on the
 // edges alone (no grid); built on first use and kept by the plan.
-fcfc_status plan_bin_table(Plan* p, const Lut1D** out);  // (dy, dz, kx, float bits of the x reach)
+fcfc_status plan_bin_table(Plan* p, const Lut1D** out);
+// Table over the first-axis squared edges for squared lengths formed in FP32
+// from components each within e_axis of their FP64 values (triangle sides);
+// rebuilt when e_axis changes, kept by the plan.
+fcfc_status plan_side_table(Plan* p, double e_axis, const Lut1D** out);
 
 // Fixed-point scale 2^S of the exact weighted sums (plan.cpp): every non-zero
 // product of nfactors (2: pairs, 3: triangles) weights is an integer below

@@ -239,6 +239,25 @@ fcfc_status plan_bin_table(Plan* p, const Lut1D** out) {
     return FCFC_OK;
 }
 
+fcfc_status plan_side_table(Plan* p, double e_axis, const Lut1D** out) {
+    if (p->luttri.n == 0 || p->luttri_e != e_axis) {
+        // |Q32 - Q64| <= 2 sqrt3 e sqrt(Q) + 3 e^2 + 3.3 u Q for a squared
+        // length formed by an fma chain from FP32 components each within e of
+        // the FP64 ones (the same form as the pair counts' squared separation)
+        ErrModel m;
+        m.A = 2.0 * sqrt(3.0) * e_axis;
+        m.B = 3.0 * e_axis * e_axis;
+        m.C = 3.3 * U32 + 1e-15;
+        const int lg = p->tune.lut_log2 > 0 ? std::min(14, std::max(8, p->tune.lut_log2)) : 13;
+        Lut1D t;
+        FCFC_TRY(build_lut(t, p->e1, m, lg));
+        p->luttri = t;
+        p->luttri_e = e_axis;
+    }
+    *out = &p->luttri;
+    return FCFC_OK;
+}
+
 fcfc_status plan_finalize_numerics(Plan* p) {
     const Grid& g = p->grid;
     const double u = U32;

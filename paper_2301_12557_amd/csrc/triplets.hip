@@ -35,6 +35,7 @@
 namespace fcfc {
 
 constexpr int TRI_CAP = 128;       // list entries per LDS region (two regions per wave)
+constexpr int TRI_PAIRS = TRI_CAP * (TRI_CAP - 1) / 2;  // pairs of one full list
 constexpr int TRI_MAX_WAVES = 16;
 constexpr int TRI_MAX_BINS = 32;   // sorted bin triples: C(34, 3) = 5984 u64 counters
 
@@ -47,15 +48,16 @@ struct TriArgs {
     int nst;
     int nx, ny, nz;
     double L, halfL;          // L > 0: periodic
-    double inner;             // > 0: a primary farther than this from every face needs no wrap for its pairs
+    double inner;             // > 0: a primary farther than this from every face has no wrapped neighbour
+    int exact_pairs;          // 1: two neighbours may differ by more than L/2 per axis (L < 4 r): FP64 sides
     int64_t n;
     const double* w;          // sorted weights (weighted counts)
     double wscale;            // 2^S
     unsigned long long* out_w;  // 2 per counter: low, high 64 bits of a signed 128-bit sum
     int off_wl;               // LDS: three u64 limbs per counter
-    const uint4* tab;         // binning tables blob (binlut.h layout)
+    const uint4* tab;         // table blob for FP32 squared sides (binlut.h layout)
     int tab_words;
-    int off_band, off_e, off_hist, off_t3, off_lists;
+    int off_band, off_e, off_hist, off_t3, off_ptab, off_lists;
     int nb;
     float scale, vmax;
     int nhist;                // sorted bin triples
@@ -64,19 +66,35 @@ struct TriArgs {
     unsigned long long* stats;  // [0] side evaluations, [1] FP64 rechecks
 };
 
-// Squared separation of (bx, by, bz) - (ax, ay, az): per-axis minimum image
-// in a periodic box, then (dx dx + dy dy) + dz dz, no fused operations.
+// Squared separation of (bx, by, bz) - (ax, ay, az), the definition: per-axis
+// minimum image in a periodic box, then (dx dx + dy dy) + dz dz, no fused
+// operations.
 __device__ __attribute__((always_inline)) inline double side2(double ax, double ay, double az, double bx, double by,
                                                               double bz, double L, double h) {
     double dx = bx - ax, dy = by - ay, dz = bz - az;
     if (L > 0.0) {
-        // the same two candidate results as "if (d > h) d -= L; else if
-        // (d < -h) d += L", chosen by selects instead of branches
         dx = dx > h ? dx - L : (dx < -h ? dx + L : dx);
         dy = dy > h ? dy - L : (dy < -h ? dy + L : dy);
         dz = dz > h ? dz - L : (dz < -h ? dz + L : dz);
     }
     return (dx * dx + dy * dy) + dz * dz;  // built with -ffp-contract=off
+}
+
+// Bin of a squared side v formed in FP32 (table bands cover its error): the
+// bin, -1 (out of range) or -2 (inside an edge's band: the FP64 side decides).
+__device__ __attribute__((always_inline)) inline int bin32(const BinTable& T, float v) {
+    const bool ok = v < T.vmax;
+    int e = T.lut[ok ? (uint32_t)(v * T.scale) : 0u];
+    e = ok ? e : -1;
+    if (e < -1) {
+        const int k0 = -2 - e;
+        e = bin_near(T, k0, v);
+        if (e == -2)
+            e = bin_hot(T.band, T.nb, k0, v);
+        else if (e >= T.nb)
+            e = -1;
+    }
+    return e;
 }
 
 // Counter of the sorted bin triple a <= b <= c: C(c+2, 3) + C(b+1, 2) + a,
@@ -89,12 +107,13 @@ __device__ __attribute__((always_inline)) inline int tri_slot(const int* t3, int
     return t3[hi] + (int)(__umul24((uint32_t)mid, (uint32_t)mid + 1u) >> 1) + lo;
 }
 
+// A list of neighbours of the primary: each entry's displacement from the
+// primary in FP32 with the bin of its side to the primary (bits of .w), its
+// sorted index and, for weighted counts, its weight.
 struct TriList {
-    double* x;
-    double* y;
-    double* z;
-    double* w;  // weighted counts only
-    int* b;
+    float4* d;
+    uint32_t* idx;
+    double* w;
 };
 
 // weight of a triangle: the three weights sorted by value, fl(fl(a b) c)
@@ -124,21 +143,24 @@ __device__ inline uint32_t lane_prefix_tri(uint64_t m) {
 
 // Scan the cells around primary i (cell cx, cy, cz) and keep the neighbours
 // j > i with side ij in range whose position in the scan order lies in
-// [lo, lo + TRI_CAP), into R.  Returns the number found up to the point the
-// scan stopped (all of them when `whole`).
+// [lo, lo + TRI_CAP), into R.  The side is the FP64 displacement of the
+// definition (minimum image when Lw > 0), binned from its FP32 square; a side
+// inside an edge's band is binned from its FP64 square.  Returns the number
+// found up to the point the scan stopped (all of them when `whole`).
 template <bool W>
 __device__ uint32_t tri_gather(const TriArgs& a, const BinTable& T, int64_t i, double xi, double yi, double zi,
-                               uint32_t icell, int cx, int cy, int cz, uint32_t lo, bool whole, const TriList& R,
-                               int lane, unsigned long long& nside, uint32_t& rechk) {
+                               uint32_t icell, int cx, int cy, int cz, double Lw, uint32_t lo, bool whole,
+                               const TriList& R, int lane, unsigned long long& nside, uint32_t& rechk) {
     uint32_t running = 0;
     const uint32_t hi = lo + TRI_CAP;
     for (int s = 0; s < a.nst; s++) {
         const int4 o = a.stencil[s];
         int x = cx + o.x, y = cy + o.y, z = cz + o.z;
         if (a.L > 0.0) {
-            x = ((x % a.nx) + a.nx) % a.nx;
-            y = ((y % a.ny) + a.ny) % a.ny;
-            z = ((z % a.nz) + a.nz) % a.nz;
+            // an offset is never longer than the grid (tri_stencil): one wrap
+            x += x < 0 ? a.nx : (x >= a.nx ? -a.nx : 0);
+            y += y < 0 ? a.ny : (y >= a.ny ? -a.ny : 0);
+            z += z < 0 ? a.nz : (z >= a.nz ? -a.nz : 0);
         } else if (x < 0 || x >= a.nx || y < 0 || y >= a.ny || z < 0 || z >= a.nz) {
             continue;
         }
@@ -149,12 +171,23 @@ __device__ uint32_t tri_gather(const TriArgs& a, const BinTable& T, int64_t i, d
         for (uint32_t j0 = b0; j0 < b1; j0 += 64) {
             const uint32_t j = j0 + (uint32_t)lane;
             int bin = -1;
-            double xj = 0, yj = 0, zj = 0;
+            float4 e = make_float4(0.f, 0.f, 0.f, 0.f);
             if (j < b1 && (int64_t)j > i) {
-                xj = a.pos[3 * (size_t)j];
-                yj = a.pos[3 * (size_t)j + 1];
-                zj = a.pos[3 * (size_t)j + 2];
-                bin = bin_value_nonneg(T, side2(xi, yi, zi, xj, yj, zj, a.L, a.halfL), rechk);
+                double dx = a.pos[3 * (size_t)j] - xi, dy = a.pos[3 * (size_t)j + 1] - yi,
+                       dz = a.pos[3 * (size_t)j + 2] - zi;
+                if (Lw > 0.0) {
+                    const double h = a.halfL;
+                    dx = dx > h ? dx - Lw : (dx < -h ? dx + Lw : dx);
+                    dy = dy > h ? dy - Lw : (dy < -h ? dy + Lw : dy);
+                    dz = dz > h ? dz - Lw : (dz < -h ? dz + Lw : dz);
+                }
+                e = make_float4((float)dx, (float)dy, (float)dz, 0.f);
+                bin = bin32(T, __builtin_fmaf(e.z, e.z, __builtin_fmaf(e.y, e.y, e.x * e.x)));
+                if (bin == -2) {
+                    rechk++;
+                    bin = bin_exact(T.E, T.nb, (dx * dx + dy * dy) + dz * dz);
+                }
+                e.w = __int_as_float(bin);
                 nside++;
             }
             const bool ok = bin >= 0;
@@ -162,12 +195,10 @@ __device__ uint32_t tri_gather(const TriArgs& a, const BinTable& T, int64_t i, d
             if (ok) {
                 const uint32_t seq = running + lane_prefix_tri(m);
                 if (seq >= lo && seq < hi) {
-                    const uint32_t e = seq - lo;
-                    R.x[e] = xj;
-                    R.y[e] = yj;
-                    R.z[e] = zj;
-                    R.b[e] = bin;
-                    if (W) R.w[e] = a.w[j];
+                    const uint32_t k = seq - lo;
+                    R.d[k] = e;
+                    R.idx[k] = j;
+                    if (W) R.w[k] = a.w[j];
                 }
             }
             running += (uint32_t)__popcll(m);
@@ -187,30 +218,48 @@ __device__ __attribute__((always_inline)) inline void tri_decode(int t, int& p, 
     p = t - (int)(__umul24((uint32_t)q, (uint32_t)q - 1u) >> 1);
 }
 
+// The side between list entries p and q: FP32 from the two displacements
+// (both within reach of the primary, so their difference is the minimum image
+// with no wrap), binned; inside a band, the FP64 side of the definition from
+// the sorted positions.
+// EXACT: the box is too small for that (L < 4 r): every side is the FP64 one.
+template <bool EXACT>
+__device__ __attribute__((always_inline)) inline int tri_side_bin(const TriArgs& a, const BinTable& T, float4 ep,
+                                                                 float4 eq, const uint32_t* pidx, int p,
+                                                                 const uint32_t* qidx, int q, uint32_t& rechk) {
+    const float ex = eq.x - ep.x, ey = eq.y - ep.y, ez = eq.z - ep.z;
+    int b = EXACT ? -2 : bin32(T, __builtin_fmaf(ez, ez, __builtin_fmaf(ey, ey, ex * ex)));
+    if (b == -2) {
+        rechk++;
+        const double* pp = a.pos + 3 * (size_t)pidx[p];
+        const double* pq = a.pos + 3 * (size_t)qidx[q];
+        b = bin_exact(T.E, T.nb, side2(pp[0], pp[1], pp[2], pq[0], pq[1], pq[2], a.L, a.halfL));
+    }
+    return b;
+}
+
 // Every pair p < q of one list, two pairs per lane per step (t and t + 64),
-// both pairs' LDS reads issued before either side is formed.
-template <bool W>
-__device__ void tri_self(const TriArgs& a, const BinTable& T, const TriList& R, int m, double L, double wi,
-                         const int* t3, unsigned long long* hist, unsigned long long* wl, int lane, unsigned long long& nside,
-                         uint32_t& rechk) {
+// (p, q) of pair t from the LDS pair table.
+template <bool W, bool EXACT>
+__device__ void tri_self(const TriArgs& a, const BinTable& T, const TriList& R, int m, double wi, const int* t3,
+                         const uint16_t* ptab, unsigned long long* hist, unsigned long long* wl, int lane,
+                         unsigned long long& nside, uint32_t& rechk) {
     const int npair = m * (m - 1) / 2;
     for (int t = lane; t < npair; t += 128) {
         const bool two = t + 64 < npair;
-        int p0, q0, p1, q1;
-        tri_decode(t, p0, q0);
-        tri_decode(two ? t + 64 : t, p1, q1);
-        const double ax = R.x[p0], ay = R.y[p0], az = R.z[p0], bx = R.x[q0], by = R.y[q0], bz = R.z[q0];
-        const double cx = R.x[p1], cy = R.y[p1], cz = R.z[p1], dx = R.x[q1], dy = R.y[q1], dz = R.z[q1];
-        const int b0 = bin_value_nonneg(T, side2(ax, ay, az, bx, by, bz, L, a.halfL), rechk);
-        const int b1 = two ? bin_value_nonneg(T, side2(cx, cy, cz, dx, dy, dz, L, a.halfL), rechk) : -1;
+        const uint32_t pq0 = ptab[t], pq1 = ptab[two ? t + 64 : t];
+        const int p0 = pq0 & 255, q0 = pq0 >> 8, p1 = pq1 & 255, q1 = pq1 >> 8;
+        const float4 a0 = R.d[p0], b0 = R.d[q0], a1 = R.d[p1], b1 = R.d[q1];
+        const int s0 = tri_side_bin<EXACT>(a, T, a0, b0, R.idx, p0, R.idx, q0, rechk);
+        const int s1 = two ? tri_side_bin<EXACT>(a, T, a1, b1, R.idx, p1, R.idx, q1, rechk) : -1;
         nside += two ? 2 : 1;
-        if (b0 >= 0) {
-            const int k = tri_slot(t3, R.b[p0], R.b[q0], b0);
+        if (s0 >= 0) {
+            const int k = tri_slot(t3, __float_as_int(a0.w), __float_as_int(b0.w), s0);
             atomicAdd(&hist[k], 1ull);
             if (W) tri_add_weight(wl, a.nhist, k, tri_weight(wi, R.w[p0], R.w[q0]) * a.wscale);
         }
-        if (b1 >= 0) {
-            const int k = tri_slot(t3, R.b[p1], R.b[q1], b1);
+        if (s1 >= 0) {
+            const int k = tri_slot(t3, __float_as_int(a1.w), __float_as_int(b1.w), s1);
             atomicAdd(&hist[k], 1ull);
             if (W) tri_add_weight(wl, a.nhist, k, tri_weight(wi, R.w[p1], R.w[q1]) * a.wscale);
         }
@@ -219,28 +268,28 @@ __device__ void tri_self(const TriArgs& a, const BinTable& T, const TriList& R, 
 
 // Every pair of an earlier list P (m1 entries) and a later list Q (m2), two
 // entries of Q per lane per step.
-template <bool W>
+template <bool W, bool EXACT>
 __device__ void tri_cross(const TriArgs& a, const BinTable& T, const TriList& P, int m1, const TriList& Q, int m2,
-                          double L, double wi, const int* t3, unsigned long long* hist, unsigned long long* wl, int lane,
+                          double wi, const int* t3, unsigned long long* hist, unsigned long long* wl, int lane,
                           unsigned long long& nside, uint32_t& rechk) {
     for (int p = 0; p < m1; p++) {
-        const double px = P.x[p], py = P.y[p], pz = P.z[p];
-        const int pb = P.b[p];
+        const float4 ep = P.d[p];
+        const int pb = __float_as_int(ep.w);
         const double pw = W ? P.w[p] : 0.0;
         for (int q = lane; q < m2; q += 128) {
             const bool two = q + 64 < m2;
             const int q1 = two ? q + 64 : q;
-            const double bx = Q.x[q], by = Q.y[q], bz = Q.z[q], dx = Q.x[q1], dy = Q.y[q1], dz = Q.z[q1];
-            const int b0 = bin_value_nonneg(T, side2(px, py, pz, bx, by, bz, L, a.halfL), rechk);
-            const int b1 = two ? bin_value_nonneg(T, side2(px, py, pz, dx, dy, dz, L, a.halfL), rechk) : -1;
+            const float4 e0 = Q.d[q], e1 = Q.d[q1];
+            const int s0 = tri_side_bin<EXACT>(a, T, ep, e0, P.idx, p, Q.idx, q, rechk);
+            const int s1 = two ? tri_side_bin<EXACT>(a, T, ep, e1, P.idx, p, Q.idx, q1, rechk) : -1;
             nside += two ? 2 : 1;
-            if (b0 >= 0) {
-                const int k = tri_slot(t3, pb, Q.b[q], b0);
+            if (s0 >= 0) {
+                const int k = tri_slot(t3, pb, __float_as_int(e0.w), s0);
                 atomicAdd(&hist[k], 1ull);
                 if (W) tri_add_weight(wl, a.nhist, k, tri_weight(wi, pw, Q.w[q]) * a.wscale);
             }
-            if (b1 >= 0) {
-                const int k = tri_slot(t3, pb, Q.b[q1], b1);
+            if (s1 >= 0) {
+                const int k = tri_slot(t3, pb, __float_as_int(e1.w), s1);
                 atomicAdd(&hist[k], 1ull);
                 if (W) tri_add_weight(wl, a.nhist, k, tri_weight(wi, pw, Q.w[q1]) * a.wscale);
             }
@@ -248,10 +297,10 @@ __device__ void tri_cross(const TriArgs& a, const BinTable& T, const TriList& P,
     }
 }
 
-// LDS bytes of one list region
+// LDS bytes of one list region: displacement + bin (16), index (4), weight (8)
 template <bool W>
 constexpr int tri_region_bytes() {
-    return TRI_CAP * (W ? 36 : 28);
+    return TRI_CAP * (W ? 28 : 20);
 }
 
 template <bool W>
@@ -265,6 +314,12 @@ __global__ __launch_bounds__(TRI_MAX_WAVES * 64) void k_triplets(TriArgs a) {
         for (int k = tid; k < a.nhist; k += nthr) h[k] = 0ull;
         int* t3w = (int*)(smem + a.off_t3);
         for (int k = tid; k <= TRI_MAX_BINS; k += nthr) t3w[k] = k * (k + 1) * (k + 2) / 6;
+        uint16_t* pt = (uint16_t*)(smem + a.off_ptab);
+        for (int t = tid; t < TRI_PAIRS; t += nthr) {
+            int p, q;
+            tri_decode(t, p, q);
+            pt[t] = (uint16_t)(p | (q << 8));
+        }
         if (W) {
             unsigned long long* z = (unsigned long long*)(smem + a.off_wl);
             for (int k = tid; k < 3 * a.nhist; k += nthr) z[k] = 0ull;
@@ -280,23 +335,18 @@ __global__ __launch_bounds__(TRI_MAX_WAVES * 64) void k_triplets(TriArgs a) {
     T.nb = a.nb;
     unsigned long long* hist = (unsigned long long*)(smem + a.off_hist);
     const int* t3 = (const int*)(smem + a.off_t3);
+    const uint16_t* ptab = (const uint16_t*)(smem + a.off_ptab);
     unsigned long long* wl = W ? (unsigned long long*)(smem + a.off_wl) : nullptr;
     const int lane = tid & 63, wave = tid >> 6;
-    // two regions per wave, each x[CAP], y[CAP], z[CAP] (FP64), w[CAP] when
-    // weighted, and b[CAP]
     constexpr int RB = tri_region_bytes<W>();
     char* base = smem + a.off_lists + (size_t)wave * 2 * RB;
     TriList R1, R2;
-    R1.x = (double*)base;
-    R1.y = R1.x + TRI_CAP;
-    R1.z = R1.y + TRI_CAP;
-    R1.w = R1.z + TRI_CAP;
-    R1.b = (int*)(W ? R1.w + TRI_CAP : R1.z + TRI_CAP);
-    R2.x = (double*)(base + RB);
-    R2.y = R2.x + TRI_CAP;
-    R2.z = R2.y + TRI_CAP;
-    R2.w = R2.z + TRI_CAP;
-    R2.b = (int*)(W ? R2.w + TRI_CAP : R2.z + TRI_CAP);
+    R1.d = (float4*)base;
+    R1.idx = (uint32_t*)(R1.d + TRI_CAP);
+    R1.w = (double*)(R1.idx + TRI_CAP);
+    R2.d = (float4*)(base + RB);
+    R2.idx = (uint32_t*)(R2.d + TRI_CAP);
+    R2.w = (double*)(R2.idx + TRI_CAP);
     unsigned long long nside = 0;
     uint32_t rechk = 0;
     for (;;) {
@@ -311,27 +361,32 @@ __global__ __launch_bounds__(TRI_MAX_WAVES * 64) void k_triplets(TriArgs a) {
         const int cx = (int)(cell % (uint32_t)a.nx);
         const int cy = (int)((cell / (uint32_t)a.nx) % (uint32_t)a.ny);
         const int cz = (int)(cell / ((uint32_t)a.nx * (uint32_t)a.ny));
-        const uint32_t m = tri_gather<W>(a, T, i, xi, yi, zi, cell, cx, cy, cz, 0, true, R1, lane, nside, rechk);
-        if (m < 2) continue;
-        // every neighbour of a primary this far inside the box is unwrapped,
-        // and two of them differ by less than L/2 per axis: the minimum image
-        // would change nothing, so the pairs skip it
+        // a primary this far inside the box has no neighbour across a face:
+        // its sides need no minimum image
         const bool inside = a.inner > 0.0 && xi > a.inner && xi < a.L - a.inner && yi > a.inner &&
                             yi < a.L - a.inner && zi > a.inner && zi < a.L - a.inner;
-        const double Lp = inside ? 0.0 : a.L;
+        const double Lw = inside ? 0.0 : a.L;
+        const uint32_t m = tri_gather<W>(a, T, i, xi, yi, zi, cell, cx, cy, cz, Lw, 0, true, R1, lane, nside, rechk);
+        if (m < 2) continue;
         const uint32_t nch = (m + TRI_CAP - 1) / TRI_CAP;
         for (uint32_t A = 0; A < nch; A++) {
             if (A > 0) {
                 wave_sync_lds_tri();
-                tri_gather<W>(a, T, i, xi, yi, zi, cell, cx, cy, cz, A * TRI_CAP, false, R1, lane, nside, rechk);
+                tri_gather<W>(a, T, i, xi, yi, zi, cell, cx, cy, cz, Lw, A * TRI_CAP, false, R1, lane, nside, rechk);
             }
             const int mA = (int)std::min<uint32_t>(TRI_CAP, m - A * TRI_CAP);
-            tri_self<W>(a, T, R1, mA, Lp, wi, t3, hist, wl, lane, nside, rechk);
+            if (a.exact_pairs)
+                tri_self<W, true>(a, T, R1, mA, wi, t3, ptab, hist, wl, lane, nside, rechk);
+            else
+                tri_self<W, false>(a, T, R1, mA, wi, t3, ptab, hist, wl, lane, nside, rechk);
             for (uint32_t B = A + 1; B < nch; B++) {
                 wave_sync_lds_tri();
-                tri_gather<W>(a, T, i, xi, yi, zi, cell, cx, cy, cz, B * TRI_CAP, false, R2, lane, nside, rechk);
+                tri_gather<W>(a, T, i, xi, yi, zi, cell, cx, cy, cz, Lw, B * TRI_CAP, false, R2, lane, nside, rechk);
                 const int mB = (int)std::min<uint32_t>(TRI_CAP, m - B * TRI_CAP);
-                tri_cross<W>(a, T, R1, mA, R2, mB, Lp, wi, t3, hist, wl, lane, nside, rechk);
+                if (a.exact_pairs)
+                    tri_cross<W, true>(a, T, R1, mA, R2, mB, wi, t3, hist, wl, lane, nside, rechk);
+                else
+                    tri_cross<W, false>(a, T, R1, mA, R2, mB, wi, t3, hist, wl, lane, nside, rechk);
             }
         }
         wave_sync_lds_tri();
@@ -488,9 +543,18 @@ extern "C" fcfc_status fcfc_count_triplets(fcfc_plan_t plan, fcfc_cells_t cells,
     int S = 0;
     if (weighted) FCFC_TRY(weight_scale_rule(c->wmin, c->wmax, c->wmin, c->wmax, 3, &S));
     hipStream_t st = (hipStream_t)stream;
-    const Lut1D* Tp = nullptr;
-    FCFC_TRY(plan_bin_table(p, &Tp));
     const Grid& g = c->grid;
+    const double Lbox = g.L > 0 ? g.L : 0.0;
+    // neighbours lie within r' (r plus room for rounding) of the primary
+    const double rr = p->rprune * (1.0 + 1e-6) + 1e-9 * Lbox;
+    // FP32 sides: a displacement from the primary is the FP64 one rounded to
+    // FP32 (u r' per axis); the side between two neighbours is the rounded
+    // difference of two of them (u 2 r' more), and the FP64 sides of the
+    // definition carry a few ulps of the coordinates; twice that for margin
+    const double U = 5.9604644775390625e-08;
+    const double e_axis = 2.0 * (4.0 * U * rr + 4.0 * 2.220446049250313e-16 * (Lbox + rr));
+    const Lut1D* Tp = nullptr;
+    FCFC_TRY(plan_side_table(p, e_axis, &Tp));
     std::vector<int4> sten;
     tri_stencil(g, p->rprune, sten);
 
@@ -502,7 +566,8 @@ extern "C" fcfc_status fcfc_count_triplets(fcfc_plan_t plan, fcfc_cells_t cells,
     a.off_e = B.off_e;
     a.off_hist = B.bytes;
     a.off_t3 = a.off_hist + bin_al16(a.nhist * 8);
-    a.off_wl = a.off_t3 + bin_al16((TRI_MAX_BINS + 1) * 4);
+    a.off_ptab = a.off_t3 + bin_al16((TRI_MAX_BINS + 1) * 4);
+    a.off_wl = a.off_ptab + bin_al16(TRI_PAIRS * 2);
     a.off_lists = a.off_wl + (weighted ? bin_al16(a.nhist * 24) : 0);
     const int per_wave = 2 * (weighted ? tri_region_bytes<true>() : tri_region_bytes<false>());
     int dev = 0, maxlds = 65536;
@@ -556,11 +621,10 @@ extern "C" fcfc_status fcfc_count_triplets(fcfc_plan_t plan, fcfc_cells_t cells,
         a.nz = g.nz;
         a.L = g.L > 0 ? g.L : 0.0;
         a.halfL = a.L * 0.5;
-        // neighbours lie within r (slightly more, for rounding) of the
-        // primary; pairs of them differ by less than 2 r' per axis, which
-        // needs 2 r' <= L / 2
-        const double rr = p->rprune * (1.0 + 1e-6) + 1e-9 * a.L;
+        // two neighbours differ by less than 2 r' per axis: with 2 r' <= L / 2
+        // that difference is their minimum image
         a.inner = (a.L > 0 && 4.0 * rr <= a.L) ? rr : 0.0;
+        a.exact_pairs = (a.L > 0 && 4.0 * rr > a.L) ? 1 : 0;
         a.n = c->n;
         a.tab = (const uint4*)blk;
         a.tab_words = B.bytes / 16;
