@@ -44,7 +44,7 @@ struct TriArgs {
     const uint32_t* cs;       // cell_start, ncell + 1
     const uint32_t* xkey;     // sorted keys: cell << xbits | sub-cell x
     int xbits;
-    const int4* stencil;      // cell offsets (dx, dy, dz, 0)
+    const int4* stencil;      // rows of cells: (dy, dz, first dx, last dx)
     int nst;
     int nx, ny, nz;
     double L, halfL;          // L > 0: periodic
@@ -155,53 +155,71 @@ __device__ uint32_t tri_gather(const TriArgs& a, const BinTable& T, int64_t i, d
     const uint32_t hi = lo + TRI_CAP;
     for (int s = 0; s < a.nst; s++) {
         const int4 o = a.stencil[s];
-        int x = cx + o.x, y = cy + o.y, z = cz + o.z;
+        int y = cy + o.x, z = cz + o.y, xa = cx + o.z, xb = cx + o.w;
+        // the row's run of cells: one piece, or two where a periodic run wraps
+        // (a run is never longer than the row, so it wraps once at most)
+        int pa1 = 1, pb1 = 0;
         if (a.L > 0.0) {
-            // an offset is never longer than the grid (tri_stencil): one wrap
-            x += x < 0 ? a.nx : (x >= a.nx ? -a.nx : 0);
             y += y < 0 ? a.ny : (y >= a.ny ? -a.ny : 0);
             z += z < 0 ? a.nz : (z >= a.nz ? -a.nz : 0);
-        } else if (x < 0 || x >= a.nx || y < 0 || y >= a.ny || z < 0 || z >= a.nz) {
-            continue;
+            if (xa < 0) {
+                pa1 = 0;
+                pb1 = xb;
+                xa += a.nx;
+                xb = a.nx - 1;
+            } else if (xb >= a.nx) {
+                pa1 = 0;
+                pb1 = xb - a.nx;
+                xb = a.nx - 1;
+            }
+        } else {
+            if (y < 0 || y >= a.ny || z < 0 || z >= a.nz) continue;
+            xa = max(xa, 0);
+            xb = min(xb, a.nx - 1);
         }
-        const uint32_t cell = ((uint32_t)z * (uint32_t)a.ny + (uint32_t)y) * (uint32_t)a.nx + (uint32_t)x;
-        // points are sorted by cell: a cell below the primary's holds only j < i
-        if (cell < icell) continue;
-        const uint32_t b0 = a.cs[cell], b1 = a.cs[cell + 1];
-        for (uint32_t j0 = b0; j0 < b1; j0 += 64) {
-            const uint32_t j = j0 + (uint32_t)lane;
-            int bin = -1;
-            float4 e = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (j < b1 && (int64_t)j > i) {
-                double dx = a.pos[3 * (size_t)j] - xi, dy = a.pos[3 * (size_t)j + 1] - yi,
-                       dz = a.pos[3 * (size_t)j + 2] - zi;
-                if (Lw > 0.0) {
-                    const double h = a.halfL;
-                    dx = dx > h ? dx - Lw : (dx < -h ? dx + Lw : dx);
-                    dy = dy > h ? dy - Lw : (dy < -h ? dy + Lw : dy);
-                    dz = dz > h ? dz - Lw : (dz < -h ? dz + Lw : dz);
+        const uint32_t row = ((uint32_t)z * (uint32_t)a.ny + (uint32_t)y) * (uint32_t)a.nx;
+        for (int piece = 0; piece < 2; piece++) {
+            const int x0 = piece ? pa1 : xa, x1 = piece ? pb1 : xb;
+            if (x0 > x1) continue;
+            // points are sorted by cell: only those after the primary count
+            uint32_t b0 = a.cs[row + (uint32_t)x0];
+            const uint32_t b1 = a.cs[row + (uint32_t)x1 + 1u];
+            if ((int64_t)b0 <= i) b0 = (uint32_t)(i + 1);
+            for (uint32_t j0 = b0; j0 < b1; j0 += 64) {
+                const uint32_t j = j0 + (uint32_t)lane;
+                int bin = -1;
+                float4 e = make_float4(0.f, 0.f, 0.f, 0.f);
+                if (j < b1) {
+                    double dx = a.pos[3 * (size_t)j] - xi, dy = a.pos[3 * (size_t)j + 1] - yi,
+                           dz = a.pos[3 * (size_t)j + 2] - zi;
+                    if (Lw > 0.0) {
+                        const double h = a.halfL;
+                        dx = dx > h ? dx - Lw : (dx < -h ? dx + Lw : dx);
+                        dy = dy > h ? dy - Lw : (dy < -h ? dy + Lw : dy);
+                        dz = dz > h ? dz - Lw : (dz < -h ? dz + Lw : dz);
+                    }
+                    e = make_float4((float)dx, (float)dy, (float)dz, 0.f);
+                    bin = bin32(T, __builtin_fmaf(e.z, e.z, __builtin_fmaf(e.y, e.y, e.x * e.x)));
+                    if (bin == -2) {
+                        rechk++;
+                        bin = bin_exact(T.E, T.nb, (dx * dx + dy * dy) + dz * dz);
+                    }
+                    e.w = __int_as_float(bin);
+                    nside++;
                 }
-                e = make_float4((float)dx, (float)dy, (float)dz, 0.f);
-                bin = bin32(T, __builtin_fmaf(e.z, e.z, __builtin_fmaf(e.y, e.y, e.x * e.x)));
-                if (bin == -2) {
-                    rechk++;
-                    bin = bin_exact(T.E, T.nb, (dx * dx + dy * dy) + dz * dz);
+                const bool ok = bin >= 0;
+                const uint64_t m = __ballot(ok);
+                if (ok) {
+                    const uint32_t seq = running + lane_prefix_tri(m);
+                    if (seq >= lo && seq < hi) {
+                        const uint32_t k = seq - lo;
+                        R.d[k] = e;
+                        R.idx[k] = j;
+                        if (W) R.w[k] = a.w[j];
+                    }
                 }
-                e.w = __int_as_float(bin);
-                nside++;
+                running += (uint32_t)__popcll(m);
             }
-            const bool ok = bin >= 0;
-            const uint64_t m = __ballot(ok);
-            if (ok) {
-                const uint32_t seq = running + lane_prefix_tri(m);
-                if (seq >= lo && seq < hi) {
-                    const uint32_t k = seq - lo;
-                    R.d[k] = e;
-                    R.idx[k] = j;
-                    if (W) R.w[k] = a.w[j];
-                }
-            }
-            running += (uint32_t)__popcll(m);
         }
         if (!whole && running >= hi) break;
     }
@@ -499,6 +517,25 @@ static void tri_stencil(const Grid& g, double rprune, std::vector<int4>& st) {
             }
 }
 
+// The stencil as rows: the cells of one (dy, dz) form one run of x offsets
+// (the prune keeps |dx| up to a bound, or a whole short periodic axis), stored
+// as (dy, dz, first dx, last dx).
+static void tri_rows(std::vector<int4>& st) {
+    std::vector<int4> rows;
+    for (const int4& c : st) {
+        bool found = false;
+        for (int4& r : rows)
+            if (r.x == c.y && r.y == c.z) {
+                r.z = std::min(r.z, c.x);
+                r.w = std::max(r.w, c.x);
+                found = true;
+                break;
+            }
+        if (!found) rows.push_back(make_int4(c.y, c.z, c.x, c.x));
+    }
+    st.swap(rows);
+}
+
 }  // namespace fcfc
 
 using namespace fcfc;
@@ -557,6 +594,7 @@ extern "C" fcfc_status fcfc_count_triplets(fcfc_plan_t plan, fcfc_cells_t cells,
     FCFC_TRY(plan_side_table(p, e_axis, &Tp));
     std::vector<int4> sten;
     tri_stencil(g, p->rprune, sten);
+    tri_rows(sten);
 
     TriArgs a{};
     std::vector<char> blob_h;
