@@ -12,9 +12,11 @@
 // Lists longer than the LDS region are taken in chunks: chunk A against itself
 // and against every later chunk B, each chunk rebuilt by rescanning the cells.
 //
-// All sides are FP64, in the same operation order as the pair definition, and
-// binned with the look-up table of binlut.h, so the counts are exact.  On
-// gfx950 FP64 vector arithmetic runs at the rate of unpacked FP32.
+// Sides are formed in FP32 from displacements relative to the primary and
+// binned with a banded look-up table (binlut.h) whose bands cover the FP32
+// error; a side inside an edge's band is formed again in FP64, in the same
+// operation order as the pair definition, and binned exactly, so the counts
+// equal those of the FP64 definition.
 //
 // Weighted counts: a triangle weighs fl(fl(a b) c) for its three point
 // weights sorted by value, a <= b <= c (independent of the point order); a
