@@ -38,6 +38,8 @@ namespace fcfc {
 
 constexpr int TRI_CAP = 128;       // list entries per LDS region (two regions per wave)
 constexpr int TRI_PAIRS = TRI_CAP * (TRI_CAP - 1) / 2;  // pairs of one full list
+constexpr int TRI_PTAB_WORDS = (TRI_PAIRS + 127) / 128 * 64;  // two pairs per word
+constexpr int TRI_ORDERED_MAX_BINS = 16;  // ordered counters (nb^3 of them) up to this many bins
 constexpr int TRI_MAX_WAVES = 16;
 constexpr int TRI_MAX_BINS = 32;   // sorted bin triples: C(34, 3) = 5984 u64 counters
 
@@ -60,9 +62,11 @@ struct TriArgs {
     const uint4* tab;         // table blob for FP32 squared sides (binlut.h layout)
     int tab_words;
     int off_band, off_e, off_hist, off_t3, off_ptab, off_lists;
+    int lists_words;          // 16-byte words of the list regions
     int nb;
     float scale, vmax;
-    int nhist;                // sorted bin triples
+    float top;                // index of the table's last entry (out of range), as a float
+    int nhist;                // counters: sorted bin triples, or nb^3 ordered ones
     unsigned long long* out;  // nhist counters (accumulated)
     uint32_t* cursor;
     unsigned long long* stats;  // [0] side evaluations, [1] FP64 rechecks
@@ -82,12 +86,12 @@ __device__ __attribute__((always_inline)) inline double side2(double ax, double 
     return (dx * dx + dy * dy) + dz * dz;  // built with -ffp-contract=off
 }
 
-// Bin of a squared side v formed in FP32 (table bands cover its error): the
-// bin, -1 (out of range) or -2 (inside an edge's band: the FP64 side decides).
-__device__ __attribute__((always_inline)) inline int bin32(const BinTable& T, float v) {
-    const bool ok = v < T.vmax;
-    int e = T.lut[ok ? (uint32_t)(v * T.scale) : 0u];
-    e = ok ? e : -1;
+// Bin of a squared side v >= 0 formed in FP32 (table bands cover its error):
+// the bin, -1 (out of range) or -2 (inside an edge's band: the FP64 side
+// decides).  The index is clamped to the table's last entry, which lies above
+// the top band and holds "out of range".
+__device__ __attribute__((always_inline)) inline int bin32(const BinTable& T, float top, float v) {
+    int e = T.lut[(uint32_t)fminf(v * T.scale, top)];
     if (e < -1) {
         const int k0 = -2 - e;
         e = bin_near(T, k0, v);
@@ -109,9 +113,20 @@ __device__ __attribute__((always_inline)) inline int tri_slot(const int* t3, int
     return t3[hi] + (int)(__umul24((uint32_t)mid, (uint32_t)mid + 1u) >> 1) + lo;
 }
 
+// Counter of the ordered bin triple (b1, b2, b3): (b1 nb + b2) nb + b3.  A list
+// entry of bin b holds the code b nb^2 | (b nb) << 16, so the counter of the
+// triangle (primary, p, q) with third side in bin s is
+// (code_p & 0xffff) + (code_q >> 16) + s.  The six orders of a triple are
+// summed into its sorted bin after the count.
+__device__ __attribute__((always_inline)) inline uint32_t tri_code(uint32_t bin, uint32_t nb) {
+    const uint32_t c1 = __umul24(bin, nb);
+    return __umul24(c1, nb) | (c1 << 16);
+}
+
 // A list of neighbours of the primary: each entry's displacement from the
-// primary in FP32 with the bin of its side to the primary (bits of .w), its
-// sorted index and, for weighted counts, its weight.
+// primary in FP32 with the bin of its side to the primary, or that bin's code
+// for ordered counters (bits of .w), its sorted index and, for weighted
+// counts, its weight.
 struct TriList {
     float4* d;
     uint32_t* idx;
@@ -148,8 +163,9 @@ __device__ inline uint32_t lane_prefix_tri(uint64_t m) {
 // [lo, lo + TRI_CAP), into R.  The side is the FP64 displacement of the
 // definition (minimum image when Lw > 0), binned from its FP32 square; a side
 // inside an edge's band is binned from its FP64 square.  Returns the number
-// found up to the point the scan stopped (all of them when `whole`).
-template <bool W>
+// found up to the point the scan stopped (all of them when `whole`).  nside
+// (wave-uniform) counts the points scanned.
+template <bool W, bool U>
 __device__ uint32_t tri_gather(const TriArgs& a, const BinTable& T, int64_t i, double xi, double yi, double zi,
                                uint32_t icell, int cx, int cy, int cz, double Lw, uint32_t lo, bool whole,
                                const TriList& R, int lane, unsigned long long& nside, uint32_t& rechk) {
@@ -187,6 +203,7 @@ __device__ uint32_t tri_gather(const TriArgs& a, const BinTable& T, int64_t i, d
             uint32_t b0 = a.cs[row + (uint32_t)x0];
             const uint32_t b1 = a.cs[row + (uint32_t)x1 + 1u];
             if ((int64_t)b0 <= i) b0 = (uint32_t)(i + 1);
+            if (b1 > b0) nside += b1 - b0;
             for (uint32_t j0 = b0; j0 < b1; j0 += 64) {
                 const uint32_t j = j0 + (uint32_t)lane;
                 int bin = -1;
@@ -201,13 +218,12 @@ __device__ uint32_t tri_gather(const TriArgs& a, const BinTable& T, int64_t i, d
                         dz = dz > h ? dz - Lw : (dz < -h ? dz + Lw : dz);
                     }
                     e = make_float4((float)dx, (float)dy, (float)dz, 0.f);
-                    bin = bin32(T, __builtin_fmaf(e.z, e.z, __builtin_fmaf(e.y, e.y, e.x * e.x)));
+                    bin = bin32(T, a.top, __builtin_fmaf(e.z, e.z, __builtin_fmaf(e.y, e.y, e.x * e.x)));
                     if (bin == -2) {
                         rechk++;
                         bin = bin_exact(T.E, T.nb, (dx * dx + dy * dy) + dz * dz);
                     }
-                    e.w = __int_as_float(bin);
-                    nside++;
+                    e.w = __uint_as_float(U ? tri_code((uint32_t)bin, (uint32_t)a.nb) : (uint32_t)bin);
                 }
                 const bool ok = bin >= 0;
                 const uint64_t m = __ballot(ok);
@@ -243,14 +259,17 @@ __device__ __attribute__((always_inline)) inline void tri_decode(int t, int& p, 
 // with no wrap), binned; inside a band, the FP64 side of the definition from
 // the sorted positions.
 // EXACT: the box is too small for that (L < 4 r): every side is the FP64 one.
+// `live` false: a padding pair whose result is discarded (not counted as a
+// recheck); its entries are valid, so the recheck's reads stay in bounds.
 template <bool EXACT>
 __device__ __attribute__((always_inline)) inline int tri_side_bin(const TriArgs& a, const BinTable& T, float4 ep,
                                                                  float4 eq, const uint32_t* pidx, int p,
-                                                                 const uint32_t* qidx, int q, uint32_t& rechk) {
+                                                                 const uint32_t* qidx, int q, bool live,
+                                                                 uint32_t& rechk) {
     const float ex = eq.x - ep.x, ey = eq.y - ep.y, ez = eq.z - ep.z;
-    int b = EXACT ? -2 : bin32(T, __builtin_fmaf(ez, ez, __builtin_fmaf(ey, ey, ex * ex)));
+    int b = EXACT ? -2 : bin32(T, a.top, __builtin_fmaf(ez, ez, __builtin_fmaf(ey, ey, ex * ex)));
     if (b == -2) {
-        rechk++;
+        rechk += live ? 1u : 0u;
         const double* pp = a.pos + 3 * (size_t)pidx[p];
         const double* pq = a.pos + 3 * (size_t)qidx[q];
         b = bin_exact(T.E, T.nb, side2(pp[0], pp[1], pp[2], pq[0], pq[1], pq[2], a.L, a.halfL));
@@ -258,28 +277,41 @@ __device__ __attribute__((always_inline)) inline int tri_side_bin(const TriArgs&
     return b;
 }
 
-// Every pair p < q of one list, two pairs per lane per step (t and t + 64),
-// (p, q) of pair t from the LDS pair table.
-template <bool W, bool EXACT>
+// Counter of the triangle whose two sides to the primary are list entries with
+// .w bits wp and wq and whose third side is in bin s.
+template <bool U>
+__device__ __attribute__((always_inline)) inline int tri_counter(const int* t3, uint32_t wp, uint32_t wq, int s) {
+    if (U) return (int)((wp & 0xffffu) + (wq >> 16)) + s;
+    return tri_slot(t3, (int)wp, (int)wq, s);
+}
+
+// Every pair p < q of one list, two pairs per lane per step (t and t + 64).
+// The pair table holds, for step j and lane l, pairs j 128 + l and
+// j 128 + 64 + l as (p | q << 8) in the low and high halves of one word.
+// The second pair of the last step may lie past the list: it is computed on
+// valid entries and discarded.
+template <bool W, bool U, bool EXACT>
 __device__ void tri_self(const TriArgs& a, const BinTable& T, const TriList& R, int m, double wi, const int* t3,
-                         const uint16_t* ptab, unsigned long long* hist, unsigned long long* wl, int lane,
+                         const uint32_t* ptab, unsigned long long* hist, unsigned long long* wl, int lane,
                          unsigned long long& nside, uint32_t& rechk) {
     const int npair = m * (m - 1) / 2;
-    for (int t = lane; t < npair; t += 128) {
+    nside += (unsigned long long)npair;
+    const uint32_t* pt = ptab + lane;
+    for (int t = lane; t < npair; t += 128, pt += 64) {
         const bool two = t + 64 < npair;
-        const uint32_t pq0 = ptab[t], pq1 = ptab[two ? t + 64 : t];
-        const int p0 = pq0 & 255, q0 = pq0 >> 8, p1 = pq1 & 255, q1 = pq1 >> 8;
+        const uint32_t w = *pt;
+        const int p0 = w & 255, q0 = (w >> 8) & 255, p1 = (w >> 16) & 255, q1 = w >> 24;
         const float4 a0 = R.d[p0], b0 = R.d[q0], a1 = R.d[p1], b1 = R.d[q1];
-        const int s0 = tri_side_bin<EXACT>(a, T, a0, b0, R.idx, p0, R.idx, q0, rechk);
-        const int s1 = two ? tri_side_bin<EXACT>(a, T, a1, b1, R.idx, p1, R.idx, q1, rechk) : -1;
-        nside += two ? 2 : 1;
+        const int s0 = tri_side_bin<EXACT>(a, T, a0, b0, R.idx, p0, R.idx, q0, true, rechk);
+        int s1 = tri_side_bin<EXACT>(a, T, a1, b1, R.idx, p1, R.idx, q1, two, rechk);
+        s1 = two ? s1 : -1;
         if (s0 >= 0) {
-            const int k = tri_slot(t3, __float_as_int(a0.w), __float_as_int(b0.w), s0);
+            const int k = tri_counter<U>(t3, __float_as_uint(a0.w), __float_as_uint(b0.w), s0);
             atomicAdd(&hist[k], 1ull);
             if (W) tri_add_weight(wl, a.nhist, k, tri_weight(wi, R.w[p0], R.w[q0]) * a.wscale);
         }
         if (s1 >= 0) {
-            const int k = tri_slot(t3, __float_as_int(a1.w), __float_as_int(b1.w), s1);
+            const int k = tri_counter<U>(t3, __float_as_uint(a1.w), __float_as_uint(b1.w), s1);
             atomicAdd(&hist[k], 1ull);
             if (W) tri_add_weight(wl, a.nhist, k, tri_weight(wi, R.w[p1], R.w[q1]) * a.wscale);
         }
@@ -288,28 +320,29 @@ __device__ void tri_self(const TriArgs& a, const BinTable& T, const TriList& R, 
 
 // Every pair of an earlier list P (m1 entries) and a later list Q (m2), two
 // entries of Q per lane per step.
-template <bool W, bool EXACT>
+template <bool W, bool U, bool EXACT>
 __device__ void tri_cross(const TriArgs& a, const BinTable& T, const TriList& P, int m1, const TriList& Q, int m2,
                           double wi, const int* t3, unsigned long long* hist, unsigned long long* wl, int lane,
                           unsigned long long& nside, uint32_t& rechk) {
+    nside += (unsigned long long)m1 * (unsigned long long)m2;
     for (int p = 0; p < m1; p++) {
         const float4 ep = P.d[p];
-        const int pb = __float_as_int(ep.w);
+        const uint32_t pb = __float_as_uint(ep.w);
         const double pw = W ? P.w[p] : 0.0;
         for (int q = lane; q < m2; q += 128) {
             const bool two = q + 64 < m2;
             const int q1 = two ? q + 64 : q;
             const float4 e0 = Q.d[q], e1 = Q.d[q1];
-            const int s0 = tri_side_bin<EXACT>(a, T, ep, e0, P.idx, p, Q.idx, q, rechk);
-            const int s1 = two ? tri_side_bin<EXACT>(a, T, ep, e1, P.idx, p, Q.idx, q1, rechk) : -1;
-            nside += two ? 2 : 1;
+            const int s0 = tri_side_bin<EXACT>(a, T, ep, e0, P.idx, p, Q.idx, q, true, rechk);
+            int s1 = tri_side_bin<EXACT>(a, T, ep, e1, P.idx, p, Q.idx, q1, two, rechk);
+            s1 = two ? s1 : -1;
             if (s0 >= 0) {
-                const int k = tri_slot(t3, pb, __float_as_int(e0.w), s0);
+                const int k = tri_counter<U>(t3, pb, __float_as_uint(e0.w), s0);
                 atomicAdd(&hist[k], 1ull);
                 if (W) tri_add_weight(wl, a.nhist, k, tri_weight(wi, pw, Q.w[q]) * a.wscale);
             }
             if (s1 >= 0) {
-                const int k = tri_slot(t3, pb, __float_as_int(e1.w), s1);
+                const int k = tri_counter<U>(t3, pb, __float_as_uint(e1.w), s1);
                 atomicAdd(&hist[k], 1ull);
                 if (W) tri_add_weight(wl, a.nhist, k, tri_weight(wi, pw, Q.w[q1]) * a.wscale);
             }
@@ -323,7 +356,9 @@ constexpr int tri_region_bytes() {
     return TRI_CAP * (W ? 28 : 20);
 }
 
-template <bool W>
+// U: ordered counters (nb^3 of them, unweighted counts with few bins);
+// otherwise sorted-triple counters.
+template <bool W, bool U>
 __global__ __launch_bounds__(TRI_MAX_WAVES * 64) void k_triplets(TriArgs a) {
     extern __shared__ __align__(16) char smem[];
     const int tid = threadIdx.x, nthr = blockDim.x;
@@ -334,16 +369,28 @@ __global__ __launch_bounds__(TRI_MAX_WAVES * 64) void k_triplets(TriArgs a) {
         for (int k = tid; k < a.nhist; k += nthr) h[k] = 0ull;
         int* t3w = (int*)(smem + a.off_t3);
         for (int k = tid; k <= TRI_MAX_BINS; k += nthr) t3w[k] = k * (k + 1) * (k + 2) / 6;
-        uint16_t* pt = (uint16_t*)(smem + a.off_ptab);
-        for (int t = tid; t < TRI_PAIRS; t += nthr) {
-            int p, q;
-            tri_decode(t, p, q);
-            pt[t] = (uint16_t)(p | (q << 8));
+        uint32_t* pt = (uint32_t*)(smem + a.off_ptab);
+        for (int f = tid; f < TRI_PTAB_WORDS; f += nthr) {
+            // word f: step j = f / 64, lane l = f % 64, pairs j 128 + l and j 128 + 64 + l
+            const int t0 = (f >> 6) * 128 + (f & 63);
+            uint32_t v = 0;
+            for (int h2 = 0; h2 < 2; h2++) {
+                const int t = t0 + 64 * h2;
+                if (t < TRI_PAIRS) {
+                    int p, q;
+                    tri_decode(t, p, q);
+                    v |= (uint32_t)(p | (q << 8)) << (16 * h2);
+                }
+            }
+            pt[f] = v;
         }
         if (W) {
             unsigned long long* z = (unsigned long long*)(smem + a.off_wl);
             for (int k = tid; k < 3 * a.nhist; k += nthr) z[k] = 0ull;
         }
+        // list regions start zeroed: a padding pair reads valid indices
+        uint4* lz = (uint4*)(smem + a.off_lists);
+        for (int k = tid; k < a.lists_words; k += nthr) lz[k] = make_uint4(0u, 0u, 0u, 0u);
     }
     __syncthreads();
     BinTable T;
@@ -355,7 +402,7 @@ __global__ __launch_bounds__(TRI_MAX_WAVES * 64) void k_triplets(TriArgs a) {
     T.nb = a.nb;
     unsigned long long* hist = (unsigned long long*)(smem + a.off_hist);
     const int* t3 = (const int*)(smem + a.off_t3);
-    const uint16_t* ptab = (const uint16_t*)(smem + a.off_ptab);
+    const uint32_t* ptab = (const uint32_t*)(smem + a.off_ptab);
     unsigned long long* wl = W ? (unsigned long long*)(smem + a.off_wl) : nullptr;
     const int lane = tid & 63, wave = tid >> 6;
     constexpr int RB = tri_region_bytes<W>();
@@ -372,7 +419,7 @@ __global__ __launch_bounds__(TRI_MAX_WAVES * 64) void k_triplets(TriArgs a) {
     for (;;) {
         uint32_t ii = 0;
         if (lane == 0) ii = atomicAdd(a.cursor, 1u);
-        ii = __shfl(ii, 0, 64);
+        ii = __builtin_amdgcn_readfirstlane(ii);
         if ((int64_t)ii >= a.n) break;
         const int64_t i = ii;
         const double xi = a.pos[3 * (size_t)i], yi = a.pos[3 * (size_t)i + 1], zi = a.pos[3 * (size_t)i + 2];
@@ -386,27 +433,27 @@ __global__ __launch_bounds__(TRI_MAX_WAVES * 64) void k_triplets(TriArgs a) {
         const bool inside = a.inner > 0.0 && xi > a.inner && xi < a.L - a.inner && yi > a.inner &&
                             yi < a.L - a.inner && zi > a.inner && zi < a.L - a.inner;
         const double Lw = inside ? 0.0 : a.L;
-        const uint32_t m = tri_gather<W>(a, T, i, xi, yi, zi, cell, cx, cy, cz, Lw, 0, true, R1, lane, nside, rechk);
+        const uint32_t m = tri_gather<W, U>(a, T, i, xi, yi, zi, cell, cx, cy, cz, Lw, 0, true, R1, lane, nside, rechk);
         if (m < 2) continue;
         const uint32_t nch = (m + TRI_CAP - 1) / TRI_CAP;
         for (uint32_t A = 0; A < nch; A++) {
             if (A > 0) {
                 wave_sync_lds_tri();
-                tri_gather<W>(a, T, i, xi, yi, zi, cell, cx, cy, cz, Lw, A * TRI_CAP, false, R1, lane, nside, rechk);
+                tri_gather<W, U>(a, T, i, xi, yi, zi, cell, cx, cy, cz, Lw, A * TRI_CAP, false, R1, lane, nside, rechk);
             }
             const int mA = (int)std::min<uint32_t>(TRI_CAP, m - A * TRI_CAP);
             if (a.exact_pairs)
-                tri_self<W, true>(a, T, R1, mA, wi, t3, ptab, hist, wl, lane, nside, rechk);
+                tri_self<W, U, true>(a, T, R1, mA, wi, t3, ptab, hist, wl, lane, nside, rechk);
             else
-                tri_self<W, false>(a, T, R1, mA, wi, t3, ptab, hist, wl, lane, nside, rechk);
+                tri_self<W, U, false>(a, T, R1, mA, wi, t3, ptab, hist, wl, lane, nside, rechk);
             for (uint32_t B = A + 1; B < nch; B++) {
                 wave_sync_lds_tri();
-                tri_gather<W>(a, T, i, xi, yi, zi, cell, cx, cy, cz, Lw, B * TRI_CAP, false, R2, lane, nside, rechk);
+                tri_gather<W, U>(a, T, i, xi, yi, zi, cell, cx, cy, cz, Lw, B * TRI_CAP, false, R2, lane, nside, rechk);
                 const int mB = (int)std::min<uint32_t>(TRI_CAP, m - B * TRI_CAP);
                 if (a.exact_pairs)
-                    tri_cross<W, true>(a, T, R1, mA, R2, mB, wi, t3, hist, wl, lane, nside, rechk);
+                    tri_cross<W, U, true>(a, T, R1, mA, R2, mB, wi, t3, hist, wl, lane, nside, rechk);
                 else
-                    tri_cross<W, false>(a, T, R1, mA, R2, mB, wi, t3, hist, wl, lane, nside, rechk);
+                    tri_cross<W, U, false>(a, T, R1, mA, R2, mB, wi, t3, hist, wl, lane, nside, rechk);
             }
         }
         wave_sync_lds_tri();
@@ -428,11 +475,8 @@ __global__ __launch_bounds__(TRI_MAX_WAVES * 64) void k_triplets(TriArgs a) {
             }
         }
     }
-    // statistics: one atomic per wave
-    for (int o = 32; o >= 1; o >>= 1) {
-        nside += __shfl_xor(nside, o, 64);
-        rechk += __shfl_xor(rechk, o, 64);
-    }
+    // statistics: one atomic per wave (nside is the same in every lane)
+    for (int o = 32; o >= 1; o >>= 1) rechk += __shfl_xor(rechk, o, 64);
     if (lane == 0) {
         atomicAdd(&a.stats[0], nside);
         if (rechk) atomicAdd(&a.stats[1], (unsigned long long)rechk);
@@ -445,6 +489,32 @@ __global__ void k_tri_expand(const unsigned long long* __restrict__ c, int nb, i
     if (f >= nb * nb * nb) return;
     const int a = f / (nb * nb), b = (f / nb) % nb, cc = f % nb;
     out[f] = (a <= b && b <= cc) ? (int64_t)c[cc * (cc + 1) * (cc + 2) / 6 + b * (b + 1) / 2 + a] : 0;
+}
+
+// ordered-triple counters -> the row-major [nb][nb][nb] histogram: bin
+// (a, b, c), a <= b <= c, sums the counters of the distinct orders of its bins
+__global__ void k_tri_fold(const unsigned long long* __restrict__ c, int nb, int64_t* __restrict__ out) {
+    const int f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= nb * nb * nb) return;
+    const int a = f / (nb * nb), b = (f / nb) % nb, cc = f % nb;
+    if (!(a <= b && b <= cc)) {
+        out[f] = 0;
+        return;
+    }
+    const int v[3] = {a, b, cc};
+    const int perm[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+    unsigned long long sum = 0;
+    int seen[6];
+    int ns = 0;
+    for (int k = 0; k < 6; k++) {
+        const int idx = (v[perm[k][0]] * nb + v[perm[k][1]]) * nb + v[perm[k][2]];
+        bool dup = false;
+        for (int u = 0; u < ns; u++) dup = dup || seen[u] == idx;
+        if (dup) continue;
+        seen[ns++] = idx;
+        sum += c[idx];
+    }
+    out[f] = (int64_t)sum;
 }
 
 // signed 128-bit fixed point (lo, hi) times 2^-S, rounded once to nearest even
@@ -601,13 +671,16 @@ extern "C" fcfc_status fcfc_count_triplets(fcfc_plan_t plan, fcfc_cells_t cells,
     TriArgs a{};
     std::vector<char> blob_h;
     const BinBlob B = bin_blob(*Tp, blob_h);
-    a.nhist = (nb + 2) * (nb + 1) * nb / 6;
+    // unweighted counts with few bins use nb^3 ordered counters (no sort of
+    // the three bins per triangle), folded into sorted bins afterwards
+    const bool ordered = !weighted && nb <= TRI_ORDERED_MAX_BINS;
+    a.nhist = ordered ? nb * nb * nb : (nb + 2) * (nb + 1) * nb / 6;
     a.off_band = B.off_band;
     a.off_e = B.off_e;
     a.off_hist = B.bytes;
     a.off_t3 = a.off_hist + bin_al16(a.nhist * 8);
     a.off_ptab = a.off_t3 + bin_al16((TRI_MAX_BINS + 1) * 4);
-    a.off_wl = a.off_ptab + bin_al16(TRI_PAIRS * 2);
+    a.off_wl = a.off_ptab + bin_al16(TRI_PTAB_WORDS * 4);
     a.off_lists = a.off_wl + (weighted ? bin_al16(a.nhist * 24) : 0);
     const int per_wave = 2 * (weighted ? tri_region_bytes<true>() : tri_region_bytes<false>());
     int dev = 0, maxlds = 65536;
@@ -621,7 +694,11 @@ extern "C" fcfc_status fcfc_count_triplets(fcfc_plan_t plan, fcfc_cells_t cells,
         return FCFC_ERANGE;
     }
     const int lds = a.off_lists + waves * per_wave;
-    const void* kern = weighted ? (const void*)k_triplets<true> : (const void*)k_triplets<false>;
+    a.lists_words = waves * per_wave / 16;
+    const int variant = weighted ? 2 : (ordered ? 1 : 0);
+    const void* kern = weighted  ? (const void*)k_triplets<true, false>
+                       : ordered ? (const void*)k_triplets<false, true>
+                                 : (const void*)k_triplets<false, false>;
 
     // device block: tables, stencil, counters, weighted sums, cursor
     const size_t sz_tab = (size_t)B.bytes, sz_st = sten.size() * sizeof(int4), sz_out = (size_t)a.nhist * 8,
@@ -671,15 +748,16 @@ extern "C" fcfc_status fcfc_count_triplets(fcfc_plan_t plan, fcfc_cells_t cells,
         a.nb = nb;
         a.scale = B.scale;
         a.vmax = B.vmax;
+        a.top = (float)(B.nt - 1);
         a.out = (unsigned long long*)(blk + o_out);
         a.cursor = (uint32_t*)(blk + o_cur);
         a.stats = (unsigned long long*)p->stats_dev;
-        static bool attr_set[2][64] = {};
-        if (dev < 64 && !attr_set[weighted][dev]) {
+        static bool attr_set[3][64] = {};
+        if (dev >= 64 || !attr_set[variant][dev]) {
             if (hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, maxlds) != hipSuccess)
                 s = FCFC_EHIP;
-            else
-                attr_set[weighted][dev] = true;
+            else if (dev < 64)
+                attr_set[variant][dev] = true;
         }
         int occ = 0;
         if (s == FCFC_OK && hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, waves * 64, lds) != hipSuccess)
@@ -691,15 +769,24 @@ extern "C" fcfc_status fcfc_count_triplets(fcfc_plan_t plan, fcfc_cells_t cells,
             if (hipEventRecord(p->ev0, st) != hipSuccess) s = FCFC_EHIP;
             if (s == FCFC_OK) {
                 if (weighted)
-                    hipLaunchKernelGGL(k_triplets<true>, dim3((unsigned)nblk), dim3(waves * 64), (size_t)lds, st, a);
+                    hipLaunchKernelGGL((k_triplets<true, false>), dim3((unsigned)nblk), dim3(waves * 64), (size_t)lds,
+                                       st, a);
+                else if (ordered)
+                    hipLaunchKernelGGL((k_triplets<false, true>), dim3((unsigned)nblk), dim3(waves * 64), (size_t)lds,
+                                       st, a);
                 else
-                    hipLaunchKernelGGL(k_triplets<false>, dim3((unsigned)nblk), dim3(waves * 64), (size_t)lds, st, a);
+                    hipLaunchKernelGGL((k_triplets<false, false>), dim3((unsigned)nblk), dim3(waves * 64), (size_t)lds,
+                                       st, a);
                 if (hipGetLastError() != hipSuccess || hipEventRecord(p->ev1, st) != hipSuccess) s = FCFC_EHIP;
             }
             if (s == FCFC_OK) {
                 const int nf = nb * nb * nb;
-                hipLaunchKernelGGL(k_tri_expand, dim3((nf + 255) / 256), dim3(256), 0, st,
-                                   (const unsigned long long*)(blk + o_out), nb, d_counts);
+                if (ordered)
+                    hipLaunchKernelGGL(k_tri_fold, dim3((nf + 255) / 256), dim3(256), 0, st,
+                                       (const unsigned long long*)(blk + o_out), nb, d_counts);
+                else
+                    hipLaunchKernelGGL(k_tri_expand, dim3((nf + 255) / 256), dim3(256), 0, st,
+                                       (const unsigned long long*)(blk + o_out), nb, d_counts);
                 if (weighted)
                     hipLaunchKernelGGL(k_tri_expand_w, dim3((nf + 255) / 256), dim3(256), 0, st,
                                        (const unsigned long long*)(blk + o_w), nb, S, d_wcounts);
