@@ -37,8 +37,9 @@
 namespace fcfc {
 
 constexpr int TRI_CAP = 128;       // list entries per LDS region (two regions per wave)
-constexpr int TRI_PAIRS = TRI_CAP * (TRI_CAP - 1) / 2;  // pairs of one full list
-constexpr int TRI_PTAB_WORDS = (TRI_PAIRS + 127) / 128 * 64;  // two pairs per word
+// pairs of a list taken by column q in groups (p, q), (p + 1, q), p even; a
+// full list has TRI_CAP^2 / 4 groups
+constexpr int TRI_GROUPS = TRI_CAP / 2 * ((TRI_CAP + 1) / 2);
 constexpr int TRI_ORDERED_MAX_BINS = 16;  // ordered counters (nb^3 of them) up to this many bins
 constexpr int TRI_MAX_WAVES = 16;
 constexpr int TRI_MAX_BINS = 32;   // sorted bin triples: C(34, 3) = 5984 u64 counters
@@ -245,15 +246,6 @@ __device__ uint32_t tri_gather(const TriArgs& a, const BinTable& T, int64_t i, d
     return running;
 }
 
-// (p, q) of pair t = q (q - 1) / 2 + p, 0 <= p < q; the hardware square root
-// is within an ulp, and the two corrections make q exact.
-__device__ __attribute__((always_inline)) inline void tri_decode(int t, int& p, int& q) {
-    q = (int)((1.0f + __builtin_amdgcn_sqrtf(1.0f + 8.0f * (float)t)) * 0.5f);
-    if ((int)(__umul24((uint32_t)q, (uint32_t)q - 1u) >> 1) > t) q--;
-    if ((int)(__umul24((uint32_t)q + 1u, (uint32_t)q) >> 1) <= t) q++;
-    p = t - (int)(__umul24((uint32_t)q, (uint32_t)q - 1u) >> 1);
-}
-
 // The side between list entries p and q: FP32 from the two displacements
 // (both within reach of the primary, so their difference is the minimum image
 // with no wrap), binned; inside a band, the FP64 side of the definition from
@@ -285,35 +277,35 @@ __device__ __attribute__((always_inline)) inline int tri_counter(const int* t3, 
     return tri_slot(t3, (int)wp, (int)wq, s);
 }
 
-// Every pair p < q of one list, two pairs per lane per step (t and t + 64).
-// The pair table holds, for step j and lane l, pairs j 128 + l and
-// j 128 + 64 + l as (p | q << 8) in the low and high halves of one word.
-// The second pair of the last step may lie past the list: it is computed on
-// valid entries and discarded.
+// Every pair p < q of one list.  Each lane takes a group (p, q), (p + 1, q)
+// from the group table (p | q << 8, by column q, so the first G(m) groups are
+// those of a list of m entries), reading the entry of q once for both pairs.
+// When p + 1 = q the group has one pair: the second is formed on valid
+// entries and discarded.
 template <bool W, bool U, bool EXACT>
 __device__ void tri_self(const TriArgs& a, const BinTable& T, const TriList& R, int m, double wi, const int* t3,
-                         const uint32_t* ptab, unsigned long long* hist, unsigned long long* wl, int lane,
+                         const uint16_t* gtab, unsigned long long* hist, unsigned long long* wl, int lane,
                          unsigned long long& nside, uint32_t& rechk) {
-    const int npair = m * (m - 1) / 2;
-    nside += (unsigned long long)npair;
-    const uint32_t* pt = ptab + lane;
-    for (int t = lane; t < npair; t += 128, pt += 64) {
-        const bool two = t + 64 < npair;
-        const uint32_t w = *pt;
-        const int p0 = w & 255, q0 = (w >> 8) & 255, p1 = (w >> 16) & 255, q1 = w >> 24;
-        const float4 a0 = R.d[p0], b0 = R.d[q0], a1 = R.d[p1], b1 = R.d[q1];
-        const int s0 = tri_side_bin<EXACT>(a, T, a0, b0, R.idx, p0, R.idx, q0, true, rechk);
-        int s1 = tri_side_bin<EXACT>(a, T, a1, b1, R.idx, p1, R.idx, q1, two, rechk);
+    nside += (unsigned long long)(m * (m - 1) / 2);
+    const int ng = (m / 2) * ((m + 1) / 2);
+    for (int g = lane; g < ng; g += 64) {
+        const uint32_t w = gtab[g];
+        const int p0 = w & 255, q = w >> 8, p1 = p0 + 1;
+        const bool two = p1 < q;
+        const float4 eq = R.d[q], a0 = R.d[p0], a1 = R.d[p1];
+        const int s0 = tri_side_bin<EXACT>(a, T, a0, eq, R.idx, p0, R.idx, q, true, rechk);
+        int s1 = tri_side_bin<EXACT>(a, T, a1, eq, R.idx, p1, R.idx, q, two, rechk);
         s1 = two ? s1 : -1;
+        const uint32_t cq = __float_as_uint(eq.w);
         if (s0 >= 0) {
-            const int k = tri_counter<U>(t3, __float_as_uint(a0.w), __float_as_uint(b0.w), s0);
+            const int k = tri_counter<U>(t3, __float_as_uint(a0.w), cq, s0);
             atomicAdd(&hist[k], 1ull);
-            if (W) tri_add_weight(wl, a.nhist, k, tri_weight(wi, R.w[p0], R.w[q0]) * a.wscale);
+            if (W) tri_add_weight(wl, a.nhist, k, tri_weight(wi, R.w[p0], R.w[q]) * a.wscale);
         }
         if (s1 >= 0) {
-            const int k = tri_counter<U>(t3, __float_as_uint(a1.w), __float_as_uint(b1.w), s1);
+            const int k = tri_counter<U>(t3, __float_as_uint(a1.w), cq, s1);
             atomicAdd(&hist[k], 1ull);
-            if (W) tri_add_weight(wl, a.nhist, k, tri_weight(wi, R.w[p1], R.w[q1]) * a.wscale);
+            if (W) tri_add_weight(wl, a.nhist, k, tri_weight(wi, R.w[p1], R.w[q]) * a.wscale);
         }
     }
 }
@@ -369,20 +361,14 @@ __global__ __launch_bounds__(TRI_MAX_WAVES * 64) void k_triplets(TriArgs a) {
         for (int k = tid; k < a.nhist; k += nthr) h[k] = 0ull;
         int* t3w = (int*)(smem + a.off_t3);
         for (int k = tid; k <= TRI_MAX_BINS; k += nthr) t3w[k] = k * (k + 1) * (k + 2) / 6;
-        uint32_t* pt = (uint32_t*)(smem + a.off_ptab);
-        for (int f = tid; f < TRI_PTAB_WORDS; f += nthr) {
-            // word f: step j = f / 64, lane l = f % 64, pairs j 128 + l and j 128 + 64 + l
-            const int t0 = (f >> 6) * 128 + (f & 63);
-            uint32_t v = 0;
-            for (int h2 = 0; h2 < 2; h2++) {
-                const int t = t0 + 64 * h2;
-                if (t < TRI_PAIRS) {
-                    int p, q;
-                    tri_decode(t, p, q);
-                    v |= (uint32_t)(p | (q << 8)) << (16 * h2);
-                }
-            }
-            pt[f] = v;
+        uint16_t* gt = (uint16_t*)(smem + a.off_ptab);
+        for (int g = tid; g < TRI_GROUPS; g += nthr) {
+            // column q holds ceil(q / 2) groups; the columns before q hold G(q)
+            int q = (int)(2.0f * __builtin_amdgcn_sqrtf((float)g));
+            while (q > 1 && (q / 2) * ((q + 1) / 2) > g) q--;
+            while (((q + 1) / 2) * ((q + 2) / 2) <= g) q++;
+            const int p = 2 * (g - (q / 2) * ((q + 1) / 2));
+            gt[g] = (uint16_t)(p | (q << 8));
         }
         if (W) {
             unsigned long long* z = (unsigned long long*)(smem + a.off_wl);
@@ -402,7 +388,7 @@ __global__ __launch_bounds__(TRI_MAX_WAVES * 64) void k_triplets(TriArgs a) {
     T.nb = a.nb;
     unsigned long long* hist = (unsigned long long*)(smem + a.off_hist);
     const int* t3 = (const int*)(smem + a.off_t3);
-    const uint32_t* ptab = (const uint32_t*)(smem + a.off_ptab);
+    const uint16_t* ptab = (const uint16_t*)(smem + a.off_ptab);
     unsigned long long* wl = W ? (unsigned long long*)(smem + a.off_wl) : nullptr;
     const int lane = tid & 63, wave = tid >> 6;
     constexpr int RB = tri_region_bytes<W>();
@@ -680,7 +666,7 @@ extern "C" fcfc_status fcfc_count_triplets(fcfc_plan_t plan, fcfc_cells_t cells,
     a.off_hist = B.bytes;
     a.off_t3 = a.off_hist + bin_al16(a.nhist * 8);
     a.off_ptab = a.off_t3 + bin_al16((TRI_MAX_BINS + 1) * 4);
-    a.off_wl = a.off_ptab + bin_al16(TRI_PTAB_WORDS * 4);
+    a.off_wl = a.off_ptab + bin_al16(TRI_GROUPS * 2);
     a.off_lists = a.off_wl + (weighted ? bin_al16(a.nhist * 24) : 0);
     const int per_wave = 2 * (weighted ? tri_region_bytes<true>() : tri_region_bytes<false>());
     int dev = 0, maxlds = 65536;
