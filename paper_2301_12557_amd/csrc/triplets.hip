@@ -4,11 +4,12 @@
 // three sides s = |x_b - x_a| (Sect. 2.5; minimum image in a periodic box)
 // lie in [e_0, e_n), into the bin of its sorted side bins (a <= b <= c).
 //
-// Each wave takes one primary point i at a time (sorted order, from a global
-// cursor).  It gathers the points j > i whose side ij is in range from the
-// cells around i's cell into an LDS list (ballot compaction; the list is the
-// scan order of the cells), then bins every pair (p, q) of the list by its
-// third side.  A triangle is found exactly once, from its lowest sorted index.
+// Each wave takes primaries i in sorted order, a few at a time from a global
+// cursor.  It gathers the points after i (in the order of their coordinates,
+// z first) whose side to i is in range from the cells around i's cell into an
+// LDS list (ballot compaction; the list is the scan order of the cells), then
+// bins every pair (p, q) of the list by its third side.  A triangle is found
+// exactly once, from its first vertex in that order.
 // Lists longer than the LDS region are taken in chunks: chunk A against itself
 // and against every later chunk B, each chunk rebuilt by rescanning the cells.
 //
@@ -70,6 +71,7 @@ struct TriArgs {
     int nhist;                // counters: sorted bin triples, or nb^3 ordered ones
     unsigned long long* out;  // nhist counters (accumulated)
     uint32_t* cursor;
+    uint32_t claim;           // primaries taken per claim of the cursor
     unsigned long long* stats;  // [0] side evaluations, [1] FP64 rechecks
 };
 
@@ -159,73 +161,148 @@ __device__ inline uint32_t lane_prefix_tri(uint64_t m) {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
 
+// One candidate neighbour j of the primary: the FP64 displacement of the
+// definition (minimum image when Lw > 0), rounded to FP32, with the bin of its
+// squared length (from the FP32 square; inside an edge's band from the FP64
+// one) or -1.
+template <bool U>
+__device__ __attribute__((always_inline)) inline int tri_point(const TriArgs& a, const BinTable& T, double dx,
+                                                              double dy, double dz, double Lw, float4& e,
+                                                              uint32_t& rechk) {
+    if (Lw > 0.0) {
+        const double h = a.halfL;
+        dx = dx > h ? dx - Lw : (dx < -h ? dx + Lw : dx);
+        dy = dy > h ? dy - Lw : (dy < -h ? dy + Lw : dy);
+        dz = dz > h ? dz - Lw : (dz < -h ? dz + Lw : dz);
+    }
+    e = make_float4((float)dx, (float)dy, (float)dz, 0.f);
+    int bin = bin32(T, a.top, __builtin_fmaf(e.z, e.z, __builtin_fmaf(e.y, e.y, e.x * e.x)));
+    if (bin == -2) {
+        rechk++;
+        bin = bin_exact(T.E, T.nb, (dx * dx + dy * dy) + dz * dz);
+    }
+    e.w = __uint_as_float(U ? tri_code((uint32_t)bin, (uint32_t)a.nb) : (uint32_t)bin);
+    return bin;
+}
+
 // Scan the cells around primary i (cell cx, cy, cz) and keep the neighbours
-// j > i with side ij in range whose position in the scan order lies in
-// [lo, lo + TRI_CAP), into R.  The side is the FP64 displacement of the
-// definition (minimum image when Lw > 0), binned from its FP32 square; a side
-// inside an edge's band is binned from its FP64 square.  Returns the number
-// found up to the point the scan stopped (all of them when `whole`).  nside
-// (wave-uniform) counts the points scanned.
+// after i with side ij in range whose position in the scan order lies in
+// [lo, lo + TRI_CAP), into R.  Returns the number found up to the point the
+// scan stopped (all of them when `whole`).  nside (wave-uniform) counts the
+// points scanned.
+//
+// "After" is the order of the stored coordinates (z, then y, then x, then the
+// sorted index): a triangle is found once, from its first vertex in that
+// order.  A plane through the primary splits its neighbourhood in halves, so
+// the lists are about equally long (an order by cell splits it at cell faces,
+// and the pairs of the longer lists cost more than the shorter ones save).
+// Rows of a higher z cell lie wholly after i and rows of a lower one wholly
+// before it (the cell of a coordinate never decreases as it grows); rows of
+// i's own z cell are tested point by point.
+//
+// The scan order is the stencil's rows in turn, each row's one or two index
+// ranges (a periodic run of cells wraps once at most), and the points of a
+// range by index.  The ranges of up to 32 rows are fetched at once, one per
+// lane, and their concatenation is then taken 128 positions at a time, two
+// per lane, so that the loads of a step do not wait on one another.
 template <bool W, bool U>
 __device__ uint32_t tri_gather(const TriArgs& a, const BinTable& T, int64_t i, double xi, double yi, double zi,
                                uint32_t icell, int cx, int cy, int cz, double Lw, uint32_t lo, bool whole,
                                const TriList& R, int lane, unsigned long long& nside, uint32_t& rechk) {
     uint32_t running = 0;
     const uint32_t hi = lo + TRI_CAP;
-    for (int s = 0; s < a.nst; s++) {
-        const int4 o = a.stencil[s];
-        int y = cy + o.x, z = cz + o.y, xa = cx + o.z, xb = cx + o.w;
-        // the row's run of cells: one piece, or two where a periodic run wraps
-        // (a run is never longer than the row, so it wraps once at most)
-        int pa1 = 1, pb1 = 0;
-        if (a.L > 0.0) {
-            y += y < 0 ? a.ny : (y >= a.ny ? -a.ny : 0);
-            z += z < 0 ? a.nz : (z >= a.nz ? -a.nz : 0);
-            if (xa < 0) {
-                pa1 = 0;
-                pb1 = xb;
-                xa += a.nx;
-                xb = a.nx - 1;
-            } else if (xb >= a.nx) {
-                pa1 = 0;
-                pb1 = xb - a.nx;
-                xb = a.nx - 1;
-            }
-        } else {
-            if (y < 0 || y >= a.ny || z < 0 || z >= a.nz) continue;
-            xa = max(xa, 0);
-            xb = min(xb, a.nx - 1);
-        }
-        const uint32_t row = ((uint32_t)z * (uint32_t)a.ny + (uint32_t)y) * (uint32_t)a.nx;
-        for (int piece = 0; piece < 2; piece++) {
-            const int x0 = piece ? pa1 : xa, x1 = piece ? pb1 : xb;
-            if (x0 > x1) continue;
-            // points are sorted by cell: only those after the primary count
-            uint32_t b0 = a.cs[row + (uint32_t)x0];
-            const uint32_t b1 = a.cs[row + (uint32_t)x1 + 1u];
-            if ((int64_t)b0 <= i) b0 = (uint32_t)(i + 1);
-            if (b1 > b0) nside += b1 - b0;
-            for (uint32_t j0 = b0; j0 < b1; j0 += 64) {
-                const uint32_t j = j0 + (uint32_t)lane;
-                int bin = -1;
-                float4 e = make_float4(0.f, 0.f, 0.f, 0.f);
-                if (j < b1) {
-                    double dx = a.pos[3 * (size_t)j] - xi, dy = a.pos[3 * (size_t)j + 1] - yi,
-                           dz = a.pos[3 * (size_t)j + 2] - zi;
-                    if (Lw > 0.0) {
-                        const double h = a.halfL;
-                        dx = dx > h ? dx - Lw : (dx < -h ? dx + Lw : dx);
-                        dy = dy > h ? dy - Lw : (dy < -h ? dy + Lw : dy);
-                        dz = dz > h ? dz - Lw : (dz < -h ? dz + Lw : dz);
-                    }
-                    e = make_float4((float)dx, (float)dy, (float)dz, 0.f);
-                    bin = bin32(T, a.top, __builtin_fmaf(e.z, e.z, __builtin_fmaf(e.y, e.y, e.x * e.x)));
-                    if (bin == -2) {
-                        rechk++;
-                        bin = bin_exact(T.E, T.nb, (dx * dx + dy * dy) + dz * dz);
-                    }
-                    e.w = __uint_as_float(U ? tri_code((uint32_t)bin, (uint32_t)a.nb) : (uint32_t)bin);
+    for (int s0 = 0; s0 < a.nst; s0 += 32) {
+        // lane l: range (l & 1) of row s0 + l / 2; mixed: a row of i's z cell
+        uint32_t b0 = 0, b1 = 0;
+        bool mixed = false;
+        const int s = s0 + (lane >> 1);
+        if (s < a.nst) {
+            const int4 o = a.stencil[s];
+            int y = cy + o.x, z = cz + o.y, xa = cx + o.z, xb = cx + o.w;
+            int pa1 = 1, pb1 = 0;
+            bool inside_grid = true;
+            if (a.L > 0.0) {
+                y += y < 0 ? a.ny : (y >= a.ny ? -a.ny : 0);
+                z += z < 0 ? a.nz : (z >= a.nz ? -a.nz : 0);
+                if (xa < 0) {
+                    pa1 = 0;
+                    pb1 = xb;
+                    xa += a.nx;
+                    xb = a.nx - 1;
+                } else if (xb >= a.nx) {
+                    pa1 = 0;
+                    pb1 = xb - a.nx;
+                    xb = a.nx - 1;
                 }
+            } else {
+                inside_grid = y >= 0 && y < a.ny && z >= 0 && z < a.nz;
+                xa = max(xa, 0);
+                xb = min(xb, a.nx - 1);
+            }
+            const int x0 = (lane & 1) ? pa1 : xa, x1 = (lane & 1) ? pb1 : xb;
+            if (inside_grid && x0 <= x1 && z >= cz) {
+                const uint32_t row = ((uint32_t)z * (uint32_t)a.ny + (uint32_t)y) * (uint32_t)a.nx;
+                b0 = a.cs[row + (uint32_t)x0];
+                b1 = a.cs[row + (uint32_t)x1 + 1u];
+                mixed = z == cz;
+            }
+        }
+        const uint32_t cnt = b1 - b0;
+        uint32_t incl = cnt;
+        for (int d = 1; d < 64; d <<= 1) {
+            const uint32_t v = (uint32_t)__shfl_up((int)incl, d, 64);
+            if (lane >= d) incl += v;
+        }
+        const uint32_t excl = incl - cnt;
+        const uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
+        // ranges not yet used up, in scan order (wave-uniform); ranges of i's z cell
+        uint64_t open = __ballot(cnt > 0);
+        const uint64_t mixm = __ballot(mixed);
+        bool stop = false;
+        for (uint32_t c0 = 0; c0 < total && !stop; c0 += 128) {
+            const uint32_t g0 = c0 + (uint32_t)lane, g1 = g0 + 64u;
+            uint32_t j0 = 0, j1 = 0;
+            bool t0 = false, t1 = false;  // the point lies in i's z cell: test its order
+            while (open) {
+                const int L = __builtin_ctzll(open);
+                const uint32_t se = (uint32_t)__builtin_amdgcn_readlane((int)excl, L);
+                const uint32_t sc = (uint32_t)__builtin_amdgcn_readlane((int)cnt, L);
+                const uint32_t sb = (uint32_t)__builtin_amdgcn_readlane((int)b0, L);
+                const bool mx = (mixm >> L) & 1ull;
+                if (se >= c0 + 128u) break;
+                if (g0 - se < sc) {
+                    j0 = sb + (g0 - se);
+                    t0 = mx;
+                }
+                if (g1 - se < sc) {
+                    j1 = sb + (g1 - se);
+                    t1 = mx;
+                }
+                if (se + sc > c0 + 128u) break;  // the range goes on into the next step
+                open &= open - 1;
+            }
+            const bool v0 = g0 < total, v1 = g1 < total;
+            double p0x = 0, p0y = 0, p0z = 0, p1x = 0, p1y = 0, p1z = 0;
+            if (v0) {
+                p0x = a.pos[3 * (size_t)j0];
+                p0y = a.pos[3 * (size_t)j0 + 1];
+                p0z = a.pos[3 * (size_t)j0 + 2];
+            }
+            if (v1) {
+                p1x = a.pos[3 * (size_t)j1];
+                p1y = a.pos[3 * (size_t)j1 + 1];
+                p1z = a.pos[3 * (size_t)j1 + 2];
+            }
+#pragma unroll
+            for (int h = 0; h < 2; h++) {
+                const uint32_t j = h ? j1 : j0;
+                const double px = h ? p1x : p0x, py = h ? p1y : p0y, pz = h ? p1z : p0z;
+                const bool after = !(h ? t1 : t0) ||
+                                   (pz > zi || (pz == zi && (py > yi || (py == yi && (px > xi || (px == xi && j > i))))));
+                const bool v = (h ? v1 : v0) && after;
+                float4 e = make_float4(0.f, 0.f, 0.f, 0.f);
+                int bin = -1;
+                if (v) bin = tri_point<U>(a, T, px - xi, py - yi, pz - zi, Lw, e, rechk);
                 const bool ok = bin >= 0;
                 const uint64_t m = __ballot(ok);
                 if (ok) {
@@ -239,8 +316,10 @@ __device__ uint32_t tri_gather(const TriArgs& a, const BinTable& T, int64_t i, d
                 }
                 running += (uint32_t)__popcll(m);
             }
+            nside += min(total - c0, 128u);
+            stop = !whole && running >= hi;
         }
-        if (!whole && running >= hi) break;
+        if (stop) break;
     }
     wave_sync_lds_tri();
     return running;
@@ -402,12 +481,19 @@ __global__ __launch_bounds__(TRI_MAX_WAVES * 64) void k_triplets(TriArgs a) {
     R2.w = (double*)(R2.idx + TRI_CAP);
     unsigned long long nside = 0;
     uint32_t rechk = 0;
+    // Primaries are claimed `claim` at a time: one atomic per primary on the
+    // one cursor serialised the whole grid (about 11 ns per claim).
+    uint32_t next = 0, last = 0;
     for (;;) {
-        uint32_t ii = 0;
-        if (lane == 0) ii = atomicAdd(a.cursor, 1u);
-        ii = __builtin_amdgcn_readfirstlane(ii);
-        if ((int64_t)ii >= a.n) break;
-        const int64_t i = ii;
+        if (next >= last) {
+            uint32_t base = 0;
+            if (lane == 0) base = atomicAdd(a.cursor, a.claim);
+            base = __builtin_amdgcn_readfirstlane(base);
+            if ((int64_t)base >= a.n) break;
+            next = base;
+            last = (uint32_t)std::min<int64_t>((int64_t)base + a.claim, a.n);
+        }
+        const int64_t i = next++;
         const double xi = a.pos[3 * (size_t)i], yi = a.pos[3 * (size_t)i + 1], zi = a.pos[3 * (size_t)i + 2];
         const double wi = W ? a.w[i] : 0.0;
         const uint32_t cell = a.xkey[i] >> a.xbits;
@@ -752,6 +838,8 @@ extern "C" fcfc_status fcfc_count_triplets(fcfc_plan_t plan, fcfc_cells_t cells,
             int64_t nblk = (int64_t)device_cu_count() * std::max(1, occ);
             const int64_t need = std::max<int64_t>(1, (c->n + waves - 1) / waves);
             nblk = std::min(nblk, need);
+            // about eight claims per wave, at most 32 primaries each
+            a.claim = (uint32_t)std::max<int64_t>(1, std::min<int64_t>(32, c->n / (nblk * waves * 8)));
             if (hipEventRecord(p->ev0, st) != hipSuccess) s = FCFC_EHIP;
             if (s == FCFC_OK) {
                 if (weighted)
