@@ -356,35 +356,53 @@ __device__ __attribute__((always_inline)) inline int tri_counter(const int* t3, 
     return tri_slot(t3, (int)wp, (int)wq, s);
 }
 
-// Every pair p < q of one list.  Each lane takes a group (p, q), (p + 1, q)
+// Every pair p < q of one list.  Each lane takes groups (p, q), (p + 1, q)
 // from the group table (p | q << 8, by column q, so the first G(m) groups are
-// those of a list of m entries), reading the entry of q once for both pairs.
-// When p + 1 = q the group has one pair: the second is formed on valid
-// entries and discarded.
+// those of a list of m entries), reading the entry of q once for both pairs,
+// two groups per step (g and g + 64) so that their reads overlap.  When
+// p + 1 = q the group has one pair; a second group past the list repeats the
+// first.  Such pairs are formed on valid entries and discarded.
 template <bool W, bool U, bool EXACT>
 __device__ void tri_self(const TriArgs& a, const BinTable& T, const TriList& R, int m, double wi, const int* t3,
                          const uint16_t* gtab, unsigned long long* hist, unsigned long long* wl, int lane,
                          unsigned long long& nside, uint32_t& rechk) {
     nside += (unsigned long long)(m * (m - 1) / 2);
     const int ng = (m / 2) * ((m + 1) / 2);
-    for (int g = lane; g < ng; g += 64) {
-        const uint32_t w = gtab[g];
-        const int p0 = w & 255, q = w >> 8, p1 = p0 + 1;
-        const bool two = p1 < q;
-        const float4 eq = R.d[q], a0 = R.d[p0], a1 = R.d[p1];
-        const int s0 = tri_side_bin<EXACT>(a, T, a0, eq, R.idx, p0, R.idx, q, true, rechk);
-        int s1 = tri_side_bin<EXACT>(a, T, a1, eq, R.idx, p1, R.idx, q, two, rechk);
-        s1 = two ? s1 : -1;
-        const uint32_t cq = __float_as_uint(eq.w);
-        if (s0 >= 0) {
-            const int k = tri_counter<U>(t3, __float_as_uint(a0.w), cq, s0);
-            atomicAdd(&hist[k], 1ull);
-            if (W) tri_add_weight(wl, a.nhist, k, tri_weight(wi, R.w[p0], R.w[q]) * a.wscale);
+    for (int g = lane; g < ng; g += 128) {
+        const bool second = g + 64 < ng;
+        const uint32_t wA = gtab[g], wB = gtab[second ? g + 64 : g];
+        int p[4], q[4];
+        bool live[4];
+        p[0] = wA & 255;
+        q[0] = wA >> 8;
+        p[1] = p[0] + 1;
+        q[1] = q[0];
+        p[2] = wB & 255;
+        q[2] = wB >> 8;
+        p[3] = p[2] + 1;
+        q[3] = q[2];
+        live[0] = true;
+        live[1] = p[1] < q[1];
+        live[2] = second;
+        live[3] = second && p[3] < q[3];
+        const float4 eqA = R.d[q[0]], eqB = R.d[q[2]];
+        float4 ep[4];
+#pragma unroll
+        for (int u = 0; u < 4; u++) ep[u] = R.d[p[u]];
+        int sb[4];
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            sb[u] = tri_side_bin<EXACT>(a, T, ep[u], u < 2 ? eqA : eqB, R.idx, p[u], R.idx, q[u], live[u], rechk);
+            sb[u] = live[u] ? sb[u] : -1;
         }
-        if (s1 >= 0) {
-            const int k = tri_counter<U>(t3, __float_as_uint(a1.w), cq, s1);
-            atomicAdd(&hist[k], 1ull);
-            if (W) tri_add_weight(wl, a.nhist, k, tri_weight(wi, R.w[p1], R.w[q]) * a.wscale);
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            if (sb[u] >= 0) {
+                const uint32_t cq = __float_as_uint(u < 2 ? eqA.w : eqB.w);
+                const int k = tri_counter<U>(t3, __float_as_uint(ep[u].w), cq, sb[u]);
+                atomicAdd(&hist[k], 1ull);
+                if (W) tri_add_weight(wl, a.nhist, k, tri_weight(wi, R.w[p[u]], R.w[q[u]]) * a.wscale);
+            }
         }
     }
 }
