@@ -397,11 +397,16 @@ __device__ void tri_self(const TriArgs& a, const BinTable& T, const TriList& R, 
         }
 #pragma unroll
         for (int u = 0; u < 4; u++) {
-            if (sb[u] >= 0) {
-                const uint32_t cq = __float_as_uint(u < 2 ? eqA.w : eqB.w);
-                const int k = tri_counter<U>(t3, __float_as_uint(ep[u].w), cq, sb[u]);
-                atomicAdd(&hist[k], 1ull);
-                if (W) tri_add_weight(wl, a.nhist, k, tri_weight(wi, R.w[p[u]], R.w[q[u]]) * a.wscale);
+            const uint32_t cq = __float_as_uint(u < 2 ? eqA.w : eqB.w);
+            const int k = tri_counter<U>(t3, __float_as_uint(ep[u].w), cq, max(sb[u], 0));
+            if (W) {
+                if (sb[u] >= 0) {
+                    atomicAdd(&hist[k], 1ull);
+                    tri_add_weight(wl, a.nhist, k, tri_weight(wi, R.w[p[u]], R.w[q[u]]) * a.wscale);
+                }
+            } else {
+                // a pair out of range adds to this lane's dump counter (no branch)
+                atomicAdd(&hist[sb[u] >= 0 ? k : a.nhist + lane], 1ull);
             }
         }
     }
@@ -768,7 +773,7 @@ extern "C" fcfc_status fcfc_count_triplets(fcfc_plan_t plan, fcfc_cells_t cells,
     a.off_band = B.off_band;
     a.off_e = B.off_e;
     a.off_hist = B.bytes;
-    a.off_t3 = a.off_hist + bin_al16(a.nhist * 8);
+    a.off_t3 = a.off_hist + bin_al16((a.nhist + 64) * 8);  // counters, then 64 dump counters
     a.off_ptab = a.off_t3 + bin_al16((TRI_MAX_BINS + 1) * 4);
     a.off_wl = a.off_ptab + bin_al16(TRI_GROUPS * 2);
     a.off_lists = a.off_wl + (weighted ? bin_al16(a.nhist * 24) : 0);
