@@ -448,7 +448,7 @@ fcfc_status fcfc_diag_transcendental(double *rsq_max_rel, double *rcp_max_rel, d
  *   mu_tolA, mu_tolC  (s, mu): a pair whose FP32 mu*n2 lies closer than
  *              mu_tolA * rsq(d2) + mu_tolC to an interior mu edge is rechecked
  *   trans_rel  relative error assumed for the hardware rsq and rcp
- *   has_big    the tables with twice the entries exist (fcfc_plan_table 2, 3)
+ *   has_big    the larger tables exist (fcfc_plan_table 2, 3)
  * Errors: FCFC_EINVAL (null), FCFC_ESTATE (open box before its bounds are set).
  */
 typedef struct fcfc_numerics {
@@ -465,8 +465,9 @@ fcfc_status fcfc_plan_numerics(fcfc_plan_t plan, fcfc_numerics *out);
 /*
  * fcfc_plan_table -- copy one of a plan's squared-separation look-up tables
  * (Sect. 3.2.3) with its bands.  which: 0 the first axis (s or s_perp), 1 the
- * second ((s_perp, pi): pi), 2 and 3 the same with twice the entries (when
- * has_big).  Host only.  Every output may be NULL.
+ * second ((s_perp, pi): pi), 2 and 3 the same with more entries (when
+ * has_big: twice as many for s and (s, mu), four times for (s_perp, pi)).
+ * Host only.  Every output may be NULL.
  *   E          n+1 squared edges e_k * e_k in FP64 (n = bins of the axis)
  *   lo, hi     n+1 FP32 band ends: an FP32 value v < lo[k] stands for a
  *              squared separation below E[k], v >= hi[k] for one at or above

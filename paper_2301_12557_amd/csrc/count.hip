@@ -59,6 +59,7 @@ __device__ inline Item ldc_item(const Item* p, uint32_t i) {
 enum { COUNT_SINGLE = 0, COUNT_BATCH = 1, COUNT_TREE = 2 };
 constexpr int CT_MAX = 1024;        // threads per workgroup (16 waves: 4 per SIMD, one workgroup per CU)
 constexpr int QCAP = 192;           // compaction queue entries per wave (63 + 64 P), plus one dump entry
+constexpr int QCAP_MID = 127;       // mid-point queues (16-byte entries) drain after each A point: 63 + 64
 // recheck entries per wave: RB_FLUSH - 1 waiting plus the up to 64 of one
 // binning pass (rechecks are rare; a small buffer leaves LDS for more waves)
 constexpr int RB_FLUSH = 32;
@@ -527,7 +528,7 @@ void k_count(const CountArgs* argp) {
     s.hist = (uint32_t*)(smem + a.off_hist);
     s.wl = (unsigned long long*)(smem + a.off_whist);
     constexpr int QS = QStride<KIND, LOS>::value;
-    s.qf = (float*)(smem + a.off_q) + (size_t)wave * (QCAP + 1) * QS;
+    s.qf = (float*)(smem + a.off_q) + (size_t)wave * ((QS == 4 ? QCAP_MID : QCAP) + 1) * QS;
     s.qf_lane = s.qf + lane * QS;
     s.rb = (uint32_t*)(smem + a.off_rb) + (size_t)wave * RB_CAP * 3;
     s.astage = (float4*)(smem + a.off_astage) + (size_t)wave * ASTAGE;
@@ -883,8 +884,16 @@ void k_count(const CountArgs* argp) {
                             }
                         }
                         qn += (int)__popcll(m);
+                        if (QS == 4 && qn >= 64) {
+                            // 16-byte entries: drain after each A point, so the
+                            // queue holds at most 63 + 64 entries
+                            wave_sync_lds();
+                            bin_queue<KIND, LOS, W>(a, k, s, hist_l, qn - 64, 64, lane, c);
+                            wave_sync_lds();
+                            qn -= 64;
+                        }
                     }
-                    while (qn >= 64) {
+                    while (QS != 4 && qn >= 64) {
                         wave_sync_lds();
                         bin_queue<KIND, LOS, W>(a, k, s, hist_l, qn - 64, 64, lane, c);
                         wave_sync_lds();
@@ -1135,7 +1144,7 @@ static fcfc_status setup_launch(Plan* p, bool is_auto, bool weighted, bool batch
     L.nrows = stencil_rows(p, is_auto, L.rows);
     const bool two = (p->kind == FCFC_BIN_SPERP_PI);
     const bool mid = (p->los == FCFC_LOS_MIDPOINT && p->kind != FCFC_BIN_S);
-    const int qbytes = (QCAP + 1) * (mid ? 16 : 12);
+    const int qbytes = mid ? (QCAP_MID + 1) * 16 : (QCAP + 1) * 12;
     const int per_wave = qbytes + RB_CAP * 12 + (mid ? ASTAGE * 16 : 0);
     int dev = 0, maxlds = 65536;
     FCFC_HIP(hipGetDevice(&dev));

@@ -274,8 +274,10 @@ fcfc_status plan_finalize_numerics(Plan* p) {
     d2m.C = 3.3 * u + 1e-15;
     int lg = p->tune.lut_log2 > 0 ? std::min(14, std::max(8, p->tune.lut_log2)) : 13;
 
-    // With the default size, tables with twice the entries are built too; a
-    // count uses them when they leave as many waves resident.
+    // With the default size, larger tables are built too (twice the entries
+    // for s and (s, mu); for the (s_perp, pi) pair, whose default tables are
+    // half size, four times); a count uses them when they leave as many waves
+    // resident.
     const bool big = p->tune.lut_log2 <= 0;
     p->has_big = false;
     p->lut1b = Lut1D();
@@ -330,8 +332,8 @@ fcfc_status plan_finalize_numerics(Plan* p) {
         FCFC_TRY(build_lut(p->lut1, p->e1, m1, std::max(8, lg - 1)));
         FCFC_TRY(build_lut(p->lut2, p->e2, m2, std::max(8, lg - 1)));
         if (big) {
-            FCFC_TRY(build_lut(p->lut1b, p->e1, m1, lg));
-            FCFC_TRY(build_lut(p->lut2b, p->e2, m2, lg));
+            FCFC_TRY(build_lut(p->lut1b, p->e1, m1, std::min(14, lg + 1)));
+            FCFC_TRY(build_lut(p->lut2b, p->e2, m2, std::min(14, lg + 1)));
         }
         double S = p->lut1.E[p->n1] + p->lut2.E[p->n2];
         p->r2prune32 = f32_up(S + 1.5 * d2m(S) + 2.0 * S * 1.2e-7);
