@@ -527,3 +527,73 @@ def test_kernel_fp32_decisions_match_the_oracle(gi):
     # two thirds of the pairs are built within a few ulps of an edge and are
     # mostly rechecked; pairs at the workload's own separations rarely are
     assert u_rate < 0.02
+
+
+# ---------------------------------------------------------------------------
+# triangle sides
+# ---------------------------------------------------------------------------
+
+U32 = 2.0 ** -24
+U64 = 2.0 ** -53
+
+
+def _min_image(d, box):
+    if box <= 0:
+        return d
+    h = 0.5 * box
+    return np.where(d > h, d - box, np.where(d < -h, d + box, d))
+
+
+@pytest.mark.parametrize("box,r,scale", [(1000.0, 30.0, 1000.0), (120.0, 30.0, 120.0), (0.0, 30.0, 2000.0)])
+def test_triangle_side_fp32_error_within_the_band_model(box, r, scale):
+    """The triangle kernel bins the side between two neighbours p, q of a
+    primary from their FP32 displacements (each the FP64 displacement of the
+    definition, minimum image in a periodic box, rounded to FP32): the FP32
+    difference per axis and the fma chain of its squares.  Its table bands are
+    built from |Q32 - Q64| <= 2 sqrt3 e sqrt(Q) + 3 e^2 + 3.3 u Q with e twice
+    the per-axis error 4 u r' + 4 u64 (L + r').  Checked here against the FP64
+    side of the definition formed directly from the stored positions, over
+    random and adversarial triples: neighbours at the reach in every axis,
+    across the periodic faces, and far from the origin of an open box."""
+    rng = np.random.default_rng(int(box) + 7)
+    n = 400_000
+    rr = r * (1.0 + 1e-6) + 1e-9 * max(box, 0.0)
+    e = 2.0 * (4.0 * U32 * rr + 4.0 * 2.0 ** -52 * (max(box, 0.0) + rr))
+    hi = box if box > 0 else scale
+    P = rng.uniform(0.0, hi, (n, 3))
+    # neighbour offsets: uniform in the ball, or on the reach along the axes
+    off = []
+    for _ in range(2):
+        v = rng.normal(size=(n, 3))
+        v /= np.linalg.norm(v, axis=1)[:, None]
+        rad = r * rng.uniform(0, 1, n) ** (1 / 3)
+        edge = rng.random(n) < 0.3
+        rad[edge] = r * (1 - rng.uniform(0, 1e-6, edge.sum()))
+        axis = rng.random(n) < 0.2
+        v[axis] = np.sign(rng.normal(size=(axis.sum(), 3))) / np.sqrt(3.0)
+        off.append(v * rad[:, None])
+    if box > 0:
+        # primaries within r of a face, so that neighbours wrap
+        face = rng.random(n) < 0.5
+        P[face, 0] = rng.uniform(0, r, face.sum())
+    Q1 = P + off[0]
+    Q2 = P + off[1]
+    if box > 0:
+        Q1 = np.mod(Q1, box)
+        Q2 = np.mod(Q2, box)
+    # the kernel: FP64 displacements from the primary, rounded to FP32
+    d1 = _min_image(Q1 - P, box).astype(F32)
+    d2 = _min_image(Q2 - P, box).astype(F32)
+    ex = d2 - d1
+    v32 = fma32(ex[:, 2], ex[:, 2], fma32(ex[:, 1], ex[:, 1], ex[:, 0] * ex[:, 0])).astype(F64)
+    # the definition, from the stored positions
+    D = _min_image(Q2 - Q1, box)
+    V = (D[:, 0] * D[:, 0] + D[:, 1] * D[:, 1]) + D[:, 2] * D[:, 2]
+    bound = 2.0 * np.sqrt(3.0) * e * np.sqrt(V) + 3.0 * e * e + (3.3 * U32 + 1e-15) * V
+    err = np.abs(v32 - V)
+    share = float(np.max(err / bound))
+    print(f"[bands] triangle sides, box {box}, r {r}: {n} pairs, largest share of the bound used {share:.3f}")
+    assert share < 1.0
+    # the bound is not loose by orders of magnitude (it would then send many
+    # sides to the FP64 recheck for nothing)
+    assert share > 0.05
