@@ -48,6 +48,8 @@ def parse():
     ap.add_argument("--binning-values", type=float, default=6.4e9, help="squared separations per binning call")
     ap.add_argument("--no-triplets", action="store_true", help="skip the triangle-count measurement")
     ap.add_argument("--no-c3", action="store_true", help="skip the full-size C3 survey counts (DD, DR, RR)")
+    ap.add_argument("--no-fixed", action="store_true",
+                    help="skip the roofline of C2 unweighted, C5 and C1 beside the headline")
     ap.add_argument("--shards", type=int, default=0,
                     help="also count each of G work-list shards (one GPU's share of a G-GPU run) and report "
                          "their kernel times")
@@ -338,6 +340,43 @@ def c5_section(fcfc, synth, model):
     res["learned_k_gain"] = res["analytic"]["ms"] / res["learned_k"]["ms"]
     res["autotuned_gain"] = res["analytic"]["ms"] / res["autotuned"]["ms"]
     return res
+
+
+def fixed_axis_section(fcfc, synth, torch, x2):
+    """The counting kernel's roofline on the other fixed-axis workloads: C2
+    unweighted (the headline catalogue), C5 and C1.  Kernel time by HIP events,
+    best of 3 launches on one cell set."""
+    out = {}
+
+    def run(name, desc, x, kind, e1, e2, box):
+        plan = fcfc.Plan(kind, e1, e2, box=box, n_hint=len(x))
+        cells = plan.build_cells(x)
+        ks = []
+        for _ in range(3):
+            plan.count(cells)
+            ks.append(plan.stats()["kernel_ms"])
+        st = plan.stats()
+        k = min(ks)
+        achieved = FLOP_PER_DISTANCE * st["candidates"] / (k * 1e-3) / 1e12
+        out[name] = {"workload": desc, "kernel_ms": k, "distance_evaluations": st["candidates"],
+                     "in_range_pairs": st["in_range"], "kernel_pairs_per_s": st["in_range"] / (k * 1e-3),
+                     "cells_per_rmax": st["cells_per_rmax"],
+                     "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                                  "frac": achieved / PEAK_FP32_TFLOPS}}
+        cells.close()
+        plan.close()
+
+    w2 = synth.workload(2)
+    run("c2_unweighted", "C2 catalogue, (s,mu) 40x100, LOS z, auto, unweighted", x2, "smu", w2["edges1"],
+        w2["edges2"], 2000.0)
+    x5 = synth.lognormal_box_torch(10_000_000, 3000.0, synth.config_seed(5), device="cuda")
+    run("c5", "C5: periodic L=3000, 10,000,000 lognormal points (GPU generator), 50 log s bins [0.1,50), auto",
+        x5, "s", synth.log_edges(0.1, 50.0, 50), None, 3000.0)
+    del x5
+    w1 = synth.workload(1)
+    run("c1", "C1: periodic L=1000, 20,000 uniform points, 40 s bins [0,200), auto",
+        torch.from_numpy(w1["x1"]).to("cuda"), "s", w1["edges1"], None, 1000.0)
+    return out
 
 
 def clustered_section(fcfc, synth, model):
@@ -904,6 +943,11 @@ def main():
             "atomic_time_ms_at_peak": atomic_time * 1e3, "kernel_ms": kernel_ms,
             "frac": atomic_time / kernel_s}
         log(f"measured peaks: {pk}")
+    if args.workload == "c2" and not args.no_fixed:
+        from paper_2301_12557_amd import synth
+        res["fixed_axis"] = fixed_axis_section(fcfc, synth, torch, x)
+        log("fixed-axis workloads: " + " ".join(f"{k} {v['kernel_ms']:.2f} ms ({v['roofline']['frac']:.3f})"
+                                                for k, v in res["fixed_axis"].items()))
     if not (args.no_c4 and args.no_learned):
         from paper_2301_12557_amd import synth
         mocks = make_mocks(synth, args.c4_mocks)
