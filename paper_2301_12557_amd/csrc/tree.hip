@@ -12,8 +12,9 @@
 //
 // Level by level, the points of each node are ordered along the axis of the
 // longest extent of the node's region (the parent's region cut at the
-// parent's split): a stable sort by the FP32 coordinate on that axis, then a
-// stable sort by node, both with the library's LSD radix sort.  The paper
+// parent's split): one LSD radix sort of a 32-bit key, the node in the high
+// bits and the coordinate on 2^(32 - l) steps across the node's region in the
+// low ones.  The paper
 // splits along the axis of largest variance; the region's extent needs no
 // reduction over the points and gives the same tree on any device.
 #include <math.h>
@@ -30,10 +31,6 @@ namespace fcfc {
 __host__ __device__ inline uint32_t tunit_bound(int l, uint64_t k, uint64_t nl) { return (uint32_t)((k * nl) >> l); }
 __device__ inline uint32_t tnode_of_unit(int l, uint64_t u, uint64_t nl) {
     return (uint32_t)((((u + 1) << l) - 1) / nl);
-}
-__device__ inline uint32_t ordered_f32(float f) {
-    const uint32_t b = __float_as_uint(f);
-    return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
 }
 
 // axis of the longest extent of each node's region at level l (ties: lowest axis)
@@ -53,22 +50,29 @@ __global__ void k_tree_dims(int l, const double* __restrict__ region, int* __res
     dims[k] = d;
 }
 
+// Sort key of each element at level l: its node (the high l bits; nodes lie
+// in position order, so sorting keeps every node's range) and its coordinate
+// along the node's axis, placed on 2^(32 - l) steps across the node's region
+// (the low bits).  Points on one step keep their order; any order of them is
+// a valid split, since every box is formed from the points afterwards.
 __global__ void k_tree_keys(int l, int64_t n, int leaf, uint64_t nl, const double* __restrict__ xyz,
-                            const uint32_t* __restrict__ idx, const int* __restrict__ dims, uint32_t* __restrict__ key,
+                            const uint32_t* __restrict__ idx, const int* __restrict__ dims,
+                            const double* __restrict__ region, uint32_t* __restrict__ key,
                             uint32_t* __restrict__ val) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const uint32_t k = tnode_of_unit(l, (uint64_t)i / (uint64_t)leaf, nl);
-    key[i] = ordered_f32((float)xyz[3 * (size_t)idx[i] + dims[k]]);
+    const int d = dims[k];
+    const double* r = region + 6 * ((size_t)(1u << l) - 1 + k);
+    const double lo = r[d], ext = r[3 + d] - r[d];
+    const double x = xyz[3 * (size_t)idx[i] + d];
+    const int b = 32 - l;
+    const double steps = ldexp(1.0, b);
+    double t = ext > 0.0 ? (x - lo) / ext * steps : 0.0;
+    t = fmin(fmax(t, 0.0), steps - 1.0);
+    const uint64_t q = (uint64_t)t;
+    key[i] = (uint32_t)((b < 32 ? ((uint64_t)k << b) : 0ull) | q);
     val[i] = (uint32_t)i;
-}
-
-// node of each element's position before the coordinate sort
-__global__ void k_tree_nodekeys(int l, int64_t n, int leaf, uint64_t nl, const uint32_t* __restrict__ val,
-                                uint32_t* __restrict__ key) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    key[i] = tnode_of_unit(l, (uint64_t)val[i] / (uint64_t)leaf, nl);
 }
 
 __global__ void k_tree_permute(int64_t n, const uint32_t* __restrict__ val, const uint32_t* __restrict__ in,
@@ -301,12 +305,9 @@ fcfc_status build_tree(Plan* p, const fcfc_catalog* cat, hipStream_t st, Cells**
         const unsigned nb = blocks_for((int64_t)1 << l);
         hipLaunchKernelGGL(k_tree_dims, dim3(nb), dim3(256), 0, st, l, region, dims);
         hipLaunchKernelGGL(k_tree_keys, dim3(blocks_for(n)), dim3(256), 0, st, l, n, leaf, nl, cat->xyz, idx, dims,
-                           key, val);
+                           region, key, val);
         uint32_t *k0 = key, *v0 = val, *k1 = tk, *v1 = tv;
         radix_sort_pairs(&k0, &v0, &k1, &v1, n, 32, sort_scr, st);
-        // v0: positions ordered by coordinate; now stably by node
-        hipLaunchKernelGGL(k_tree_nodekeys, dim3(blocks_for(n)), dim3(256), 0, st, l, n, leaf, nl, v0, k0);
-        if (l > 0) radix_sort_pairs(&k0, &v0, &k1, &v1, n, l, sort_scr, st);
         hipLaunchKernelGGL(k_tree_permute, dim3(blocks_for(n)), dim3(256), 0, st, n, v0, idx, idx2);
         std::swap(idx, idx2);
         hipLaunchKernelGGL(k_tree_regions, dim3(nb), dim3(256), 0, st, l, leaf, nl, cat->xyz, idx, dims, region);
