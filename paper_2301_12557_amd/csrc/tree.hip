@@ -494,11 +494,14 @@ __global__ __launch_bounds__(256) void k_tree_items(TreeWL w, const uint32_t* __
     if (!items) icount[tid] = cnt;
 }
 
-// B tree level whose subtrees the work-list threads take: about 2^16 threads
+// B tree level whose subtrees the work-list threads take: about 2^19 threads
+// (each walks its subtree alone, so it takes many of them to cover the
+// latency of the walk; on MI355X 2^16 left the full C3 DR work list at 100 ms,
+// 2^19 at 55 ms)
 int tree_wl_split(const Cells* ca, const Cells* cb) {
     const uint64_t nla = tree_leaves(ca);
     int s = 0;
-    while (s < cb->tree_levels && (nla << s) < 65536) s++;
+    while (s < cb->tree_levels && (nla << s) < 524288) s++;
     return s;
 }
 
