@@ -79,6 +79,32 @@ def test_grid_sizes_agree():
         assert_same(got, ref, what=f"k={k}")
 
 
+def test_vertex_order_ties_and_many_stencil_rows():
+    """A triangle is found from its first vertex in the order of the stored
+    coordinates (z, y, x, then index): an open lattice puts many points on
+    one z plane, one y line and one spot (duplicates), so every tie-break of
+    that order decides.  Clustered points with 4 cells per r_max give more
+    than 32 stencil rows (the gather fetches them 32 at a time) and chunked
+    lists, with ordered counters (13 bins) and sorted ones (20 bins)."""
+    g = np.arange(5, dtype=np.float64)
+    lat = np.stack(np.meshgrid(g, g, g, indexing="ij"), -1).reshape(-1, 3)
+    lat = np.concatenate([lat, lat[::7]])  # duplicated points
+    e = [0.0, 0.5, 1.2, 1.5, 1.8, 2.1, 3.1]
+    note("triplets: open lattice 5^3 with duplicates")
+    got, _ = _gpu_tri(lat, e, 0.0)
+    assert_same(got, oracle.triplets(lat, edges=e, box=0.0, method="brute"), what="open lattice")
+    rng = np.random.default_rng(21)
+    cen = rng.uniform(10, 40, (4, 3))
+    x = cen[rng.integers(0, 4, 1500)] + rng.normal(0, 1.0, (1500, 3))
+    x = np.concatenate([x, rng.uniform(0, 50, (500, 3))])
+    for nb in (13, 20):
+        e = np.linspace(0.0, 5.0, nb + 1)
+        ref = oracle.triplets(x, edges=e, box=0.0)
+        note(f"triplets: clustered open box, 4 cells per r_max, {nb} bins")
+        got, st = _gpu_tri(x, e, 0.0, cells_per_rmax=4)
+        assert_same(got, ref, what=f"clustered k=4 nb={nb}")
+
+
 def test_tiny_catalogues():
     rng = np.random.default_rng(14)
     e = [0.0, 1.0, 2.0, 3.0]
