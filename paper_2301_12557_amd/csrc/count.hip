@@ -504,13 +504,15 @@ __device__ __attribute__((always_inline)) inline void bin_queue(ArgsRef a, const
 // waves per SIMD, which leaves each lane 80 VGPRs (512 per SIMD, allocated 8 at
 // a time): one register more drops a wave from every SIMD (on MI355X the
 // batched 200-mock pipeline ran 156 ms per 50 mocks at 79 VGPRs, 199 ms at 81).
-// Weighted and mid-point counts are held to 16 waves per CU by their LDS
-// tables and queues, so they keep the registers (capping the mid-point ones
-// at 80 only added spills).
+// Unweighted s counts are held to 64 VGPRs, eight waves per SIMD in two
+// 16-wave workgroups (C5 on MI355X: 4.21 -> 4.01 ms; the few spills sit in
+// the per-item code, outside the loop over B points).  Weighted and mid-point counts are held to 16 waves per
+// CU by their LDS tables and queues, so they keep the registers (capping the
+// mid-point ones at 80 only added spills).
 // MODE: COUNT_SINGLE (one grid count), COUNT_BATCH (a stacked build's pair
 // list) or COUNT_TREE (a count over k-d tree leaves).
 template <int KIND, int LOS, bool AUTO, bool W, int P, int MODE>
-__global__ __launch_bounds__(CT_MAX) __attribute__((amdgpu_waves_per_eu((W || LOS || MODE == COUNT_TREE) ? 4 : 6)))
+__global__ __launch_bounds__(CT_MAX) __attribute__((amdgpu_waves_per_eu((W || LOS || MODE == COUNT_TREE) ? 4 : (KIND == FCFC_BIN_S ? 8 : 6))))
 void k_count(const CountArgs* argp) {
     constexpr bool BATCH = MODE == COUNT_BATCH;
     constexpr bool TREE = MODE == COUNT_TREE;
@@ -1160,7 +1162,8 @@ static fcfc_status setup_launch(Plan* p, bool is_auto, bool weighted, bool batch
                (weighted ? al16(p->nbins * 16) : 0);
     };
     // Workgroup size for a given shared part, and the waves resident per CU.
-    // Default, from timings on MI355X: two 12-wave workgroups per CU (three
+    // Default, from timings on MI355X: two 16-wave workgroups per CU when
+    // the registers and the LDS allow it, else two 12-wave workgroups (three
     // waves per SIMD each) when they fit, else one workgroup of the largest
     // even wave count that fits (odd counts leave the SIMDs unevenly loaded
     // and ran measurably slower).
@@ -1172,8 +1175,13 @@ static fcfc_status setup_launch(Plan* p, bool is_auto, bool weighted, bool batch
         } else {
             waves = 16;
             while (waves > 1 && lds_for(waves) > maxlds) waves--;
-            int occ12 = 0;
-            if (lds_for(12) <= maxlds &&
+            int occ16 = 0, occ12 = 0;
+            if (waves == 16 &&
+                hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ16, (const void*)L.kern, 16 * 64, lds_for(16)) ==
+                    hipSuccess &&
+                occ16 >= 2)
+                waves = 16;
+            else if (lds_for(12) <= maxlds &&
                 hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ12, (const void*)L.kern, 12 * 64, lds_for(12)) ==
                     hipSuccess &&
                 occ12 >= 2)
