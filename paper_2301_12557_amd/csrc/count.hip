@@ -500,19 +500,21 @@ __device__ __attribute__((always_inline)) inline void bin_queue(ArgsRef a, const
     }
 }
 
-// Unweighted counts along a fixed axis run two 12-wave workgroups per CU, six
-// waves per SIMD, which leaves each lane 80 VGPRs (512 per SIMD, allocated 8 at
-// a time): one register more drops a wave from every SIMD (on MI355X the
-// batched 200-mock pipeline ran 156 ms per 50 mocks at 79 VGPRs, 199 ms at 81).
-// Unweighted s counts are held to 64 VGPRs, eight waves per SIMD in two
-// 16-wave workgroups (C5 on MI355X: 4.21 -> 4.01 ms; the few spills sit in
-// the per-item code, outside the loop over B points).  Weighted and mid-point counts are held to 16 waves per
+// Unweighted (s_perp, pi) counts along a fixed axis run two 12-wave
+// workgroups per CU, six waves per SIMD, which leaves each lane 80 VGPRs (512
+// per SIMD, allocated 8 at a time): one register more drops a wave from every
+// SIMD (on MI355X the batched 200-mock pipeline ran 156 ms per 50 mocks at 79
+// VGPRs, 199 ms at 81, when it ran at six waves).
+// Unweighted s and (s, mu) counts are held to 64 VGPRs, eight waves per SIMD
+// in two 16-wave workgroups (on MI355X: C5 4.21 -> 4.01 ms, C2 unweighted
+// 4.46 -> 4.32 ms, the 200-mock batch 8 % faster; the spills this costs sit
+// in the per-item code, outside the loop over B points).  Weighted and mid-point counts are held to 16 waves per
 // CU by their LDS tables and queues, so they keep the registers (capping the
 // mid-point ones at 80 only added spills).
 // MODE: COUNT_SINGLE (one grid count), COUNT_BATCH (a stacked build's pair
 // list) or COUNT_TREE (a count over k-d tree leaves).
 template <int KIND, int LOS, bool AUTO, bool W, int P, int MODE>
-__global__ __launch_bounds__(CT_MAX) __attribute__((amdgpu_waves_per_eu((W || LOS || MODE == COUNT_TREE) ? 4 : (KIND == FCFC_BIN_S ? 8 : 6))))
+__global__ __launch_bounds__(CT_MAX) __attribute__((amdgpu_waves_per_eu((W || LOS || MODE == COUNT_TREE) ? 4 : (KIND != FCFC_BIN_SPERP_PI ? 8 : 6))))
 void k_count(const CountArgs* argp) {
     constexpr bool BATCH = MODE == COUNT_BATCH;
     constexpr bool TREE = MODE == COUNT_TREE;
